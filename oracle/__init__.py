@@ -1,0 +1,201 @@
+"""FP64 CPU oracle for the 3rd-order SRM stochastic wave (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The GPU library never imports,
+links or executes anything here, and this package imports nothing from it.
+
+The arithmetic lives in ``srm3_oracle.c`` (plain C, FP64, libm cos/sin, OpenMP
+over independent outputs).  This file only builds and marshals:
+
+* ``phases``          -- fixed-point phase angle of every line (Philox4x32-10)
+* ``biphase``         -- fixed-point biphase table (seeded or zero)
+* ``line_terms``      -- raw bicoherence sum, rescale factor, Sigma, pair count
+* ``coefficients``    -- C_k by explicit enumeration of the pair set P(k)
+* ``field`` / ``field_points`` / ``field_nested`` -- direct cosine sums
+
+Every function cites the part of the paper it follows in the C source.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "srm3_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_lp = ctypes.POINTER(ctypes.c_long)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into ``oracle/liboracle.so`` with gcc (FP64, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int), ("nw", ctypes.c_int), ("W", ctypes.c_int),
+                ("dk", ctypes.c_double), ("dw", ctypes.c_double),
+                ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.oracle_phases.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _u32p]
+        L.oracle_biphase.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _u32p]
+        L.oracle_line_terms.argtypes = [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_int,
+                                        _dp, _dp, _dp, _lp]
+        L.oracle_line_terms.restype = ctypes.c_int
+        L.oracle_coefficients.argtypes = [ctypes.POINTER(_Problem), _u32p, ctypes.c_long,
+                                          _lp, _dp]
+        L.oracle_coefficients.restype = ctypes.c_int
+        L.oracle_field_flat.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
+        L.oracle_field_nested.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
+        L.oracle_field_points.argtypes = [ctypes.c_int] * 4 + [_dp, ctypes.c_long, _ip, _ip, _dp]
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+    return out
+
+
+def phases(n_kappa: int, n_omega: int, seed: int) -> np.ndarray:
+    U = np.zeros((n_kappa, 2 * n_omega - 1), dtype=np.uint32)
+    lib().oracle_phases(n_kappa, n_omega, ctypes.c_uint64(int(seed)), _ptr(U, _u32p))
+    return U
+
+
+def biphase(support_w: int, seed: Optional[int]) -> np.ndarray:
+    """Seeded biphase table; ``seed=None`` gives beta == 0."""
+    n = 2 * support_w - 1
+    B = np.zeros((n, n), dtype=np.uint32)
+    mode = 1 if seed is None else 0
+    lib().oracle_biphase(support_w, mode, ctypes.c_uint64(0 if seed is None else int(seed)),
+                         _ptr(B, _u32p))
+    return B
+
+
+class Problem:
+    """Inputs of one simulation (host FP64 arrays), kept alive for ctypes."""
+
+    def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, b2, beta, cap):
+        self.S = np.ascontiguousarray(S, dtype=np.float64)
+        self.b2 = np.ascontiguousarray(b2, dtype=np.float64)
+        self.beta = np.ascontiguousarray(beta, dtype=np.uint32)
+        nc, nwc = 2 * n_omega - 1, 2 * support_w - 1
+        assert self.S.shape == (n_kappa, nc)
+        assert self.b2.shape == (nwc, nwc) and self.beta.shape == (nwc, nwc)
+        assert 1 <= support_w <= n_omega
+        self.n_kappa, self.n_omega, self.W = n_kappa, n_omega, support_w
+        self.d_kappa, self.d_omega, self.cap = d_kappa, d_omega, cap
+        self._c = _Problem(n_kappa, n_omega, support_w, d_kappa, d_omega,
+                           _ptr(self.S, _dp), _ptr(self.b2, _dp), _ptr(self.beta, _u32p), cap)
+
+    @classmethod
+    def from_workload(cls, wl, beta_zero: bool = False, b2=None, beta=None, S=None,
+                      cap=None):
+        b2 = wl.b2_dense() if b2 is None else b2
+        if beta is None:
+            beta = biphase(wl.support_w, None if beta_zero else wl.beta_seed)
+        return cls(wl.n_kappa, wl.n_omega, wl.support_w, wl.d_kappa, wl.d_omega,
+                   wl.spectrum() if S is None else S, b2, beta,
+                   wl.cap if cap is None else cap)
+
+    @property
+    def n_cols(self):
+        return 2 * self.n_omega - 1
+
+    def line_terms(self, kk: int, kw: int):
+        sr, rho, sig = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        npairs = ctypes.c_long()
+        st = lib().oracle_line_terms(ctypes.byref(self._c), kk, kw, ctypes.byref(sr),
+                                     ctypes.byref(rho), ctypes.byref(sig), ctypes.byref(npairs))
+        return dict(status=st, sigma_raw=sr.value, rho=rho.value, sigma=sig.value,
+                    npairs=npairs.value)
+
+    def coefficients(self, seed: Optional[int] = None, U: Optional[np.ndarray] = None,
+                     lines: Optional[np.ndarray] = None) -> np.ndarray:
+        """C_k (complex128) for all lines ([n_kappa][2nw-1]) or the given flat line ids."""
+        if U is None:
+            U = phases(self.n_kappa, self.n_omega, seed)
+        U = np.ascontiguousarray(U, dtype=np.uint32)
+        full = lines is None
+        if full:
+            lines = np.arange(self.n_kappa * self.n_cols, dtype=np.int64)
+        lines = np.ascontiguousarray(lines, dtype=np.int64)
+        out = np.zeros((lines.size, 2), dtype=np.float64)
+        st = lib().oracle_coefficients(ctypes.byref(self._c), _ptr(U, _u32p), lines.size,
+                                       lines.ctypes.data_as(_lp), _ptr(out, _dp))
+        if st != 0:
+            raise ValueError(f"oracle: pure spectrum not positive (status {st})")
+        C = out[:, 0] + 1j * out[:, 1]
+        return C.reshape(self.n_kappa, self.n_cols) if full else C
+
+
+def _cbuf(C):
+    C = np.ascontiguousarray(C, dtype=np.complex128)
+    return np.ascontiguousarray(np.stack([C.real, C.imag], axis=-1))
+
+
+def field(C: np.ndarray, n_x: int, n_t: int) -> np.ndarray:
+    """Direct cosine sum over all lines at every grid point, [n_x][n_t]."""
+    nk, nc = C.shape
+    nw = (nc + 1) // 2
+    buf = _cbuf(C)
+    u = np.zeros((n_x, n_t), dtype=np.float64)
+    lib().oracle_field_flat(nk, nw, n_x, n_t, _ptr(buf, _dp), _ptr(u, _dp))
+    return u
+
+
+def field_nested(C: np.ndarray, n_x: int, n_t: int) -> np.ndarray:
+    nk, nc = C.shape
+    nw = (nc + 1) // 2
+    buf = _cbuf(C)
+    u = np.zeros((n_x, n_t), dtype=np.float64)
+    lib().oracle_field_nested(nk, nw, n_x, n_t, _ptr(buf, _dp), _ptr(u, _dp))
+    return u
+
+
+def field_points(C: np.ndarray, n_x: int, n_t: int, mx, mt) -> np.ndarray:
+    nk, nc = C.shape
+    nw = (nc + 1) // 2
+    buf = _cbuf(C)
+    mx = np.ascontiguousarray(mx, dtype=np.int32)
+    mt = np.ascontiguousarray(mt, dtype=np.int32)
+    u = np.zeros(mx.size, dtype=np.float64)
+    lib().oracle_field_points(nk, nw, n_x, n_t, _ptr(buf, _dp), mx.size,
+                              _ptr(mx, _ip), _ptr(mt, _ip), _ptr(u, _dp))
+    return u
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())

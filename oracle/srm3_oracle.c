@@ -1,0 +1,284 @@
+/*
+ * FP64 CPU oracle for the 3rd-order Spectral Representation Method (SRM) for
+ * 1-D stochastic waves u(x, t) (Vandanapu & Shields, Section 4.1 and 4.3).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may build, load or call this file.  It shares
+ * no code, header, table or constant generator with the GPU library.
+ *
+ * It is deliberately plain: every coefficient is built by enumerating the set
+ * of interacting line pairs explicitly and calling libm cos/sin on the summed
+ * angle; the field is a direct cosine sum.  Everything is IEEE FP64.
+ *
+ * Definitions (readings of the paper are listed in the design notes):
+ *  - Lines: k = (kk, kw) with 0 <= kk < NK and -NW < kw < NW (signed frequency,
+ *    half-plane kappa >= 0, Section 2 symmetries).  Line value S_k = S(kappa, omega).
+ *  - Phase of line k: phi_k = 2 pi U_k / 2^32, U_k = Philox4x32-10 word 0 with
+ *    key = realization seed, counter = (kk, kw as uint32, 0, 0).
+ *  - Biphase: beta(iw, jw) = 2 pi V / 2^32, V = Philox word 0 with key = beta
+ *    seed, counter = (max(iw,jw), min(iw,jw), 1, 0) -- symmetric in (iw, jw).
+ *  - P(k): unordered pairs {i, j} of lines with i + j = k (both components),
+ *    |iw| < W and |jw| < W, self pair i = j included, each pair once
+ *    (Eq. truncated_cosines_1d_wave, read as "each unordered pair once").
+ *  - rho_k = min(1, cap / sum_{P(k)} b2_raw) (cap > 0), b_p^2 = rho_k b2_raw,
+ *    Sigma_k = sum_{P(k)} b_p^2, pure part sqrt(1 - Sigma_k) (Eq. pure with b_p^2).
+ *  - C_k = 2 sqrt(S_k dk dw) [ sqrt(1 - Sigma_k) e^{i phi_k}
+ *          + sum_{p in P(k)} b_p e^{i (phi_i + phi_j + beta_p)} ]   (Section 4.3)
+ *  - u(mx, mt) = sum_k Re[ C_k exp(2 pi i (kk mx / NX + kw mt / NT)) ]
+ *    (Section 4.3 with dk dx = 2 pi / NX, dw dt = 2 pi / NT).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TWO_PI 6.283185307179586476925286766559
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from the published description (Salmon, Moraes, Dror and   */
+/* Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of */
+/* two 32x32->64 multiplies with key-dependent xors, a Weyl key schedule.     */
+/* ------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2],
+                          uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint64_t key)
+{
+    uint32_t ctr[4] = {c0, c1, c2, 0u};
+    uint32_t k[2] = {(uint32_t)(key & 0xffffffffu), (uint32_t)(key >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, k, out);
+    return out[0];
+}
+
+/* Random phase angles (fixed point, 2^32 == 2 pi) of every line, [nk][2nw-1]. */
+void oracle_phases(int nk, int nw, uint64_t seed, uint32_t *U)
+{
+    const int nc = 2 * nw - 1;
+    for (int kk = 0; kk < nk; ++kk)
+        for (int kw = -(nw - 1); kw <= nw - 1; ++kw)
+            U[(size_t)kk * nc + (kw + nw - 1)] =
+                philox_word0((uint32_t)kk, (uint32_t)(int32_t)kw, 0u, seed);
+}
+
+/* Biphase table (fixed point) over signed frequency indices |iw|,|jw| < W,
+ * [2W-1][2W-1], symmetric.  mode 0: drawn from the seed; mode 1: zero. */
+void oracle_biphase(int W, int mode, uint64_t beta_seed, uint32_t *beta)
+{
+    const int n = 2 * W - 1;
+    for (int iw = -(W - 1); iw <= W - 1; ++iw)
+        for (int jw = -(W - 1); jw <= W - 1; ++jw) {
+            uint32_t v = 0u;
+            if (mode == 0) {
+                int hi = iw >= jw ? iw : jw, lo = iw >= jw ? jw : iw;
+                v = philox_word0((uint32_t)(int32_t)hi, (uint32_t)(int32_t)lo, 1u, beta_seed);
+            }
+            beta[(size_t)(iw + W - 1) * n + (jw + W - 1)] = v;
+        }
+}
+
+typedef struct {
+    int nk, nw, W;
+    double dk, dw;
+    const double *S;        /* [nk][2nw-1] */
+    const double *b2;       /* [2W-1][2W-1] raw squared bicoherence */
+    const uint32_t *beta;   /* [2W-1][2W-1] fixed-point biphase */
+    double cap;             /* > 0: per-line cap on sum b^2; <= 0: none */
+} oracle_problem;
+
+/* Is the pair (i, j), i + j = k, the canonical member of its unordered pair? */
+static int canonical(int ik, int iw, int jk, int jw)
+{
+    return (ik > jk) || (ik == jk && iw >= jw);
+}
+
+/* Enumerate P(k) and return the raw bicoherence sum and the pair count. */
+static double raw_sum(const oracle_problem *p, int kk, int kw, long *npairs)
+{
+    const int W = p->W, n = 2 * W - 1;
+    double s = 0.0;
+    long cnt = 0;
+    for (int ik = 0; ik <= kk; ++ik) {
+        const int jk = kk - ik;
+        for (int iw = -(W - 1); iw <= W - 1; ++iw) {
+            const int jw = kw - iw;
+            if (jw <= -W || jw >= W) continue;
+            if (!canonical(ik, iw, jk, jw)) continue;
+            s += p->b2[(size_t)(iw + W - 1) * n + (jw + W - 1)];
+            ++cnt;
+        }
+    }
+    if (npairs) *npairs = cnt;
+    return s;
+}
+
+/* Per-line quantities: raw sum, rescale factor rho, Sigma, pair count.
+ * Returns 0, or 2 if Sigma_k >= 1 (pure spectrum not positive). */
+int oracle_line_terms(const oracle_problem *p, int kk, int kw, double *sigma_raw,
+                      double *rho, double *sigma, long *npairs)
+{
+    double sr = raw_sum(p, kk, kw, npairs);
+    double r = 1.0;
+    if (p->cap > 0.0 && sr > p->cap) r = p->cap / sr;
+    if (sigma_raw) *sigma_raw = sr;
+    if (rho) *rho = r;
+    if (sigma) *sigma = r * sr;
+    return (r * sr >= 1.0) ? 2 : 0;
+}
+
+/* Coefficients C_k for the given lines (flat index kk*(2nw-1) + kw + nw - 1),
+ * output interleaved re/im.  U: phases of this realization [nk][2nw-1]. */
+int oracle_coefficients(const oracle_problem *p, const uint32_t *U, long nlines,
+                        const long *lines, double *C)
+{
+    const int nw = p->nw, nc = 2 * nw - 1, W = p->W, n = 2 * W - 1;
+    int status = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : status)
+    for (long q = 0; q < nlines; ++q) {
+        const long flat = lines[q];
+        const int kk = (int)(flat / nc), kw = (int)(flat % nc) - (nw - 1);
+        double rho, sigma;
+        int st = oracle_line_terms(p, kk, kw, NULL, &rho, &sigma, NULL);
+        if (st) { status = st; C[2 * q] = NAN; C[2 * q + 1] = NAN; continue; }
+        const double S = p->S[flat];
+        const double amp = 2.0 * sqrt(S * p->dk * p->dw);
+        const double phik = TWO_PI * (double)U[flat] / 4294967296.0;
+        double re = sqrt(1.0 - sigma) * cos(phik);
+        double im = sqrt(1.0 - sigma) * sin(phik);
+        for (int ik = 0; ik <= kk; ++ik) {
+            const int jk = kk - ik;
+            for (int iw = -(W - 1); iw <= W - 1; ++iw) {
+                const int jw = kw - iw;
+                if (jw <= -W || jw >= W) continue;
+                if (!canonical(ik, iw, jk, jw)) continue;
+                const size_t e = (size_t)(iw + W - 1) * n + (jw + W - 1);
+                const double bp = sqrt(rho * p->b2[e]);
+                const uint32_t ang = U[(size_t)ik * nc + (iw + nw - 1)]
+                                   + U[(size_t)jk * nc + (jw + nw - 1)]
+                                   + p->beta[e];            /* exact mod 2^32 */
+                const double th = TWO_PI * (double)ang / 4294967296.0;
+                re += bp * cos(th);
+                im += bp * sin(th);
+            }
+        }
+        C[2 * q] = amp * re;
+        C[2 * q + 1] = amp * im;
+    }
+    return status;
+}
+
+static long long posmod(long long a, long long m)
+{
+    long long r = a % m;
+    return r < 0 ? r + m : r;
+}
+
+/* Direct cosine sum at every grid point (flat form), u: [nx][nt]. */
+void oracle_field_flat(int nk, int nw, int nx, int nt, const double *C, double *u)
+{
+    const int nc = 2 * nw - 1;
+    const long long M = (long long)nx * nt;
+#pragma omp parallel for schedule(static)
+    for (int mx = 0; mx < nx; ++mx)
+        for (int mt = 0; mt < nt; ++mt) {
+            double acc = 0.0;
+            for (int kk = 0; kk < nk; ++kk)
+                for (int kw = -(nw - 1); kw <= nw - 1; ++kw) {
+                    const size_t f = (size_t)kk * nc + (kw + nw - 1);
+                    const long long a = posmod((long long)kk * mx * nt + (long long)kw * mt * nx, M);
+                    const double th = TWO_PI * (double)a / (double)M;
+                    acc += C[2 * f] * cos(th) - C[2 * f + 1] * sin(th);
+                }
+            u[(size_t)mx * nt + mt] = acc;
+        }
+}
+
+/* Direct cosine sum at selected points (flat form). */
+void oracle_field_points(int nk, int nw, int nx, int nt, const double *C, long npts,
+                         const int *mx, const int *mt, double *u)
+{
+    const int nc = 2 * nw - 1;
+    const long long M = (long long)nx * nt;
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < npts; ++q) {
+        double acc = 0.0;
+        for (int kk = 0; kk < nk; ++kk)
+            for (int kw = -(nw - 1); kw <= nw - 1; ++kw) {
+                const size_t f = (size_t)kk * nc + (kw + nw - 1);
+                const long long a = posmod((long long)kk * mx[q] * nt + (long long)kw * mt[q] * nx, M);
+                const double th = TWO_PI * (double)a / (double)M;
+                acc += C[2 * f] * cos(th) - C[2 * f + 1] * sin(th);
+            }
+        u[q] = acc;
+    }
+}
+
+/* The same sum in nested order: first over kw for every (kk, mt), then over
+ * kk.  Angles are reduced exactly in integers before scaling. */
+void oracle_field_nested(int nk, int nw, int nx, int nt, const double *C, double *u)
+{
+    const int nc = 2 * nw - 1;
+    double *G = (double *)malloc(sizeof(double) * 2 * (size_t)nk * nt);
+    double *ct = (double *)malloc(sizeof(double) * (size_t)nt);
+    double *st = (double *)malloc(sizeof(double) * (size_t)nt);
+    double *cx = (double *)malloc(sizeof(double) * (size_t)nx);
+    double *sx = (double *)malloc(sizeof(double) * (size_t)nx);
+    for (int n = 0; n < nt; ++n) { ct[n] = cos(TWO_PI * n / nt); st[n] = sin(TWO_PI * n / nt); }
+    for (int n = 0; n < nx; ++n) { cx[n] = cos(TWO_PI * n / nx); sx[n] = sin(TWO_PI * n / nx); }
+#pragma omp parallel for schedule(static)
+    for (int kk = 0; kk < nk; ++kk)
+        for (int mt = 0; mt < nt; ++mt) {
+            double gr = 0.0, gi = 0.0;
+            for (int kw = -(nw - 1); kw <= nw - 1; ++kw) {
+                const size_t f = (size_t)kk * nc + (kw + nw - 1);
+                const int a = (int)posmod((long long)kw * mt, nt);
+                gr += C[2 * f] * ct[a] - C[2 * f + 1] * st[a];
+                gi += C[2 * f] * st[a] + C[2 * f + 1] * ct[a];
+            }
+            G[2 * ((size_t)kk * nt + mt)] = gr;
+            G[2 * ((size_t)kk * nt + mt) + 1] = gi;
+        }
+#pragma omp parallel for schedule(static)
+    for (int mx = 0; mx < nx; ++mx)
+        for (int mt = 0; mt < nt; ++mt) {
+            double acc = 0.0;
+            for (int kk = 0; kk < nk; ++kk) {
+                const int a = (int)posmod((long long)kk * mx, nx);
+                const double *g = G + 2 * ((size_t)kk * nt + mt);
+                acc += g[0] * cx[a] - g[1] * sx[a];
+            }
+            u[(size_t)mx * nt + mt] = acc;
+        }
+    free(G); free(ct); free(st); free(cx); free(sx);
+}
+
+/* Threads the OpenMP runtime will use (for reporting). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
