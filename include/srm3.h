@@ -1,0 +1,166 @@
+/*
+ * srm3 -- 3rd-order Spectral Representation Method for skewed non-Gaussian
+ * 1-D stochastic waves u(x, t) on one MI355X (gfx950).
+ *
+ * Method: Vandanapu & Shields, "Simulation of non-Gaussian wind field as a
+ * 3rd-order stochastic wave", Section 4.1 (direct double cosine sum) and
+ * Section 4.3 (FFT form: per-line coefficients B(+/-) followed by a 2-D
+ * inverse DFT).  The library builds, for every wavenumber-frequency line
+ * k = (k_kappa, k_omega), the coefficient
+ *
+ *   C_k = 2 sqrt(S_k dk dw) [ sqrt(1 - Sigma_k) e^{i phi_k}
+ *                             + sum_{p={i,j}, i+j=k} b_p e^{i(phi_i + phi_j + beta_p)} ]
+ *
+ * (pure amplitude of Eq. pure with b_p^2, plus the pair sum of biamplitude x
+ * phase factor), then evaluates u(m_x dx, m_t dt) = Re sum_k C_k
+ * exp(2 pi i (k_kappa m_x / n_x + k_omega m_t / n_t)) with dk dx = 2 pi / n_x,
+ * dw dt = 2 pi / n_t (Section 4.3 interval relations).
+ *
+ * Conventions shared by every entry point
+ *  - Lines: 0 <= k_kappa < n_kappa, -n_omega < k_omega < n_omega (one line per
+ *    signed frequency; kappa >= 0 half plane, Section 2).  Arrays over lines
+ *    are row-major [n_kappa][2 n_omega - 1]; column c holds k_omega = c - (n_omega - 1).
+ *  - Pairs: unordered {i, j} with i + j = k in both components, both partners
+ *    inside the bicoherence support |i_omega|, |j_omega| < support_w, self pair
+ *    included, each pair counted once.
+ *  - Phases: phi_k = 2 pi U / 2^32 with U the first word of Philox4x32-10
+ *    (Salmon et al., SC'11) under key = realization seed (low word first) and
+ *    counter = (k_kappa, (uint32)k_omega, 0, 0).  Seeded biphases use key =
+ *    beta_seed and counter = (max(i_w, j_w), min(i_w, j_w), 1, 0).
+ *  - Streams: every device action is enqueued on the caller's hipStream_t
+ *    (passed as void*; NULL = the default stream).  Calls return before the
+ *    work finishes.  One plan may be driven by one stream at a time.
+ *  - Errors: no exception crosses the ABI.  Arguments are validated before any
+ *    device work; a failing call returns a non-zero srm3_status and leaves a
+ *    message for srm3_last_error() (thread-local).
+ *  - Ownership: host inputs are copied during the call and may be freed when
+ *    it returns.  The plan owns every device buffer it allocates.  Output
+ *    buffers are device memory owned by the caller.
+ */
+#ifndef SRM3_H
+#define SRM3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srm3_plan_s *srm3_plan_t;
+
+typedef enum {
+    SRM3_OK = 0,
+    SRM3_E_INVALID = 1,        /* bad argument (null pointer, size, NaN, negative S, asymmetric table) */
+    SRM3_E_PURE_NEGATIVE = 2,  /* some line has Sigma_k >= 1: pure spectrum not positive (Section 5) */
+    SRM3_E_NOMEM = 3,          /* device or host allocation failed */
+    SRM3_E_DEVICE = 4,         /* a HIP runtime call or kernel launch failed */
+    SRM3_E_UNSUPPORTED = 5     /* valid but outside this build's limits (see srm3_plan) */
+} srm3_status;
+
+typedef enum { SRM3_FP64 = 0, SRM3_FP32 = 1 } srm3_precision;
+
+typedef enum {
+    SRM3_BISPEC_NONE = 0,      /* b == 0: the 2nd-order (Gaussian) SRM of Section 3 */
+    SRM3_BISPEC_SEPARABLE = 1, /* b^2_raw(i_w, j_w) = g2[i_w] * g2[j_w] */
+    SRM3_BISPEC_DENSE = 2      /* b^2_raw given as a full symmetric table */
+} srm3_bispec_kind;
+
+typedef enum {
+    SRM3_BETA_SEEDED = 0,      /* beta drawn uniformly on [0, 2 pi) from beta_seed */
+    SRM3_BETA_ZERO = 1,        /* beta == 0 (real positive bispectrum, as in Section 5) */
+    SRM3_BETA_TABLE = 2        /* beta given as a symmetric fixed-point table */
+} srm3_beta_mode;
+
+/* Discretisation (Section 4.1 grid definitions, Section 4.3 interval relations). */
+typedef struct {
+    int32_t n_kappa;   /* wavenumber lines, >= 1 */
+    int32_t n_omega;   /* frequency lines per sign, >= 1 (2 n_omega - 1 signed lines) */
+    double d_kappa;    /* wavenumber step [rad/m], > 0 */
+    double d_omega;    /* frequency step [rad/s], > 0 */
+    int32_t n_x;       /* field points in x: power of two, n_kappa <= n_x <= 16384
+                          (<= 8192 for SRM3_FP64) */
+    int32_t n_t;       /* field points in t: power of two, 2 n_omega - 1 <= n_t <= 16384
+                          (<= 8192 for SRM3_FP64) */
+} srm3_grid;
+
+/* Power spectrum sampled on the lines (Section 4.1): host FP64
+ * [n_kappa][2 n_omega - 1], finite and >= 0. */
+typedef struct {
+    const double *S;
+} srm3_spectrum;
+
+/* Bicoherence and biphase over the frequency indices of a pair (the raw
+ * squared bicoherence b^2_raw(i_w, j_w) before the per-line cap).  Indices run
+ * over |i_w|, |j_w| < support_w, stored at [i_w + support_w - 1]. */
+typedef struct {
+    int32_t kind;            /* srm3_bispec_kind */
+    const double *g2;        /* SEPARABLE: host [2W-1], finite, >= 0 */
+    const double *b2;        /* DENSE: host [2W-1][2W-1], symmetric, finite, >= 0 */
+    const uint32_t *beta;    /* BETA_TABLE: host [2W-1][2W-1] symmetric, 2^32 == 2 pi */
+    int32_t support_w;       /* W, 1 <= W <= n_omega */
+    double cap;              /* > 0: per line, b^2_p = min(1, cap / sum_{P(k)} b^2_raw) b^2_raw;
+                                <= 0: no rescale */
+    int32_t beta_mode;       /* srm3_beta_mode */
+    uint64_t beta_seed;      /* BETA_SEEDED: Philox key */
+} srm3_bispectrum;
+
+/* Build a plan: validates every input, computes on the host in FP64 the
+ * per-line raw bicoherence sums, the cap factor rho_k, Sigma_k and the two
+ * amplitudes A_pure = 2 sqrt(S dk dw (1 - Sigma)) and A_pair = 2 sqrt(S dk dw
+ * rho) (Eq. pure, Section 4.3), the complex pair weight table
+ * W[i_w][j_w] = sqrt(b^2_raw) e^{i beta} and the transform twiddles, and
+ * uploads them on `hip_stream` (the call synchronises that stream before it
+ * returns).  bispectrum may be NULL (== SRM3_BISPEC_NONE).
+ * Returns SRM3_E_PURE_NEGATIVE if any line has Sigma_k >= 1 and
+ * SRM3_E_UNSUPPORTED for sizes outside the limits of srm3_grid. */
+srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
+                      const srm3_bispectrum *bispectrum, int32_t precision,
+                      void *hip_stream, srm3_plan_t *out_plan);
+
+/* Generate `batch` realizations (Section 4.3): phases from seeds[b] (host
+ * array), pair sums, coefficients, 2-D inverse DFT.  out_dev: device buffer of
+ * batch * n_x * n_t values of the plan's precision (float or double), layout
+ * [b][m_x][m_t].  The plan's workspace grows on first use of a larger batch
+ * (that call allocates device memory). */
+srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch,
+                          void *out_dev, void *hip_stream);
+
+/* Coefficients only: C_dev receives batch * n_kappa * (2 n_omega - 1) complex
+ * values (interleaved re, im; float or double) laid out [b][k_kappa][c]. */
+srm3_status srm3_coefficients(srm3_plan_t plan, const uint64_t *seeds, int32_t batch,
+                              void *C_dev, void *hip_stream);
+
+/* Transform only (Section 4.3, last step): field from caller-supplied device
+ * coefficients laid out as for srm3_coefficients. */
+srm3_status srm3_transform(srm3_plan_t plan, const void *C_dev, int32_t batch,
+                           void *out_dev, void *hip_stream);
+
+/* Device workspace bytes that srm3_generate needs for `batch` realizations. */
+srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes);
+
+/* Number of unordered pair terms of one realization (sum over lines of |P(k)|). */
+srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms);
+
+/* Per-kernel device time, measured with HIP events recorded on the launch
+ * stream around every launch while profiling is on.  Kernel ids:
+ * 0 phases, 1 pair sum, 2 assemble + t-transform, 3 x-transform. */
+typedef struct {
+    double ms[4];          /* summed elapsed time per kernel id */
+    int64_t launches[4];   /* launches per kernel id */
+} srm3_profile;
+
+srm3_status srm3_profile_enable(srm3_plan_t plan, int32_t enable); /* clears the record */
+srm3_status srm3_profile_read(srm3_plan_t plan, srm3_profile *out); /* waits for the events */
+
+/* Release every device buffer of the plan.  NULL is a no-op. */
+void srm3_destroy(srm3_plan_t plan);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *srm3_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRM3_H */

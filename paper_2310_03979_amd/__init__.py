@@ -1,0 +1,9 @@
+"""srm3: 3rd-order Spectral Representation Method stochastic waves on MI355X.
+
+The generator itself is the HIP library ``libsrm3.so`` (see ``include/srm3.h``);
+this package only builds it and marshals arguments to it.
+"""
+from .srm3 import (SRM3_FP32, SRM3_FP64, Plan, Srm3Error, load, plan_from_workload,  # noqa: F401
+                   srm3_coefficients, srm3_destroy, srm3_generate, srm3_last_error, srm3_pair_terms,
+                   srm3_plan, srm3_profile_enable, srm3_profile_read, srm3_transform,
+                   srm3_workspace_bytes)

@@ -1,0 +1,736 @@
+// HIP kernels of the srm3 generator for gfx950 (CDNA4, wave64).
+//
+//  phases      : Philox phase of every line -> unit phase factors, in two layouts
+//  pair sum    : T_k = sum_{p={i,j} in P(k)} W(i_w, j_w) z_i z_j   (Section 4.3 pair term)
+//  tfft        : C_k = A_pure z_k + A_pair (T_k + diagonal fix), placed at bin
+//                (k_kappa, k_omega mod n_t), inverse DFT along t (Stockham, LDS)
+//  xfft        : inverse DFT along x over the n_kappa live rows, real part out
+#include "srm3_internal.hpp"
+
+namespace srm3 {
+
+namespace {
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ void two_sum(T &s, T &c, T x)
+{
+    // Knuth's error-free transformation: s + x == snew + err exactly.
+    const T snew = s + x;
+    const T bp = snew - s;
+    const T err = (s - (snew - bp)) + (x - bp);
+    s = snew;
+    c += err;
+}
+
+// ---------------------------------------------------------------------------
+// Phases.  One thread per (realization, padded row, column).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, int b0, Geometry g,
+                                                    typename vec<T>::v2 *__restrict__ zrow,
+                                                    T *__restrict__ zcol)
+{
+    using T2 = typename vec<T>::v2;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int bl = blockIdx.y;
+    const long per = static_cast<long>(g.nkp) * g.nc;
+    if (idx >= per) return;
+    const int kk = static_cast<int>(idx / g.nc);
+    const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
+    const int kw = c - (g.nw - 1);
+    const int b = b0 + bl;
+    T cz = T(0), sz = T(0);
+    if (kk < g.nk) {
+        const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u,
+                                        0u, seeds.s[bl]);
+        double s, co;
+        sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
+        cz = static_cast<T>(co);
+        sz = static_cast<T>(s);
+        T2 v;
+        v.x = cz;
+        v.y = sz;
+        zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
+    }
+    const int ic = c - (g.nw - g.W);
+    if (ic >= 0 && ic < g.ncw) {
+        // planes (re + im, re, im), each [ncw][nkp]
+        const long plane = static_cast<long>(g.ncw) * g.nkp;
+        T *zc = zcol + static_cast<long>(b) * 3 * plane + static_cast<long>(ic) * g.nkp + kk;
+        zc[0] = cz + sz;
+        zc[plane] = cz;
+        zc[2 * plane] = sz;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pair sum.
+//
+// Output line k = (kk, kw).  Unordered pairs are split by kappa: pairs with
+// i_kappa > j_kappa are every ordered split of the frequency with j_kappa <
+// kk/2; pairs inside row kk/2 (kk even) are the ordered splits with weight 1/2
+// plus, for kw even, half the self pair (added when the coefficient is
+// assembled).  So
+//     T_k = sum_{jk <= kk/2} f(jk) sum_{iw} W(iw, kw - iw) z[kk - jk][iw] z[jk][kw - iw],
+//     f = 1 for 2 jk < kk, 1/2 for 2 jk == kk.
+// A wave owns 64 consecutive output columns (one per lane) and R consecutive
+// rows K0..K0+R-1.  For a fixed partner column iw the a-operand z[kk-jk][iw]
+// is the same for all lanes (held in scalar registers as a sliding window along
+// kappa), the b-operand W(iw, kw-iw) z[jk][kw-iw] is per lane and reused over
+// the R rows.  Complex products use the 3-multiply form with precomputed sums
+// (a.re + a.im stored with z, b.re + b.im and b.im - b.re formed per step):
+//     K1 += (a.re + a.im) b.re,  K2 += a.re (b.im - b.re),  K3 += a.im (b.re + b.im)
+//     re = K1 - K3,  im = K1 + K2.
+// In FP32 the partial sums are flushed every few hundred terms into an
+// error-free (two-sum) accumulator.
+// ---------------------------------------------------------------------------
+struct PairsumArgs {
+    const void *zrow;
+    const void *zcol;
+    const void *wtab;
+    void *tout;
+    Geometry g;
+    int batch;
+    int n_rowblocks;
+    int n_ctiles;
+    int n_cgroups;
+    int flush_terms;
+};
+
+constexpr int kWavesPerBlock = 4;
+
+// NS steps of the kappa loop starting at b-row J, fully unrolled so that the
+// sliding a-window is plain register renaming.  Steps s < NFULL are at full
+// weight; step s >= NFULL is triangular with t = s - NFULL (row r > 2t full,
+// r == 2t half, r < 2t skipped).  On entry cw[r] = a-values of row K0 - J + r
+// (three planes); a full bulk block (NS == R == NFULL) leaves the values of
+// rows K0 - J - R + r there for the next block.  bA/bB carry b-rows J, J + 1
+// in and J + NS, J + NS + 1 out (prefetched two steps ahead).
+template <typename T, int R, int NS, int NFULL>
+__device__ __forceinline__ void pair_block(T (&K1)[R], T (&K2)[R], T (&K3)[R], T (&cs)[R], T (&cr)[R],
+                                           T (&ci)[R], typename vec<T>::v2 &bA, typename vec<T>::v2 &bB,
+                                           const typename vec<T>::v2 w,
+                                           const typename vec<T>::v2 *__restrict__ bcol, long nc, int J,
+                                           int jk_last, const T *__restrict__ as_,
+                                           const T *__restrict__ ar_, const T *__restrict__ ai_, int K0)
+{
+    using T2 = typename vec<T>::v2;
+    constexpr bool BULK = (NS == R && NFULL == R);
+    // v[m] = a-values of row K0 - J - R + m, m in [0, 2R)
+    T vs[2 * R], vr[2 * R], vi[2 * R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        vs[R + r] = cs[r];
+        vr[R + r] = cr[r];
+        vi[R + r] = ci[r];
+    }
+    T2 bq[NS + 2];
+    bq[0] = bA;
+    bq[1] = bB;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int jk = J + s;
+        if (BULK || s + 2 < NS) bq[s + 2] = bcol[min(jk + 2, jk_last) * nc];
+        const T2 bv = bq[s];
+        const T bre = w.x * bv.x - w.y * bv.y;
+        const T bim = fma_(w.x, bv.y, w.y * bv.x);
+        const T db = bim - bre, sb = bre + bim;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m = r - s + R;
+            const int t = s - NFULL;
+            if (s < NFULL || r > 2 * t) {
+                K1[r] = fma_(vs[m], bre, K1[r]);
+                K2[r] = fma_(vr[m], db, K2[r]);
+                K3[r] = fma_(vi[m], sb, K3[r]);
+            } else if (r == 2 * t) {
+                const T h = T(0.5);
+                K1[r] = fma_(vs[m], h * bre, K1[r]);
+                K2[r] = fma_(vr[m], h * db, K2[r]);
+                K3[r] = fma_(vi[m], h * sb, K3[r]);
+            }
+        }
+        // a-values of row K0 - J - 1 - s (m = R - 1 - s), first used at step s + 1
+        if (BULK || s + 1 < NS) {
+            const int row = BULK ? K0 - J - 1 - s : max(K0 - J - 1 - s, 0);
+            vs[R - 1 - s] = as_[row];
+            vr[R - 1 - s] = ar_[row];
+            vi[R - 1 - s] = ai_[row];
+        }
+    }
+    bA = bq[NS];
+    bB = bq[NS + 1];
+    if (BULK) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cs[r] = vs[r];
+            cr[r] = vr[r];
+            ci[r] = vi[r];
+        }
+    }
+}
+
+template <typename T, int R, bool COMP>
+__global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    const Geometry &g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    const int per_kb = a.batch * a.n_cgroups;
+    const int bid = blockIdx.x;
+    const int kb = a.n_rowblocks - 1 - bid / per_kb;     // heaviest row blocks first
+    const int rem = bid - (bid / per_kb) * per_kb;
+    const int b = rem / a.n_cgroups;
+    const int ct = (rem - b * a.n_cgroups) * kWavesPerBlock + wave;
+    if (ct >= a.n_ctiles) return;
+
+    const int K0 = kb * R;
+    const int kc = ct * 64 + lane;
+    const bool lane_ok = kc < g.nc;
+    const int kw = kc - (g.nw - 1);
+    const int Wm1 = g.W - 1;
+    const int kw_lo = ct * 64 - (g.nw - 1);
+    const int kw_hi = min(ct * 64 + 63, g.nc - 1) - (g.nw - 1);
+    const int iw_lo = max(-Wm1, kw_lo - Wm1);
+    const int iw_hi = min(Wm1, kw_hi + Wm1);
+    const long nc = g.nc;
+
+    const T2 *__restrict__ zrow_b = static_cast<const T2 *>(a.zrow) + static_cast<long>(b) * g.nk * nc;
+    const long plane = static_cast<long>(g.ncw) * g.nkp;
+    const T *__restrict__ zcol_b = static_cast<const T *>(a.zcol) + static_cast<long>(b) * 3 * plane;
+    const T2 *__restrict__ wtab = static_cast<const T2 *>(a.wtab);
+
+    T sre[R], sim[R], cre[R], cim[R];
+    T K1[R], K2[R], K3[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        sre[r] = sim[r] = cre[r] = cim[r] = T(0);
+        K1[r] = K2[r] = K3[r] = T(0);
+    }
+
+    const int nbulk = K0 / 2;
+    const int jk_last = nbulk + R / 2 - 1;   // last b row used (rows < n_kappa)
+    const int steps_per_ic = nbulk + R / 2;
+    const int flush_every = COMP ? max(1, a.flush_terms / steps_per_ic) : 0x7fffffff;
+    int since_flush = 0;
+
+    for (int iw = iw_lo; iw <= iw_hi; ++iw) {
+        const int jw = kw - iw;
+        const bool ok = lane_ok && jw > -g.W && jw < g.W;
+        T2 w;
+        if (ok) {
+            w = wtab[static_cast<long>(iw + Wm1) * g.ncw + (jw + Wm1)];
+        } else {
+            w.x = T(0);
+            w.y = T(0);
+        }
+        const int jc = min(max(jw + g.nw - 1, 0), g.nc - 1);
+        const T2 *__restrict__ bcol = zrow_b + jc;
+        const T *__restrict__ as_ = zcol_b + static_cast<long>(iw + Wm1) * g.nkp;
+        const T *__restrict__ ar_ = as_ + plane;
+        const T *__restrict__ ai_ = as_ + 2 * plane;
+
+        // a-window: (cs, cr, ci)[r] = (re + im, re, im) of z[K0 + r][iw]
+        T cs[R], cr[R], ci[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cs[r] = as_[K0 + r];
+            cr[r] = ar_[K0 + r];
+            ci[r] = ai_[K0 + r];
+        }
+        T2 bA = bcol[0];
+        T2 bB = bcol[min(1, jk_last) * nc];
+        // bulk: nbulk = K0/2 steps in blocks of R, then R/2 full steps when
+        // nbulk is an odd multiple of R/2, then the R/2 triangular steps
+        const int nblk = __builtin_amdgcn_readfirstlane(nbulk / R);
+        int J = 0;
+        if (nblk > 0) {
+#pragma clang loop unroll(disable)
+            do {
+                pair_block<T, R, R, R>(K1, K2, K3, cs, cr, ci, bA, bB, w, bcol, nc, J, jk_last, as_, ar_,
+                                       ai_, K0);
+                J += R;
+            } while (J < nblk * R);
+        }
+        if (nbulk - J > 0) {
+            pair_block<T, R, R, R / 2>(K1, K2, K3, cs, cr, ci, bA, bB, w, bcol, nc, J, jk_last, as_, ar_,
+                                       ai_, K0);
+        } else {
+            pair_block<T, R, R / 2, 0>(K1, K2, K3, cs, cr, ci, bA, bB, w, bcol, nc, J, jk_last, as_, ar_,
+                                       ai_, K0);
+        }
+        if (COMP && ++since_flush >= flush_every) {
+            since_flush = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                two_sum(sre[r], cre[r], K1[r] - K3[r]);
+                two_sum(sim[r], cim[r], K1[r] + K2[r]);
+                K1[r] = K2[r] = K3[r] = T(0);
+            }
+        }
+    }
+
+    T2 *__restrict__ tout = static_cast<T2 *>(a.tout) + static_cast<long>(b) * g.nk * nc;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        T re, im;
+        if (COMP) {
+            two_sum(sre[r], cre[r], K1[r] - K3[r]);
+            two_sum(sim[r], cim[r], K1[r] + K2[r]);
+            re = sre[r] + cre[r];
+            im = sim[r] + cim[r];
+        } else {
+            re = K1[r] - K3[r];
+            im = K1[r] + K2[r];
+        }
+        const int kk = K0 + r;
+        if (lane_ok && kk < g.nk) {
+            T2 v;
+            v.x = re;
+            v.y = im;
+            tout[static_cast<long>(kk) * nc + kc] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Stockham inverse DFT in LDS (radix-4 stages, one radix-2 stage when log2 N
+// is odd), for `nbatch` transforms of length N stored `ld` apart.  Every stage
+// reads its inputs into registers, synchronises, then writes the permuted
+// outputs (natural order at the end).  tw[n] = exp(+2 pi i n / N).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ typename vec<T>::v2 cmul(typename vec<T>::v2 a, typename vec<T>::v2 b)
+{
+    typename vec<T>::v2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = fma_(a.x, b.y, a.y * b.x);
+    return r;
+}
+
+template <typename T, int MAXB>
+__device__ void fft_lds(typename vec<T>::v2 *buf, int N, int ld, int nbatch,
+                        const typename vec<T>::v2 *__restrict__ tw)
+{
+    using T2 = typename vec<T>::v2;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    int Ns = 1;
+    const int q4 = N >> 2;
+    while (Ns * 4 <= N) {
+        const int total = nbatch * q4;
+        const int s = N / (4 * Ns);
+        T2 y[MAXB][4];
+        int dst[MAXB];
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            const int q = tid + i * nthr;
+            dst[i] = -1;
+            if (q < total) {
+                const int f = q / q4, j = q - f * q4;
+                T2 *B = buf + static_cast<long>(f) * ld;
+                const int k = j & (Ns - 1);
+                const T2 x0 = B[j];
+                const T2 x1 = cmul<T>(B[j + q4], tw[k * s]);
+                const T2 x2 = cmul<T>(B[j + 2 * q4], tw[2 * k * s]);
+                const T2 x3 = cmul<T>(B[j + 3 * q4], tw[3 * k * s]);
+                const T ar = x0.x + x2.x, ai = x0.y + x2.y;
+                const T br = x0.x - x2.x, bi = x0.y - x2.y;
+                const T cr = x1.x + x3.x, ci = x1.y + x3.y;
+                const T dr = x1.x - x3.x, di = x1.y - x3.y;
+                y[i][0].x = ar + cr; y[i][0].y = ai + ci;
+                y[i][1].x = br - di; y[i][1].y = bi + dr;   // x0 + i x1 - x2 - i x3
+                y[i][2].x = ar - cr; y[i][2].y = ai - ci;
+                y[i][3].x = br + di; y[i][3].y = bi - dr;   // x0 - i x1 - x2 + i x3
+                dst[i] = f * ld + (j / Ns) * 4 * Ns + k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            if (dst[i] >= 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) buf[dst[i] + r * Ns] = y[i][r];
+            }
+        }
+        __syncthreads();
+        Ns *= 4;
+    }
+    if (Ns < N) {   // one radix-2 stage, Ns == N / 2
+        const int q2 = N >> 1;
+        const int total = nbatch * q2;
+        T2 y[2 * MAXB][2];
+        int dst[2 * MAXB];
+#pragma unroll
+        for (int i = 0; i < 2 * MAXB; ++i) {
+            const int q = tid + i * nthr;
+            dst[i] = -1;
+            if (q < total) {
+                const int f = q / q2, j = q - f * q2;
+                T2 *B = buf + static_cast<long>(f) * ld;
+                const T2 x0 = B[j];
+                const T2 x1 = cmul<T>(B[j + q2], tw[j]);
+                y[i][0].x = x0.x + x1.x; y[i][0].y = x0.y + x1.y;
+                y[i][1].x = x0.x - x1.x; y[i][1].y = x0.y - x1.y;
+                dst[i] = f * ld + j;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2 * MAXB; ++i) {
+            if (dst[i] >= 0) {
+                buf[dst[i]] = y[i][0];
+                buf[dst[i] + q2] = y[i][1];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+struct TfftArgs {
+    Geometry g;
+    int mode;
+    const void *cin;      // mode 1: [B][nk][nc]
+    const void *zrow;     // mode 0
+    const void *tsum;     // mode 0
+    const void *amp_pure; // [nk][nc]
+    const void *amp_pair; // [nk][nc]
+    const void *wtab;     // [ncw][ncw]
+    const void *tw;       // [nt]
+    void *gout;           // [B][nk][nt]
+};
+
+// Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
+template <typename T>
+__device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, int b, int kk, int c,
+                                                             const typename vec<T>::v2 *zrow,
+                                                             const typename vec<T>::v2 *tsum,
+                                                             const T *ap, const T *ac,
+                                                             const typename vec<T>::v2 *wtab)
+{
+    using T2 = typename vec<T>::v2;
+    const long li = static_cast<long>(kk) * g.nc + c;
+    const long bi = static_cast<long>(b) * g.nk * g.nc + li;
+    T2 t = tsum[bi];
+    const int kw = c - (g.nw - 1);
+    if (((kk | kw) & 1) == 0) {
+        const int hw = kw / 2;
+        if (hw > -g.W && hw < g.W) {
+            // half of the self pair {(kk/2, kw/2), (kk/2, kw/2)}
+            const T2 w = wtab[static_cast<long>(hw + g.W - 1) * g.ncw + (hw + g.W - 1)];
+            const T2 zh = zrow[static_cast<long>(b) * g.nk * g.nc + static_cast<long>(kk / 2) * g.nc + hw + g.nw - 1];
+            const T2 z2 = cmul<T>(zh, zh);
+            const T2 d = cmul<T>(w, z2);
+            t.x += T(0.5) * d.x;
+            t.y += T(0.5) * d.y;
+        }
+    }
+    const T2 z = zrow[bi];
+    const T p = ap[li], q = ac[li];
+    T2 C;
+    C.x = fma_(p, z.x, q * t.x);
+    C.y = fma_(p, z.y, q * t.y);
+    return C;
+}
+
+template <typename T, int MAXB>
+__global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    extern __shared__ unsigned char smem_raw[];
+    T2 *buf = reinterpret_cast<T2 *>(smem_raw);
+    const Geometry &g = a.g;
+    const int row = blockIdx.x;                 // b * nk + kk
+    const int b = row / g.nk, kk = row - b * g.nk;
+    for (int n = threadIdx.x; n < g.nt; n += blockDim.x) {
+        T2 zero;
+        zero.x = T(0);
+        zero.y = T(0);
+        buf[n] = zero;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+        const int kw = c - (g.nw - 1);
+        const int bin = kw < 0 ? kw + g.nt : kw;
+        T2 C;
+        if (a.mode == 0) {
+            C = assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow),
+                                 static_cast<const T2 *>(a.tsum), static_cast<const T *>(a.amp_pure),
+                                 static_cast<const T *>(a.amp_pair), static_cast<const T2 *>(a.wtab));
+        } else {
+            C = static_cast<const T2 *>(a.cin)[static_cast<long>(row) * g.nc + c];
+        }
+        buf[bin] = C;
+    }
+    __syncthreads();
+    fft_lds<T, MAXB>(buf, g.nt, g.nt, 1, static_cast<const T2 *>(a.tw));
+    T2 *gout = static_cast<T2 *>(a.gout) + static_cast<long>(row) * g.nt;
+    for (int n = threadIdx.x; n < g.nt; n += blockDim.x) gout[n] = buf[n];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void assemble_kernel(TfftArgs a, typename vec<T>::v2 *cout)
+{
+    using T2 = typename vec<T>::v2;
+    const Geometry &g = a.g;
+    const long per = static_cast<long>(g.nk) * g.nc;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= per) return;
+    const int kk = static_cast<int>(idx / g.nc);
+    const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
+    cout[static_cast<long>(b) * per + idx] =
+        assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
+                         static_cast<const T *>(a.amp_pure), static_cast<const T *>(a.amp_pair),
+                         static_cast<const T2 *>(a.wtab));
+}
+
+struct XfftArgs {
+    Geometry g;
+    int tcols;           // columns (t samples) per block
+    const void *gin;     // [B][nk][nt]
+    const void *tw;      // [nx]
+    void *out;           // [B][nx][nt] real
+};
+
+template <typename T, int MAXB>
+__global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    extern __shared__ unsigned char smem_raw[];
+    T2 *buf = reinterpret_cast<T2 *>(smem_raw);
+    const Geometry &g = a.g;
+    const int b = blockIdx.y;
+    const int mt0 = blockIdx.x * a.tcols;
+    const int tc = a.tcols;
+    const int ld = g.nx;
+    for (int n = threadIdx.x; n < tc * g.nx; n += blockDim.x) {
+        T2 zero;
+        zero.x = T(0);
+        zero.y = T(0);
+        buf[n] = zero;
+    }
+    __syncthreads();
+    const T2 *gin = static_cast<const T2 *>(a.gin) + static_cast<long>(b) * g.nk * g.nt;
+    for (int n = threadIdx.x; n < tc * g.nk; n += blockDim.x) {
+        const int kk = n / tc, col = n - kk * tc;
+        buf[col * ld + kk] = gin[static_cast<long>(kk) * g.nt + mt0 + col];
+    }
+    __syncthreads();
+    fft_lds<T, MAXB>(buf, g.nx, ld, tc, static_cast<const T2 *>(a.tw));
+    T *out = static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
+    for (int n = threadIdx.x; n < tc * g.nx; n += blockDim.x) {
+        const int mx = n / tc, col = n - mx * tc;
+        out[static_cast<long>(mx) * g.nt + mt0 + col] = buf[col * ld + mx].x;
+    }
+}
+
+constexpr int kFftMaxB = 4;
+
+int fft_threads(int butterflies)
+{
+    int t = (butterflies + kFftMaxB - 1) / kFftMaxB;
+    t = ((t + 63) / 64) * 64;
+    if (t < 64) t = 64;
+    if (t > 1024) t = 1024;
+    return t;
+}
+
+}  // namespace
+
+int pairsum_rows_per_wave(int nk, int precision)
+{
+    const int cap = precision == SRM3_FP64 ? 8 : 16;
+    int r = 2;
+    while (r * 2 <= cap && r * 2 <= nk) r *= 2;
+    return r;
+}
+
+size_t workspace_bytes(const Geometry &g, int precision, int batch)
+{
+    const size_t e = precision == SRM3_FP64 ? 8 : 4;
+    const size_t lines = static_cast<size_t>(g.nk) * g.nc;
+    auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    return al(batch * lines * 2 * e) + al(static_cast<size_t>(batch) * g.ncw * g.nkp * 3 * e) +
+           al(batch * lines * 2 * e) + al(static_cast<size_t>(batch) * g.nk * g.nt * 2 * e);
+}
+
+Workspace carve_workspace(const Geometry &g, int precision, int batch, void *base)
+{
+    const size_t e = precision == SRM3_FP64 ? 8 : 4;
+    const size_t lines = static_cast<size_t>(g.nk) * g.nc;
+    auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    char *p = static_cast<char *>(base);
+    Workspace w;
+    w.zrow = p;
+    p += al(batch * lines * 2 * e);
+    w.zcol = p;
+    p += al(static_cast<size_t>(batch) * g.ncw * g.nkp * 3 * e);
+    w.tsum = p;
+    p += al(batch * lines * 2 * e);
+    w.g = p;
+    return w;
+}
+
+template <typename T>
+static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, int batch, const Workspace &ws,
+                           hipStream_t st)
+{
+    using T2 = typename vec<T>::v2;
+    const long per = static_cast<long>(g.nkp) * g.nc;
+    const unsigned gx = static_cast<unsigned>((per + 255) / 256);
+    for (int b0 = 0; b0 < batch; b0 += kMaxSeedsPerLaunch) {
+        const int nb = std::min(kMaxSeedsPerLaunch, batch - b0);
+        SeedChunk sc{};
+        for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
+        phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, b0, g, static_cast<T2 *>(ws.zrow),
+                                                       static_cast<T *>(ws.zcol));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, int batch,
+                         const Workspace &ws, hipStream_t st)
+{
+    return precision == SRM3_FP64 ? phases_t<double>(g, seeds, batch, ws, st)
+                                  : phases_t<float>(g, seeds, batch, ws, st);
+}
+
+template <typename T, int R, bool COMP>
+static hipError_t pairsum_t(const Geometry &g, const void *wtab, int batch, const Workspace &ws,
+                            hipStream_t st)
+{
+    PairsumArgs a;
+    a.zrow = ws.zrow;
+    a.zcol = ws.zcol;
+    a.wtab = wtab;
+    a.tout = ws.tsum;
+    a.g = g;
+    a.batch = batch;
+    a.n_rowblocks = g.nkp / R;
+    a.n_ctiles = (g.nc + 63) / 64;
+    a.n_cgroups = (a.n_ctiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    a.flush_terms = 256;
+    const long blocks = static_cast<long>(a.n_rowblocks) * batch * a.n_cgroups;
+    pairsum_kernel<T, R, COMP><<<dim3(static_cast<unsigned>(blocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
+                          const Workspace &ws, hipStream_t st)
+{
+    if (precision == SRM3_FP64) {
+        switch (g.R) {
+        case 2: return pairsum_t<double, 2, false>(g, wtab, batch, ws, st);
+        case 4: return pairsum_t<double, 4, false>(g, wtab, batch, ws, st);
+        case 8: return pairsum_t<double, 8, false>(g, wtab, batch, ws, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (g.R) {
+    case 2: return pairsum_t<float, 2, true>(g, wtab, batch, ws, st);
+    case 4: return pairsum_t<float, 4, true>(g, wtab, batch, ws, st);
+    case 8: return pairsum_t<float, 8, true>(g, wtab, batch, ws, st);
+    case 16: return pairsum_t<float, 16, true>(g, wtab, batch, ws, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const void *ap, const void *ac,
+                         const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st)
+{
+    TfftArgs a;
+    a.g = g;
+    a.mode = mode;
+    a.cin = cin;
+    a.zrow = ws.zrow;
+    a.tsum = ws.tsum;
+    a.amp_pure = ap;
+    a.amp_pair = ac;
+    a.wtab = wtab;
+    a.tw = tw;
+    a.gout = ws.g;
+    const int thr = fft_threads(g.nt / 2);
+    const size_t lds = static_cast<size_t>(g.nt) * sizeof(typename vec<T>::v2);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T, kFftMaxB>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    tfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(batch * g.nk)), thr, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const void *ap,
+                       const void *ac, const void *wtab, const void *tw, int batch, const Workspace &ws,
+                       hipStream_t st)
+{
+    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, ap, ac, wtab, tw, batch, ws, st)
+                                  : tfft_t<float>(g, mode, cin, ap, ac, wtab, tw, batch, ws, st);
+}
+
+template <typename T>
+static hipError_t assemble_t(const Geometry &g, const void *ap, const void *ac, const void *wtab,
+                             int batch, const Workspace &ws, void *cout, hipStream_t st)
+{
+    TfftArgs a{};
+    a.g = g;
+    a.zrow = ws.zrow;
+    a.tsum = ws.tsum;
+    a.amp_pure = ap;
+    a.amp_pair = ac;
+    a.wtab = wtab;
+    const long per = static_cast<long>(g.nk) * g.nc;
+    assemble_kernel<T><<<dim3(static_cast<unsigned>((per + 255) / 256), batch), 256, 0, st>>>(
+        a, static_cast<typename vec<T>::v2 *>(cout));
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const Geometry &g, int precision, const void *ap, const void *ac,
+                           const void *wtab, int batch, const Workspace &ws, void *cout, hipStream_t st)
+{
+    return precision == SRM3_FP64 ? assemble_t<double>(g, ap, ac, wtab, batch, ws, cout, st)
+                                  : assemble_t<float>(g, ap, ac, wtab, batch, ws, cout, st);
+}
+
+template <typename T>
+static hipError_t xfft_t(const Geometry &g, const void *tw, int batch, const Workspace &ws, void *out,
+                         hipStream_t st)
+{
+    XfftArgs a;
+    a.g = g;
+    const size_t col_bytes = static_cast<size_t>(g.nx) * sizeof(typename vec<T>::v2);
+    int tc = static_cast<int>(std::max<size_t>(1, 65536 / col_bytes));
+    if (tc > 16) tc = 16;
+    if (tc > g.nt) tc = g.nt;
+    a.tcols = tc;
+    a.gin = ws.g;
+    a.tw = tw;
+    a.out = out;
+    const int thr = fft_threads(tc * g.nx / 2);
+    const size_t lds = tc * col_bytes;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T, kFftMaxB>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    xfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(g.nt / tc), batch), thr, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int batch, const Workspace &ws,
+                       void *out, hipStream_t st)
+{
+    return precision == SRM3_FP64 ? xfft_t<double>(g, tw, batch, ws, out, st)
+                                  : xfft_t<float>(g, tw, batch, ws, out, st);
+}
+
+}  // namespace srm3

@@ -1,0 +1,289 @@
+"""Python binding of ``libsrm3.so`` (argument marshalling only).
+
+Every step of the generator runs in the HIP library; PyTorch supplies device
+memory (tensors) and the current HIP stream.  Function names mirror the C-ABI
+declared in ``include/srm3.h``.  If the library is not built this module
+raises on first use -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrm3.so")
+
+SRM3_FP64, SRM3_FP32 = 0, 1
+SRM3_BISPEC_NONE, SRM3_BISPEC_SEPARABLE, SRM3_BISPEC_DENSE = 0, 1, 2
+SRM3_BETA_SEEDED, SRM3_BETA_ZERO, SRM3_BETA_TABLE = 0, 1, 2
+STATUS = {0: "SRM3_OK", 1: "SRM3_E_INVALID", 2: "SRM3_E_PURE_NEGATIVE", 3: "SRM3_E_NOMEM",
+          4: "SRM3_E_DEVICE", 5: "SRM3_E_UNSUPPORTED"}
+KERNELS = ("phases", "pairsum", "tfft", "xfft")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+class Srm3Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_kappa", ctypes.c_int32), ("n_omega", ctypes.c_int32),
+                ("d_kappa", ctypes.c_double), ("d_omega", ctypes.c_double),
+                ("n_x", ctypes.c_int32), ("n_t", ctypes.c_int32)]
+
+
+class _Spectrum(ctypes.Structure):
+    _fields_ = [("S", _dp)]
+
+
+class _Bispectrum(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("g2", _dp), ("b2", _dp), ("beta", _u32p),
+                ("support_w", ctypes.c_int32), ("cap", ctypes.c_double),
+                ("beta_mode", ctypes.c_int32), ("beta_seed", ctypes.c_uint64)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
+
+
+_lib = None
+
+
+def load():
+    """Load libsrm3.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsrm3.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_2310_03979_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.srm3_plan.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Spectrum),
+                            ctypes.POINTER(_Bispectrum), ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.srm3_generate.argtypes = [vp, _u64p, ctypes.c_int32, vp, vp]
+    L.srm3_coefficients.argtypes = [vp, _u64p, ctypes.c_int32, vp, vp]
+    L.srm3_transform.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
+    L.srm3_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.srm3_pair_terms.argtypes = [vp, _dp]
+    L.srm3_profile_enable.argtypes = [vp, ctypes.c_int32]
+    L.srm3_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
+    L.srm3_destroy.argtypes = [vp]
+    L.srm3_destroy.restype = None
+    L.srm3_last_error.restype = ctypes.c_char_p
+    for f in ("srm3_plan", "srm3_generate", "srm3_coefficients", "srm3_transform",
+              "srm3_workspace_bytes", "srm3_pair_terms", "srm3_profile_enable",
+              "srm3_profile_read"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def srm3_last_error() -> str:
+    return load().srm3_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise Srm3Error(status, srm3_last_error())
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Plan:
+    """Owner of a ``srm3_plan_t`` handle plus the sizes needed to check tensors."""
+
+    def __init__(self, handle, grid: dict, precision: int, support_w: int):
+        self._h = handle
+        self.grid = dict(grid)
+        self.precision = precision
+        self.support_w = support_w
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan destroyed")
+        return self._h
+
+    @property
+    def field_shape(self):
+        return (self.grid["n_x"], self.grid["n_t"])
+
+    @property
+    def coeff_shape(self):
+        return (self.grid["n_kappa"], 2 * self.grid["n_omega"] - 1)
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.precision == SRM3_FP64 else torch.float32
+
+    def __del__(self):
+        try:
+            if self._h is not None and _lib is not None:
+                _lib.srm3_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def _precision(p) -> int:
+    if isinstance(p, str):
+        return {"fp64": SRM3_FP64, "f64": SRM3_FP64, "fp32": SRM3_FP32, "f32": SRM3_FP32}[p.lower()]
+    return int(p)
+
+
+def srm3_plan(grid: dict, S: np.ndarray, bispectrum: Optional[dict] = None, precision="fp64",
+              stream=None) -> Plan:
+    """Build a plan.  ``grid``: n_kappa, n_omega, d_kappa, d_omega, n_x, n_t.
+
+    ``bispectrum`` keys: kind ('none' | 'separable' | 'dense'), g2, b2, beta (uint32
+    table), support_w, cap, beta_mode ('seeded' | 'zero' | 'table'), beta_seed.
+    """
+    L = load()
+    g = _Grid(int(grid["n_kappa"]), int(grid["n_omega"]), float(grid["d_kappa"]),
+              float(grid["d_omega"]), int(grid["n_x"]), int(grid["n_t"]))
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    spec = _Spectrum(S.ctypes.data_as(_dp))
+    keep = [S]
+    bp = None
+    W = 1
+    if bispectrum is not None:
+        kinds = {"none": 0, "separable": 1, "dense": 2}
+        modes = {"seeded": 0, "zero": 1, "table": 2}
+        kind = bispectrum.get("kind", "separable")
+        kind = kinds[kind] if isinstance(kind, str) else int(kind)
+        mode = bispectrum.get("beta_mode", "seeded")
+        mode = modes[mode] if isinstance(mode, str) else int(mode)
+        W = int(bispectrum.get("support_w", grid["n_omega"]))
+        b = _Bispectrum()
+        b.kind = kind
+        b.support_w = W
+        b.cap = float(bispectrum.get("cap", 0.9))
+        b.beta_mode = mode
+        b.beta_seed = int(bispectrum.get("beta_seed", 0))
+        if bispectrum.get("g2") is not None:
+            g2 = np.ascontiguousarray(bispectrum["g2"], dtype=np.float64)
+            keep.append(g2)
+            b.g2 = g2.ctypes.data_as(_dp)
+        if bispectrum.get("b2") is not None:
+            b2 = np.ascontiguousarray(bispectrum["b2"], dtype=np.float64)
+            keep.append(b2)
+            b.b2 = b2.ctypes.data_as(_dp)
+        if bispectrum.get("beta") is not None:
+            bt = np.ascontiguousarray(bispectrum["beta"], dtype=np.uint32)
+            keep.append(bt)
+            b.beta = bt.ctypes.data_as(_u32p)
+        bp = ctypes.byref(b)
+    h = ctypes.c_void_p()
+    _check(L.srm3_plan(ctypes.byref(g), ctypes.byref(spec), bp, _precision(precision),
+                       _stream_ptr(stream), ctypes.byref(h)))
+    del keep
+    return Plan(h, grid, _precision(precision), W)
+
+
+def _seeds(seeds) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(-1))
+
+
+def _check_tensor(t, dtype, numel, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} dtype {t.dtype} != {dtype}")
+    if not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{what} must be contiguous with >= {numel} elements")
+
+
+def srm3_generate(plan: Plan, seeds: Sequence[int], out, stream=None):
+    """Write ``len(seeds)`` fields into ``out`` ([B][n_x][n_t], plan precision)."""
+    s = _seeds(seeds)
+    nx, nt = plan.field_shape
+    _check_tensor(out, plan.real_dtype, s.size * nx * nt, "out")
+    _check(load().srm3_generate(plan.handle, s.ctypes.data_as(_u64p), s.size,
+                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def srm3_coefficients(plan: Plan, seeds: Sequence[int], C_out, stream=None):
+    """Coefficients C_k ([B][n_kappa][2 n_omega - 1] complex) into ``C_out``."""
+    import torch
+    s = _seeds(seeds)
+    nk, nc = plan.coeff_shape
+    cdt = torch.complex128 if plan.precision == SRM3_FP64 else torch.complex64
+    _check_tensor(C_out, cdt, s.size * nk * nc, "C_out")
+    _check(load().srm3_coefficients(plan.handle, s.ctypes.data_as(_u64p), s.size,
+                                    ctypes.c_void_p(C_out.data_ptr()), _stream_ptr(stream)))
+    return C_out
+
+
+def srm3_transform(plan: Plan, C, out, batch: Optional[int] = None, stream=None):
+    import torch
+    nk, nc = plan.coeff_shape
+    nx, nt = plan.field_shape
+    B = C.numel() // (nk * nc) if batch is None else batch
+    cdt = torch.complex128 if plan.precision == SRM3_FP64 else torch.complex64
+    _check_tensor(C, cdt, B * nk * nc, "C")
+    _check_tensor(out, plan.real_dtype, B * nx * nt, "out")
+    _check(load().srm3_transform(plan.handle, ctypes.c_void_p(C.data_ptr()), B,
+                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def srm3_workspace_bytes(plan: Plan, batch: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().srm3_workspace_bytes(plan.handle, batch, ctypes.byref(n)))
+    return int(n.value)
+
+
+def srm3_pair_terms(plan: Plan) -> float:
+    v = ctypes.c_double()
+    _check(load().srm3_pair_terms(plan.handle, ctypes.byref(v)))
+    return float(v.value)
+
+
+def srm3_profile_enable(plan: Plan, enable: bool = True):
+    _check(load().srm3_profile_enable(plan.handle, 1 if enable else 0))
+
+
+def srm3_profile_read(plan: Plan) -> dict:
+    p = _Profile()
+    _check(load().srm3_profile_read(plan.handle, ctypes.byref(p)))
+    return {k: (p.ms[i], int(p.launches[i])) for i, k in enumerate(KERNELS)}
+
+
+def srm3_destroy(plan: Plan):
+    if plan._h is not None:
+        load().srm3_destroy(plan._h)
+        plan._h = None
+
+
+def plan_from_workload(wl, precision="fp64", beta_mode="seeded", stream=None, dense=False,
+                       **overrides) -> Plan:
+    """Convenience: plan for a ``srm3_inputs.Workload`` (separable bicoherence)."""
+    bis = dict(kind="dense" if dense else "separable", support_w=wl.support_w, cap=wl.cap,
+               beta_mode=beta_mode, beta_seed=wl.beta_seed)
+    if dense:
+        bis["b2"] = wl.b2_dense()
+    else:
+        bis["g2"] = wl.g2()
+    bis.update(overrides)
+    return srm3_plan(wl.grid_dict(), wl.spectrum(), bis, precision, stream)
