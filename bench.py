@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark: space-time grid points/s of the 3rd-order SRM wave generator.
+
+One step = one ``srm3_generate`` call producing a batch of realizations of the
+256 x 1024-line workload (512 x 2048 field, batch 64, FP32 fixed-point-phase
+path): phases, pair sums, coefficients and the 2-D inverse DFT, with the plan
+(spectrum, bicoherence table) resident on the device.  Also reported:
+
+* plain   -- the same realizations, one non-batched call per realization
+* fp64    -- the batched FP64 path
+* roofline -- the pair-sum kernel (the dominant kernel), timed with HIP events
+              recorded by the library on its launch stream during the timed steps
+* cpu_baseline -- the FP64 oracle on this host, on a bounded sample
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import srm3_inputs as inp  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
+PEAK_FP64_TFLOPS = 78.6       # MI355X vector FP64 (published)
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_PAIR_TERM = 14      # complex product z_i z_j (6) x W (6) + accumulate (2)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS))
+    ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def timed_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(wl, target_s):
+    """FP64 oracle on this host: coefficients of a random sample of lines of
+    realization 0 (timed, extrapolated to all pair terms of a realization) plus
+    the full nested direct-sum field of one realization (timed)."""
+    import oracle
+    oracle.lib()
+    P = oracle.Problem.from_workload(wl)
+    seed = int(wl.seeds()[0])
+    U = oracle.phases(wl.n_kappa, wl.n_omega, seed)
+    rng = np.random.default_rng(1)
+    # pair count per line = ((kk + 1) n_w(kw) + diag) / 2; sample until ~target_s
+    n_lines = wl.n_lines
+    lines_done, terms_done, t_coef = 0, 0.0, 0.0
+    batch = 32
+    while t_coef < target_s and lines_done < n_lines:
+        lines = rng.integers(0, n_lines, batch).astype(np.int64)
+        terms = 0.0
+        for f in lines:
+            kk, c = divmod(int(f), wl.n_cols)
+            terms += P.line_terms(kk, c - (wl.n_omega - 1))["npairs"]
+        t0 = time.perf_counter()
+        P.coefficients(U=U, lines=lines)
+        t_coef += time.perf_counter() - t0
+        lines_done += batch
+        terms_done += terms
+        batch = min(4096, batch * 2)
+    total_terms = pair_terms_total(wl)
+    t_coef_full = t_coef / terms_done * total_terms
+    C = np.zeros((wl.n_kappa, wl.n_cols), complex)
+    C.real = np.random.default_rng(2).standard_normal(C.shape)
+    t0 = time.perf_counter()
+    oracle.field_nested(C, wl.n_x, wl.n_t)
+    t_field = time.perf_counter() - t0
+    per_real = t_coef_full + t_field
+    return {
+        "value": wl.grid_points / per_real,
+        "unit": "grid points/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle, realization 0 of {wl.name}: coefficients of {lines_done} random "
+                   f"lines ({terms_done:.3g} pair terms, {t_coef:.1f} s) extrapolated to all "
+                   f"{total_terms:.4g} pair terms; full nested direct-sum field ({t_field:.1f} s)"),
+        "pair_terms_per_s": terms_done / t_coef,
+        "seconds_per_realization": per_real,
+    }
+
+
+def pair_terms_total(wl):
+    nk, nw, W = wl.n_kappa, wl.n_omega, wl.support_w
+    tot = 0.0
+    for kw in range(-(nw - 1), nw):
+        n_w = max(0, min(W - 1, kw + W - 1) - max(-(W - 1), kw - (W - 1)) + 1)
+        ordered = n_w * nk * (nk + 1) / 2
+        diag = len(range(0, nk, 2)) if (kw % 2 == 0 and abs(kw // 2) < W) else 0
+        tot += 0.5 * (ordered + diag)
+    return tot
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28                      # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(realizations shard across GPUs with no communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    import paper_2310_03979_amd as srm3
+    srm3.load()
+    if not torch.cuda.is_available():
+        sys.exit("bench.py needs a GPU")
+
+    wl = inp.WORKLOADS[args.workload]
+    B = args.batch or wl.batch
+    seeds = wl.seeds(B)
+    grid_points = wl.grid_points * B
+    log(f"[bench] workload {wl.name} batch {B} steps {args.steps} warmup {args.warmup}")
+
+    plan32 = srm3.plan_from_workload(wl, "fp32")
+    out32 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+    terms = srm3.srm3_pair_terms(plan32)
+
+    # ---- batched FP32 (the measured step) ----
+    for _ in range(args.warmup):
+        srm3.srm3_generate(plan32, seeds, out32)
+    torch.cuda.synchronize()
+    srm3.srm3_profile_enable(plan32, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srm3.srm3_generate(plan32, seeds, out32)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    prof = srm3.srm3_profile_read(plan32)
+    srm3.srm3_profile_enable(plan32, False)
+    log(f"[bench] batched fp32: {dt * 1e3:.2f} ms/step, kernels {prof}")
+
+    ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
+    achieved_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+    roofline = {
+        "bound": "alu",
+        "kernel": "pairsum_kernel<float,16,true>",
+        "achieved": round(achieved_tflops, 3),
+        "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+        "traffic": None,
+        "pair_terms_per_launch": terms * B,
+        "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
+        "avg_launch_ms": round(ps_ms, 4),
+        "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
+    }
+    kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()}
+
+    extra = {}
+    # ---- plain: one call per realization, same kernels ----
+    if not args.no_plain:
+        out1 = torch.empty((1, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+
+        def plain():
+            for s in seeds:
+                srm3.srm3_generate(plan32, [int(s)], out1)
+        dtp = timed_steps(torch, plain, 1, 1)
+        extra["plain_fp32_grid_points_per_s"] = grid_points / dtp
+        extra["plain_fp32_ms_per_batch"] = round(dtp * 1e3, 3)
+        extra["batched_over_plain"] = round(dtp / dt, 3)
+        log(f"[bench] plain fp32: {dtp * 1e3:.2f} ms per {B} realizations")
+    # ---- batched FP64 ----
+    if not args.no_fp64 and wl.n_t <= 8192:
+        plan64 = srm3.plan_from_workload(wl, "fp64")
+        out64 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float64, device="cuda")
+        srm3.srm3_profile_enable(plan64, True)
+        dt64 = timed_steps(torch, lambda: srm3.srm3_generate(plan64, seeds, out64), 1, 1)
+        p64 = srm3.srm3_profile_read(plan64)
+        ps64 = p64["pairsum"][0] / max(1, p64["pairsum"][1])
+        extra["fp64_grid_points_per_s"] = grid_points / dt64
+        extra["fp64_pairsum_tflops"] = round(FLOPS_PER_PAIR_TERM * terms * B / (ps64 * 1e-3) / 1e12, 3)
+        extra["fp64_pairsum_frac_of_fp64_peak"] = round(extra["fp64_pairsum_tflops"] / PEAK_FP64_TFLOPS, 4)
+        del out64, plan64
+        log(f"[bench] batched fp64: {dt64 * 1e3:.2f} ms/step")
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] oracle CPU baseline ...")
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+        log(f"[bench] oracle: {cpu['value']:.4g} grid points/s on {cpu['cores']} threads")
+
+    rec = {
+        "metric": "space-time grid points/sec, batched FP32 vs plain; p50/p99 request latency",
+        "value": grid_points / dt,
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.n_kappa}x{wl.n_omega} lines, {wl.n_x}x{wl.n_t} field, "
+                               f"batch {B}, bicoherence support {wl.support_w}",
+                   "global_batch": B, "precision": "fp32 fixed-point phases, compensated pair sums"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_avg_ms": kernel_ms,
+        "pair_terms_per_realization": terms,
+    }
+    rec.update(extra)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()
