@@ -98,7 +98,10 @@ struct PairsumArgs {
     int n_ctiles;
     int n_cgroups;
     int flush_terms;
+    int per_xcd;      // > 0: XCD-blocked order (see pairsum_kernel), 0: interleaved
 };
+
+constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 constexpr int kWavesPerBlock = 4;
 
@@ -180,12 +183,30 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
     const Geometry &g = a.g;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    const int per_kb = a.batch * a.n_cgroups;
+    // Work item -> (realization b, row block kb, column group cg).  In the
+    // XCD-blocked order each XCD (block id mod 8) walks its own contiguous
+    // range of realizations, heaviest row blocks first within a realization,
+    // so the z rows of the realization in flight stay in that XCD's L2.  The
+    // interleaved order (small batches) walks row blocks heaviest first across
+    // all realizations, spreading every row block over all XCDs.
     const int bid = blockIdx.x;
-    const int kb = a.n_rowblocks - 1 - bid / per_kb;     // heaviest row blocks first
-    const int rem = bid - (bid / per_kb) * per_kb;
-    const int b = rem / a.n_cgroups;
-    const int ct = (rem - b * a.n_cgroups) * kWavesPerBlock + wave;
+    int b, kb, cg;
+    if (a.per_xcd > 0) {
+        const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
+        const int per_b = a.n_rowblocks * a.n_cgroups;
+        if (work >= a.batch * per_b) return;
+        b = work / per_b;
+        const int rem = work - b * per_b;
+        kb = a.n_rowblocks - 1 - rem / a.n_cgroups;
+        cg = rem - (rem / a.n_cgroups) * a.n_cgroups;
+    } else {
+        const int per_kb = a.batch * a.n_cgroups;
+        kb = a.n_rowblocks - 1 - bid / per_kb;
+        const int rem = bid - (bid / per_kb) * per_kb;
+        b = rem / a.n_cgroups;
+        cg = rem - b * a.n_cgroups;
+    }
+    const int ct = cg * kWavesPerBlock + wave;
     if (ct >= a.n_ctiles) return;
 
     const int K0 = kb * R;
@@ -616,7 +637,9 @@ static hipError_t pairsum_t(const Geometry &g, const void *wtab, int batch, cons
     a.n_ctiles = (g.nc + 63) / 64;
     a.n_cgroups = (a.n_ctiles + kWavesPerBlock - 1) / kWavesPerBlock;
     a.flush_terms = 256;
-    const long blocks = static_cast<long>(a.n_rowblocks) * batch * a.n_cgroups;
+    const long work = static_cast<long>(a.n_rowblocks) * batch * a.n_cgroups;
+    a.per_xcd = batch >= kNumXcd ? static_cast<int>((work + kNumXcd - 1) / kNumXcd) : 0;
+    const long blocks = a.per_xcd > 0 ? static_cast<long>(a.per_xcd) * kNumXcd : work;
     pairsum_kernel<T, R, COMP><<<dim3(static_cast<unsigned>(blocks)), 64 * kWavesPerBlock, 0, st>>>(a);
     return hipGetLastError();
 }

@@ -143,6 +143,22 @@ def test_batch_invariance_and_determinism(lib, precision):
     assert torch.equal(out[2], one[0])
 
 
+def test_batch_orders_agree(lib):
+    """Batches of 5 (interleaved block order) and 12 (XCD-blocked order) give
+    bitwise the same realizations."""
+    torch = _torch()
+    wl = inp.small_grid(32, 96, support_w=80, n_x=32, n_t=256)
+    bis, _ = _bispec(wl, "separable", "seeded")
+    plan = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), bis, "fp32")
+    seeds = list(range(100, 112))
+    big = torch.empty((12, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+    lib.srm3_generate(plan, seeds, big)
+    small = torch.empty((5, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+    lib.srm3_generate(plan, seeds[3:8], small)
+    torch.cuda.synchronize()
+    assert torch.equal(big[3:8], small)
+
+
 def test_zero_batch_and_bad_tensors(lib):
     torch = _torch()
     wl = inp.small_grid(4, 4)
