@@ -153,8 +153,81 @@ typedef struct {
 srm3_status srm3_profile_enable(srm3_plan_t plan, int32_t enable); /* clears the record */
 srm3_status srm3_profile_read(srm3_plan_t plan, srm3_profile *out); /* waits for the events */
 
-/* Release every device buffer of the plan.  NULL is a no-op. */
+/* Replace the plan's spectrum (same grid and bicoherence table): host FP64
+ * [n_kappa][2 n_omega - 1], validated like srm3_plan; synchronises the stream. */
+srm3_status srm3_set_spectrum(srm3_plan_t plan, const srm3_spectrum *spectrum, void *hip_stream);
+
+/* Parameters of the wind-field spectrum of Section 5 (workload normalisation):
+ * S(kappa, omega) = 200 u*^2 (z/U) / (1 + 50 f z/U)^(5/3) * (a/pi) / (a^2 + kappa^2),
+ * f = |omega| / 2 pi, a = lam |omega| / (2 pi U), S(., 0) = 0. */
+typedef struct {
+    double u_star;   /* shear velocity [m/s], >= 0 */
+    double z;        /* height [m], > 0 */
+    double U;        /* mean wind speed [m/s], > 0 */
+    double lam;      /* Davenport coherence decay, > 0 */
+} srm3_kaimal_davenport;
+
+/* Evaluate that spectrum on the lines of `grid` into device memory S_dev
+ * (FP64 [n_kappa][2 n_omega - 1], caller-owned), stream-ordered.  Used to give
+ * each request of a batch or server its own spectrum without host traffic. */
+srm3_status srm3_spectrum_kaimal_davenport(const srm3_grid *grid, const srm3_kaimal_davenport *params,
+                                           double *S_dev, void *hip_stream);
+
+/* Release every device buffer of the plan.  NULL is a no-op.  Batches and
+ * servers that use the plan must be destroyed first. */
 void srm3_destroy(srm3_plan_t plan);
+
+/* ---- uneven batches: many realizations of mixed grids in one persistent launch ----
+ * One generation request: a realization of `plan` (grid, bicoherence table,
+ * spectrum) with its own seed, bicoherence scale and optionally its own
+ * spectrum.  With b2_scale = c, b^2_raw -> c b^2_raw for this realization (the
+ * per-line cap is applied after scaling).  S_dev (device FP64, may be NULL =
+ * the plan's spectrum) must hold finite values >= 0 and stay valid while the
+ * batch exists.  out_dev: [n_x][n_t] in the plan's precision. */
+typedef struct {
+    srm3_plan_t plan;
+    uint64_t seed;
+    double b2_scale;
+    const double *S_dev;
+    void *out_dev;
+} srm3_request;
+
+typedef struct srm3_batch_s *srm3_batch_t;
+
+enum {
+    SRM3_BATCH_GRAPH = 1,     /* capture the launch sequence in a hipGraph at the first run, replay after */
+    SRM3_BATCH_AUTOTUNE = 2   /* pick rows per wave and persistent grid size by timing at the first run;
+                                 choices are cached in $SRM3_TUNE_CACHE (default ~/.cache/srm3_tune.txt) */
+};
+
+/* Prepare a batch of n requests sharing one precision (plans may differ).
+ * Allocates one workspace slice per request and builds the work list: every
+ * (request, row block, column group) item, ordered by request cost and cut
+ * into eight queues, one per XCD.  Host arrays are copied; plans must
+ * outlive the batch.  Fails with SRM3_E_PURE_NEGATIVE if a scaled request
+ * would make some Sigma_k >= 1. */
+srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags, void *hip_stream,
+                              srm3_batch_t *out);
+/* Run the batch: phases of every request, one persistent pair-sum launch over
+ * all work items, then the transforms per plan.  seeds: host [n] in request
+ * order (NULL = the seeds of the requests).  Stream-ordered; the first run
+ * also tunes and/or captures when the flags ask for it (that run synchronises). */
+srm3_status srm3_batch_run(srm3_batch_t batch, const uint64_t *seeds, void *hip_stream);
+
+typedef struct {
+    double pair_terms;      /* unordered pair terms over all requests */
+    double run_ms;          /* device time of the last run (HIP events), -1 if none */
+    double pairsum_ms;      /* pair-sum launch time of the last non-graph run, else -1 */
+    int32_t rows_per_wave;  /* tile shape in use */
+    int32_t blocks_per_cu;  /* persistent workgroups per compute unit */
+    int32_t work_items;
+    int32_t groups;         /* distinct plans */
+} srm3_batch_stats;
+srm3_status srm3_batch_info(srm3_batch_t batch, srm3_batch_stats *out); /* waits for the last run */
+void srm3_batch_destroy(srm3_batch_t batch);   /* NULL is a no-op */
+
+/* One-shot uneven generation: create, run, synchronise, destroy. */
+srm3_status srm3_generate_uneven(const srm3_request *reqs, int32_t n, void *hip_stream);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *srm3_last_error(void);

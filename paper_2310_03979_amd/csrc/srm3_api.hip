@@ -1,12 +1,21 @@
 // C-ABI of the srm3 library: plan construction (host, FP64), generation
-// launch sequences, error reporting and event-based kernel timing.
+// launch sequences, uneven batches (persistent launch, hipGraph, autotuner),
+// error reporting and event-based kernel timing.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
+
+#include <sys/stat.h>
 
 #include "srm3_internal.hpp"
 
@@ -30,6 +39,9 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 struct DevBuf {
     void *p = nullptr;
     size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release()
     {
@@ -48,15 +60,20 @@ struct DevBuf {
     }
 };
 
+srm3_status dev_err(hipError_t e, const char *what)
+{
+    return fail(SRM3_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
 }  // namespace
 
 struct srm3_plan_s {
     Geometry g{};
     int precision = SRM3_FP64;
-    double dk = 0, dw = 0;
+    double dk = 0, dw = 0, cap = 0, max_sig = 0;
     double pair_terms = 0;
     int device = 0;
-    DevBuf wtab, amp_pure, amp_pair, tw_t, tw_x, ws;
+    DevBuf wtab, S, sig, tw_t, tw_x, ws;
     int ws_batch = 0;
     // profiling
     bool prof = false;
@@ -70,11 +87,6 @@ struct srm3_plan_s {
 
 namespace {
 
-srm3_status dev_err(hipError_t e, const char *what)
-{
-    return fail(SRM3_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
 template <typename T>
 std::vector<unsigned char> to_bytes(const std::vector<double> &v)
 {
@@ -84,17 +96,21 @@ std::vector<unsigned char> to_bytes(const std::vector<double> &v)
     return out;
 }
 
-srm3_status upload(DevBuf &buf, const std::vector<double> &v, int precision, hipStream_t st)
+srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_t st)
 {
-    std::vector<unsigned char> bytes =
-        precision == SRM3_FP64 ? to_bytes<double>(v) : to_bytes<float>(v);
-    hipError_t e = buf.alloc(bytes.size());
-    if (e != hipSuccess) return fail(SRM3_E_NOMEM, "hipMalloc(%zu): %s", bytes.size(), hipGetErrorString(e));
-    e = hipMemcpyAsync(buf.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice, st);
+    hipError_t e = buf.alloc(bytes);
+    if (e != hipSuccess) return fail(SRM3_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    e = hipMemcpyAsync(buf.p, data, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return dev_err(e, "hipMemcpyAsync");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
     return SRM3_OK;
+}
+
+srm3_status upload(DevBuf &buf, const std::vector<double> &v, int precision, hipStream_t st)
+{
+    std::vector<unsigned char> bytes = precision == SRM3_FP64 ? to_bytes<double>(v) : to_bytes<float>(v);
+    return upload_bytes(buf, bytes.data(), bytes.size(), st);
 }
 
 // exp(+2 pi i n / N), n < N, interleaved
@@ -102,7 +118,6 @@ std::vector<double> twiddles(int N)
 {
     std::vector<double> v(2 * static_cast<size_t>(N));
     for (int n = 0; n < N; ++n) {
-        // reduce to the first octant-free form through long double for accuracy
         const long double a = 2.0L * 3.14159265358979323846264338327950288L * n / N;
         v[2 * n] = static_cast<double>(cosl(a));
         v[2 * n + 1] = static_cast<double>(sinl(a));
@@ -156,12 +171,17 @@ srm3_status check_batch(srm3_plan_t p, const void *seeds, int32_t batch, const v
     return SRM3_OK;
 }
 
-srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const Workspace &ws,
-                      hipStream_t st)
+AmpRef plan_amp(srm3_plan_t p)
+{
+    return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
+                  p->dk * p->dw, p->cap};
+}
+
+srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const Workspace &ws, hipStream_t st)
 {
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
-    hipError_t e = launch_phases(p->g, p->precision, seeds, batch, ws, st);
+    hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, ws, st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
     if ((s = event_pair(p, 1, st, true))) return s;
@@ -171,20 +191,33 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     return SRM3_OK;
 }
 
-srm3_status run_back(srm3_plan_t p, int mode, const void *cin, int32_t batch, const Workspace &ws,
-                     void *out, hipStream_t st)
+srm3_status run_back(srm3_plan_t p, int mode, const void *cin, int32_t batch, const Workspace &ws, void *out,
+                     hipStream_t st)
 {
     srm3_status s;
     if ((s = event_pair(p, 2, st, true))) return s;
-    hipError_t e = launch_tfft(p->g, p->precision, mode, cin, p->amp_pure.p, p->amp_pair.p, p->wtab.p,
-                               p->tw_t.p, batch, ws, st);
+    hipError_t e = launch_tfft(p->g, p->precision, mode, cin, plan_amp(p), p->wtab.p, p->tw_t.p, batch, ws, st);
     if (e != hipSuccess) return dev_err(e, "t-transform kernel");
     if ((s = event_pair(p, 2, st, false))) return s;
     if ((s = event_pair(p, 3, st, true))) return s;
-    e = launch_xfft(p->g, p->precision, p->tw_x.p, batch, ws, out, st);
+    e = launch_xfft(p->g, p->precision, p->tw_x.p, batch, ws, out, nullptr, st);
     if (e != hipSuccess) return dev_err(e, "x-transform kernel");
     if ((s = event_pair(p, 3, st, false))) return s;
     return SRM3_OK;
+}
+
+srm3_status check_spectrum(const double *S, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (!(S[i] >= 0) || !std::isfinite(S[i])) return fail(SRM3_E_INVALID, "S[%zu] must be finite and >= 0", i);
+    return SRM3_OK;
+}
+
+// Largest Sigma_k over the lines at a given b^2 scale.
+double max_sigma(double max_sig, double cap, double scale)
+{
+    const double s = scale * max_sig;
+    return (cap > 0 && s > cap) ? cap : s;
 }
 
 }  // namespace
@@ -193,32 +226,28 @@ extern "C" {
 
 const char *srm3_last_error(void) { return g_err; }
 
-srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
-                      const srm3_bispectrum *bispectrum, int32_t precision, void *hip_stream,
-                      srm3_plan_t *out_plan)
+srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, const srm3_bispectrum *bispectrum,
+                      int32_t precision, void *hip_stream, srm3_plan_t *out_plan)
 {
     g_err[0] = 0;
     if (!out_plan) return fail(SRM3_E_INVALID, "out_plan is NULL");
     *out_plan = nullptr;
     if (!grid || !spectrum || !spectrum->S) return fail(SRM3_E_INVALID, "grid/spectrum is NULL");
-    if (precision != SRM3_FP64 && precision != SRM3_FP32)
-        return fail(SRM3_E_INVALID, "precision %d", precision);
+    if (precision != SRM3_FP64 && precision != SRM3_FP32) return fail(SRM3_E_INVALID, "precision %d", precision);
     const int nk = grid->n_kappa, nw = grid->n_omega, nx = grid->n_x, nt = grid->n_t;
     if (nk < 1 || nw < 1) return fail(SRM3_E_INVALID, "n_kappa=%d n_omega=%d must be >= 1", nk, nw);
     if (!(grid->d_kappa > 0) || !(grid->d_omega > 0) || !std::isfinite(grid->d_kappa) ||
         !std::isfinite(grid->d_omega))
         return fail(SRM3_E_INVALID, "d_kappa/d_omega must be finite and > 0");
-    if (!is_pow2(nx) || !is_pow2(nt))
-        return fail(SRM3_E_UNSUPPORTED, "n_x=%d n_t=%d must be powers of two", nx, nt);
+    if (!is_pow2(nx) || !is_pow2(nt)) return fail(SRM3_E_UNSUPPORTED, "n_x=%d n_t=%d must be powers of two", nx, nt);
     const int nc = 2 * nw - 1;
     if (nx < nk || nt < nc)
-        return fail(SRM3_E_INVALID, "field %dx%d smaller than the line grid (need n_x >= %d, n_t >= %d)",
-                    nx, nt, nk, nc);
+        return fail(SRM3_E_INVALID, "field %dx%d smaller than the line grid (need n_x >= %d, n_t >= %d)", nx, nt,
+                    nk, nc);
     const int tmax = precision == SRM3_FP64 ? 8192 : 16384;   // one transform fits 128 KB of LDS
     if (nt > tmax || nx > tmax)
         return fail(SRM3_E_UNSUPPORTED, "n_t=%d / n_x=%d above this build's limit %d", nt, nx, tmax);
-    if (static_cast<long long>(nk) * nc > (1LL << 30))
-        return fail(SRM3_E_UNSUPPORTED, "line grid too large");
+    if (static_cast<long long>(nk) * nc > (1LL << 30)) return fail(SRM3_E_UNSUPPORTED, "line grid too large");
 
     // ---- bicoherence description ----
     srm3_bispectrum none{};
@@ -239,7 +268,6 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
         return fail(SRM3_E_INVALID, "beta table is NULL");
     if (!std::isfinite(bs.cap)) return fail(SRM3_E_INVALID, "cap is not finite");
 
-    // raw squared bicoherence table over the support
     std::vector<double> b2(static_cast<size_t>(ncw) * ncw, 0.0);
     if (bs.kind == SRM3_BISPEC_SEPARABLE) {
         for (int i = 0; i < ncw; ++i)
@@ -258,7 +286,6 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
                 b2[static_cast<size_t>(i) * ncw + j] = v;
             }
     }
-    // biphase (fixed point)
     std::vector<uint32_t> beta(static_cast<size_t>(ncw) * ncw, 0u);
     if (bs.kind != SRM3_BISPEC_NONE) {
         if (bs.beta_mode == SRM3_BETA_SEEDED) {
@@ -280,54 +307,46 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
         }
     }
 
-    // ---- spectrum ----
     const double *S = spectrum->S;
     const size_t nlines = static_cast<size_t>(nk) * nc;
-    for (size_t i = 0; i < nlines; ++i)
-        if (!(S[i] >= 0) || !std::isfinite(S[i]))
-            return fail(SRM3_E_INVALID, "S[%zu] must be finite and >= 0", i);
+    srm3_status s = check_spectrum(S, nlines);
+    if (s) return s;
 
-    // ---- per-line sums (ordered frequency splits + self pair), FP64 ----
-    // D[kw] = sum_{iw} b2(iw, kw - iw) over the support; an output line with
-    // k_kappa = kk has (kk + 1) kappa splits, so the ordered sum is (kk+1) D[kw]
-    // and the unordered sum half of it plus half the self pair.
+    // ---- per-line unit-scale raw pair sums (ordered frequency splits + self pair), FP64 ----
+    // D[kw] = sum_{iw} b2(iw, kw - iw) over the support; a line with k_kappa
+    // = kk has (kk + 1) kappa splits, so its ordered sum is (kk+1) D[kw] and
+    // its unordered sum half of that plus half the self pair.
     std::vector<double> D(nc, 0.0);
+    std::vector<long> nsplit(nc, 0);
     for (int kw = -(nw - 1); kw <= nw - 1; ++kw) {
-        double s = 0.0;
+        double acc = 0.0;
         for (int iw = -(W - 1); iw <= W - 1; ++iw) {
             const int jw = kw - iw;
             if (jw <= -W || jw >= W) continue;
-            s += b2[static_cast<size_t>(iw + W - 1) * ncw + (jw + W - 1)];
+            acc += b2[static_cast<size_t>(iw + W - 1) * ncw + (jw + W - 1)];
+            ++nsplit[kw + nw - 1];
         }
-        D[kw + nw - 1] = s;
+        D[kw + nw - 1] = acc;
     }
-    std::vector<double> ap(nlines), ac(nlines);
-    double pair_terms = 0.0;
-    const double dkdw = grid->d_kappa * grid->d_omega;
+    std::vector<double> sig(nlines);
+    double pair_terms = 0.0, max_sig = 0.0;
     for (int kk = 0; kk < nk; ++kk)
         for (int c = 0; c < nc; ++c) {
             const int kw = c - (nw - 1);
             double diag = 0.0;
-            long nsplit = 0;
-            for (int iw = -(W - 1); iw <= W - 1; ++iw)
-                if (kw - iw > -W && kw - iw < W) ++nsplit;
             int self = 0;
             if ((kk % 2) == 0 && (kw % 2) == 0 && kw / 2 > -W && kw / 2 < W) {
                 diag = b2[static_cast<size_t>(kw / 2 + W - 1) * ncw + (kw / 2 + W - 1)];
                 self = 1;
             }
-            pair_terms += 0.5 * (static_cast<double>(kk + 1) * nsplit + self);
-            const double sraw = 0.5 * ((kk + 1) * D[c] + diag);
-            double rho = 1.0;
-            if (bs.cap > 0 && sraw > bs.cap) rho = bs.cap / sraw;
-            const double sigma = rho * sraw;
-            if (sigma >= 1.0)
-                return fail(SRM3_E_PURE_NEGATIVE,
-                            "line (%d, %d): sum of b^2 = %.6g >= 1, pure spectrum not positive", kk, kw, sigma);
-            const size_t li = static_cast<size_t>(kk) * nc + c;
-            ap[li] = 2.0 * std::sqrt(S[li] * dkdw * (1.0 - sigma));
-            ac[li] = 2.0 * std::sqrt(S[li] * dkdw * rho);
+            pair_terms += 0.5 * (static_cast<double>(kk + 1) * nsplit[c] + self);
+            const double v = 0.5 * ((kk + 1) * D[c] + diag);
+            sig[static_cast<size_t>(kk) * nc + c] = v;
+            max_sig = std::max(max_sig, v);
         }
+    if (max_sigma(max_sig, bs.cap, 1.0) >= 1.0)
+        return fail(SRM3_E_PURE_NEGATIVE, "a line has sum of b^2 = %.6g >= 1: pure spectrum not positive",
+                    max_sigma(max_sig, bs.cap, 1.0));
 
     // complex weight table W = sqrt(b2) e^{i beta}
     std::vector<double> wt(2 * static_cast<size_t>(ncw) * ncw);
@@ -343,6 +362,8 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
     p->precision = precision;
     p->dk = grid->d_kappa;
     p->dw = grid->d_omega;
+    p->cap = bs.cap;
+    p->max_sig = max_sig;
     p->pair_terms = pair_terms;
     Geometry &g = p->g;
     g.nk = nk;
@@ -356,15 +377,48 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
     g.nkp = ((nk + g.R - 1) / g.R) * g.R;
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return dev_err(e, "hipGetDevice");
+    e = prepare_transforms(precision);
+    if (e != hipSuccess) return dev_err(e, "hipFuncSetAttribute");
 
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    srm3_status s;
     if ((s = upload(p->wtab, wt, precision, st))) return s;
-    if ((s = upload(p->amp_pure, ap, precision, st))) return s;
-    if ((s = upload(p->amp_pair, ac, precision, st))) return s;
+    if ((s = upload_bytes(p->S, S, nlines * sizeof(double), st))) return s;
+    if ((s = upload_bytes(p->sig, sig.data(), nlines * sizeof(double), st))) return s;
     if ((s = upload(p->tw_t, twiddles(nt), precision, st))) return s;
     if ((s = upload(p->tw_x, twiddles(nx), precision, st))) return s;
     *out_plan = p.release();
+    return SRM3_OK;
+}
+
+srm3_status srm3_set_spectrum(srm3_plan_t plan, const srm3_spectrum *spectrum, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!plan || !spectrum || !spectrum->S) return fail(SRM3_E_INVALID, "plan/spectrum is NULL");
+    const size_t n = static_cast<size_t>(plan->g.nk) * plan->g.nc;
+    srm3_status s = check_spectrum(spectrum->S, n);
+    if (s) return s;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipMemcpyAsync(plan->S.p, spectrum->S, n * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return dev_err(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
+    return SRM3_OK;
+}
+
+srm3_status srm3_spectrum_kaimal_davenport(const srm3_grid *grid, const srm3_kaimal_davenport *params,
+                                           double *S_dev, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!grid || !params || !S_dev) return fail(SRM3_E_INVALID, "NULL argument");
+    if (grid->n_kappa < 1 || grid->n_omega < 1 || !(grid->d_kappa > 0) || !(grid->d_omega > 0))
+        return fail(SRM3_E_INVALID, "bad grid");
+    if (!(params->U > 0) || !(params->z > 0) || !(params->u_star >= 0) || !(params->lam > 0) ||
+        !std::isfinite(params->U) || !std::isfinite(params->z) || !std::isfinite(params->u_star) ||
+        !std::isfinite(params->lam))
+        return fail(SRM3_E_INVALID, "spectrum parameters must be finite (U, z, lambda > 0, u* >= 0)");
+    hipError_t e = launch_spectrum(grid->n_kappa, grid->n_omega, grid->d_kappa, grid->d_omega, params->u_star,
+                                   params->z, params->U, params->lam, S_dev, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return dev_err(e, "spectrum kernel");
     return SRM3_OK;
 }
 
@@ -394,8 +448,7 @@ srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms)
     return SRM3_OK;
 }
 
-srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *out_dev,
-                          void *hip_stream)
+srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *out_dev, void *hip_stream)
 {
     g_err[0] = 0;
     srm3_status s = check_batch(plan, seeds, batch, out_dev);
@@ -408,8 +461,7 @@ srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch
     return run_back(plan, 0, nullptr, batch, ws, out_dev, st);
 }
 
-srm3_status srm3_coefficients(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *C_dev,
-                              void *hip_stream)
+srm3_status srm3_coefficients(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *C_dev, void *hip_stream)
 {
     g_err[0] = 0;
     srm3_status s = check_batch(plan, seeds, batch, C_dev);
@@ -419,14 +471,12 @@ srm3_status srm3_coefficients(srm3_plan_t plan, const uint64_t *seeds, int32_t b
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const Workspace ws = carve_workspace(plan->g, plan->precision, batch, plan->ws.p);
     if ((s = run_front(plan, seeds, batch, ws, st))) return s;
-    hipError_t e = launch_assemble(plan->g, plan->precision, plan->amp_pure.p, plan->amp_pair.p,
-                                   plan->wtab.p, batch, ws, C_dev, st);
+    hipError_t e = launch_assemble(plan->g, plan->precision, plan_amp(plan), plan->wtab.p, batch, ws, C_dev, st);
     if (e != hipSuccess) return dev_err(e, "assemble kernel");
     return SRM3_OK;
 }
 
-srm3_status srm3_transform(srm3_plan_t plan, const void *C_dev, int32_t batch, void *out_dev,
-                           void *hip_stream)
+srm3_status srm3_transform(srm3_plan_t plan, const void *C_dev, int32_t batch, void *out_dev, void *hip_stream)
 {
     g_err[0] = 0;
     srm3_status s = check_batch(plan, C_dev, batch, out_dev);
@@ -467,6 +517,478 @@ srm3_status srm3_profile_read(srm3_plan_t plan, srm3_profile *out)
         out->launches[r.kernel] += 1;
     }
     return SRM3_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Uneven batches: requests with mixed plans in one persistent pair-sum launch
+// ===========================================================================
+struct srm3_batch_s {
+    int precision = 0;
+    int n = 0;
+    int flags = 0;
+    std::vector<srm3_request> req;     // caller order
+    struct Group {
+        srm3_plan_t plan;
+        std::vector<int> members;      // caller indices, slot = position
+        Geometry g;                    // with the batch's R
+        size_t ws_off = 0;
+        int first = 0;                 // offset of the group in the device arrays
+    };
+    std::vector<Group> groups;
+    int R = 0;                         // rows per wave of the persistent launch
+    int blocks_per_cu = 2;
+    int n_cu = 256;
+    DevBuf ws, seeds, scales, sptr, outs, preq, pitem, qbegin, qnext;
+    int n_items = 0;
+    uint64_t *seeds_host = nullptr;    // pinned staging
+    hipEvent_t copy_done = nullptr;
+    bool copy_pending = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double pair_terms = 0;
+    bool tuned = false;
+    bool ran = false, ps_timed = false;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;     // pair sum (direct runs)
+    hipEvent_t run_a = nullptr, run_b = nullptr;   // whole run
+};
+
+namespace {
+
+int rows_for(int nk, int precision, int R_pref)
+{
+    int r = R_pref > 0 ? R_pref : pairsum_rows_per_wave(nk, precision);
+    const int cap = precision == SRM3_FP64 ? 8 : 16;
+    if (r > cap) r = cap;
+    while (r > 2 && r > nk) r /= 2;
+    return r;
+}
+
+// Relative cost of one work item: kappa steps times the widest partner range
+// of its column tiles.
+double item_cost(const Geometry &g, int R, int kb, int cg)
+{
+    const int wpb = waves_per_block();
+    const int nct = (g.nc + 63) / 64;
+    int widest = 0;
+    for (int w = 0; w < wpb; ++w) {
+        const int ct = cg * wpb + w;
+        if (ct >= nct) break;
+        const int kw_lo = ct * 64 - (g.nw - 1);
+        const int kw_hi = std::min(ct * 64 + 63, g.nc - 1) - (g.nw - 1);
+        const int lo = std::max(-(g.W - 1), kw_lo - (g.W - 1));
+        const int hi = std::min(g.W - 1, kw_hi + (g.W - 1));
+        widest = std::max(widest, hi - lo + 1);
+    }
+    return static_cast<double>(kb * R / 2 + R / 2) * widest;
+}
+
+// (Re)build layouts and work queues for rows-per-wave R and grid size.
+srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
+{
+    b->R = R;
+    size_t off = 0;
+    auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    int first = 0;
+    for (auto &gr : b->groups) {
+        gr.g = gr.plan->g;
+        gr.g.R = rows_for(gr.g.nk, b->precision, R);
+        gr.g.nkp = ((gr.g.nk + gr.g.R - 1) / gr.g.R) * gr.g.R;
+        if (gr.g.R != R)
+            return fail(SRM3_E_UNSUPPORTED, "a %dx%d grid needs rows per wave %d != %d of the batch", gr.g.nk,
+                        gr.g.nw, gr.g.R, R);
+        gr.ws_off = off;
+        gr.first = first;
+        off += al(workspace_bytes(gr.g, b->precision, static_cast<int>(gr.members.size())));
+        first += static_cast<int>(gr.members.size());
+    }
+    if (b->ws.n < off) {
+        hipError_t e = b->ws.alloc(off);
+        if (e != hipSuccess) return fail(SRM3_E_NOMEM, "batch workspace hipMalloc(%zu): %s", off, hipGetErrorString(e));
+    }
+    // per-request descriptors (device order = group order) and work items
+    const size_t rb = persistent_req_bytes(), ib = persistent_item_bytes();
+    std::vector<unsigned char> reqs(rb * b->n);
+    struct It {
+        int req, kb, cg;
+        double cost;
+    };
+    std::vector<std::vector<It>> per_req(b->n);
+    std::vector<double> req_cost(b->n, 0.0);
+    const size_t e = b->precision == SRM3_FP64 ? 8 : 4;
+    for (auto &gr : b->groups) {
+        const Workspace ws = carve_workspace(gr.g, b->precision, static_cast<int>(gr.members.size()),
+                                             static_cast<char *>(b->ws.p) + gr.ws_off);
+        const size_t lines = static_cast<size_t>(gr.g.nk) * gr.g.nc;
+        const size_t plane3 = static_cast<size_t>(3) * gr.g.ncw * gr.g.nkp;
+        const int nrb = gr.g.nkp / gr.g.R;
+        const int ncg = ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
+        for (size_t slot = 0; slot < gr.members.size(); ++slot) {
+            const int d = gr.first + static_cast<int>(slot);
+            fill_persistent_req(reqs.data() + rb * d, gr.g, static_cast<char *>(ws.zrow) + slot * lines * 2 * e,
+                                static_cast<char *>(ws.zcol) + slot * plane3 * e,
+                                static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
+            for (int kb = nrb - 1; kb >= 0; --kb)
+                for (int cg = 0; cg < ncg; ++cg) {
+                    const double c = item_cost(gr.g, gr.g.R, kb, cg);
+                    per_req[d].push_back({d, kb, cg, c});
+                    req_cost[d] += c;
+                }
+        }
+    }
+    // Order: requests by descending cost, items of a request heaviest first;
+    // cut into kXcds contiguous runs of equal cost (one queue per XCD).
+    std::vector<int> order(b->n);
+    for (int i = 0; i < b->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return req_cost[x] > req_cost[y]; });
+    std::vector<It> all;
+    double total = 0.0;
+    for (int d : order) {
+        auto &v = per_req[d];
+        std::stable_sort(v.begin(), v.end(), [](const It &x, const It &y) { return x.cost > y.cost; });
+        for (auto &it : v) {
+            all.push_back(it);
+            total += it.cost;
+        }
+    }
+    std::vector<int> qbegin(kXcds + 1, 0);
+    double acc = 0.0;
+    int q = 1;
+    for (size_t i = 0; i < all.size(); ++i) {
+        while (q < kXcds && acc >= total * q / kXcds) qbegin[q++] = static_cast<int>(i);
+        acc += all[i].cost;
+    }
+    while (q <= kXcds) qbegin[q++] = static_cast<int>(all.size());
+    std::vector<unsigned char> items(ib * std::max<size_t>(1, all.size()));
+    for (size_t i = 0; i < all.size(); ++i) fill_persistent_item(items.data() + ib * i, all[i].req, all[i].kb, all[i].cg);
+    b->n_items = static_cast<int>(all.size());
+    srm3_status s;
+    if ((s = upload_bytes(b->preq, reqs.data(), reqs.size(), st))) return s;
+    if ((s = upload_bytes(b->pitem, items.data(), items.size(), st))) return s;
+    if ((s = upload_bytes(b->qbegin, qbegin.data(), qbegin.size() * sizeof(int), st))) return s;
+    if (!b->qnext.p) {
+        hipError_t er = b->qnext.alloc(kXcds * sizeof(int));
+        if (er != hipSuccess) return fail(SRM3_E_NOMEM, "hipMalloc: %s", hipGetErrorString(er));
+    }
+    return SRM3_OK;
+}
+
+// The launch sequence of one run (stream-ordered; capturable).
+srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
+{
+    for (auto &gr : b->groups) {
+        const Workspace ws = carve_workspace(gr.g, b->precision, static_cast<int>(gr.members.size()),
+                                             static_cast<char *>(b->ws.p) + gr.ws_off);
+        hipError_t e = launch_phases(gr.g, b->precision, nullptr, static_cast<const uint64_t *>(b->seeds.p) + gr.first,
+                                     static_cast<int>(gr.members.size()), ws, st);
+        if (e != hipSuccess) return dev_err(e, "phase kernel");
+    }
+    if (time_pairsum) (void)hipEventRecord(b->ev_a, st);
+    hipError_t e = launch_pairsum_persistent(b->precision, b->R, b->preq.p, b->pitem.p,
+                                             static_cast<const int *>(b->qbegin.p), static_cast<int *>(b->qnext.p),
+                                             b->n_cu * b->blocks_per_cu, st);
+    if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
+    if (time_pairsum) (void)hipEventRecord(b->ev_b, st);
+    for (auto &gr : b->groups) {
+        const int nb = static_cast<int>(gr.members.size());
+        const Workspace ws = carve_workspace(gr.g, b->precision, nb, static_cast<char *>(b->ws.p) + gr.ws_off);
+        AmpRef amp = plan_amp(gr.plan);
+        amp.scale_b = static_cast<const double *>(b->scales.p) + gr.first;
+        amp.S_b = static_cast<const double *const *>(b->sptr.p) + gr.first;
+        e = launch_tfft(gr.g, b->precision, 0, nullptr, amp, gr.plan->wtab.p, gr.plan->tw_t.p, nb, ws, st);
+        if (e != hipSuccess) return dev_err(e, "t-transform kernel");
+        e = launch_xfft(gr.g, b->precision, gr.plan->tw_x.p, nb, ws, nullptr,
+                        static_cast<void *const *>(b->outs.p) + gr.first, st);
+        if (e != hipSuccess) return dev_err(e, "x-transform kernel");
+    }
+    return SRM3_OK;
+}
+
+srm3_status batch_copy_seeds(srm3_batch_t b, const uint64_t *seeds, hipStream_t st)
+{
+    if (b->copy_pending) {
+        hipError_t e = hipEventSynchronize(b->copy_done);
+        if (e != hipSuccess) return dev_err(e, "hipEventSynchronize");
+    }
+    for (auto &gr : b->groups)
+        for (size_t slot = 0; slot < gr.members.size(); ++slot)
+            b->seeds_host[gr.first + slot] = seeds ? seeds[gr.members[slot]] : b->req[gr.members[slot]].seed;
+    hipError_t e = hipMemcpyAsync(b->seeds.p, b->seeds_host, b->n * sizeof(uint64_t), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return dev_err(e, "hipMemcpyAsync");
+    e = hipEventRecord(b->copy_done, st);
+    if (e != hipSuccess) return dev_err(e, "hipEventRecord");
+    b->copy_pending = true;
+    return SRM3_OK;
+}
+
+std::string tune_cache_path()
+{
+    const char *p = std::getenv("SRM3_TUNE_CACHE");
+    if (p && *p) return p;
+    const char *h = std::getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/srm3_tune.txt";
+}
+
+std::string batch_signature(srm3_batch_t b)
+{
+    std::map<std::string, int> count;
+    for (auto &gr : b->groups) {
+        std::ostringstream k;
+        k << gr.plan->g.nk << 'x' << gr.plan->g.nw << 'w' << gr.plan->g.W;
+        count[k.str()] += static_cast<int>(gr.members.size());
+    }
+    std::ostringstream o;
+    o << (b->precision == SRM3_FP64 ? "fp64" : "fp32") << ";cu" << b->n_cu;
+    for (auto &kv : count) o << ';' << kv.first << '*' << kv.second;
+    return o.str();
+}
+
+bool tune_lookup(const std::string &sig, int *R, int *bpc)
+{
+    std::ifstream f(tune_cache_path());
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream ls(line);
+        std::string s;
+        int r, c;
+        if (ls >> s >> r >> c && s == sig) {
+            *R = r;
+            *bpc = c;
+            found = true;
+        }
+    }
+    return found;
+}
+
+void tune_store(const std::string &sig, int R, int bpc)
+{
+    const std::string path = tune_cache_path();
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    std::ofstream f(path, std::ios::app);
+    if (f) f << sig << ' ' << R << ' ' << bpc << '\n';
+}
+
+}  // namespace
+
+extern "C" {
+
+srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags, void *hip_stream,
+                              srm3_batch_t *out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(SRM3_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!reqs || n <= 0) return fail(SRM3_E_INVALID, "no requests");
+    const int precision = reqs[0].plan ? reqs[0].plan->precision : -1;
+    for (int i = 0; i < n; ++i) {
+        const srm3_request &r = reqs[i];
+        if (!r.plan || !r.out_dev) return fail(SRM3_E_INVALID, "request %d: NULL plan or output", i);
+        if (r.plan->precision != precision)
+            return fail(SRM3_E_INVALID, "request %d: all requests of a batch share one precision", i);
+        if (!(r.b2_scale > 0) || !std::isfinite(r.b2_scale))
+            return fail(SRM3_E_INVALID, "request %d: b2_scale must be finite and > 0", i);
+        if (max_sigma(r.plan->max_sig, r.plan->cap, r.b2_scale) >= 1.0)
+            return fail(SRM3_E_PURE_NEGATIVE, "request %d: scaled sum of b^2 reaches 1", i);
+    }
+    std::unique_ptr<srm3_batch_s> b(new (std::nothrow) srm3_batch_s);
+    if (!b) return fail(SRM3_E_NOMEM, "host allocation failed");
+    b->precision = precision;
+    b->n = n;
+    b->flags = flags;
+    b->req.assign(reqs, reqs + n);
+    std::map<srm3_plan_t, int> gi;
+    for (int i = 0; i < n; ++i) {
+        auto it = gi.find(reqs[i].plan);
+        if (it == gi.end()) {
+            gi[reqs[i].plan] = static_cast<int>(b->groups.size());
+            b->groups.push_back({reqs[i].plan, {i}, reqs[i].plan->g, 0, 0});
+        } else {
+            b->groups[it->second].members.push_back(i);
+        }
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        b->n_cu = prop.multiProcessorCount;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // the largest rows per wave every grid of the batch supports
+    int R = precision == SRM3_FP64 ? 8 : 16;
+    for (auto &gr : b->groups) R = std::min(R, rows_for(gr.plan->g.nk, precision, 0));
+    srm3_status s = batch_layout(b.get(), R, st);
+    if (s) return s;
+    for (auto &gr : b->groups) b->pair_terms += gr.plan->pair_terms * gr.members.size();
+    // per-request device arrays in group order
+    std::vector<double> scales(n);
+    std::vector<const double *> sptr(n);
+    std::vector<void *> outs(n);
+    for (auto &gr : b->groups)
+        for (size_t slot = 0; slot < gr.members.size(); ++slot) {
+            const srm3_request &r = reqs[gr.members[slot]];
+            scales[gr.first + slot] = r.b2_scale;
+            sptr[gr.first + slot] = r.S_dev;
+            outs[gr.first + slot] = r.out_dev;
+        }
+    if ((s = upload_bytes(b->scales, scales.data(), n * sizeof(double), st))) return s;
+    if ((s = upload_bytes(b->sptr, sptr.data(), n * sizeof(void *), st))) return s;
+    if ((s = upload_bytes(b->outs, outs.data(), n * sizeof(void *), st))) return s;
+    hipError_t e = b->seeds.alloc(n * sizeof(uint64_t));
+    if (e != hipSuccess) return fail(SRM3_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    e = hipHostMalloc(reinterpret_cast<void **>(&b->seeds_host), n * sizeof(uint64_t), hipHostMallocDefault);
+    if (e != hipSuccess) return fail(SRM3_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    if ((e = hipEventCreateWithFlags(&b->copy_done, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreate(&b->ev_a)) != hipSuccess || (e = hipEventCreate(&b->ev_b)) != hipSuccess ||
+        (e = hipEventCreate(&b->run_a)) != hipSuccess || (e = hipEventCreate(&b->run_b)) != hipSuccess)
+        return dev_err(e, "hipEventCreate");
+    *out = b.release();
+    return SRM3_OK;
+}
+
+// Time the candidate tile shapes on a stride sample of the batch (requests
+// sorted by cost) and keep the fastest; the choice is cached by signature.
+static srm3_status batch_autotune(srm3_batch_t b, hipStream_t st)
+{
+    const std::string sig = batch_signature(b);
+    int R = b->R, bpc = b->blocks_per_cu;
+    if (tune_lookup(sig, &R, &bpc)) {
+        b->blocks_per_cu = bpc;
+        return R == b->R ? SRM3_OK : batch_layout(b, R, st);
+    }
+    std::vector<int> order(b->n);
+    for (int i = 0; i < b->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->req[x].plan->pair_terms > b->req[y].plan->pair_terms; });
+    const int want = 16;
+    const int stride = std::max(1, b->n / want);
+    std::vector<srm3_request> sub;
+    for (int i = 0; i < b->n; i += stride) sub.push_back(b->req[order[i]]);
+    srm3_batch_t t = nullptr;
+    srm3_status s = srm3_batch_create(sub.data(), static_cast<int32_t>(sub.size()), 0, st, &t);
+    if (s) return s;
+    const int Rmax = t->R;
+    float best = 1e30f;
+    int bestR = Rmax, bestC = t->blocks_per_cu;
+    for (int r : {Rmax, Rmax / 2}) {
+        if (r < 2) continue;
+        if (r != t->R && (s = batch_layout(t, r, st))) break;
+        for (int c : {1, 2, 4}) {
+            t->blocks_per_cu = c;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && !s; ++rep) {   // second repetition is the one timed
+                if ((s = batch_copy_seeds(t, nullptr, st))) break;
+                if ((s = batch_launch(t, st, true))) break;
+                hipError_t e = hipStreamSynchronize(st);
+                if (e != hipSuccess) s = dev_err(e, "hipStreamSynchronize");
+                else (void)hipEventElapsedTime(&ms, t->ev_a, t->ev_b);
+            }
+            if (s) break;
+            if (ms < best) {
+                best = ms;
+                bestR = r;
+                bestC = c;
+            }
+        }
+        if (s) break;
+    }
+    srm3_batch_destroy(t);
+    if (s) return s;
+    if (bestR != b->R && (s = batch_layout(b, bestR, st))) return s;
+    b->blocks_per_cu = bestC;
+    tune_store(sig, bestR, bestC);
+    return SRM3_OK;
+}
+
+srm3_status srm3_batch_run(srm3_batch_t b, const uint64_t *seeds, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!b) return fail(SRM3_E_INVALID, "batch is NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    srm3_status s;
+    if ((b->flags & SRM3_BATCH_AUTOTUNE) && !b->tuned) {
+        if ((s = batch_autotune(b, st))) return s;
+        b->tuned = true;
+    }
+    if ((s = batch_copy_seeds(b, seeds, st))) return s;
+    b->ran = true;
+    if (b->flags & SRM3_BATCH_GRAPH) {
+        if (!b->exec) {
+            hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return dev_err(e, "hipStreamCreate");
+            e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return dev_err(e, "hipStreamBeginCapture");
+            s = batch_launch(b, b->cap_stream, false);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(b->cap_stream, &graph);
+            if (s) return s;
+            if (e2 != hipSuccess) return dev_err(e2, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                return dev_err(e, "hipGraphInstantiate");
+            }
+        }
+        (void)hipEventRecord(b->run_a, st);
+        hipError_t e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) return dev_err(e, "hipGraphLaunch");
+        (void)hipEventRecord(b->run_b, st);
+        b->ps_timed = false;
+        return SRM3_OK;
+    }
+    (void)hipEventRecord(b->run_a, st);
+    if ((s = batch_launch(b, st, true))) return s;
+    (void)hipEventRecord(b->run_b, st);
+    b->ps_timed = true;
+    return SRM3_OK;
+}
+
+srm3_status srm3_batch_info(srm3_batch_t b, srm3_batch_stats *out)
+{
+    if (!b || !out) return fail(SRM3_E_INVALID, "bad argument");
+    out->pair_terms = b->pair_terms;
+    out->rows_per_wave = b->R;
+    out->blocks_per_cu = b->blocks_per_cu;
+    out->work_items = b->n_items;
+    out->groups = static_cast<int32_t>(b->groups.size());
+    out->run_ms = -1.0;
+    out->pairsum_ms = -1.0;
+    float ms = 0.f;
+    if (b->ran) {
+        hipError_t e = hipEventSynchronize(b->run_b);
+        if (e != hipSuccess) return dev_err(e, "hipEventSynchronize");
+        if (hipEventElapsedTime(&ms, b->run_a, b->run_b) == hipSuccess) out->run_ms = ms;
+        if (b->ps_timed && hipEventElapsedTime(&ms, b->ev_a, b->ev_b) == hipSuccess) out->pairsum_ms = ms;
+    }
+    return SRM3_OK;
+}
+
+void srm3_batch_destroy(srm3_batch_t b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->seeds_host) (void)hipHostFree(b->seeds_host);
+    if (b->copy_done) (void)hipEventDestroy(b->copy_done);
+    for (hipEvent_t ev : {b->ev_a, b->ev_b, b->run_a, b->run_b})
+        if (ev) (void)hipEventDestroy(ev);
+    delete b;
+}
+
+srm3_status srm3_generate_uneven(const srm3_request *reqs, int32_t n, void *hip_stream)
+{
+    srm3_batch_t b = nullptr;
+    srm3_status s = srm3_batch_create(reqs, n, 0, hip_stream, &b);
+    if (s) return s;
+    s = srm3_batch_run(b, nullptr, hip_stream);
+    if (!s) {
+        hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+        if (e != hipSuccess) s = dev_err(e, "hipStreamSynchronize");
+    }
+    srm3_batch_destroy(b);
+    return s;
 }
 
 }  // extern "C"

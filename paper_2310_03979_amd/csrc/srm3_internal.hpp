@@ -66,21 +66,45 @@ struct Workspace {
 size_t workspace_bytes(const Geometry &g, int precision, int batch);
 Workspace carve_workspace(const Geometry &g, int precision, int batch, void *base);
 
+// Inputs of the FP64 amplitude computation done on the device (see
+// assemble_line): plan spectrum, unit-scale raw pair sums, optional
+// per-realization b^2 scales and spectra (device arrays indexed by the
+// realization within a launch).
+struct AmpRef {
+    const double *S;
+    const double *sig;
+    const double *scale_b;
+    const double *const *S_b;
+    double dkdw;
+    double cap;
+};
+
 // Kernel launchers (stream-ordered, return the launch status).
-hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, int batch,
-                         const Workspace &ws, hipStream_t st);
+hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, const uint64_t *seeds_dev,
+                         int batch, const Workspace &ws, hipStream_t st);
 hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
                           const Workspace &ws, hipStream_t st);
+// Persistent pair sum over a device work list (all requests share R).
+hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
+                                     int *q_next, int nblocks, hipStream_t st);
+size_t persistent_req_bytes();
+size_t persistent_item_bytes();
+void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const void *zcol, void *tsum,
+                         const void *wtab);
+void fill_persistent_item(void *dst, int req, int kb, int cg);
+int waves_per_block();
+constexpr int kXcds = 8;
 // mode 0: assemble C from pair sums and phases; mode 1: read C from `cin`.
-hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin,
-                       const void *amp_pure, const void *amp_pair, const void *wtab,
-                       const void *tw_t, int batch, const Workspace &ws, hipStream_t st);
-hipError_t launch_assemble(const Geometry &g, int precision, const void *amp_pure,
-                           const void *amp_pair, const void *wtab, int batch,
+hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
+                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st);
+hipError_t launch_assemble(const Geometry &g, int precision, const AmpRef &amp, const void *wtab, int batch,
                            const Workspace &ws, void *cout, hipStream_t st);
-hipError_t launch_xfft(const Geometry &g, int precision, const void *tw_x, int batch,
-                       const Workspace &ws, void *out, hipStream_t st);
+hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int batch, const Workspace &ws,
+                       void *out, void *const *out_b, hipStream_t st);
+hipError_t launch_spectrum(int nk, int nw, double dk, double dw, double u_star, double z, double U, double lam,
+                           double *S, hipStream_t st);
 
 int pairsum_rows_per_wave(int nk, int precision);
+hipError_t prepare_transforms(int precision);
 
 }  // namespace srm3

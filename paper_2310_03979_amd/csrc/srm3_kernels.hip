@@ -5,6 +5,8 @@
 //  tfft        : C_k = A_pure z_k + A_pair (T_k + diagonal fix), placed at bin
 //                (k_kappa, k_omega mod n_t), inverse DFT along t (Stockham, LDS)
 //  xfft        : inverse DFT along x over the n_kappa live rows, real part out
+#include <cstring>
+
 #include "srm3_internal.hpp"
 
 namespace srm3 {
@@ -29,7 +31,8 @@ __device__ __forceinline__ void two_sum(T &s, T &c, T x)
 // Phases.  One thread per (realization, padded row, column).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, int b0, Geometry g,
+__global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
+                                                    int b0, Geometry g,
                                                     typename vec<T>::v2 *__restrict__ zrow,
                                                     T *__restrict__ zcol)
 {
@@ -44,8 +47,8 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, int b0, Geo
     const int b = b0 + bl;
     T cz = T(0), sz = T(0);
     if (kk < g.nk) {
-        const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u,
-                                        0u, seeds.s[bl]);
+        const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
+        const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
         double s, co;
         sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
         cz = static_cast<T>(co);
@@ -102,6 +105,7 @@ struct PairsumArgs {
 };
 
 constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
+constexpr int kFlushTerms = 256;
 
 constexpr int kWavesPerBlock = 4;
 
@@ -176,39 +180,17 @@ __device__ __forceinline__ void pair_block(T (&K1)[R], T (&K2)[R], T (&K3)[R], T
     }
 }
 
+// One tile of the pair sum for one realization: output rows K0 = kb*R ..
+// K0+R-1 and the 64 output columns of column tile ct (one per lane).
 template <typename T, int R, bool COMP>
-__global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
+__device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename vec<T>::v2 *__restrict__ zrow_b,
+                                             const T *__restrict__ zcol_b,
+                                             const typename vec<T>::v2 *__restrict__ wtab,
+                                             typename vec<T>::v2 *__restrict__ tout_b, int kb, int ct,
+                                             int flush_terms)
 {
     using T2 = typename vec<T>::v2;
-    const Geometry &g = a.g;
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    // Work item -> (realization b, row block kb, column group cg).  In the
-    // XCD-blocked order each XCD (block id mod 8) walks its own contiguous
-    // range of realizations, heaviest row blocks first within a realization,
-    // so the z rows of the realization in flight stay in that XCD's L2.  The
-    // interleaved order (small batches) walks row blocks heaviest first across
-    // all realizations, spreading every row block over all XCDs.
-    const int bid = blockIdx.x;
-    int b, kb, cg;
-    if (a.per_xcd > 0) {
-        const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
-        const int per_b = a.n_rowblocks * a.n_cgroups;
-        if (work >= a.batch * per_b) return;
-        b = work / per_b;
-        const int rem = work - b * per_b;
-        kb = a.n_rowblocks - 1 - rem / a.n_cgroups;
-        cg = rem - (rem / a.n_cgroups) * a.n_cgroups;
-    } else {
-        const int per_kb = a.batch * a.n_cgroups;
-        kb = a.n_rowblocks - 1 - bid / per_kb;
-        const int rem = bid - (bid / per_kb) * per_kb;
-        b = rem / a.n_cgroups;
-        cg = rem - b * a.n_cgroups;
-    }
-    const int ct = cg * kWavesPerBlock + wave;
-    if (ct >= a.n_ctiles) return;
-
     const int K0 = kb * R;
     const int kc = ct * 64 + lane;
     const bool lane_ok = kc < g.nc;
@@ -220,10 +202,7 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
     const int iw_hi = min(Wm1, kw_hi + Wm1);
     const long nc = g.nc;
 
-    const T2 *__restrict__ zrow_b = static_cast<const T2 *>(a.zrow) + static_cast<long>(b) * g.nk * nc;
     const long plane = static_cast<long>(g.ncw) * g.nkp;
-    const T *__restrict__ zcol_b = static_cast<const T *>(a.zcol) + static_cast<long>(b) * 3 * plane;
-    const T2 *__restrict__ wtab = static_cast<const T2 *>(a.wtab);
 
     T sre[R], sim[R], cre[R], cim[R];
     T K1[R], K2[R], K3[R];
@@ -236,7 +215,7 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
     const int nbulk = K0 / 2;
     const int jk_last = nbulk + R / 2 - 1;   // last b row used (rows < n_kappa)
     const int steps_per_ic = nbulk + R / 2;
-    const int flush_every = COMP ? max(1, a.flush_terms / steps_per_ic) : 0x7fffffff;
+    const int flush_every = COMP ? max(1, flush_terms / steps_per_ic) : 0x7fffffff;
     int since_flush = 0;
 
     for (int iw = iw_lo; iw <= iw_hi; ++iw) {
@@ -295,7 +274,6 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
         }
     }
 
-    T2 *__restrict__ tout = static_cast<T2 *>(a.tout) + static_cast<long>(b) * g.nk * nc;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         T re, im;
@@ -313,9 +291,116 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
             T2 v;
             v.x = re;
             v.y = im;
-            tout[static_cast<long>(kk) * nc + kc] = v;
+            tout_b[static_cast<long>(kk) * nc + kc] = v;
         }
     }
+}
+
+template <typename T, int R, bool COMP>
+__global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    const Geometry &g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    // Work item -> (realization b, row block kb, column group cg).  In the
+    // XCD-blocked order each XCD (block id mod 8) walks its own contiguous
+    // range of realizations, heaviest row blocks first within a realization,
+    // so the z rows of the realization in flight stay in that XCD's L2.  The
+    // interleaved order (small batches) walks row blocks heaviest first across
+    // all realizations, spreading every row block over all XCDs.
+    const int bid = blockIdx.x;
+    int b, kb, cg;
+    if (a.per_xcd > 0) {
+        const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
+        const int per_b = a.n_rowblocks * a.n_cgroups;
+        if (work >= a.batch * per_b) return;
+        b = work / per_b;
+        const int rem = work - b * per_b;
+        kb = a.n_rowblocks - 1 - rem / a.n_cgroups;
+        cg = rem - (rem / a.n_cgroups) * a.n_cgroups;
+    } else {
+        const int per_kb = a.batch * a.n_cgroups;
+        kb = a.n_rowblocks - 1 - bid / per_kb;
+        const int rem = bid - (bid / per_kb) * per_kb;
+        b = rem / a.n_cgroups;
+        cg = rem - b * a.n_cgroups;
+    }
+    const int ct = cg * kWavesPerBlock + wave;
+    if (ct >= a.n_ctiles) return;
+    const long plane = static_cast<long>(g.ncw) * g.nkp;
+    const long lines = static_cast<long>(g.nk) * g.nc;
+    pairsum_tile<T, R, COMP>(g, static_cast<const T2 *>(a.zrow) + b * lines,
+                             static_cast<const T *>(a.zcol) + b * 3 * plane,
+                             static_cast<const T2 *>(a.wtab), static_cast<T2 *>(a.tout) + b * lines, kb, ct,
+                             a.flush_terms);
+}
+
+// Persistent pair sum over an uneven work list.  Work items (request, row
+// block, column group) sit in eight queues, one per XCD, each a contiguous
+// run of the cost-sorted list so that an XCD works on few requests at a time.
+// A block first drains the queue of its own XCD (block id mod 8), then steals
+// from the others.  The computation of an item does not depend on which block
+// runs it, so results are bitwise those of the direct launch.
+struct PReq {
+    Geometry g;
+    const void *zrow;
+    const void *zcol;
+    void *tsum;
+    const void *wtab;
+    int n_ctiles;
+    int pad;
+};
+struct PItem {
+    int req, kb, cg, pad;
+};
+struct PersistArgs {
+    const PReq *reqs;
+    const PItem *items;
+    const int *q_begin;   // [kNumXcd + 1]
+    int *q_next;          // [kNumXcd] counters, zero at launch
+    int flush_terms;
+};
+
+template <typename T, int R, bool COMP>
+__global__ __launch_bounds__(256) void pairsum_persistent(PersistArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int home = blockIdx.x % kNumXcd;
+    int tries = 0;   // meaningful in thread 0 only
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tries < kNumXcd) {
+                const int q = (home + tries) % kNumXcd;
+                const int i = a.q_begin[q] + atomicAdd(&a.q_next[q], 1);
+                if (i < a.q_begin[q + 1]) {
+                    it = i;
+                    break;
+                }
+                ++tries;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it < 0) break;
+        const PItem w = a.items[it];
+        const PReq &rq = a.reqs[w.req];
+        const int ct = w.cg * kWavesPerBlock + wave;
+        if (ct < rq.n_ctiles)
+            pairsum_tile<T, R, COMP>(rq.g, static_cast<const T2 *>(rq.zrow), static_cast<const T *>(rq.zcol),
+                                     static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, ct,
+                                     a.flush_terms);
+    }
+}
+
+__global__ void fill_int_kernel(int *p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -411,14 +496,28 @@ __device__ void fft_lds(typename vec<T>::v2 *buf, int N, int ld, int nbatch,
     }
 }
 
+// Amplitudes of Eq. pure and the pair term, per line and realization, in
+// FP64 (1 - Sigma cancels near the cap):
+//   s_raw = scale * sig, rho = min(1, cap / s_raw), Sigma = rho s_raw,
+//   A_pure = 2 sqrt(S dk dw (1 - Sigma)),  A_pair = 2 sqrt(S dk dw rho scale).
+// `sig` is the raw (unit-scale) bicoherence sum of the line's pair set; the
+// weight table holds sqrt(b2_raw), so sqrt(scale) goes into A_pair.
+struct AmpArgs {
+    const double *S;          // plan spectrum [nk][nc]
+    const double *sig;        // unit-scale raw pair sums [nk][nc]
+    const double *scale_b;    // per realization b^2 scale, or null (1)
+    const double *const *S_b; // per realization spectrum, or null (plan's)
+    double dkdw;
+    double cap;
+};
+
 struct TfftArgs {
     Geometry g;
     int mode;
     const void *cin;      // mode 1: [B][nk][nc]
     const void *zrow;     // mode 0
     const void *tsum;     // mode 0
-    const void *amp_pure; // [nk][nc]
-    const void *amp_pair; // [nk][nc]
+    AmpArgs amp;
     const void *wtab;     // [ncw][ncw]
     const void *tw;       // [nt]
     void *gout;           // [B][nk][nt]
@@ -429,7 +528,7 @@ template <typename T>
 __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, int b, int kk, int c,
                                                              const typename vec<T>::v2 *zrow,
                                                              const typename vec<T>::v2 *tsum,
-                                                             const T *ap, const T *ac,
+                                                             const AmpArgs &amp,
                                                              const typename vec<T>::v2 *wtab)
 {
     using T2 = typename vec<T>::v2;
@@ -449,8 +548,14 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
             t.y += T(0.5) * d.y;
         }
     }
+    const double *Sp = (amp.S_b && amp.S_b[b]) ? amp.S_b[b] : amp.S;
+    const double sc = amp.scale_b ? amp.scale_b[b] : 1.0;
+    const double sraw = sc * amp.sig[li];
+    const double rho = (amp.cap > 0.0 && sraw > amp.cap) ? amp.cap / sraw : 1.0;
+    const double base = Sp[li] * amp.dkdw;
+    const T p = static_cast<T>(2.0 * sqrt(base * (1.0 - rho * sraw)));
+    const T q = static_cast<T>(2.0 * sqrt(base * rho * sc));
     const T2 z = zrow[bi];
-    const T p = ap[li], q = ac[li];
     T2 C;
     C.x = fma_(p, z.x, q * t.x);
     C.y = fma_(p, z.y, q * t.y);
@@ -478,9 +583,8 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         const int bin = kw < 0 ? kw + g.nt : kw;
         T2 C;
         if (a.mode == 0) {
-            C = assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow),
-                                 static_cast<const T2 *>(a.tsum), static_cast<const T *>(a.amp_pure),
-                                 static_cast<const T *>(a.amp_pair), static_cast<const T2 *>(a.wtab));
+            C = assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
+                                 a.amp, static_cast<const T2 *>(a.wtab));
         } else {
             C = static_cast<const T2 *>(a.cin)[static_cast<long>(row) * g.nc + c];
         }
@@ -504,8 +608,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(TfftArgs a, typename vec<
     const int kk = static_cast<int>(idx / g.nc);
     const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
     cout[static_cast<long>(b) * per + idx] =
-        assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
-                         static_cast<const T *>(a.amp_pure), static_cast<const T *>(a.amp_pair),
+        assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow), static_cast<const T2 *>(a.tsum), a.amp,
                          static_cast<const T2 *>(a.wtab));
 }
 
@@ -515,6 +618,7 @@ struct XfftArgs {
     const void *gin;     // [B][nk][nt]
     const void *tw;      // [nx]
     void *out;           // [B][nx][nt] real
+    void *const *out_b;  // per realization output, or null (out + b * nx * nt)
 };
 
 template <typename T, int MAXB>
@@ -542,11 +646,35 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
     }
     __syncthreads();
     fft_lds<T, MAXB>(buf, g.nx, ld, tc, static_cast<const T2 *>(a.tw));
-    T *out = static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
+    T *out = a.out_b ? static_cast<T *>(a.out_b[b]) : static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
     for (int n = threadIdx.x; n < tc * g.nx; n += blockDim.x) {
         const int mx = n / tc, col = n - mx * tc;
         out[static_cast<long>(mx) * g.nt + mt0 + col] = buf[col * ld + mx].x;
     }
+}
+
+// Spectrum on the lines from the Kaimal frequency spectrum times the exact
+// Fourier transform of the Davenport coherence (the wind-field example of
+// Section 5, in the workload normalisation), FP64; S(., 0) = 0.
+__global__ __launch_bounds__(256) void spectrum_kernel(int nk, int nw, double dk, double dw, double u_star,
+                                                       double z, double U, double lam, double *S)
+{
+    const int nc = 2 * nw - 1;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= static_cast<long>(nk) * nc) return;
+    const int kk = static_cast<int>(idx / nc);
+    const int kw = static_cast<int>(idx - static_cast<long>(kk) * nc) - (nw - 1);
+    double v = 0.0;
+    if (kw != 0) {
+        const double two_pi = 6.283185307179586476925286766559;
+        const double w = fabs(static_cast<double>(kw)) * dw;
+        const double f = w / two_pi;
+        const double sw = 200.0 * u_star * u_star * (z / U) / pow(1.0 + 50.0 * f * z / U, 5.0 / 3.0);
+        const double a = lam * w / (two_pi * U);
+        const double kap = kk * dk;
+        v = sw * (a / 3.14159265358979323846264338327950288) / (a * a + kap * kap);
+    }
+    S[idx] = v;
 }
 
 constexpr int kFftMaxB = 4;
@@ -597,8 +725,8 @@ Workspace carve_workspace(const Geometry &g, int precision, int batch, void *bas
 }
 
 template <typename T>
-static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, int batch, const Workspace &ws,
-                           hipStream_t st)
+static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint64_t *seeds_dev, int batch,
+                           const Workspace &ws, hipStream_t st)
 {
     using T2 = typename vec<T>::v2;
     const long per = static_cast<long>(g.nkp) * g.nc;
@@ -606,8 +734,9 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, int batch, 
     for (int b0 = 0; b0 < batch; b0 += kMaxSeedsPerLaunch) {
         const int nb = std::min(kMaxSeedsPerLaunch, batch - b0);
         SeedChunk sc{};
-        for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
-        phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, b0, g, static_cast<T2 *>(ws.zrow),
+        if (!seeds_dev)
+            for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
+        phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, seeds_dev, b0, g, static_cast<T2 *>(ws.zrow),
                                                        static_cast<T *>(ws.zcol));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -615,11 +744,11 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, int batch, 
     return hipSuccess;
 }
 
-hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, int batch,
-                         const Workspace &ws, hipStream_t st)
+hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, const uint64_t *seeds_dev,
+                         int batch, const Workspace &ws, hipStream_t st)
 {
-    return precision == SRM3_FP64 ? phases_t<double>(g, seeds, batch, ws, st)
-                                  : phases_t<float>(g, seeds, batch, ws, st);
+    return precision == SRM3_FP64 ? phases_t<double>(g, seeds, seeds_dev, batch, ws, st)
+                                  : phases_t<float>(g, seeds, seeds_dev, batch, ws, st);
 }
 
 template <typename T, int R, bool COMP>
@@ -636,7 +765,7 @@ static hipError_t pairsum_t(const Geometry &g, const void *wtab, int batch, cons
     a.n_rowblocks = g.nkp / R;
     a.n_ctiles = (g.nc + 63) / 64;
     a.n_cgroups = (a.n_ctiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    a.flush_terms = 256;
+    a.flush_terms = kFlushTerms;
     const long work = static_cast<long>(a.n_rowblocks) * batch * a.n_cgroups;
     a.per_xcd = batch >= kNumXcd ? static_cast<int>((work + kNumXcd - 1) / kNumXcd) : 0;
     const long blocks = a.per_xcd > 0 ? static_cast<long>(a.per_xcd) * kNumXcd : work;
@@ -664,9 +793,70 @@ hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, in
     }
 }
 
+template <typename T, int R, bool COMP>
+static hipError_t persistent_t(const void *reqs, const void *items, const int *q_begin, int *q_next, int nblocks,
+                               hipStream_t st)
+{
+    fill_int_kernel<<<1, 64, 0, st>>>(q_next, kNumXcd, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PersistArgs a;
+    a.reqs = static_cast<const PReq *>(reqs);
+    a.items = static_cast<const PItem *>(items);
+    a.q_begin = q_begin;
+    a.q_next = q_next;
+    a.flush_terms = kFlushTerms;
+    pairsum_persistent<T, R, COMP><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
+                                     int *q_next, int nblocks, hipStream_t st)
+{
+    if (precision == SRM3_FP64) {
+        switch (R) {
+        case 2: return persistent_t<double, 2, false>(reqs, items, q_begin, q_next, nblocks, st);
+        case 4: return persistent_t<double, 4, false>(reqs, items, q_begin, q_next, nblocks, st);
+        case 8: return persistent_t<double, 8, false>(reqs, items, q_begin, q_next, nblocks, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (R) {
+    case 2: return persistent_t<float, 2, true>(reqs, items, q_begin, q_next, nblocks, st);
+    case 4: return persistent_t<float, 4, true>(reqs, items, q_begin, q_next, nblocks, st);
+    case 8: return persistent_t<float, 8, true>(reqs, items, q_begin, q_next, nblocks, st);
+    case 16: return persistent_t<float, 16, true>(reqs, items, q_begin, q_next, nblocks, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t persistent_req_bytes() { return sizeof(PReq); }
+size_t persistent_item_bytes() { return sizeof(PItem); }
+
+void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const void *zcol, void *tsum,
+                         const void *wtab)
+{
+    PReq r{};
+    r.g = g;
+    r.zrow = zrow;
+    r.zcol = zcol;
+    r.tsum = tsum;
+    r.wtab = wtab;
+    r.n_ctiles = (g.nc + 63) / 64;
+    std::memcpy(dst, &r, sizeof r);
+}
+
+void fill_persistent_item(void *dst, int req, int kb, int cg)
+{
+    PItem it{req, kb, cg, 0};
+    std::memcpy(dst, &it, sizeof it);
+}
+
+int waves_per_block() { return kWavesPerBlock; }
+
 template <typename T>
-static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const void *ap, const void *ac,
-                         const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st)
+static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const AmpRef &amp, const void *wtab,
+                         const void *tw, int batch, const Workspace &ws, hipStream_t st)
 {
     TfftArgs a;
     a.g = g;
@@ -674,41 +864,32 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const voi
     a.cin = cin;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp_pure = ap;
-    a.amp_pair = ac;
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap};
     a.wtab = wtab;
     a.tw = tw;
     a.gout = ws.g;
     const int thr = fft_threads(g.nt / 2);
     const size_t lds = static_cast<size_t>(g.nt) * sizeof(typename vec<T>::v2);
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T, kFftMaxB>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-    }
     tfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(batch * g.nk)), thr, lds, st>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const void *ap,
-                       const void *ac, const void *wtab, const void *tw, int batch, const Workspace &ws,
-                       hipStream_t st)
+hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
+                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st)
 {
-    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, ap, ac, wtab, tw, batch, ws, st)
-                                  : tfft_t<float>(g, mode, cin, ap, ac, wtab, tw, batch, ws, st);
+    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, amp, wtab, tw, batch, ws, st)
+                                  : tfft_t<float>(g, mode, cin, amp, wtab, tw, batch, ws, st);
 }
 
 template <typename T>
-static hipError_t assemble_t(const Geometry &g, const void *ap, const void *ac, const void *wtab,
-                             int batch, const Workspace &ws, void *cout, hipStream_t st)
+static hipError_t assemble_t(const Geometry &g, const AmpRef &amp, const void *wtab, int batch,
+                             const Workspace &ws, void *cout, hipStream_t st)
 {
     TfftArgs a{};
     a.g = g;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp_pure = ap;
-    a.amp_pair = ac;
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap};
     a.wtab = wtab;
     const long per = static_cast<long>(g.nk) * g.nc;
     assemble_kernel<T><<<dim3(static_cast<unsigned>((per + 255) / 256), batch), 256, 0, st>>>(
@@ -716,16 +897,16 @@ static hipError_t assemble_t(const Geometry &g, const void *ap, const void *ac, 
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const Geometry &g, int precision, const void *ap, const void *ac,
-                           const void *wtab, int batch, const Workspace &ws, void *cout, hipStream_t st)
+hipError_t launch_assemble(const Geometry &g, int precision, const AmpRef &amp, const void *wtab, int batch,
+                           const Workspace &ws, void *cout, hipStream_t st)
 {
-    return precision == SRM3_FP64 ? assemble_t<double>(g, ap, ac, wtab, batch, ws, cout, st)
-                                  : assemble_t<float>(g, ap, ac, wtab, batch, ws, cout, st);
+    return precision == SRM3_FP64 ? assemble_t<double>(g, amp, wtab, batch, ws, cout, st)
+                                  : assemble_t<float>(g, amp, wtab, batch, ws, cout, st);
 }
 
 template <typename T>
 static hipError_t xfft_t(const Geometry &g, const void *tw, int batch, const Workspace &ws, void *out,
-                         hipStream_t st)
+                         void *const *out_b, hipStream_t st)
 {
     XfftArgs a;
     a.g = g;
@@ -737,23 +918,46 @@ static hipError_t xfft_t(const Geometry &g, const void *tw, int batch, const Wor
     a.gin = ws.g;
     a.tw = tw;
     a.out = out;
+    a.out_b = out_b;
     const int thr = fft_threads(tc * g.nx / 2);
     const size_t lds = tc * col_bytes;
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T, kFftMaxB>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 static_cast<int>(lds));
-        if (e != hipSuccess) return e;
-    }
     xfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(g.nt / tc), batch), thr, lds, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int batch, const Workspace &ws,
-                       void *out, hipStream_t st)
+                       void *out, void *const *out_b, hipStream_t st)
 {
-    return precision == SRM3_FP64 ? xfft_t<double>(g, tw, batch, ws, out, st)
-                                  : xfft_t<float>(g, tw, batch, ws, out, st);
+    return precision == SRM3_FP64 ? xfft_t<double>(g, tw, batch, ws, out, out_b, st)
+                                  : xfft_t<float>(g, tw, batch, ws, out, out_b, st);
+}
+
+// Allow the transform kernels the 128 KB of LDS a length-16384 FP32 (8192
+// FP64) transform needs.  Called once when a plan is built, never during a
+// stream capture.
+template <typename T>
+static hipError_t prepare_t()
+{
+    const int lds = 131072;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T, kFftMaxB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T, kFftMaxB>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t prepare_transforms(int precision)
+{
+    return precision == SRM3_FP64 ? prepare_t<double>() : prepare_t<float>();
+}
+
+hipError_t launch_spectrum(int nk, int nw, double dk, double dw, double u_star, double z, double U, double lam,
+                           double *S, hipStream_t st)
+{
+    const long n = static_cast<long>(nk) * (2 * nw - 1);
+    spectrum_kernel<<<dim3(static_cast<unsigned>((n + 255) / 256)), 256, 0, st>>>(nk, nw, dk, dw, u_star, z, U,
+                                                                                   lam, S);
+    return hipGetLastError();
 }
 
 }  // namespace srm3

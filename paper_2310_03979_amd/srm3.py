@@ -54,6 +54,26 @@ class _Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
 
 
+class _KaimalDavenport(ctypes.Structure):
+    _fields_ = [("u_star", ctypes.c_double), ("z", ctypes.c_double), ("U", ctypes.c_double),
+                ("lam", ctypes.c_double)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("b2_scale", ctypes.c_double),
+                ("S_dev", ctypes.c_void_p), ("out_dev", ctypes.c_void_p)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("pair_terms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("pairsum_ms", ctypes.c_double), ("rows_per_wave", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("work_items", ctypes.c_int32),
+                ("groups", ctypes.c_int32)]
+
+
+SRM3_BATCH_GRAPH, SRM3_BATCH_AUTOTUNE = 1, 2
+
+
 _lib = None
 
 
@@ -79,9 +99,20 @@ def load():
     L.srm3_destroy.argtypes = [vp]
     L.srm3_destroy.restype = None
     L.srm3_last_error.restype = ctypes.c_char_p
+    L.srm3_set_spectrum.argtypes = [vp, ctypes.POINTER(_Spectrum), vp]
+    L.srm3_spectrum_kaimal_davenport.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_KaimalDavenport),
+                                                 vp, vp]
+    L.srm3_batch_create.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, ctypes.c_int32, vp,
+                                    ctypes.POINTER(vp)]
+    L.srm3_batch_run.argtypes = [vp, _u64p, vp]
+    L.srm3_batch_info.argtypes = [vp, ctypes.POINTER(_BatchStats)]
+    L.srm3_batch_destroy.argtypes = [vp]
+    L.srm3_batch_destroy.restype = None
+    L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
     for f in ("srm3_plan", "srm3_generate", "srm3_coefficients", "srm3_transform",
               "srm3_workspace_bytes", "srm3_pair_terms", "srm3_profile_enable",
-              "srm3_profile_read"):
+              "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
+              "srm3_batch_create", "srm3_batch_run", "srm3_batch_info", "srm3_generate_uneven"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -287,3 +318,98 @@ def plan_from_workload(wl, precision="fp64", beta_mode="seeded", stream=None, de
         bis["g2"] = wl.g2()
     bis.update(overrides)
     return srm3_plan(wl.grid_dict(), wl.spectrum(), bis, precision, stream)
+
+
+def srm3_set_spectrum(plan: Plan, S: np.ndarray, stream=None):
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    if S.shape != plan.coeff_shape:
+        raise ValueError(f"S shape {S.shape} != {plan.coeff_shape}")
+    spec = _Spectrum(S.ctypes.data_as(_dp))
+    _check(load().srm3_set_spectrum(plan.handle, ctypes.byref(spec), _stream_ptr(stream)))
+
+
+def srm3_spectrum_kaimal_davenport(grid: dict, S_out, u_star=1.5, z=50.0, U=30.0, lam=10.0,
+                                   stream=None):
+    """Evaluate the wind-field spectrum on the line grid into the device tensor S_out (float64)."""
+    import torch
+    nk, nc = int(grid["n_kappa"]), 2 * int(grid["n_omega"]) - 1
+    _check_tensor(S_out, torch.float64, nk * nc, "S_out")
+    g = _Grid(nk, int(grid["n_omega"]), float(grid["d_kappa"]), float(grid["d_omega"]),
+              int(grid.get("n_x", 1)), int(grid.get("n_t", 1)))
+    p = _KaimalDavenport(u_star, z, U, lam)
+    _check(load().srm3_spectrum_kaimal_davenport(ctypes.byref(g), ctypes.byref(p),
+                                                 ctypes.c_void_p(S_out.data_ptr()), _stream_ptr(stream)))
+    return S_out
+
+
+def _requests(reqs):
+    """reqs: sequence of dicts with plan, seed, out, optional b2_scale, S (device tensor)."""
+    arr = (_Request * len(reqs))()
+    for i, r in enumerate(reqs):
+        plan, out = r["plan"], r["out"]
+        nx, nt = plan.field_shape
+        _check_tensor(out, plan.real_dtype, nx * nt, f"request {i} out")
+        S = r.get("S")
+        if S is not None:
+            import torch
+            _check_tensor(S, torch.float64, plan.coeff_shape[0] * plan.coeff_shape[1], f"request {i} S")
+        arr[i] = _Request(plan.handle, int(r["seed"]), float(r.get("b2_scale", 1.0)),
+                          None if S is None else S.data_ptr(), out.data_ptr())
+    return arr
+
+
+class Batch:
+    """An uneven batch (srm3_batch_t); keeps the request tensors alive."""
+
+    def __init__(self, reqs, flags=0, stream=None):
+        self._reqs = list(reqs)
+        arr = _requests(self._reqs)
+        h = ctypes.c_void_p()
+        _check(load().srm3_batch_create(arr, len(arr), int(flags), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, seeds=None, stream=None):
+        if seeds is None:
+            _check(load().srm3_batch_run(self._h, None, _stream_ptr(stream)))
+        else:
+            s = _seeds(seeds)
+            if s.size != len(self._reqs):
+                raise ValueError("one seed per request")
+            _check(load().srm3_batch_run(self._h, s.ctypes.data_as(_u64p), _stream_ptr(stream)))
+
+    def info(self) -> dict:
+        st = _BatchStats()
+        _check(load().srm3_batch_info(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _BatchStats._fields_}
+
+    def destroy(self):
+        if self._h is not None and _lib is not None:
+            _lib.srm3_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def srm3_batch_create(reqs, flags=0, stream=None) -> Batch:
+    return Batch(reqs, flags, stream)
+
+
+def srm3_batch_run(batch: Batch, seeds=None, stream=None):
+    batch.run(seeds, stream)
+
+
+def srm3_batch_info(batch: Batch) -> dict:
+    return batch.info()
+
+
+def srm3_batch_destroy(batch: Batch):
+    batch.destroy()
+
+
+def srm3_generate_uneven(reqs, stream=None):
+    arr = _requests(reqs)
+    _check(load().srm3_generate_uneven(arr, len(arr), _stream_ptr(stream)))

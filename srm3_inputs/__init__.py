@@ -165,9 +165,16 @@ def small_grid(n_kappa: int, n_omega: int, support_w: Optional[int] = None,
     w = n_omega if support_w is None else support_w
     return Workload(f"grid_{n_kappa}x{n_omega}_w{w}", n_kappa, n_omega,
                     2 * math.pi / (n_kappa * 10.0), 4 * math.pi / n_omega,
-                    2 * n_kappa if n_x is None else n_x,
-                    2 * n_omega if n_t is None else n_t, w, batch, 4 * math.pi,
+                    next_pow2(2 * n_kappa) if n_x is None else n_x,
+                    next_pow2(2 * n_omega) if n_t is None else n_t, w, batch, 4 * math.pi,
                     seed_base=seed_base, **kw)
+
+
+def next_pow2(n: int) -> int:
+    p = 1
+    while p < n:
+        p *= 2
+    return p
 
 
 # --------------------------------------------------------------------------
