@@ -229,6 +229,46 @@ void srm3_batch_destroy(srm3_batch_t batch);   /* NULL is a no-op */
 /* One-shot uneven generation: create, run, synchronise, destroy. */
 srm3_status srm3_generate_uneven(const srm3_request *reqs, int32_t n, void *hip_stream);
 
+/* ---- request server: continuous (iteration-level) batching ----
+ * Requests wait in FIFO order until a slot is free and their workspace fits
+ * in the server's device arena (admission by HBM footprint; head-of-line
+ * requests are never skipped).  Each srm3_server_step() retires finished
+ * requests, admits what fits, and enqueues one step of work: pair-sum work
+ * items taken round-robin from every active request (enough to fill the GPU
+ * twice and at least step_pair_terms pair terms) in one persistent launch,
+ * then the transforms of the requests whose work has all been issued.  A
+ * request admitted between steps joins the next step, sharing the GPU with
+ * the requests already running.  A request's result does not depend on what
+ * it was batched with. */
+typedef struct srm3_server_s *srm3_server_t;
+
+typedef struct {
+    int32_t precision;        /* SRM3_FP32 or SRM3_FP64; every request must match */
+    int32_t max_active;       /* resident requests at once (slots), 1..4096 */
+    size_t hbm_budget;        /* bytes of the device arena holding request workspaces (allocated once) */
+    double step_pair_terms;   /* minimum pair terms per step; <= 0: 2e11 */
+} srm3_server_config;
+
+typedef struct {
+    int32_t queued, active, finishing, completed;  /* requests in each state after the call */
+    int32_t launched;                              /* 1 if this call enqueued a step */
+    int64_t steps;                                 /* steps enqueued so far */
+} srm3_server_state;
+
+srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, srm3_server_t *out);
+/* Queue a request.  If `spectrum` is given, the request's spectrum is
+ * evaluated on the device at admission into its own arena space (req->S_dev
+ * must then be NULL).  out_dev must stay valid until the ticket completes.
+ * SRM3_E_NOMEM if the request could never fit the arena. */
+srm3_status srm3_server_submit(srm3_server_t srv, const srm3_request *req,
+                               const srm3_kaimal_davenport *spectrum, int64_t *ticket);
+/* One scheduling iteration (non-blocking: does nothing while two steps are in flight). */
+srm3_status srm3_server_step(srm3_server_t srv, srm3_server_state *state);
+/* Tickets whose fields are complete, oldest first; *n receives the count. */
+srm3_status srm3_server_poll(srm3_server_t srv, int64_t *tickets, int32_t max, int32_t *n);
+/* Wait for all enqueued work and free the server (queued requests are dropped). */
+void srm3_server_destroy(srm3_server_t srv);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *srm3_last_error(void);
 

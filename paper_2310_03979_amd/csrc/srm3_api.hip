@@ -21,7 +21,7 @@
 
 using namespace srm3;
 
-namespace {
+namespace srm3 {
 
 thread_local char g_err[512] = "";
 
@@ -34,66 +34,26 @@ srm3_status fail(srm3_status s, const char *fmt, ...)
     return s;
 }
 
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t n = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf() { release(); }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-    hipError_t alloc(size_t bytes)
-    {
-        release();
-        if (bytes == 0) bytes = 256;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e == hipSuccess) n = bytes;
-        else p = nullptr;
-        return e;
-    }
-};
-
 srm3_status dev_err(hipError_t e, const char *what)
 {
     return fail(SRM3_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace
-
-struct srm3_plan_s {
-    Geometry g{};
-    int precision = SRM3_FP64;
-    double dk = 0, dw = 0, cap = 0, max_sig = 0;
-    double pair_terms = 0;
-    int device = 0;
-    DevBuf wtab, S, sig, tw_t, tw_x, ws;
-    int ws_batch = 0;
-    // profiling
-    bool prof = false;
-    struct Rec {
-        int kernel;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;
-    std::vector<hipEvent_t> pool;
-};
-
-namespace {
-
-template <typename T>
-std::vector<unsigned char> to_bytes(const std::vector<double> &v)
+void DevBuf::release()
 {
-    std::vector<unsigned char> out(v.size() * sizeof(T));
-    T *p = reinterpret_cast<T *>(out.data());
-    for (size_t i = 0; i < v.size(); ++i) p[i] = static_cast<T>(v[i]);
-    return out;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+}
+
+hipError_t DevBuf::alloc(size_t bytes)
+{
+    release();
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) n = bytes;
+    else p = nullptr;
+    return e;
 }
 
 srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_t st)
@@ -105,6 +65,46 @@ srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
     return SRM3_OK;
+}
+
+AmpRef plan_amp(srm3_plan_t p)
+{
+    return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
+                  p->dk * p->dw, p->cap};
+}
+
+double max_sigma(double max_sig, double cap, double scale)
+{
+    const double s = scale * max_sig;
+    return (cap > 0 && s > cap) ? cap : s;
+}
+
+int rows_for(int nk, int precision, int R_pref)
+{
+    int r = R_pref > 0 ? R_pref : pairsum_rows_per_wave(nk, precision);
+    const int cap = precision == SRM3_FP64 ? 8 : 16;
+    if (r > cap) r = cap;
+    while (r > 2 && r > nk) r /= 2;
+    return r;
+}
+
+}  // namespace srm3
+
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+namespace {
+
+template <typename T>
+std::vector<unsigned char> to_bytes(const std::vector<double> &v)
+{
+    std::vector<unsigned char> out(v.size() * sizeof(T));
+    T *p = reinterpret_cast<T *>(out.data());
+    for (size_t i = 0; i < v.size(); ++i) p[i] = static_cast<T>(v[i]);
+    return out;
 }
 
 srm3_status upload(DevBuf &buf, const std::vector<double> &v, int precision, hipStream_t st)
@@ -171,12 +171,6 @@ srm3_status check_batch(srm3_plan_t p, const void *seeds, int32_t batch, const v
     return SRM3_OK;
 }
 
-AmpRef plan_amp(srm3_plan_t p)
-{
-    return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
-                  p->dk * p->dw, p->cap};
-}
-
 srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const Workspace &ws, hipStream_t st)
 {
     srm3_status s;
@@ -211,13 +205,6 @@ srm3_status check_spectrum(const double *S, size_t n)
     for (size_t i = 0; i < n; ++i)
         if (!(S[i] >= 0) || !std::isfinite(S[i])) return fail(SRM3_E_INVALID, "S[%zu] must be finite and >= 0", i);
     return SRM3_OK;
-}
-
-// Largest Sigma_k over the lines at a given b^2 scale.
-double max_sigma(double max_sig, double cap, double scale)
-{
-    const double s = scale * max_sig;
-    return (cap > 0 && s > cap) ? cap : s;
 }
 
 }  // namespace
@@ -268,13 +255,11 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
         return fail(SRM3_E_INVALID, "beta table is NULL");
     if (!std::isfinite(bs.cap)) return fail(SRM3_E_INVALID, "cap is not finite");
 
-    std::vector<double> b2(static_cast<size_t>(ncw) * ncw, 0.0);
+    // validate the bicoherence description (the weight table itself is built on the device)
     if (bs.kind == SRM3_BISPEC_SEPARABLE) {
         for (int i = 0; i < ncw; ++i)
             if (!(bs.g2[i] >= 0) || !std::isfinite(bs.g2[i]))
                 return fail(SRM3_E_INVALID, "g2[%d] must be finite and >= 0", i);
-        for (int i = 0; i < ncw; ++i)
-            for (int j = 0; j < ncw; ++j) b2[static_cast<size_t>(i) * ncw + j] = bs.g2[i] * bs.g2[j];
     } else if (bs.kind == SRM3_BISPEC_DENSE) {
         for (int i = 0; i < ncw; ++i)
             for (int j = 0; j < ncw; ++j) {
@@ -283,29 +268,19 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
                     return fail(SRM3_E_INVALID, "b2[%d][%d] must be finite and >= 0", i, j);
                 if (v != bs.b2[static_cast<size_t>(j) * ncw + i])
                     return fail(SRM3_E_INVALID, "b2 is not symmetric at [%d][%d]", i, j);
-                b2[static_cast<size_t>(i) * ncw + j] = v;
             }
     }
-    std::vector<uint32_t> beta(static_cast<size_t>(ncw) * ncw, 0u);
-    if (bs.kind != SRM3_BISPEC_NONE) {
-        if (bs.beta_mode == SRM3_BETA_SEEDED) {
-            for (int i = 0; i < ncw; ++i)
-                for (int j = 0; j < ncw; ++j) {
-                    const int iw = i - (W - 1), jw = j - (W - 1);
-                    const int hi = iw >= jw ? iw : jw, lo = iw >= jw ? jw : iw;
-                    beta[static_cast<size_t>(i) * ncw + j] =
-                        philox_word0(static_cast<uint32_t>(hi), static_cast<uint32_t>(lo), 1u, 0u, bs.beta_seed);
-                }
-        } else if (bs.beta_mode == SRM3_BETA_TABLE) {
-            for (int i = 0; i < ncw; ++i)
-                for (int j = 0; j < ncw; ++j) {
-                    const uint32_t v = bs.beta[static_cast<size_t>(i) * ncw + j];
-                    if (v != bs.beta[static_cast<size_t>(j) * ncw + i])
-                        return fail(SRM3_E_INVALID, "beta table is not symmetric at [%d][%d]", i, j);
-                    beta[static_cast<size_t>(i) * ncw + j] = v;
-                }
-        }
+    if (bs.kind != SRM3_BISPEC_NONE && bs.beta_mode == SRM3_BETA_TABLE) {
+        for (int i = 0; i < ncw; ++i)
+            for (int j = 0; j < i; ++j)
+                if (bs.beta[static_cast<size_t>(i) * ncw + j] != bs.beta[static_cast<size_t>(j) * ncw + i])
+                    return fail(SRM3_E_INVALID, "beta table is not symmetric at [%d][%d]", i, j);
     }
+    auto b2at = [&](int i, int j) -> double {
+        if (bs.kind == SRM3_BISPEC_SEPARABLE) return bs.g2[i] * bs.g2[j];
+        if (bs.kind == SRM3_BISPEC_DENSE) return bs.b2[static_cast<size_t>(i) * ncw + j];
+        return 0.0;
+    };
 
     const double *S = spectrum->S;
     const size_t nlines = static_cast<size_t>(nk) * nc;
@@ -323,7 +298,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
         for (int iw = -(W - 1); iw <= W - 1; ++iw) {
             const int jw = kw - iw;
             if (jw <= -W || jw >= W) continue;
-            acc += b2[static_cast<size_t>(iw + W - 1) * ncw + (jw + W - 1)];
+            acc += b2at(iw + W - 1, jw + W - 1);
             ++nsplit[kw + nw - 1];
         }
         D[kw + nw - 1] = acc;
@@ -336,7 +311,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
             double diag = 0.0;
             int self = 0;
             if ((kk % 2) == 0 && (kw % 2) == 0 && kw / 2 > -W && kw / 2 < W) {
-                diag = b2[static_cast<size_t>(kw / 2 + W - 1) * ncw + (kw / 2 + W - 1)];
+                diag = b2at(kw / 2 + W - 1, kw / 2 + W - 1);
                 self = 1;
             }
             pair_terms += 0.5 * (static_cast<double>(kk + 1) * nsplit[c] + self);
@@ -347,15 +322,6 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (max_sigma(max_sig, bs.cap, 1.0) >= 1.0)
         return fail(SRM3_E_PURE_NEGATIVE, "a line has sum of b^2 = %.6g >= 1: pure spectrum not positive",
                     max_sigma(max_sig, bs.cap, 1.0));
-
-    // complex weight table W = sqrt(b2) e^{i beta}
-    std::vector<double> wt(2 * static_cast<size_t>(ncw) * ncw);
-    for (size_t e = 0; e < static_cast<size_t>(ncw) * ncw; ++e) {
-        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * beta[e] / 4294967296.0L;
-        const double m = std::sqrt(b2[e]);
-        wt[2 * e] = m * static_cast<double>(cosl(ang));
-        wt[2 * e + 1] = m * static_cast<double>(sinl(ang));
-    }
 
     std::unique_ptr<srm3_plan_s> p(new (std::nothrow) srm3_plan_s);
     if (!p) return fail(SRM3_E_NOMEM, "host allocation failed");
@@ -381,7 +347,26 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (e != hipSuccess) return dev_err(e, "hipFuncSetAttribute");
 
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if ((s = upload(p->wtab, wt, precision, st))) return s;
+    {
+        // complex weight table W = sqrt(b2) e^{i beta}, built on the device
+        DevBuf g2d, b2d, betad;
+        if (bs.kind == SRM3_BISPEC_SEPARABLE && (s = upload_bytes(g2d, bs.g2, ncw * sizeof(double), st))) return s;
+        if (bs.kind == SRM3_BISPEC_DENSE &&
+            (s = upload_bytes(b2d, bs.b2, static_cast<size_t>(ncw) * ncw * sizeof(double), st)))
+            return s;
+        if (bs.kind != SRM3_BISPEC_NONE && bs.beta_mode == SRM3_BETA_TABLE &&
+            (s = upload_bytes(betad, bs.beta, static_cast<size_t>(ncw) * ncw * sizeof(uint32_t), st)))
+            return s;
+        const size_t wbytes = static_cast<size_t>(ncw) * ncw * 2 * (precision == SRM3_FP64 ? 8 : 4);
+        e = p->wtab.alloc(wbytes);
+        if (e != hipSuccess) return fail(SRM3_E_NOMEM, "hipMalloc(%zu): %s", wbytes, hipGetErrorString(e));
+        e = launch_wtable(precision, W, bs.kind, static_cast<const double *>(g2d.p),
+                          static_cast<const double *>(b2d.p), bs.beta_mode, static_cast<const uint32_t *>(betad.p),
+                          bs.beta_seed, p->wtab.p, st);
+        if (e != hipSuccess) return dev_err(e, "weight-table kernel");
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
+    }
     if ((s = upload_bytes(p->S, S, nlines * sizeof(double), st))) return s;
     if ((s = upload_bytes(p->sig, sig.data(), nlines * sizeof(double), st))) return s;
     if ((s = upload(p->tw_t, twiddles(nt), precision, st))) return s;
@@ -556,18 +541,9 @@ struct srm3_batch_s {
 
 namespace {
 
-int rows_for(int nk, int precision, int R_pref)
-{
-    int r = R_pref > 0 ? R_pref : pairsum_rows_per_wave(nk, precision);
-    const int cap = precision == SRM3_FP64 ? 8 : 16;
-    if (r > cap) r = cap;
-    while (r > 2 && r > nk) r /= 2;
-    return r;
-}
-
 // Relative cost of one work item: kappa steps times the widest partner range
 // of its column tiles.
-double item_cost(const Geometry &g, int R, int kb, int cg)
+double item_cost_impl(const Geometry &g, int R, int kb, int cg)
 {
     const int wpb = waves_per_block();
     const int nct = (g.nc + 63) / 64;
@@ -631,7 +607,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
                                 static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
             for (int kb = nrb - 1; kb >= 0; --kb)
                 for (int cg = 0; cg < ncg; ++cg) {
-                    const double c = item_cost(gr.g, gr.g.R, kb, cg);
+                    const double c = item_cost_impl(gr.g, gr.g.R, kb, cg);
                     per_req[d].push_back({d, kb, cg, c});
                     req_cost[d] += c;
                 }
@@ -773,6 +749,10 @@ void tune_store(const std::string &sig, int R, int bpc)
 
 }  // namespace
 
+namespace srm3 {
+double item_cost(const Geometry &g, int R, int kb, int cg) { return item_cost_impl(g, R, kb, cg); }
+}  // namespace srm3
+
 extern "C" {
 
 srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags, void *hip_stream,
@@ -856,14 +836,17 @@ static srm3_status batch_autotune(srm3_batch_t b, hipStream_t st)
         b->blocks_per_cu = bpc;
         return R == b->R ? SRM3_OK : batch_layout(b, R, st);
     }
+    // Sample every 8th request in cost order (all of them for small batches):
+    // about an eighth of the work, with the same mix of grid sizes, so that
+    // the number of work items per workgroup slot stays close to the batch's.
     std::vector<int> order(b->n);
     for (int i = 0; i < b->n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->req[x].plan->pair_terms > b->req[y].plan->pair_terms; });
-    const int want = 16;
-    const int stride = std::max(1, b->n / want);
+    const int stride = b->n >= 64 ? 8 : 1;
     std::vector<srm3_request> sub;
-    for (int i = 0; i < b->n; i += stride) sub.push_back(b->req[order[i]]);
+    for (int i = stride / 2; i < b->n; i += stride) sub.push_back(b->req[order[i]]);
+    if (sub.empty()) sub.push_back(b->req[order[0]]);
     srm3_batch_t t = nullptr;
     srm3_status s = srm3_batch_create(sub.data(), static_cast<int32_t>(sub.size()), 0, st, &t);
     if (s) return s;
@@ -876,7 +859,8 @@ static srm3_status batch_autotune(srm3_batch_t b, hipStream_t st)
         for (int c : {1, 2, 4}) {
             t->blocks_per_cu = c;
             float ms = 0.f;
-            for (int rep = 0; rep < 2 && !s; ++rep) {   // second repetition is the one timed
+            const int reps = (r == Rmax && c == 1) ? 2 : 1;   // the first launch also warms up
+            for (int rep = 0; rep < reps && !s; ++rep) {
                 if ((s = batch_copy_seeds(t, nullptr, st))) break;
                 if ((s = batch_launch(t, st, true))) break;
                 hipError_t e = hipStreamSynchronize(st);

@@ -101,10 +101,56 @@ hipError_t launch_assemble(const Geometry &g, int precision, const AmpRef &amp, 
                            const Workspace &ws, void *cout, hipStream_t st);
 hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int batch, const Workspace &ws,
                        void *out, void *const *out_b, hipStream_t st);
+hipError_t launch_wtable(int precision, int W, int b2_kind, const double *g2, const double *b2, int beta_mode,
+                        const uint32_t *beta_tab, uint64_t beta_seed, void *wt, hipStream_t st);
 hipError_t launch_spectrum(int nk, int nw, double dk, double dw, double u_star, double z, double U, double lam,
                            double *S, hipStream_t st);
 
 int pairsum_rows_per_wave(int nk, int precision);
 hipError_t prepare_transforms(int precision);
 
+// ---- host-side shared pieces (defined in srm3_api.hip) ----
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release();
+    hipError_t alloc(size_t bytes);
+};
+
+srm3_status fail(srm3_status s, const char *fmt, ...);
+srm3_status dev_err(hipError_t e, const char *what);
+srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_t st);
+// Largest Sigma_k over the lines at a given b^2 scale.
+double max_sigma(double max_sig, double cap, double scale);
+// Rows per wave for a grid with nk wavenumber lines (R_pref <= 0: default).
+int rows_for(int nk, int precision, int R_pref);
+// Relative cost of pair-sum work item (row block kb, column group cg).
+double item_cost(const Geometry &g, int R, int kb, int cg);
+
+}  // namespace srm3
+
+struct srm3_plan_s {
+    srm3::Geometry g{};
+    int precision = SRM3_FP64;
+    double dk = 0, dw = 0, cap = 0, max_sig = 0;
+    double pair_terms = 0;
+    int device = 0;
+    srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
+    int ws_batch = 0;
+    // profiling
+    bool prof = false;
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace srm3 {
+AmpRef plan_amp(srm3_plan_t p);
 }  // namespace srm3

@@ -653,6 +653,42 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
     }
 }
 
+// Pair weight table W[i][j] = sqrt(b2_raw(i, j)) exp(i beta(i, j)) over the
+// support |i_w|, |j_w| < W (index i_w + W - 1), computed in FP64 and stored in
+// the path precision.  b2_raw = g2[i] g2[j] (separable) or b2[i][j] (dense);
+// beta from Philox (counter (max, min, 1, 0), key beta_seed), a table, or 0.
+template <typename T>
+__global__ __launch_bounds__(256) void wtable_kernel(int W, int b2_kind, const double *__restrict__ g2,
+                                                     const double *__restrict__ b2, int beta_mode,
+                                                     const uint32_t *__restrict__ beta_tab, uint64_t beta_seed,
+                                                     typename vec<T>::v2 *__restrict__ wt)
+{
+    const int ncw = 2 * W - 1;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= static_cast<long>(ncw) * ncw) return;
+    const int i = static_cast<int>(idx / ncw), j = static_cast<int>(idx - static_cast<long>(i) * ncw);
+    double v = 0.0;
+    if (b2_kind == SRM3_BISPEC_SEPARABLE) v = g2[i] * g2[j];
+    else if (b2_kind == SRM3_BISPEC_DENSE) v = b2[idx];
+    uint32_t beta = 0u;
+    if (b2_kind != SRM3_BISPEC_NONE) {
+        if (beta_mode == SRM3_BETA_SEEDED) {
+            const int iw = i - (W - 1), jw = j - (W - 1);
+            const int hi = iw >= jw ? iw : jw, lo = iw >= jw ? jw : iw;
+            beta = philox_word0(static_cast<uint32_t>(hi), static_cast<uint32_t>(lo), 1u, 0u, beta_seed);
+        } else if (beta_mode == SRM3_BETA_TABLE) {
+            beta = beta_tab[idx];
+        }
+    }
+    double sn, cs;
+    sincospi(static_cast<double>(beta) * (1.0 / 2147483648.0), &sn, &cs);
+    const double m = sqrt(v);
+    typename vec<T>::v2 o;
+    o.x = static_cast<T>(m * cs);
+    o.y = static_cast<T>(m * sn);
+    wt[idx] = o;
+}
+
 // Spectrum on the lines from the Kaimal frequency spectrum times the exact
 // Fourier transform of the Davenport coherence (the wind-field example of
 // Section 5, in the workload normalisation), FP64; S(., 0) = 0.
@@ -949,6 +985,20 @@ static hipError_t prepare_t()
 hipError_t prepare_transforms(int precision)
 {
     return precision == SRM3_FP64 ? prepare_t<double>() : prepare_t<float>();
+}
+
+hipError_t launch_wtable(int precision, int W, int b2_kind, const double *g2, const double *b2, int beta_mode,
+                        const uint32_t *beta_tab, uint64_t beta_seed, void *wt, hipStream_t st)
+{
+    const long n = static_cast<long>(2 * W - 1) * (2 * W - 1);
+    const dim3 grid(static_cast<unsigned>((n + 255) / 256));
+    if (precision == SRM3_FP64)
+        wtable_kernel<double><<<grid, 256, 0, st>>>(W, b2_kind, g2, b2, beta_mode, beta_tab, beta_seed,
+                                                    static_cast<double2 *>(wt));
+    else
+        wtable_kernel<float><<<grid, 256, 0, st>>>(W, b2_kind, g2, b2, beta_mode, beta_tab, beta_seed,
+                                                   static_cast<float2 *>(wt));
+    return hipGetLastError();
 }
 
 hipError_t launch_spectrum(int nk, int nw, double dk, double dw, double u_star, double z, double U, double lam,

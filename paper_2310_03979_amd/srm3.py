@@ -413,3 +413,83 @@ def srm3_batch_destroy(batch: Batch):
 def srm3_generate_uneven(reqs, stream=None):
     arr = _requests(reqs)
     _check(load().srm3_generate_uneven(arr, len(arr), _stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------------------
+# request server
+# ---------------------------------------------------------------------------
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_size_t), ("step_pair_terms", ctypes.c_double)]
+
+
+class _ServerState(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("active", ctypes.c_int32), ("finishing", ctypes.c_int32),
+                ("completed", ctypes.c_int32), ("launched", ctypes.c_int32), ("steps", ctypes.c_int64)]
+
+
+def _server_lib():
+    L = load()
+    if not getattr(L, "_srv_ready", False):
+        vp = ctypes.c_void_p
+        L.srm3_server_create.argtypes = [ctypes.POINTER(_ServerConfig), vp, ctypes.POINTER(vp)]
+        L.srm3_server_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(_KaimalDavenport),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        L.srm3_server_step.argtypes = [vp, ctypes.POINTER(_ServerState)]
+        L.srm3_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]
+        L.srm3_server_destroy.argtypes = [vp]
+        L.srm3_server_destroy.restype = None
+        for f in ("srm3_server_create", "srm3_server_submit", "srm3_server_step", "srm3_server_poll"):
+            getattr(L, f).restype = ctypes.c_int
+        L._srv_ready = True
+    return L
+
+
+class Server:
+    """srm3_server_t: continuous batching of generation requests."""
+
+    def __init__(self, precision="fp32", max_active=64, hbm_budget=32 << 30, step_pair_terms=0.0,
+                 stream=None):
+        L = _server_lib()
+        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms))
+        h = ctypes.c_void_p()
+        _check(L.srm3_server_create(ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._buf = (ctypes.c_int64 * 1024)()
+
+    def submit(self, plan: Plan, seed: int, out, b2_scale: float = 1.0, S=None, spectrum=None) -> int:
+        arr = _requests([dict(plan=plan, seed=seed, out=out, b2_scale=b2_scale, S=S)])
+        sp = None
+        if spectrum is not None:
+            sp = ctypes.byref(_KaimalDavenport(float(spectrum.get("u_star", 1.5)), float(spectrum.get("z", 50.0)),
+                                               float(spectrum["U"]), float(spectrum.get("lam", 10.0))))
+        t = ctypes.c_int64()
+        _check(_server_lib().srm3_server_submit(self._h, arr, sp, ctypes.byref(t)))
+        self._keep[t.value] = (out, S)
+        return t.value
+
+    def step(self) -> dict:
+        st = _ServerState()
+        _check(_server_lib().srm3_server_step(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerState._fields_}
+
+    def poll(self):
+        n = ctypes.c_int32()
+        _check(_server_lib().srm3_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(n)))
+        done = [int(self._buf[i]) for i in range(n.value)]
+        for t in done:
+            self._keep.pop(t, None)
+        return done
+
+    def destroy(self):
+        if self._h is not None and _lib is not None:
+            _lib.srm3_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

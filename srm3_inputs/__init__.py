@@ -170,6 +170,25 @@ def small_grid(n_kappa: int, n_omega: int, support_w: Optional[int] = None,
                     seed_base=seed_base, **kw)
 
 
+def uneven_requests(n: int = 256, seed: int = 3, log2_kappa=(6, 9), log2_omega=(7, 12),
+                    scale=(0.05, 0.3), seed_base: int = 3000):
+    """The uneven-batch workload: n realizations whose line grids are drawn
+    log-uniformly (log2 N_kappa and log2 N_omega uniform integers, so every grid
+    has power-of-two sides) from 64x128 to 512x4096 lines, each with its own
+    bicoherence amplitude scale c ~ U[0.05, 0.3] (b^2_raw = c exp(...)).  Grids
+    follow the 32x64 recipe (dk = 2 pi / (N_kappa 10 m), omega_u = 4 pi, field
+    2N_kappa x 2N_omega).  Returns [(Workload with unit scale, c, seed)]."""
+    rng = np.random.default_rng(seed)
+    lk = rng.integers(log2_kappa[0], log2_kappa[1] + 1, n)
+    lw = rng.integers(log2_omega[0], log2_omega[1] + 1, n)
+    cs = rng.uniform(scale[0], scale[1], n)
+    out = []
+    for i in range(n):
+        wl = small_grid(1 << int(lk[i]), 1 << int(lw[i]), b2_scale=1.0)
+        out.append((wl, float(cs[i]), seed_base + i))
+    return out
+
+
 def next_pow2(n: int) -> int:
     p = 1
     while p < n:

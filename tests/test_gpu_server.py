@@ -1,0 +1,151 @@
+"""Request server (continuous batching) through the C-ABI: every result is the
+same alone and in the mix, admission respects the HBM budget without
+starvation, requests that arrive while others run join the next step, and
+served fields match the FP64 oracle."""
+import numpy as np
+import pytest
+
+import srm3_inputs as inp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2310_03979_amd as p
+    p.load()
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return p
+
+
+def _t():
+    import torch
+    return torch
+
+
+GRIDS = [(16, 64, 64), (32, 128, 96), (64, 48, 48)]
+
+
+def _setup(lib, n, precision="fp32", seed=0):
+    torch = _t()
+    rng = np.random.default_rng(seed)
+    plans = []
+    for nk, nw, W in GRIDS:
+        wl = inp.small_grid(nk, nw, support_w=W, b2_scale=1.0)
+        plans.append((wl, lib.plan_from_workload(wl, precision)))
+    reqs = []
+    for i in range(n):
+        wl, plan = plans[int(rng.integers(0, len(plans)))]
+        reqs.append(dict(wl=wl, plan=plan, seed=int(7000 + i), b2_scale=float(rng.uniform(0.05, 0.3)),
+                         spectrum=dict(U=float(rng.uniform(20, 45))),
+                         out=torch.empty(plan.field_shape, dtype=plan.real_dtype, device="cuda")))
+    return plans, reqs
+
+
+def _drain(srv, max_steps=100000):
+    done = []
+    for _ in range(max_steps):
+        st = srv.step()
+        done += srv.poll()
+        if st["queued"] == 0 and st["active"] == 0 and st["finishing"] == 0:
+            break
+    done += srv.poll()
+    return done
+
+
+def _alone(lib, r):
+    """The same request served by a fresh server with one slot."""
+    torch = _t()
+    out = torch.empty_like(r["out"])
+    srv = lib.srm3.Server(r["plan"].precision, max_active=1, hbm_budget=1 << 30)
+    srv.submit(r["plan"], r["seed"], out, r["b2_scale"], spectrum=r["spectrum"])
+    _drain(srv)
+    torch.cuda.synchronize()
+    srv.destroy()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_results_same_alone_and_in_the_mix(lib, precision):
+    torch = _t()
+    plans, reqs = _setup(lib, 10, precision)
+    srv = lib.srm3.Server(precision, max_active=4, hbm_budget=2 << 30)
+    tickets = [srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"]) for r in reqs]
+    done = _drain(srv)
+    torch.cuda.synchronize()
+    assert sorted(done) == sorted(tickets)
+    for r in reqs:
+        assert torch.equal(r["out"], _alone(lib, r))
+
+
+def test_served_fields_match_oracle(lib, oracle_mod):
+    torch = _t()
+    plans, reqs = _setup(lib, 4, "fp64", seed=3)
+    srv = lib.srm3.Server("fp64", max_active=3, hbm_budget=2 << 30)
+    for r in reqs:
+        srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"])
+    _drain(srv)
+    torch.cuda.synchronize()
+    for r in reqs:
+        wl = r["wl"]
+        S = inp.kaimal_davenport_lines(wl.n_kappa, wl.n_omega, wl.d_kappa, wl.d_omega, U=r["spectrum"]["U"])
+        P = oracle_mod.Problem(wl.n_kappa, wl.n_omega, wl.support_w, wl.d_kappa, wl.d_omega, S,
+                               r["b2_scale"] * wl.b2_dense(), oracle_mod.biphase(wl.support_w, wl.beta_seed),
+                               wl.cap)
+        ref = oracle_mod.field(P.coefficients(seed=r["seed"]), wl.n_x, wl.n_t)
+        got = r["out"].cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-10
+
+
+def test_admission_by_hbm_budget_without_starvation(lib):
+    torch = _t()
+    plans, reqs = _setup(lib, 8, seed=5)
+    big = max(reqs, key=lambda r: r["wl"].n_lines)
+    ws = lib.srm3_workspace_bytes(big["plan"], 1) + big["wl"].n_lines * 8 + 4096
+    srv = lib.srm3.Server("fp32", max_active=8, hbm_budget=int(1.5 * ws))
+    tickets = [srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"]) for r in reqs]
+    blocked = 0
+    done = []
+    for _ in range(100000):
+        st = srv.step()
+        if st["queued"] > 0 and st["active"] + st["finishing"] > 0:
+            blocked += 1             # requests wait for arena space, slots are free
+        done += srv.poll()
+        if len(done) == len(reqs):
+            break
+    torch.cuda.synchronize()
+    assert sorted(done) == sorted(tickets)
+    assert blocked > 0
+    for r in reqs:
+        assert torch.equal(r["out"], _alone(lib, r))
+    # a request that can never fit is refused at submission
+    tiny = lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 16)
+    with pytest.raises(lib.Srm3Error) as ei:
+        tiny.submit(big["plan"], 1, big["out"], 0.1, spectrum=big["spectrum"])
+    assert ei.value.status == 3
+
+
+def test_requests_join_while_others_run(lib):
+    torch = _t()
+    plans, reqs = _setup(lib, 6, seed=9)
+    srv = lib.srm3.Server("fp32", max_active=8, hbm_budget=2 << 30, step_pair_terms=1e6)
+    first = [srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"]) for r in reqs[:3]]
+    srv.step()
+    st = srv.step()
+    late = [srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"]) for r in reqs[3:]]
+    overlap = 0
+    done = []
+    for _ in range(100000):
+        st = srv.step()
+        if st["launched"] and st["active"] + st["finishing"] >= 2:
+            overlap += 1
+        done += srv.poll()
+        if len(done) == len(reqs):
+            break
+    torch.cuda.synchronize()
+    assert sorted(done) == sorted(first + late)
+    assert overlap > 0
+    for r in reqs:
+        assert torch.equal(r["out"], _alone(lib, r))
