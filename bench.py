@@ -45,7 +45,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3"])
+    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3", "c4"])
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests per arrival rate in the serving workload (c4)")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -208,11 +210,82 @@ def bench_uneven(args, torch, srm3):
     print(json.dumps(rec))
 
 
+def bench_serve(args, torch, srm3):
+    """Serving: requests (grid uniform over 64x256 / 256x1024 / 512x4096 /
+    1024x8192 lines, U ~ U[20, 45] m/s, spectrum evaluated on the device)
+    arrive as a Poisson process at 0.3 / 0.6 / 0.9 x the measured saturated
+    request throughput; continuous batching vs one request at a time."""
+    from paper_2310_03979_amd import serve
+    grids = [(64, 256), (256, 1024), (512, 4096), (1024, 8192)]
+    n = args.serve_requests
+    rng = np.random.default_rng(42)
+    plans = {}
+    for g in grids:
+        wl = inp.small_grid(*g, b2_scale=0.3)
+        plans[g] = (wl, srm3.plan_from_workload(wl, "fp32"))
+    reqs = []
+    for i in range(n):
+        g = grids[int(rng.integers(0, len(grids)))]
+        wl, plan = plans[g]
+        reqs.append(dict(plan=plan, seed=4000 + i, b2_scale=1.0,
+                         spectrum=dict(U=float(rng.uniform(20.0, 45.0))),
+                         out=torch.empty(plan.field_shape, dtype=torch.float32, device="cuda"),
+                         points=wl.grid_points, grid=g))
+    points = sum(r["points"] for r in reqs)
+    mix = {f"{g[0]}x{g[1]}": sum(1 for r in reqs if r["grid"] == g) for g in grids}
+    log(f"[bench] serving: {n} requests per rate, mix {mix}")
+    budget = 48 << 30
+    srv = srm3.Server("fp32", max_active=32, hbm_budget=budget)
+    prog = lambda m: log("[bench]   " + m)                 # noqa: E731
+    serve.replay(srv, reqs[:2], [0.0, 0.0])           # warm-up (first launches)
+    sat = serve.replay(srv, reqs, [0.0] * n, progress=prog)
+    thr = n / sat["makespan"]
+    log(f"[bench] saturated: {sat['makespan']:.2f} s for {n} requests ({thr:.3f} req/s)")
+    out = {"saturated": dict(makespan_s=sat["makespan"], requests_per_s=thr,
+                             grid_points_per_s=points / sat["makespan"])}
+    for f in (0.3, 0.6, 0.9):
+        arr = serve.poisson_arrivals(n, f * thr, seed=42)
+        r = serve.replay(srv, reqs, arr, progress=prog)
+        out[f"rate_{f}"] = dict(rate_req_per_s=f * thr, p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"],
+                                makespan_s=r["makespan"], grid_points_per_s=points / r["makespan"])
+        log(f"[bench] rate {f}: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
+    srv.destroy()
+    rr = srm3.Server("fp32", max_active=32, hbm_budget=budget, policy="round_robin")
+    arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
+    r = serve.replay(rr, reqs, arr, progress=prog)
+    rr.destroy()
+    out["round_robin_rate_0.9"] = dict(p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"], makespan_s=r["makespan"])
+    log(f"[bench] round-robin steps, rate 0.9: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
+    plain = srm3.Server("fp32", max_active=1, hbm_budget=budget, step_pair_terms=1e30)
+    psat = serve.replay(plain, reqs, [0.0] * n, progress=prog)
+    log(f"[bench] one at a time, saturated: {psat['makespan']:.2f} s")
+    arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
+    p9 = serve.replay(plain, reqs, arr, progress=prog)
+    plain.destroy()
+    out["plain_one_at_a_time"] = {
+        "saturated_makespan_s": psat["makespan"], "saturated_grid_points_per_s": points / psat["makespan"],
+        "rate_0.9_p50_s": p9["p50"], "rate_0.9_p99_s": p9["p99"]}
+    log(f"[bench] one at a time: saturated {psat['makespan']:.2f} s; rate 0.9 p50 {p9['p50']:.3f} "
+        f"p99 {p9['p99']:.3f} s")
+    rec = {
+        "metric": "space-time grid points/sec, batched FP32 vs plain; p50/p99 request latency",
+        "value": points / sat["makespan"], "unit": "grid points/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(sat["makespan"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: {n} requests per rate, grids 64x256/256x1024/512x4096/1024x8192 "
+                               f"lines (mix {mix}), U ~ U[20,45], Poisson arrivals (seed 42) at 0.3/0.6/0.9 x "
+                               f"saturated throughput, continuous batching (32 slots, 48 GiB arena, "
+                               f"shortest remaining work first)"},
+        "serving": out, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(realizations shard across GPUs with no communication; see the design notes)",
+              "(realizations are independent and would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -226,6 +299,9 @@ def main():
 
     if args.workload == "c3":
         bench_uneven(args, torch, srm3)
+        return
+    if args.workload == "c4":
+        bench_serve(args, torch, srm3)
         return
     wl = inp.WORKLOADS[args.workload]
     B = args.batch or wl.batch

@@ -234,19 +234,26 @@ srm3_status srm3_generate_uneven(const srm3_request *reqs, int32_t n, void *hip_
  * in the server's device arena (admission by HBM footprint; head-of-line
  * requests are never skipped).  Each srm3_server_step() retires finished
  * requests, admits what fits, and enqueues one step of work: pair-sum work
- * items taken round-robin from every active request (enough to fill the GPU
- * twice and at least step_pair_terms pair terms) in one persistent launch,
+ * items of the resident requests (shortest remaining work first, or
+ * round-robin; enough to fill the GPU twice and at least step_pair_terms pair
+ * terms) in one persistent launch,
  * then the transforms of the requests whose work has all been issued.  A
  * request admitted between steps joins the next step, sharing the GPU with
  * the requests already running.  A request's result does not depend on what
  * it was batched with. */
 typedef struct srm3_server_s *srm3_server_t;
 
+enum {
+    SRM3_SERVE_SHORTEST_FIRST = 0,  /* each step serves the requests with the least work left first */
+    SRM3_SERVE_ROUND_ROBIN = 1      /* each step takes one item from every request in turn */
+};
+
 typedef struct {
     int32_t precision;        /* SRM3_FP32 or SRM3_FP64; every request must match */
     int32_t max_active;       /* resident requests at once (slots), 1..4096 */
     size_t hbm_budget;        /* bytes of the device arena holding request workspaces (allocated once) */
     double step_pair_terms;   /* minimum pair terms per step; <= 0: 2e11 */
+    int32_t policy;           /* SRM3_SERVE_SHORTEST_FIRST or SRM3_SERVE_ROUND_ROBIN */
 } srm3_server_config;
 
 typedef struct {

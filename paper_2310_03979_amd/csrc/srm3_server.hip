@@ -9,8 +9,10 @@
 // request whose items have all been issued gets its transforms and a
 // completion event; its slot and arena space are released when that event
 // has completed.  Per-step tables travel in one host-to-device copy from a
-// pinned staging buffer (two buffers, so the host can build step i+1 while
-// step i's copy is pending).
+// pinned staging buffer.  Consecutive steps alternate between two streams,
+// each with its own staging buffers, so that a step's items start on compute
+// units the previous step's longest items leave idle; events order a
+// request's phases before its items and all its items before its transforms.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -50,6 +52,7 @@ struct SReq {
     bool fresh = false;             // admitted, phases not yet launched
     std::vector<Item> items;        // heaviest first
     size_t cursor = 0;
+    double left = 0.0;              // cost of the items not yet issued
     hipEvent_t done = nullptr;
 };
 
@@ -101,7 +104,10 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 struct srm3_server_s {
     srm3_server_config cfg{};
-    hipStream_t st = nullptr;
+    hipStream_t st = nullptr;           // caller's stream (ordering at creation and destruction)
+    hipStream_t lane[2] = {nullptr, nullptr};
+    hipEvent_t ev_phases[2] = {nullptr, nullptr}, ev_pairsum[2] = {nullptr, nullptr};
+    bool recorded[2] = {false, false};
     int R = 16;
     int n_cu = 256;
     int blocks_per_cu = 2;
@@ -110,7 +116,7 @@ struct srm3_server_s {
     // staging: headers | qbegin | preq | items
     size_t off_hdr = 0, off_q = 0, off_req = 0, off_items = 0, stage_bytes = 0;
     int max_items = 0;
-    DevBuf dev_stage, qnext;
+    DevBuf dev_stage[2], qnext[2];
     unsigned char *pinned[2] = {nullptr, nullptr};
     hipEvent_t copied[2] = {nullptr, nullptr};
     bool copy_pending[2] = {false, false};
@@ -191,6 +197,8 @@ srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, 
         return fail(SRM3_E_INVALID, "precision %d", cfg->precision);
     if (cfg->max_active < 1 || cfg->max_active > 4096) return fail(SRM3_E_INVALID, "max_active %d", cfg->max_active);
     if (cfg->hbm_budget < (1u << 16)) return fail(SRM3_E_INVALID, "hbm_budget below 64 KiB");
+    if (cfg->policy != SRM3_SERVE_SHORTEST_FIRST && cfg->policy != SRM3_SERVE_ROUND_ROBIN)
+        return fail(SRM3_E_INVALID, "policy %d", cfg->policy);
     std::unique_ptr<srm3_server_s> s(new (std::nothrow) srm3_server_s);
     if (!s) return fail(SRM3_E_NOMEM, "host allocation failed");
     s->cfg = *cfg;
@@ -211,8 +219,18 @@ srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, 
     s->off_req = s->off_q + align256(sizeof(int) * (kXcds + 1));
     s->off_items = s->off_req + align256(persistent_req_bytes() * na);
     s->stage_bytes = s->off_items + align256(persistent_item_bytes() * s->max_items);
-    if ((e = s->dev_stage.alloc(s->stage_bytes)) != hipSuccess || (e = s->qnext.alloc(kXcds * sizeof(int))) != hipSuccess)
-        return fail(SRM3_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    for (int i = 0; i < 2; ++i) {
+        if ((e = s->dev_stage[i].alloc(s->stage_bytes)) != hipSuccess ||
+            (e = s->qnext[i].alloc(kXcds * sizeof(int))) != hipSuccess)
+            return fail(SRM3_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+        if ((e = hipStreamCreateWithFlags(&s->lane[i], hipStreamNonBlocking)) != hipSuccess)
+            return dev_err(e, "hipStreamCreate");
+        if ((e = hipEventCreateWithFlags(&s->ev_phases[i], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&s->ev_pairsum[i], hipEventDisableTiming)) != hipSuccess)
+            return dev_err(e, "hipEventCreate");
+    }
+    // the arena and staging must be ready before work is enqueued on the lanes
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return dev_err(e, "hipDeviceSynchronize");
     for (int i = 0; i < 2; ++i) {
         if ((e = hipHostMalloc(reinterpret_cast<void **>(&s->pinned[i]), s->stage_bytes, hipHostMallocDefault)) !=
             hipSuccess)
@@ -258,6 +276,7 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     for (int kb = nrb - 1; kb >= 0; --kb)
         for (int cg = 0; cg < ncg; ++cg) q->items.push_back({kb, cg, item_cost(q->g, q->g.R, kb, cg)});
     std::stable_sort(q->items.begin(), q->items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+    for (const Item &it : q->items) q->left += it.cost;
     if (static_cast<int>(q->items.size()) > s->max_items) return fail(SRM3_E_UNSUPPORTED, "grid too large");
     q->ticket = s->next_ticket++;
     *ticket = q->ticket;
@@ -306,24 +325,43 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
                                 q->r.plan->wtab.p);
             fresh.push_back(q);
         }
-        // ---- this step's work: round-robin over active requests until the GPU is
-        // filled a few times over and the pair-term budget is met ----
+        // ---- this step's work: enough items to fill the GPU twice and meet the
+        // pair-term budget, taken shortest-remaining-work first (or round-robin) ----
         std::vector<std::vector<Item>> take(s->order.size());
         const double unit = 64.0 * waves_per_block() * s->R;   // pair terms per unit of item cost
         const double budget = s->cfg.step_pair_terms / unit;
         const int min_items = 2 * s->n_cu * s->blocks_per_cu;
         double spent = 0.0;
         int n_items = 0;
-        bool more = true;
-        while (more && (spent < budget || n_items < min_items) && n_items < s->max_items) {
-            more = false;
-            for (size_t i = 0; i < s->order.size() && n_items < s->max_items; ++i) {
+        auto full = [&]() { return (spent >= budget && n_items >= min_items) || n_items >= s->max_items; };
+        if (s->cfg.policy == SRM3_SERVE_SHORTEST_FIRST) {
+            std::vector<size_t> pri(s->order.size());
+            for (size_t i = 0; i < pri.size(); ++i) pri[i] = i;
+            std::stable_sort(pri.begin(), pri.end(),
+                             [&](size_t a, size_t b) { return s->order[a]->left < s->order[b]->left; });
+            for (size_t i : pri) {
                 SReq *q = s->order[i];
-                if (q->cursor >= q->items.size()) continue;
-                take[i].push_back(q->items[q->cursor++]);
-                spent += take[i].back().cost;
-                ++n_items;
-                more = true;
+                while (q->cursor < q->items.size() && !full()) {
+                    take[i].push_back(q->items[q->cursor++]);
+                    spent += take[i].back().cost;
+                    q->left -= take[i].back().cost;
+                    ++n_items;
+                }
+                if (full()) break;
+            }
+        } else {
+            bool more = true;
+            while (more && !full()) {
+                more = false;
+                for (size_t i = 0; i < s->order.size() && !full(); ++i) {
+                    SReq *q = s->order[i];
+                    if (q->cursor >= q->items.size()) continue;
+                    take[i].push_back(q->items[q->cursor++]);
+                    spent += take[i].back().cost;
+                    q->left -= take[i].back().cost;
+                    ++n_items;
+                    more = true;
+                }
             }
         }
         if (fresh.empty() && n_items == 0) goto report;
@@ -350,12 +388,14 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
             }
         while (q_ix <= kXcds) qb[q_ix++] = k;
         const size_t bytes = s->off_items + ib * static_cast<size_t>(std::max(k, 1));
-        hipError_t e = hipMemcpyAsync(s->dev_stage.p, P, bytes, hipMemcpyHostToDevice, s->st);
+        hipStream_t st = s->lane[c];
+        const int o = c ^ 1;
+        hipError_t e = hipMemcpyAsync(s->dev_stage[c].p, P, bytes, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return dev_err(e, "hipMemcpyAsync");
-        if ((e = hipEventRecord(s->copied[c], s->st)) != hipSuccess) return dev_err(e, "hipEventRecord");
+        if ((e = hipEventRecord(s->copied[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");
         s->copy_pending[c] = true;
         const SlotHeader *hdr_dev =
-            reinterpret_cast<const SlotHeader *>(static_cast<char *>(s->dev_stage.p) + s->off_hdr);
+            reinterpret_cast<const SlotHeader *>(static_cast<char *>(s->dev_stage[c].p) + s->off_hdr);
         // ---- spectra and phases of the newly admitted requests ----
         for (SReq *q : fresh) {
             char *base = static_cast<char *>(s->arena_mem.p) + q->off;
@@ -363,21 +403,27 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
             if (q->own_spec) {
                 const srm3_plan_t p = q->r.plan;
                 e = launch_spectrum(q->g.nk, q->g.nw, p->dk, p->dw, q->spec.u_star, q->spec.z, q->spec.U,
-                                    q->spec.lam, const_cast<double *>(s->hdr[q->slot].S), s->st);
+                                    q->spec.lam, const_cast<double *>(s->hdr[q->slot].S), st);
                 if (e != hipSuccess) return dev_err(e, "spectrum kernel");
             }
-            e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, ws, s->st);
+            e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, ws, st);
             if (e != hipSuccess) return dev_err(e, "phase kernel");
             q->fresh = false;
         }
+        if ((e = hipEventRecord(s->ev_phases[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");
+        // items may belong to requests admitted by the previous step on the other lane
+        if (s->recorded[o] && (e = hipStreamWaitEvent(st, s->ev_phases[o], 0)) != hipSuccess)
+            return dev_err(e, "hipStreamWaitEvent");
         // ---- pair sums ----
         if (k > 0) {
-            char *D = static_cast<char *>(s->dev_stage.p);
+            char *D = static_cast<char *>(s->dev_stage[c].p);
             e = launch_pairsum_persistent(s->cfg.precision, s->R, D + s->off_req, D + s->off_items,
-                                          reinterpret_cast<const int *>(D + s->off_q), static_cast<int *>(s->qnext.p),
-                                          s->n_cu * s->blocks_per_cu, s->st);
+                                          reinterpret_cast<const int *>(D + s->off_q),
+                                          static_cast<int *>(s->qnext[c].p), s->n_cu * s->blocks_per_cu, st);
             if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
         }
+        if ((e = hipEventRecord(s->ev_pairsum[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");
+        bool waited = false;
         // ---- transforms of requests whose work has all been issued ----
         for (size_t i = 0; i < s->order.size();) {
             SReq *q = s->order[i];
@@ -385,24 +431,31 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
                 ++i;
                 continue;
             }
+            if (!waited && s->recorded[o]) {
+                // earlier items of these requests may still run in the other lane's step
+                if ((e = hipStreamWaitEvent(st, s->ev_pairsum[o], 0)) != hipSuccess)
+                    return dev_err(e, "hipStreamWaitEvent");
+                waited = true;
+            }
             char *base = static_cast<char *>(s->arena_mem.p) + q->off;
             const Workspace ws = carve_workspace(q->g, s->cfg.precision, 1, base);
             AmpRef amp = plan_amp(q->r.plan);
             amp.scale_b = &hdr_dev[q->slot].scale;
             amp.S_b = &hdr_dev[q->slot].S;
             e = launch_tfft(q->g, s->cfg.precision, 0, nullptr, amp, q->r.plan->wtab.p, q->r.plan->tw_t.p, 1, ws,
-                            s->st);
+                            st);
             if (e != hipSuccess) return dev_err(e, "t-transform kernel");
             e = launch_xfft(q->g, s->cfg.precision, q->r.plan->tw_x.p, 1, ws, nullptr,
-                            reinterpret_cast<void *const *>(&hdr_dev[q->slot].out), s->st);
+                            reinterpret_cast<void *const *>(&hdr_dev[q->slot].out), st);
             if (e != hipSuccess) return dev_err(e, "x-transform kernel");
             if ((rc = take_event(s, &q->done))) return rc;
-            if ((e = hipEventRecord(q->done, s->st)) != hipSuccess) return dev_err(e, "hipEventRecord");
+            if ((e = hipEventRecord(q->done, st)) != hipSuccess) return dev_err(e, "hipEventRecord");
             s->finishing.push_back(q);
             s->order.erase(s->order.begin() + static_cast<long>(i));
         }
-        if ((e = hipEventRecord(s->step_done[c], s->st)) != hipSuccess) return dev_err(e, "hipEventRecord");
+        if ((e = hipEventRecord(s->step_done[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");
         s->step_pending[c] = true;
+        s->recorded[c] = true;
         s->cur ^= 1;
         ++s->steps;
         launched = true;
@@ -436,7 +489,8 @@ srm3_status srm3_server_poll(srm3_server_t s, int64_t *tickets, int32_t max, int
 void srm3_server_destroy(srm3_server_t s)
 {
     if (!s) return;
-    (void)hipStreamSynchronize(s->st);
+    for (int i = 0; i < 2; ++i)
+        if (s->lane[i]) (void)hipStreamSynchronize(s->lane[i]);
     (void)hipDeviceSynchronize();
     for (SReq *q : s->queue) delete q;
     for (SReq *q : s->order) {
@@ -450,8 +504,9 @@ void srm3_server_destroy(srm3_server_t s)
     for (hipEvent_t ev : s->ev_pool) (void)hipEventDestroy(ev);
     for (int i = 0; i < 2; ++i) {
         if (s->pinned[i]) (void)hipHostFree(s->pinned[i]);
-        if (s->copied[i]) (void)hipEventDestroy(s->copied[i]);
-        if (s->step_done[i]) (void)hipEventDestroy(s->step_done[i]);
+        for (hipEvent_t ev : {s->copied[i], s->step_done[i], s->ev_phases[i], s->ev_pairsum[i]})
+            if (ev) (void)hipEventDestroy(ev);
+        if (s->lane[i]) (void)hipStreamDestroy(s->lane[i]);
     }
     delete s;
 }

@@ -21,16 +21,21 @@ def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
 
 
 def replay(server, requests: Sequence[dict], arrivals: Sequence[float], timeout_s: float = 600.0,
-           sync=None) -> dict:
-    """requests: dicts with plan, seed, out, b2_scale, spectrum (see Server.submit)."""
+           progress=None, progress_every_s: float = 10.0) -> dict:
+    """requests: dicts with plan, seed, out, b2_scale, spectrum (see Server.submit).
+    ``progress(msg)`` is called about every ``progress_every_s`` seconds."""
     n = len(requests)
     order = np.argsort(np.asarray(arrivals), kind="stable")
     tickets = {}
     done_at = {}
     t0 = time.perf_counter()
+    last = 0.0
     nxt = 0
     while len(done_at) < n:
         now = time.perf_counter() - t0
+        if progress is not None and now - last >= progress_every_s:
+            last = now
+            progress(f"t={now:.1f}s submitted {nxt}/{n} completed {len(done_at)}/{n}")
         if now > timeout_s:
             raise TimeoutError(f"serving replay exceeded {timeout_s} s ({len(done_at)}/{n} done)")
         while nxt < n and arrivals[order[nxt]] <= now:

@@ -420,7 +420,11 @@ def srm3_generate_uneven(reqs, stream=None):
 # ---------------------------------------------------------------------------
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_size_t), ("step_pair_terms", ctypes.c_double)]
+                ("hbm_budget", ctypes.c_size_t), ("step_pair_terms", ctypes.c_double),
+                ("policy", ctypes.c_int32)]
+
+
+SRM3_SERVE_SHORTEST_FIRST, SRM3_SERVE_ROUND_ROBIN = 0, 1
 
 
 class _ServerState(ctypes.Structure):
@@ -450,9 +454,10 @@ class Server:
     """srm3_server_t: continuous batching of generation requests."""
 
     def __init__(self, precision="fp32", max_active=64, hbm_budget=32 << 30, step_pair_terms=0.0,
-                 stream=None):
+                 policy="shortest", stream=None):
         L = _server_lib()
-        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms))
+        pol = {"shortest": SRM3_SERVE_SHORTEST_FIRST, "round_robin": SRM3_SERVE_ROUND_ROBIN}[policy]
+        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms), pol)
         h = ctypes.c_void_p()
         _check(L.srm3_server_create(ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
         self._h = h

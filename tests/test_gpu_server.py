@@ -67,11 +67,12 @@ def _alone(lib, r):
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_results_same_alone_and_in_the_mix(lib, precision):
+@pytest.mark.parametrize("precision,policy", [("fp32", "shortest"), ("fp64", "shortest"),
+                                              ("fp32", "round_robin")])
+def test_results_same_alone_and_in_the_mix(lib, precision, policy):
     torch = _t()
     plans, reqs = _setup(lib, 10, precision)
-    srv = lib.srm3.Server(precision, max_active=4, hbm_budget=2 << 30)
+    srv = lib.srm3.Server(precision, max_active=4, hbm_budget=2 << 30, policy=policy)
     tickets = [srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"]) for r in reqs]
     done = _drain(srv)
     torch.cuda.synchronize()
