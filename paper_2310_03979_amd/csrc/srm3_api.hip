@@ -597,12 +597,13 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
         const Workspace ws = carve_workspace(gr.g, b->precision, static_cast<int>(gr.members.size()),
                                              static_cast<char *>(b->ws.p) + gr.ws_off);
         const size_t lines = static_cast<size_t>(gr.g.nk) * gr.g.nc;
-        const size_t plane3 = static_cast<size_t>(3) * gr.g.ncw * gr.g.nkp;
+        const size_t plane3 = a_slots(b->precision) * gr.g.ncw * gr.g.nkp;
         const int nrb = gr.g.nkp / gr.g.R;
         const int ncg = ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
         for (size_t slot = 0; slot < gr.members.size(); ++slot) {
             const int d = gr.first + static_cast<int>(slot);
-            fill_persistent_req(reqs.data() + rb * d, gr.g, static_cast<char *>(ws.zrow) + slot * lines * 2 * e,
+            fill_persistent_req(reqs.data() + rb * d, gr.g,
+                                static_cast<char *>(ws.zrow) + slot * lines * kZrowElemBytes,
                                 static_cast<char *>(ws.zcol) + slot * plane3 * e,
                                 static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
             for (int kb = nrb - 1; kb >= 0; --kb)

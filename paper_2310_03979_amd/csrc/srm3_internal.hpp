@@ -38,8 +38,14 @@ __host__ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint3
 }
 
 template <typename T> struct vec;
-template <> struct vec<float> { using v2 = float2; using v4 = float4; };
-template <> struct vec<double> { using v2 = double2; using v4 = double4; };
+// zb: element of the line-phase array read by the pair sum and the assembly,
+// 16 bytes in both precisions: FP32 (re, im, im - re, re + im), FP64 (re, im).
+template <> struct vec<float> { using v2 = float2; using v4 = float4; using zb = float4; };
+template <> struct vec<double> { using v2 = double2; using v4 = double4; using zb = double2; };
+constexpr size_t kZrowElemBytes = 16;
+// elements of the a operand per (support column, row): 3 planes in FP32,
+// 3 interleaved values padded to 4 in FP64
+inline size_t a_slots(int precision) { return precision == SRM3_FP64 ? 4 : 3; }
 
 constexpr int kMaxSeedsPerLaunch = 32;
 struct SeedChunk {
@@ -58,7 +64,8 @@ struct Geometry {
 // Device workspace of one generate call (views into the plan's buffer).
 struct Workspace {
     void *zrow;   // [B][nk][nc] complex phase factors, row-major over lines
-    void *zcol;   // [B][3][ncw][nkp] planes (re + im, re, im), kappa-contiguous per support column
+    void *zcol;   // a operand (re + im, re, im) per support column, kappa-contiguous:
+                  // FP32 [B][3][ncw][nkp] planes, FP64 [B][ncw][nkp][4] (4th slot unused)
     void *tsum;   // [B][nk][nc] complex pair sums
     void *g;      // [B][nk][nt] complex, after the t-transform
 };

@@ -27,16 +27,54 @@ __device__ __forceinline__ void two_sum(T &s, T &c, T x)
     c += err;
 }
 
+// Line phase element of the pair-sum b operand: (re, im) and the Gauss sums
+// (im - re, re + im), stored in FP32, formed on the fly in FP64.
+__device__ __forceinline__ float4 make_zb(double c, double s)
+{
+    return make_float4(static_cast<float>(c), static_cast<float>(s), static_cast<float>(s - c),
+                       static_cast<float>(c + s));
+}
+__device__ __forceinline__ double2 make_zb_d(double c, double s) { return make_double2(c, s); }
+__device__ __forceinline__ void b_ops(const float4 &v, float &re, float &db, float &sb)
+{
+    re = v.x;
+    db = v.z;
+    sb = v.w;
+}
+__device__ __forceinline__ void b_ops(const double2 &v, double &re, double &db, double &sb)
+{
+    re = v.x;
+    db = v.y - v.x;
+    sb = v.x + v.y;
+}
+__device__ __forceinline__ float2 z_of(const float4 &v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ double2 z_of(const double2 &v) { return v; }
+
+// Layout of the a operand (re + im, re, im) of support column ic, row kk:
+// FP32 keeps three kappa-contiguous planes (a block's rows load as wide scalar
+// loads); FP64 interleaves the three values per row, padded to four, so that
+// rows load one at a time and the scalar register window stays small.
+template <typename T> struct ALayout;
+template <> struct ALayout<float> {
+    static constexpr int ES = 1;       // element stride between rows
+    static constexpr int NS = 3;       // slots per (column, row)
+    __device__ static long plane(const Geometry &g) { return static_cast<long>(g.ncw) * g.nkp; }
+};
+template <> struct ALayout<double> {
+    static constexpr int ES = 4;
+    static constexpr int NS = 4;
+    __device__ static long plane(const Geometry &) { return 1; }
+};
+
 // ---------------------------------------------------------------------------
 // Phases.  One thread per (realization, padded row, column).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
                                                     int b0, Geometry g,
-                                                    typename vec<T>::v2 *__restrict__ zrow,
+                                                    typename vec<T>::zb *__restrict__ zrow,
                                                     T *__restrict__ zcol)
 {
-    using T2 = typename vec<T>::v2;
     const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int bl = blockIdx.y;
     const long per = static_cast<long>(g.nkp) * g.nc;
@@ -45,27 +83,26 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
     const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
     const int kw = c - (g.nw - 1);
     const int b = b0 + bl;
-    T cz = T(0), sz = T(0);
+    double s = 0.0, co = 0.0;
     if (kk < g.nk) {
         const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
         const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
-        double s, co;
         sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
-        cz = static_cast<T>(co);
-        sz = static_cast<T>(s);
-        T2 v;
-        v.x = cz;
-        v.y = sz;
-        zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
+        if constexpr (sizeof(T) == 4)
+            zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = make_zb(co, s);
+        else
+            zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = make_zb_d(co, s);
     }
     const int ic = c - (g.nw - g.W);
     if (ic >= 0 && ic < g.ncw) {
-        // planes (re + im, re, im), each [ncw][nkp]
-        const long plane = static_cast<long>(g.ncw) * g.nkp;
-        T *zc = zcol + static_cast<long>(b) * 3 * plane + static_cast<long>(ic) * g.nkp + kk;
-        zc[0] = cz + sz;
-        zc[plane] = cz;
-        zc[2 * plane] = sz;
+        using L = ALayout<T>;
+        const long plane = L::plane(g);
+        T *zc = zcol + static_cast<long>(b) * L::NS * g.ncw * g.nkp +
+                (static_cast<long>(ic) * g.nkp + kk) * L::ES;
+        zc[0] = static_cast<T>(co + s);
+        zc[plane] = static_cast<T>(co);
+        zc[2 * plane] = static_cast<T>(s);
+        if (L::NS == 4) zc[3] = T(0);
     }
 }
 
@@ -80,14 +117,18 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
 //     T_k = sum_{jk <= kk/2} f(jk) sum_{iw} W(iw, kw - iw) z[kk - jk][iw] z[jk][kw - iw],
 //     f = 1 for 2 jk < kk, 1/2 for 2 jk == kk.
 // A wave owns 64 consecutive output columns (one per lane) and R consecutive
-// rows K0..K0+R-1.  For a fixed partner column iw the a-operand z[kk-jk][iw]
-// is the same for all lanes (held in scalar registers as a sliding window along
-// kappa), the b-operand W(iw, kw-iw) z[jk][kw-iw] is per lane and reused over
-// the R rows.  Complex products use the 3-multiply form with precomputed sums
-// (a.re + a.im stored with z, b.re + b.im and b.im - b.re formed per step):
-//     K1 += (a.re + a.im) b.re,  K2 += a.re (b.im - b.re),  K3 += a.im (b.re + b.im)
-//     re = K1 - K3,  im = K1 + K2.
-// In FP32 the partial sums are flushed every few hundred terms into an
+// rows K0..K0+R-1.  For a fixed partner column iw the weight W(iw, kw - iw)
+// does not depend on kappa, so the inner sum over jk runs on the raw phases,
+//     P_r(iw) = sum_jk f(jk) z[K0 + r - jk][iw] z[jk][kw - iw],
+// and the weight is applied once per partner column, T_r += W P_r.  The
+// a-operand z[kk-jk][iw] is the same for all lanes (scalar registers, a
+// sliding window along kappa), the b-operand z[jk][kw-iw] is per lane and
+// reused over the R rows.  Complex products use the 3-multiply form with
+// precomputed sums (a.re + a.im stored with the a planes, b.im - b.re and
+// b.re + b.im stored with the FP32 b operand, formed per step in FP64):
+//     P1 += (a.re + a.im) b.re,  P2 += a.re (b.im - b.re),  P3 += a.im (b.re + b.im)
+//     re = P1 - P3,  im = P1 + P2.
+// In FP32 the weighted sums are flushed every few hundred terms into an
 // error-free (two-sum) accumulator.
 // ---------------------------------------------------------------------------
 struct PairsumArgs {
@@ -104,6 +145,41 @@ struct PairsumArgs {
     int per_xcd;      // > 0: XCD-blocked order (see pairsum_kernel), 0: interleaved
 };
 
+// Read-only data that does not change while a kernel runs, in the constant
+// address space: uniform loads through such a pointer become scalar loads even
+// where the kernel stores elsewhere earlier (the persistent loop).
+// (The host pass of the compiler only parses kernel bodies; it sees plain
+// pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T>
+using cptr = const T *;
+#endif
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
+{
+    return (cptr<T>)p;
+}
+
+// Device memory in the global address space: loads through such a pointer are
+// global (not flat) loads also where the pointer itself was read from memory.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+#else
+template <typename T>
+using gptr = const T *;
+#endif
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p)
+{
+    return (gptr<T>)p;
+}
+
 constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kFlushTerms = 256;
 
@@ -117,14 +193,12 @@ constexpr int kWavesPerBlock = 4;
 // rows K0 - J - R + r there for the next block.  bA/bB carry b-rows J, J + 1
 // in and J + NS, J + NS + 1 out (prefetched two steps ahead).
 template <typename T, int R, int NS, int NFULL>
-__device__ __forceinline__ void pair_block(T (&K1)[R], T (&K2)[R], T (&K3)[R], T (&cs)[R], T (&cr)[R],
-                                           T (&ci)[R], typename vec<T>::v2 &bA, typename vec<T>::v2 &bB,
-                                           const typename vec<T>::v2 w,
-                                           const typename vec<T>::v2 *__restrict__ bcol, long nc, int J,
-                                           int jk_last, const T *__restrict__ as_,
-                                           const T *__restrict__ ar_, const T *__restrict__ ai_, int K0)
+__device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T (&cs)[R], T (&cr)[R],
+                                           T (&ci)[R], typename vec<T>::zb &bA, typename vec<T>::zb &bB,
+                                           gptr<typename vec<T>::zb> bcol, long nc, int J,
+                                           int jk_last, cptr<T> as_, cptr<T> ar_, cptr<T> ai_, int K0)
 {
-    using T2 = typename vec<T>::v2;
+    using TB = typename vec<T>::zb;
     constexpr bool BULK = (NS == R && NFULL == R);
     // v[m] = a-values of row K0 - J - R + m, m in [0, 2R)
     T vs[2 * R], vr[2 * R], vi[2 * R];
@@ -134,35 +208,33 @@ __device__ __forceinline__ void pair_block(T (&K1)[R], T (&K2)[R], T (&K3)[R], T
         vr[R + r] = cr[r];
         vi[R + r] = ci[r];
     }
-    T2 bq[NS + 2];
+    TB bq[NS + 2];
     bq[0] = bA;
     bq[1] = bB;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int jk = J + s;
         if (BULK || s + 2 < NS) bq[s + 2] = bcol[min(jk + 2, jk_last) * nc];
-        const T2 bv = bq[s];
-        const T bre = w.x * bv.x - w.y * bv.y;
-        const T bim = fma_(w.x, bv.y, w.y * bv.x);
-        const T db = bim - bre, sb = bre + bim;
+        T bre, db, sb;
+        b_ops(bq[s], bre, db, sb);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int m = r - s + R;
             const int t = s - NFULL;
             if (s < NFULL || r > 2 * t) {
-                K1[r] = fma_(vs[m], bre, K1[r]);
-                K2[r] = fma_(vr[m], db, K2[r]);
-                K3[r] = fma_(vi[m], sb, K3[r]);
+                P1[r] = fma_(vs[m], bre, P1[r]);
+                P2[r] = fma_(vr[m], db, P2[r]);
+                P3[r] = fma_(vi[m], sb, P3[r]);
             } else if (r == 2 * t) {
                 const T h = T(0.5);
-                K1[r] = fma_(vs[m], h * bre, K1[r]);
-                K2[r] = fma_(vr[m], h * db, K2[r]);
-                K3[r] = fma_(vi[m], h * sb, K3[r]);
+                P1[r] = fma_(vs[m], h * bre, P1[r]);
+                P2[r] = fma_(vr[m], h * db, P2[r]);
+                P3[r] = fma_(vi[m], h * sb, P3[r]);
             }
         }
         // a-values of row K0 - J - 1 - s (m = R - 1 - s), first used at step s + 1
         if (BULK || s + 1 < NS) {
-            const int row = BULK ? K0 - J - 1 - s : max(K0 - J - 1 - s, 0);
+            const int row = (BULK ? K0 - J - 1 - s : max(K0 - J - 1 - s, 0)) * ALayout<T>::ES;
             vs[R - 1 - s] = as_[row];
             vr[R - 1 - s] = ar_[row];
             vi[R - 1 - s] = ai_[row];
@@ -183,13 +255,14 @@ __device__ __forceinline__ void pair_block(T (&K1)[R], T (&K2)[R], T (&K3)[R], T
 // One tile of the pair sum for one realization: output rows K0 = kb*R ..
 // K0+R-1 and the 64 output columns of column tile ct (one per lane).
 template <typename T, int R, bool COMP>
-__device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename vec<T>::v2 *__restrict__ zrow_b,
+__device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename vec<T>::zb *__restrict__ zrow_b,
                                              const T *__restrict__ zcol_b,
                                              const typename vec<T>::v2 *__restrict__ wtab,
                                              typename vec<T>::v2 *__restrict__ tout_b, int kb, int ct,
                                              int flush_terms)
 {
     using T2 = typename vec<T>::v2;
+    using TB = typename vec<T>::zb;
     const int lane = threadIdx.x & 63;
     const int K0 = kb * R;
     const int kc = ct * 64 + lane;
@@ -202,14 +275,15 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
     const int iw_hi = min(Wm1, kw_hi + Wm1);
     const long nc = g.nc;
 
-    const long plane = static_cast<long>(g.ncw) * g.nkp;
+    using L = ALayout<T>;
+    const long plane = L::plane(g);
 
     T sre[R], sim[R], cre[R], cim[R];
-    T K1[R], K2[R], K3[R];
+    T Kre[R], Kim[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         sre[r] = sim[r] = cre[r] = cim[r] = T(0);
-        K1[r] = K2[r] = K3[r] = T(0);
+        Kre[r] = Kim[r] = T(0);
     }
 
     const int nbulk = K0 / 2;
@@ -229,21 +303,23 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
             w.y = T(0);
         }
         const int jc = min(max(jw + g.nw - 1, 0), g.nc - 1);
-        const T2 *__restrict__ bcol = zrow_b + jc;
-        const T *__restrict__ as_ = zcol_b + static_cast<long>(iw + Wm1) * g.nkp;
-        const T *__restrict__ ar_ = as_ + plane;
-        const T *__restrict__ ai_ = as_ + 2 * plane;
+        const gptr<TB> bcol = as_global(zrow_b) + jc;
+        const cptr<T> as_ = as_const(zcol_b) + static_cast<long>(iw + Wm1) * g.nkp * L::ES;
+        const cptr<T> ar_ = as_ + plane;
+        const cptr<T> ai_ = as_ + 2 * plane;
 
         // a-window: (cs, cr, ci)[r] = (re + im, re, im) of z[K0 + r][iw]
         T cs[R], cr[R], ci[R];
+        T P1[R], P2[R], P3[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            cs[r] = as_[K0 + r];
-            cr[r] = ar_[K0 + r];
-            ci[r] = ai_[K0 + r];
+            cs[r] = as_[(K0 + r) * L::ES];
+            cr[r] = ar_[(K0 + r) * L::ES];
+            ci[r] = ai_[(K0 + r) * L::ES];
+            P1[r] = P2[r] = P3[r] = T(0);
         }
-        T2 bA = bcol[0];
-        T2 bB = bcol[min(1, jk_last) * nc];
+        TB bA = bcol[0];
+        TB bB = bcol[min(1, jk_last) * nc];
         // bulk: nbulk = K0/2 steps in blocks of R, then R/2 full steps when
         // nbulk is an odd multiple of R/2, then the R/2 triangular steps
         const int nblk = __builtin_amdgcn_readfirstlane(nbulk / R);
@@ -251,25 +327,32 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
         if (nblk > 0) {
 #pragma clang loop unroll(disable)
             do {
-                pair_block<T, R, R, R>(K1, K2, K3, cs, cr, ci, bA, bB, w, bcol, nc, J, jk_last, as_, ar_,
-                                       ai_, K0);
+                pair_block<T, R, R, R>(P1, P2, P3, cs, cr, ci, bA, bB, bcol, nc, J, jk_last, as_, ar_, ai_, K0);
                 J += R;
             } while (J < nblk * R);
         }
         if (nbulk - J > 0) {
-            pair_block<T, R, R, R / 2>(K1, K2, K3, cs, cr, ci, bA, bB, w, bcol, nc, J, jk_last, as_, ar_,
-                                       ai_, K0);
+            pair_block<T, R, R, R / 2>(P1, P2, P3, cs, cr, ci, bA, bB, bcol, nc, J, jk_last, as_, ar_, ai_, K0);
         } else {
-            pair_block<T, R, R / 2, 0>(K1, K2, K3, cs, cr, ci, bA, bB, w, bcol, nc, J, jk_last, as_, ar_,
-                                       ai_, K0);
+            pair_block<T, R, R / 2, 0>(P1, P2, P3, cs, cr, ci, bA, bB, bcol, nc, J, jk_last, as_, ar_, ai_, K0);
+        }
+        // T_r += W P_r
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T pre = P1[r] - P3[r];
+            const T pim = P1[r] + P2[r];
+            Kre[r] = fma_(w.x, pre, Kre[r]);
+            Kre[r] = fma_(-w.y, pim, Kre[r]);
+            Kim[r] = fma_(w.x, pim, Kim[r]);
+            Kim[r] = fma_(w.y, pre, Kim[r]);
         }
         if (COMP && ++since_flush >= flush_every) {
             since_flush = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                two_sum(sre[r], cre[r], K1[r] - K3[r]);
-                two_sum(sim[r], cim[r], K1[r] + K2[r]);
-                K1[r] = K2[r] = K3[r] = T(0);
+                two_sum(sre[r], cre[r], Kre[r]);
+                two_sum(sim[r], cim[r], Kim[r]);
+                Kre[r] = Kim[r] = T(0);
             }
         }
     }
@@ -278,13 +361,13 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
     for (int r = 0; r < R; ++r) {
         T re, im;
         if (COMP) {
-            two_sum(sre[r], cre[r], K1[r] - K3[r]);
-            two_sum(sim[r], cim[r], K1[r] + K2[r]);
+            two_sum(sre[r], cre[r], Kre[r]);
+            two_sum(sim[r], cim[r], Kim[r]);
             re = sre[r] + cre[r];
             im = sim[r] + cim[r];
         } else {
-            re = K1[r] - K3[r];
-            im = K1[r] + K2[r];
+            re = Kre[r];
+            im = Kim[r];
         }
         const int kk = K0 + r;
         if (lane_ok && kk < g.nk) {
@@ -329,8 +412,8 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
     if (ct >= a.n_ctiles) return;
     const long plane = static_cast<long>(g.ncw) * g.nkp;
     const long lines = static_cast<long>(g.nk) * g.nc;
-    pairsum_tile<T, R, COMP>(g, static_cast<const T2 *>(a.zrow) + b * lines,
-                             static_cast<const T *>(a.zcol) + b * 3 * plane,
+    pairsum_tile<T, R, COMP>(g, static_cast<const typename vec<T>::zb *>(a.zrow) + b * lines,
+                             static_cast<const T *>(a.zcol) + b * ALayout<T>::NS * plane,
                              static_cast<const T2 *>(a.wtab), static_cast<T2 *>(a.tout) + b * lines, kb, ct,
                              a.flush_terms);
 }
@@ -384,14 +467,15 @@ __global__ __launch_bounds__(256) void pairsum_persistent(PersistArgs a)
             s_item = it;
         }
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it < 0) break;
         const PItem w = a.items[it];
-        const PReq &rq = a.reqs[w.req];
+        const PReq rq = a.reqs[w.req];
         const int ct = w.cg * kWavesPerBlock + wave;
         if (ct < rq.n_ctiles)
-            pairsum_tile<T, R, COMP>(rq.g, static_cast<const T2 *>(rq.zrow), static_cast<const T *>(rq.zcol),
+            pairsum_tile<T, R, COMP>(rq.g, static_cast<const typename vec<T>::zb *>(rq.zrow),
+                                     static_cast<const T *>(rq.zcol),
                                      static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, ct,
                                      a.flush_terms);
     }
@@ -526,7 +610,7 @@ struct TfftArgs {
 // Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
 template <typename T>
 __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, int b, int kk, int c,
-                                                             const typename vec<T>::v2 *zrow,
+                                                             const typename vec<T>::zb *zrow,
                                                              const typename vec<T>::v2 *tsum,
                                                              const AmpArgs &amp,
                                                              const typename vec<T>::v2 *wtab)
@@ -541,7 +625,7 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
         if (hw > -g.W && hw < g.W) {
             // half of the self pair {(kk/2, kw/2), (kk/2, kw/2)}
             const T2 w = wtab[static_cast<long>(hw + g.W - 1) * g.ncw + (hw + g.W - 1)];
-            const T2 zh = zrow[static_cast<long>(b) * g.nk * g.nc + static_cast<long>(kk / 2) * g.nc + hw + g.nw - 1];
+            const T2 zh = z_of(zrow[static_cast<long>(b) * g.nk * g.nc + static_cast<long>(kk / 2) * g.nc + hw + g.nw - 1]);
             const T2 z2 = cmul<T>(zh, zh);
             const T2 d = cmul<T>(w, z2);
             t.x += T(0.5) * d.x;
@@ -555,7 +639,7 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     const double base = Sp[li] * amp.dkdw;
     const T p = static_cast<T>(2.0 * sqrt(base * (1.0 - rho * sraw)));
     const T q = static_cast<T>(2.0 * sqrt(base * rho * sc));
-    const T2 z = zrow[bi];
+    const T2 z = z_of(zrow[bi]);
     T2 C;
     C.x = fma_(p, z.x, q * t.x);
     C.y = fma_(p, z.y, q * t.y);
@@ -583,7 +667,7 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         const int bin = kw < 0 ? kw + g.nt : kw;
         T2 C;
         if (a.mode == 0) {
-            C = assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
+            C = assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::zb *>(a.zrow), static_cast<const T2 *>(a.tsum),
                                  a.amp, static_cast<const T2 *>(a.wtab));
         } else {
             C = static_cast<const T2 *>(a.cin)[static_cast<long>(row) * g.nc + c];
@@ -608,7 +692,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(TfftArgs a, typename vec<
     const int kk = static_cast<int>(idx / g.nc);
     const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
     cout[static_cast<long>(b) * per + idx] =
-        assemble_line<T>(g, b, kk, c, static_cast<const T2 *>(a.zrow), static_cast<const T2 *>(a.tsum), a.amp,
+        assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::zb *>(a.zrow), static_cast<const T2 *>(a.tsum), a.amp,
                          static_cast<const T2 *>(a.wtab));
 }
 
@@ -739,7 +823,7 @@ size_t workspace_bytes(const Geometry &g, int precision, int batch)
     const size_t e = precision == SRM3_FP64 ? 8 : 4;
     const size_t lines = static_cast<size_t>(g.nk) * g.nc;
     auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-    return al(batch * lines * 2 * e) + al(static_cast<size_t>(batch) * g.ncw * g.nkp * 3 * e) +
+    return al(batch * lines * kZrowElemBytes) + al(static_cast<size_t>(batch) * g.ncw * g.nkp * a_slots(precision) * e) +
            al(batch * lines * 2 * e) + al(static_cast<size_t>(batch) * g.nk * g.nt * 2 * e);
 }
 
@@ -751,9 +835,9 @@ Workspace carve_workspace(const Geometry &g, int precision, int batch, void *bas
     char *p = static_cast<char *>(base);
     Workspace w;
     w.zrow = p;
-    p += al(batch * lines * 2 * e);
+    p += al(batch * lines * kZrowElemBytes);
     w.zcol = p;
-    p += al(static_cast<size_t>(batch) * g.ncw * g.nkp * 3 * e);
+    p += al(static_cast<size_t>(batch) * g.ncw * g.nkp * a_slots(precision) * e);
     w.tsum = p;
     p += al(batch * lines * 2 * e);
     w.g = p;
@@ -764,7 +848,6 @@ template <typename T>
 static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint64_t *seeds_dev, int batch,
                            const Workspace &ws, hipStream_t st)
 {
-    using T2 = typename vec<T>::v2;
     const long per = static_cast<long>(g.nkp) * g.nc;
     const unsigned gx = static_cast<unsigned>((per + 255) / 256);
     for (int b0 = 0; b0 < batch; b0 += kMaxSeedsPerLaunch) {
@@ -772,7 +855,8 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
         SeedChunk sc{};
         if (!seeds_dev)
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
-        phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, seeds_dev, b0, g, static_cast<T2 *>(ws.zrow),
+        phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
+                                                       static_cast<typename vec<T>::zb *>(ws.zrow),
                                                        static_cast<T *>(ws.zcol));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
