@@ -331,7 +331,7 @@ def main():
     achieved_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
     roofline = {
         "bound": "alu",
-        "kernel": "pairsum_kernel<float,16,true>",
+        "kernel": f"pairsum_kernel<float,{srm3.srm3_rows_per_wave(plan32)},true>",
         "achieved": round(achieved_tflops, 3),
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",

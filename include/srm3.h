@@ -142,6 +142,10 @@ srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes)
 /* Number of unordered pair terms of one realization (sum over lines of |P(k)|). */
 srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms);
 
+/* Output rows per wavefront of the plan's pair-sum tile (R: each wave owns
+ * 64 frequency columns x R kappa rows); the kernel is instantiated per R. */
+srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
+
 /* Per-kernel device time, measured with HIP events recorded on the launch
  * stream around every launch while profiling is on.  Kernel ids:
  * 0 phases, 1 pair sum, 2 assemble + t-transform, 3 x-transform. */

@@ -433,6 +433,13 @@ srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms)
     return SRM3_OK;
 }
 
+srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows)
+{
+    if (!plan || !rows) return fail(SRM3_E_INVALID, "bad argument");
+    *rows = plan->g.R;
+    return SRM3_OK;
+}
+
 srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *out_dev, void *hip_stream)
 {
     g_err[0] = 0;
@@ -602,8 +609,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
         const int ncg = ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
         for (size_t slot = 0; slot < gr.members.size(); ++slot) {
             const int d = gr.first + static_cast<int>(slot);
-            fill_persistent_req(reqs.data() + rb * d, gr.g,
-                                static_cast<char *>(ws.zrow) + slot * lines * kZrowElemBytes,
+            fill_persistent_req(reqs.data() + rb * d, gr.g, static_cast<char *>(ws.zrow) + slot * lines * 2 * e,
                                 static_cast<char *>(ws.zcol) + slot * plane3 * e,
                                 static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
             for (int kb = nrb - 1; kb >= 0; --kb)

@@ -38,11 +38,8 @@ __host__ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint3
 }
 
 template <typename T> struct vec;
-// zb: element of the line-phase array read by the pair sum and the assembly,
-// 16 bytes in both precisions: FP32 (re, im, im - re, re + im), FP64 (re, im).
-template <> struct vec<float> { using v2 = float2; using v4 = float4; using zb = float4; };
-template <> struct vec<double> { using v2 = double2; using v4 = double4; using zb = double2; };
-constexpr size_t kZrowElemBytes = 16;
+template <> struct vec<float> { using v2 = float2; using v4 = float4; };
+template <> struct vec<double> { using v2 = double2; using v4 = double4; };
 // elements of the a operand per (support column, row): 3 planes in FP32,
 // 3 interleaved values padded to 4 in FP64
 inline size_t a_slots(int precision) { return precision == SRM3_FP64 ? 4 : 3; }

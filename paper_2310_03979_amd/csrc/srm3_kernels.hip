@@ -27,30 +27,107 @@ __device__ __forceinline__ void two_sum(T &s, T &c, T x)
     c += err;
 }
 
-// Line phase element of the pair-sum b operand: (re, im) and the Gauss sums
-// (im - re, re + im), stored in FP32, formed on the fly in FP64.
-__device__ __forceinline__ float4 make_zb(double c, double s)
+// Complex products of the pair sum use a 3-multiply form whose per-lane
+// operand needs one add per step: with a = z_i (uniform) and b = z_j (per lane)
+//     k1 = a.re (b.re + b.im),  k2 = (a.re + a.im) b.im,  k3 = (a.im - a.re) b.re
+//     a b = (k1 - k2) + i (k1 + k3).
+// The a operand is stored as the three values (a.re, a.re + a.im, a.im - a.re),
+// formed in FP64 by the phase kernel.
+template <typename T2, typename T>
+__device__ __forceinline__ void b_ops(const T2 &v, T &bsum, T &bim, T &bre)
 {
-    return make_float4(static_cast<float>(c), static_cast<float>(s), static_cast<float>(s - c),
-                       static_cast<float>(c + s));
+    bsum = v.x + v.y;
+    bim = v.y;
+    bre = v.x;
 }
-__device__ __forceinline__ double2 make_zb_d(double c, double s) { return make_double2(c, s); }
-__device__ __forceinline__ void b_ops(const float4 &v, float &re, float &db, float &sb)
-{
-    re = v.x;
-    db = v.z;
-    sb = v.w;
-}
-__device__ __forceinline__ void b_ops(const double2 &v, double &re, double &db, double &sb)
-{
-    re = v.x;
-    db = v.y - v.x;
-    sb = v.x + v.y;
-}
-__device__ __forceinline__ float2 z_of(const float4 &v) { return make_float2(v.x, v.y); }
-__device__ __forceinline__ double2 z_of(const double2 &v) { return v; }
 
-// Layout of the a operand (re + im, re, im) of support column ic, row kk:
+// Read-only data that does not change while a kernel runs, in the constant
+// address space: uniform loads through such a pointer become scalar loads even
+// where the kernel stores elsewhere earlier (the persistent loop).
+// (The host pass of the compiler only parses kernel bodies; it sees plain
+// pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <typename T>
+using cptr = const T *;
+#endif
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
+{
+    return (cptr<T>)p;
+}
+
+// A pointer that every lane of the wave holds, taken from the first lane so
+// that address arithmetic on it stays scalar.
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p)
+{
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(v >> 32));
+    return reinterpret_cast<T *>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// Device memory in the global address space: loads through such a pointer are
+// global (not flat) loads also where the pointer itself was read from memory.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+#else
+template <typename T>
+using gptr = const T *;
+#endif
+
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(const T *p)
+{
+    return (gptr<T>)p;
+}
+
+// The b operand is read with buffer loads: the realization's phase rows form
+// one buffer resource (uniform), the lane's column is a fixed per-lane byte
+// offset and the row a uniform byte offset, so stepping along kappa costs no
+// vector address arithmetic (and reads past the buffer return zero).
+#if defined(__HIP_DEVICE_COMPILE__)
+using brsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ brsrc make_brsrc(const void *p, unsigned bytes)
+{
+    // the resource lives in scalar registers (the base is wave-uniform);
+    // word 3 of a gfx9 raw buffer resource: 32-bit data format, no swizzle
+    return __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<void *>(p)), static_cast<short>(0),
+                                             static_cast<int>(__builtin_amdgcn_readfirstlane(bytes)), 0x00020000);
+}
+// (The loaded vector is copied out whole: extracting its lanes one by one has
+// been folded by the compiler into a single-dword load.)
+__device__ __forceinline__ float2 bload(brsrc r, unsigned voff, unsigned soff, float)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+    static_assert(sizeof(v) == sizeof(float2), "b64 load is two floats");
+    float2 f;
+    __builtin_memcpy(&f, &v, sizeof(f));
+    return f;
+}
+__device__ __forceinline__ double2 bload(brsrc r, unsigned voff, unsigned soff, double)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+    static_assert(sizeof(v) == sizeof(double2), "b128 load is two doubles");
+    double2 d;
+    __builtin_memcpy(&d, &v, sizeof(d));
+    return d;
+}
+#else
+struct brsrc {
+    const void *p;
+};
+__device__ inline brsrc make_brsrc(const void *p, unsigned) { return brsrc{p}; }
+__device__ inline float2 bload(brsrc, unsigned, unsigned, float) { return float2{}; }
+__device__ inline double2 bload(brsrc, unsigned, unsigned, double) { return double2{}; }
+#endif
+
+// Layout of the a operand (re, re + im, im - re) of support column ic, row kk:
 // FP32 keeps three kappa-contiguous planes (a block's rows load as wide scalar
 // loads); FP64 interleaves the three values per row, padded to four, so that
 // rows load one at a time and the scalar register window stays small.
@@ -72,7 +149,7 @@ template <> struct ALayout<double> {
 template <typename T>
 __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
                                                     int b0, Geometry g,
-                                                    typename vec<T>::zb *__restrict__ zrow,
+                                                    typename vec<T>::v2 *__restrict__ zrow,
                                                     T *__restrict__ zcol)
 {
     const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -88,10 +165,10 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
         const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
         sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
-        if constexpr (sizeof(T) == 4)
-            zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = make_zb(co, s);
-        else
-            zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = make_zb_d(co, s);
+        typename vec<T>::v2 v;
+        v.x = static_cast<T>(co);
+        v.y = static_cast<T>(s);
+        zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
     }
     const int ic = c - (g.nw - g.W);
     if (ic >= 0 && ic < g.ncw) {
@@ -99,9 +176,9 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         const long plane = L::plane(g);
         T *zc = zcol + static_cast<long>(b) * L::NS * g.ncw * g.nkp +
                 (static_cast<long>(ic) * g.nkp + kk) * L::ES;
-        zc[0] = static_cast<T>(co + s);
-        zc[plane] = static_cast<T>(co);
-        zc[2 * plane] = static_cast<T>(s);
+        zc[0] = static_cast<T>(co);
+        zc[plane] = static_cast<T>(co + s);
+        zc[2 * plane] = static_cast<T>(s - co);
         if (L::NS == 4) zc[3] = T(0);
     }
 }
@@ -123,11 +200,10 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
 // and the weight is applied once per partner column, T_r += W P_r.  The
 // a-operand z[kk-jk][iw] is the same for all lanes (scalar registers, a
 // sliding window along kappa), the b-operand z[jk][kw-iw] is per lane and
-// reused over the R rows.  Complex products use the 3-multiply form with
-// precomputed sums (a.re + a.im stored with the a planes, b.im - b.re and
-// b.re + b.im stored with the FP32 b operand, formed per step in FP64):
-//     P1 += (a.re + a.im) b.re,  P2 += a.re (b.im - b.re),  P3 += a.im (b.re + b.im)
-//     re = P1 - P3,  im = P1 + P2.
+// reused over the R rows.  Complex products use the 3-multiply form above
+// (a sums stored with the a planes, b.re + b.im formed per step):
+//     P1 += a.re (b.re + b.im),  P2 += (a.re + a.im) b.im,  P3 += (a.im - a.re) b.re
+//     re = P1 - P2,  im = P1 + P3.
 // In FP32 the weighted sums are flushed every few hundred terms into an
 // error-free (two-sum) accumulator.
 // ---------------------------------------------------------------------------
@@ -145,41 +221,6 @@ struct PairsumArgs {
     int per_xcd;      // > 0: XCD-blocked order (see pairsum_kernel), 0: interleaved
 };
 
-// Read-only data that does not change while a kernel runs, in the constant
-// address space: uniform loads through such a pointer become scalar loads even
-// where the kernel stores elsewhere earlier (the persistent loop).
-// (The host pass of the compiler only parses kernel bodies; it sees plain
-// pointers.)
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-#else
-template <typename T>
-using cptr = const T *;
-#endif
-
-template <typename T>
-__device__ __forceinline__ cptr<T> as_const(const T *p)
-{
-    return (cptr<T>)p;
-}
-
-// Device memory in the global address space: loads through such a pointer are
-// global (not flat) loads also where the pointer itself was read from memory.
-#if defined(__HIP_DEVICE_COMPILE__)
-template <typename T>
-using gptr = const __attribute__((address_space(1))) T *;
-#else
-template <typename T>
-using gptr = const T *;
-#endif
-
-template <typename T>
-__device__ __forceinline__ gptr<T> as_global(const T *p)
-{
-    return (gptr<T>)p;
-}
-
 constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
 constexpr int kFlushTerms = 256;
 
@@ -188,25 +229,25 @@ constexpr int kWavesPerBlock = 4;
 // NS steps of the kappa loop starting at b-row J, fully unrolled so that the
 // sliding a-window is plain register renaming.  Steps s < NFULL are at full
 // weight; step s >= NFULL is triangular with t = s - NFULL (row r > 2t full,
-// r == 2t half, r < 2t skipped).  On entry cw[r] = a-values of row K0 - J + r
-// (three planes); a full bulk block (NS == R == NFULL) leaves the values of
-// rows K0 - J - R + r there for the next block.  bA/bB carry b-rows J, J + 1
-// in and J + NS, J + NS + 1 out (prefetched two steps ahead).
+// r == 2t half, r < 2t skipped).  On entry w0/w1/w2[r] = a-values of row
+// K0 - J + r (three planes); a full bulk block (NS == R == NFULL) leaves the
+// values of rows K0 - J - R + r there for the next block.  bA/bB carry b-rows
+// J, J + 1 in and J + NS, J + NS + 1 out (prefetched two steps ahead).
 template <typename T, int R, int NS, int NFULL>
-__device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T (&cs)[R], T (&cr)[R],
-                                           T (&ci)[R], typename vec<T>::zb &bA, typename vec<T>::zb &bB,
-                                           gptr<typename vec<T>::zb> bcol, long nc, int J,
-                                           int jk_last, cptr<T> as_, cptr<T> ar_, cptr<T> ai_, int K0)
+__device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T (&w0)[R], T (&w1)[R],
+                                           T (&w2)[R], typename vec<T>::v2 &bA, typename vec<T>::v2 &bB,
+                                           brsrc bbuf, unsigned bvoff, unsigned brow_bytes, int J,
+                                           int jk_last, cptr<T> a0_, cptr<T> a1_, cptr<T> a2_, int K0)
 {
-    using TB = typename vec<T>::zb;
+    using TB = typename vec<T>::v2;
     constexpr bool BULK = (NS == R && NFULL == R);
     // v[m] = a-values of row K0 - J - R + m, m in [0, 2R)
-    T vs[2 * R], vr[2 * R], vi[2 * R];
+    T v0[2 * R], v1[2 * R], v2[2 * R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        vs[R + r] = cs[r];
-        vr[R + r] = cr[r];
-        vi[R + r] = ci[r];
+        v0[R + r] = w0[r];
+        v1[R + r] = w1[r];
+        v2[R + r] = w2[r];
     }
     TB bq[NS + 2];
     bq[0] = bA;
@@ -214,30 +255,31 @@ __device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int jk = J + s;
-        if (BULK || s + 2 < NS) bq[s + 2] = bcol[min(jk + 2, jk_last) * nc];
-        T bre, db, sb;
-        b_ops(bq[s], bre, db, sb);
+        if (BULK || s + 2 < NS)
+            bq[s + 2] = bload(bbuf, bvoff, static_cast<unsigned>(min(jk + 2, jk_last)) * brow_bytes, T(0));
+        T bsum, bim, bre;
+        b_ops(bq[s], bsum, bim, bre);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int m = r - s + R;
             const int t = s - NFULL;
             if (s < NFULL || r > 2 * t) {
-                P1[r] = fma_(vs[m], bre, P1[r]);
-                P2[r] = fma_(vr[m], db, P2[r]);
-                P3[r] = fma_(vi[m], sb, P3[r]);
+                P1[r] = fma_(v0[m], bsum, P1[r]);
+                P2[r] = fma_(v1[m], bim, P2[r]);
+                P3[r] = fma_(v2[m], bre, P3[r]);
             } else if (r == 2 * t) {
                 const T h = T(0.5);
-                P1[r] = fma_(vs[m], h * bre, P1[r]);
-                P2[r] = fma_(vr[m], h * db, P2[r]);
-                P3[r] = fma_(vi[m], h * sb, P3[r]);
+                P1[r] = fma_(v0[m], h * bsum, P1[r]);
+                P2[r] = fma_(v1[m], h * bim, P2[r]);
+                P3[r] = fma_(v2[m], h * bre, P3[r]);
             }
         }
         // a-values of row K0 - J - 1 - s (m = R - 1 - s), first used at step s + 1
         if (BULK || s + 1 < NS) {
             const int row = (BULK ? K0 - J - 1 - s : max(K0 - J - 1 - s, 0)) * ALayout<T>::ES;
-            vs[R - 1 - s] = as_[row];
-            vr[R - 1 - s] = ar_[row];
-            vi[R - 1 - s] = ai_[row];
+            v0[R - 1 - s] = a0_[row];
+            v1[R - 1 - s] = a1_[row];
+            v2[R - 1 - s] = a2_[row];
         }
     }
     bA = bq[NS];
@@ -245,9 +287,9 @@ __device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T
     if (BULK) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            cs[r] = vs[r];
-            cr[r] = vr[r];
-            ci[r] = vi[r];
+            w0[r] = v0[r];
+            w1[r] = v1[r];
+            w2[r] = v2[r];
         }
     }
 }
@@ -255,14 +297,14 @@ __device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T
 // One tile of the pair sum for one realization: output rows K0 = kb*R ..
 // K0+R-1 and the 64 output columns of column tile ct (one per lane).
 template <typename T, int R, bool COMP>
-__device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename vec<T>::zb *__restrict__ zrow_b,
+__device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename vec<T>::v2 *__restrict__ zrow_b,
                                              const T *__restrict__ zcol_b,
                                              const typename vec<T>::v2 *__restrict__ wtab,
                                              typename vec<T>::v2 *__restrict__ tout_b, int kb, int ct,
                                              int flush_terms)
 {
     using T2 = typename vec<T>::v2;
-    using TB = typename vec<T>::zb;
+    using TB = typename vec<T>::v2;
     const int lane = threadIdx.x & 63;
     const int K0 = kb * R;
     const int kc = ct * 64 + lane;
@@ -277,6 +319,9 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
 
     using L = ALayout<T>;
     const long plane = L::plane(g);
+    const unsigned brow_bytes = static_cast<unsigned>(nc * sizeof(TB));
+    const brsrc bbuf = make_brsrc(zrow_b, static_cast<unsigned>(static_cast<long>(g.nk) * brow_bytes));
+    const T *zcol_u = uniform_ptr(zcol_b);
 
     T sre[R], sim[R], cre[R], cim[R];
     T Kre[R], Kim[R];
@@ -303,23 +348,23 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
             w.y = T(0);
         }
         const int jc = min(max(jw + g.nw - 1, 0), g.nc - 1);
-        const gptr<TB> bcol = as_global(zrow_b) + jc;
-        const cptr<T> as_ = as_const(zcol_b) + static_cast<long>(iw + Wm1) * g.nkp * L::ES;
-        const cptr<T> ar_ = as_ + plane;
-        const cptr<T> ai_ = as_ + 2 * plane;
+        const unsigned bvoff = static_cast<unsigned>(jc) * static_cast<unsigned>(sizeof(TB));
+        const cptr<T> a0_ = as_const(zcol_u) + static_cast<long>(iw + Wm1) * g.nkp * L::ES;
+        const cptr<T> a1_ = a0_ + plane;
+        const cptr<T> a2_ = a0_ + 2 * plane;
 
-        // a-window: (cs, cr, ci)[r] = (re + im, re, im) of z[K0 + r][iw]
-        T cs[R], cr[R], ci[R];
+        // a-window: (w0, w1, w2)[r] = (re, re + im, im - re) of z[K0 + r][iw]
+        T w0[R], w1[R], w2[R];
         T P1[R], P2[R], P3[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            cs[r] = as_[(K0 + r) * L::ES];
-            cr[r] = ar_[(K0 + r) * L::ES];
-            ci[r] = ai_[(K0 + r) * L::ES];
+            w0[r] = a0_[(K0 + r) * L::ES];
+            w1[r] = a1_[(K0 + r) * L::ES];
+            w2[r] = a2_[(K0 + r) * L::ES];
             P1[r] = P2[r] = P3[r] = T(0);
         }
-        TB bA = bcol[0];
-        TB bB = bcol[min(1, jk_last) * nc];
+        TB bA = bload(bbuf, bvoff, 0u, T(0));
+        TB bB = bload(bbuf, bvoff, static_cast<unsigned>(min(1, jk_last)) * brow_bytes, T(0));
         // bulk: nbulk = K0/2 steps in blocks of R, then R/2 full steps when
         // nbulk is an odd multiple of R/2, then the R/2 triangular steps
         const int nblk = __builtin_amdgcn_readfirstlane(nbulk / R);
@@ -327,20 +372,23 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
         if (nblk > 0) {
 #pragma clang loop unroll(disable)
             do {
-                pair_block<T, R, R, R>(P1, P2, P3, cs, cr, ci, bA, bB, bcol, nc, J, jk_last, as_, ar_, ai_, K0);
+                pair_block<T, R, R, R>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, a0_,
+                                       a1_, a2_, K0);
                 J += R;
             } while (J < nblk * R);
         }
         if (nbulk - J > 0) {
-            pair_block<T, R, R, R / 2>(P1, P2, P3, cs, cr, ci, bA, bB, bcol, nc, J, jk_last, as_, ar_, ai_, K0);
+            pair_block<T, R, R, R / 2>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, a0_,
+                                       a1_, a2_, K0);
         } else {
-            pair_block<T, R, R / 2, 0>(P1, P2, P3, cs, cr, ci, bA, bB, bcol, nc, J, jk_last, as_, ar_, ai_, K0);
+            pair_block<T, R, R / 2, 0>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, a0_,
+                                       a1_, a2_, K0);
         }
         // T_r += W P_r
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const T pre = P1[r] - P3[r];
-            const T pim = P1[r] + P2[r];
+            const T pre = P1[r] - P2[r];
+            const T pim = P1[r] + P3[r];
             Kre[r] = fma_(w.x, pre, Kre[r]);
             Kre[r] = fma_(-w.y, pim, Kre[r]);
             Kim[r] = fma_(w.x, pim, Kim[r]);
@@ -412,7 +460,7 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
     if (ct >= a.n_ctiles) return;
     const long plane = static_cast<long>(g.ncw) * g.nkp;
     const long lines = static_cast<long>(g.nk) * g.nc;
-    pairsum_tile<T, R, COMP>(g, static_cast<const typename vec<T>::zb *>(a.zrow) + b * lines,
+    pairsum_tile<T, R, COMP>(g, static_cast<const typename vec<T>::v2 *>(a.zrow) + b * lines,
                              static_cast<const T *>(a.zcol) + b * ALayout<T>::NS * plane,
                              static_cast<const T2 *>(a.wtab), static_cast<T2 *>(a.tout) + b * lines, kb, ct,
                              a.flush_terms);
@@ -474,7 +522,7 @@ __global__ __launch_bounds__(256) void pairsum_persistent(PersistArgs a)
         const PReq rq = a.reqs[w.req];
         const int ct = w.cg * kWavesPerBlock + wave;
         if (ct < rq.n_ctiles)
-            pairsum_tile<T, R, COMP>(rq.g, static_cast<const typename vec<T>::zb *>(rq.zrow),
+            pairsum_tile<T, R, COMP>(rq.g, static_cast<const typename vec<T>::v2 *>(rq.zrow),
                                      static_cast<const T *>(rq.zcol),
                                      static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, ct,
                                      a.flush_terms);
@@ -610,7 +658,7 @@ struct TfftArgs {
 // Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
 template <typename T>
 __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, int b, int kk, int c,
-                                                             const typename vec<T>::zb *zrow,
+                                                             const typename vec<T>::v2 *zrow,
                                                              const typename vec<T>::v2 *tsum,
                                                              const AmpArgs &amp,
                                                              const typename vec<T>::v2 *wtab)
@@ -625,7 +673,7 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
         if (hw > -g.W && hw < g.W) {
             // half of the self pair {(kk/2, kw/2), (kk/2, kw/2)}
             const T2 w = wtab[static_cast<long>(hw + g.W - 1) * g.ncw + (hw + g.W - 1)];
-            const T2 zh = z_of(zrow[static_cast<long>(b) * g.nk * g.nc + static_cast<long>(kk / 2) * g.nc + hw + g.nw - 1]);
+            const T2 zh = zrow[static_cast<long>(b) * g.nk * g.nc + static_cast<long>(kk / 2) * g.nc + hw + g.nw - 1];
             const T2 z2 = cmul<T>(zh, zh);
             const T2 d = cmul<T>(w, z2);
             t.x += T(0.5) * d.x;
@@ -639,7 +687,7 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     const double base = Sp[li] * amp.dkdw;
     const T p = static_cast<T>(2.0 * sqrt(base * (1.0 - rho * sraw)));
     const T q = static_cast<T>(2.0 * sqrt(base * rho * sc));
-    const T2 z = z_of(zrow[bi]);
+    const T2 z = zrow[bi];
     T2 C;
     C.x = fma_(p, z.x, q * t.x);
     C.y = fma_(p, z.y, q * t.y);
@@ -667,7 +715,7 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         const int bin = kw < 0 ? kw + g.nt : kw;
         T2 C;
         if (a.mode == 0) {
-            C = assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::zb *>(a.zrow), static_cast<const T2 *>(a.tsum),
+            C = assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::v2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
                                  a.amp, static_cast<const T2 *>(a.wtab));
         } else {
             C = static_cast<const T2 *>(a.cin)[static_cast<long>(row) * g.nc + c];
@@ -692,7 +740,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(TfftArgs a, typename vec<
     const int kk = static_cast<int>(idx / g.nc);
     const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
     cout[static_cast<long>(b) * per + idx] =
-        assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::zb *>(a.zrow), static_cast<const T2 *>(a.tsum), a.amp,
+        assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::v2 *>(a.zrow), static_cast<const T2 *>(a.tsum), a.amp,
                          static_cast<const T2 *>(a.wtab));
 }
 
@@ -812,7 +860,7 @@ int fft_threads(int butterflies)
 
 int pairsum_rows_per_wave(int nk, int precision)
 {
-    const int cap = precision == SRM3_FP64 ? 8 : 16;
+    const int cap = 8;   // FP32: 4 waves per SIMD at R = 8 beat 2 at R = 16; FP64: 3 waves
     int r = 2;
     while (r * 2 <= cap && r * 2 <= nk) r *= 2;
     return r;
@@ -823,7 +871,7 @@ size_t workspace_bytes(const Geometry &g, int precision, int batch)
     const size_t e = precision == SRM3_FP64 ? 8 : 4;
     const size_t lines = static_cast<size_t>(g.nk) * g.nc;
     auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-    return al(batch * lines * kZrowElemBytes) + al(static_cast<size_t>(batch) * g.ncw * g.nkp * a_slots(precision) * e) +
+    return al(batch * lines * 2 * e) + al(static_cast<size_t>(batch) * g.ncw * g.nkp * a_slots(precision) * e) +
            al(batch * lines * 2 * e) + al(static_cast<size_t>(batch) * g.nk * g.nt * 2 * e);
 }
 
@@ -835,7 +883,7 @@ Workspace carve_workspace(const Geometry &g, int precision, int batch, void *bas
     char *p = static_cast<char *>(base);
     Workspace w;
     w.zrow = p;
-    p += al(batch * lines * kZrowElemBytes);
+    p += al(batch * lines * 2 * e);
     w.zcol = p;
     p += al(static_cast<size_t>(batch) * g.ncw * g.nkp * a_slots(precision) * e);
     w.tsum = p;
@@ -856,7 +904,7 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
         if (!seeds_dev)
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
         phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
-                                                       static_cast<typename vec<T>::zb *>(ws.zrow),
+                                                       static_cast<typename vec<T>::v2 *>(ws.zrow),
                                                        static_cast<T *>(ws.zcol));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

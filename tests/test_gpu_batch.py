@@ -147,10 +147,12 @@ def test_autotuned_batch_is_cached_and_accurate(lib, tmp_path, monkeypatch):
     ref = [dict(plan=r["plan"], seed=r["seed"], out=_out(r["plan"])) for r in reqs]
     tuned = lib.Batch(reqs, flags=lib.SRM3_BATCH_AUTOTUNE | lib.SRM3_BATCH_GRAPH)
     tuned.run()
-    lib.Batch(ref).run()
+    plain = lib.Batch(ref)
+    plain.run()
     torch.cuda.synchronize()
     info = tuned.info()
-    assert info["rows_per_wave"] in (8, 16) and info["blocks_per_cu"] in (1, 2, 4)
+    r_max = plain.info()["rows_per_wave"]          # the untuned batch takes the largest tile
+    assert info["rows_per_wave"] in (r_max, r_max // 2) and info["blocks_per_cu"] in (1, 2, 4)
     text = (tmp_path / "tune.txt").read_text()
     assert "fp32" in text and "32x96w80" in text
     for a, b in zip(reqs, ref):
