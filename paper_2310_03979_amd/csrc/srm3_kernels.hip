@@ -222,7 +222,7 @@ struct PairsumArgs {
 };
 
 constexpr int kNumXcd = 8;   // MI355X: workgroups are dealt round-robin to 8 XCDs
-constexpr int kFlushTerms = 256;
+constexpr int kFlushTerms = 2048;
 
 constexpr int kWavesPerBlock = 4;
 
@@ -232,8 +232,11 @@ constexpr int kWavesPerBlock = 4;
 // r == 2t half, r < 2t skipped).  On entry w0/w1/w2[r] = a-values of row
 // K0 - J + r (three planes); a full bulk block (NS == R == NFULL) leaves the
 // values of rows K0 - J - R + r there for the next block.  bA/bB carry b-rows
-// J, J + 1 in and J + NS, J + NS + 1 out (prefetched two steps ahead).
-template <typename T, int R, int NS, int NFULL>
+// J, J + 1 in and J + NS, J + NS + 1 out (prefetched two steps ahead).  The
+// first block of a partner column (FIRST) starts the sums with its first
+// step, which touches every row: all rows are full there when NFULL > 0, and
+// rows r > 0 full, row 0 half when NFULL == 0.
+template <typename T, int R, int NS, int NFULL, bool FIRST>
 __device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T (&w0)[R], T (&w1)[R],
                                            T (&w2)[R], typename vec<T>::v2 &bA, typename vec<T>::v2 &bB,
                                            brsrc bbuf, unsigned bvoff, unsigned brow_bytes, int J,
@@ -264,14 +267,26 @@ __device__ __forceinline__ void pair_block(T (&P1)[R], T (&P2)[R], T (&P3)[R], T
             const int m = r - s + R;
             const int t = s - NFULL;
             if (s < NFULL || r > 2 * t) {
-                P1[r] = fma_(v0[m], bsum, P1[r]);
-                P2[r] = fma_(v1[m], bim, P2[r]);
-                P3[r] = fma_(v2[m], bre, P3[r]);
+                if (FIRST && s == 0) {
+                    P1[r] = v0[m] * bsum;
+                    P2[r] = v1[m] * bim;
+                    P3[r] = v2[m] * bre;
+                } else {
+                    P1[r] = fma_(v0[m], bsum, P1[r]);
+                    P2[r] = fma_(v1[m], bim, P2[r]);
+                    P3[r] = fma_(v2[m], bre, P3[r]);
+                }
             } else if (r == 2 * t) {
                 const T h = T(0.5);
-                P1[r] = fma_(v0[m], h * bsum, P1[r]);
-                P2[r] = fma_(v1[m], h * bim, P2[r]);
-                P3[r] = fma_(v2[m], h * bre, P3[r]);
+                if (FIRST && s == 0) {
+                    P1[r] = v0[m] * (h * bsum);
+                    P2[r] = v1[m] * (h * bim);
+                    P3[r] = v2[m] * (h * bre);
+                } else {
+                    P1[r] = fma_(v0[m], h * bsum, P1[r]);
+                    P2[r] = fma_(v1[m], h * bim, P2[r]);
+                    P3[r] = fma_(v2[m], h * bre, P3[r]);
+                }
             }
         }
         // a-values of row K0 - J - 1 - s (m = R - 1 - s), first used at step s + 1
@@ -361,7 +376,6 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
             w0[r] = a0_[(K0 + r) * L::ES];
             w1[r] = a1_[(K0 + r) * L::ES];
             w2[r] = a2_[(K0 + r) * L::ES];
-            P1[r] = P2[r] = P3[r] = T(0);
         }
         TB bA = bload(bbuf, bvoff, 0u, T(0));
         TB bB = bload(bbuf, bvoff, static_cast<unsigned>(min(1, jk_last)) * brow_bytes, T(0));
@@ -369,21 +383,29 @@ __device__ __forceinline__ void pairsum_tile(const Geometry &g, const typename v
         // nbulk is an odd multiple of R/2, then the R/2 triangular steps
         const int nblk = __builtin_amdgcn_readfirstlane(nbulk / R);
         int J = 0;
+#define SRM3_PAIR_BLOCK(NS_, NFULL_, FIRST_)                                                                  \
+    pair_block<T, R, NS_, NFULL_, FIRST_>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, \
+                                          a0_, a1_, a2_, K0)
         if (nblk > 0) {
+            SRM3_PAIR_BLOCK(R, R, true);
+            J = R;
+            if (nblk > 1) {
 #pragma clang loop unroll(disable)
-            do {
-                pair_block<T, R, R, R>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, a0_,
-                                       a1_, a2_, K0);
-                J += R;
-            } while (J < nblk * R);
-        }
-        if (nbulk - J > 0) {
-            pair_block<T, R, R, R / 2>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, a0_,
-                                       a1_, a2_, K0);
+                do {
+                    SRM3_PAIR_BLOCK(R, R, false);
+                    J += R;
+                } while (J < nblk * R);
+            }
+            if (nbulk - J > 0)
+                SRM3_PAIR_BLOCK(R, R / 2, false);
+            else
+                SRM3_PAIR_BLOCK(R / 2, 0, false);
+        } else if (nbulk > 0) {
+            SRM3_PAIR_BLOCK(R, R / 2, true);
         } else {
-            pair_block<T, R, R / 2, 0>(P1, P2, P3, w0, w1, w2, bA, bB, bbuf, bvoff, brow_bytes, J, jk_last, a0_,
-                                       a1_, a2_, K0);
+            SRM3_PAIR_BLOCK(R / 2, 0, true);
         }
+#undef SRM3_PAIR_BLOCK
         // T_r += W P_r
 #pragma unroll
         for (int r = 0; r < R; ++r) {
