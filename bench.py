@@ -84,6 +84,7 @@ def cpu_baseline(wl, target_s):
     n_lines = wl.n_lines
     lines_done, terms_done, t_coef = 0, 0.0, 0.0
     batch = 32
+    sample_lines, sample_C = [], []
     while t_coef < target_s and lines_done < n_lines:
         lines = rng.integers(0, n_lines, batch).astype(np.int64)
         terms = 0.0
@@ -91,8 +92,9 @@ def cpu_baseline(wl, target_s):
             kk, c = divmod(int(f), wl.n_cols)
             terms += P.line_terms(kk, c - (wl.n_omega - 1))["npairs"]
         t0 = time.perf_counter()
-        P.coefficients(U=U, lines=lines)
+        sample_C.append(P.coefficients(U=U, lines=lines))
         t_coef += time.perf_counter() - t0
+        sample_lines.append(lines)
         lines_done += batch
         terms_done += terms
         batch = min(4096, batch * 2)
@@ -114,7 +116,49 @@ def cpu_baseline(wl, target_s):
                    f"{total_terms:.4g} pair terms; full nested direct-sum field ({t_field:.1f} s)"),
         "pair_terms_per_s": terms_done / t_coef,
         "seconds_per_realization": per_real,
-    }
+    }, (np.concatenate(sample_lines), np.concatenate(sample_C))
+
+
+def counter_traffic(wl):
+    """HBM bytes per pair-sum launch from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE and WRITE_SIZE passes, each scaled by
+    the reading of a plain device copy), or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pairsum_{wl.name}_counters.md")
+    src = os.path.join(ROOT, "paper_2310_03979_amd", "csrc", "srm3_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("kernel source sha256") != digest:
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def accuracy(torch, srm3, wl, plans, fields, sample):
+    """Relative L2 of the GPU coefficients of realization 0 against the FP64
+    oracle on the sampled lines, and the sample skewness of each path's fields."""
+    lines, ref = sample
+    out = {"lines_compared": int(lines.size)}
+    for name, plan in plans.items():
+        cdt = torch.complex128 if name == "fp64" else torch.complex64
+        C = torch.empty((1,) + tuple(plan.coeff_shape), dtype=cdt, device="cuda")
+        srm3.srm3_coefficients(plan, [int(wl.seeds()[0])], C)
+        got = C.reshape(-1)[torch.as_tensor(lines, device="cuda")].to(torch.complex128).cpu().numpy()
+        out[f"{name}_rel_l2_vs_oracle"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    for name, u in fields.items():
+        x = u.double()
+        x = x - x.mean()
+        out[f"{name}_skewness"] = float((x.pow(3).mean() / x.pow(2).mean().pow(1.5)).item())
+    return out
 
 
 def pair_terms_total(wl):
@@ -336,7 +380,7 @@ def main():
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-        "traffic": None,
+        "traffic": counter_traffic(wl) if B == wl.batch else None,
         "pair_terms_per_launch": terms * B,
         "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
         "avg_launch_ms": round(ps_ms, 4),
@@ -358,9 +402,13 @@ def main():
         extra["batched_over_plain"] = round(dtp / dt, 3)
         log(f"[bench] plain fp32: {dtp * 1e3:.2f} ms per {B} realizations")
     # ---- batched FP64 ----
+    plans = {"fp32": plan32}
+    fields = {"fp32": out32}
     if not args.no_fp64 and wl.n_t <= 8192:
         plan64 = srm3.plan_from_workload(wl, "fp64")
         out64 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float64, device="cuda")
+        plans["fp64"] = plan64
+        fields["fp64"] = out64
         srm3.srm3_profile_enable(plan64, True)
         dt64 = timed_steps(torch, lambda: srm3.srm3_generate(plan64, seeds, out64), 1, 1)
         p64 = srm3.srm3_profile_read(plan64)
@@ -368,15 +416,16 @@ def main():
         extra["fp64_grid_points_per_s"] = grid_points / dt64
         extra["fp64_pairsum_tflops"] = round(FLOPS_PER_PAIR_TERM * terms * B / (ps64 * 1e-3) / 1e12, 3)
         extra["fp64_pairsum_frac_of_fp64_peak"] = round(extra["fp64_pairsum_tflops"] / PEAK_FP64_TFLOPS, 4)
-        del out64, plan64
         log(f"[bench] batched fp64: {dt64 * 1e3:.2f} ms/step")
         torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")
-        cpu = cpu_baseline(wl, args.cpu_seconds)
+        cpu, sample = cpu_baseline(wl, args.cpu_seconds)
         log(f"[bench] oracle: {cpu['value']:.4g} grid points/s on {cpu['cores']} threads")
+        extra["accuracy"] = accuracy(torch, srm3, wl, plans, fields, sample)
+        log(f"[bench] accuracy: {extra['accuracy']}")
 
     rec = {
         "metric": "space-time grid points/sec, batched FP32 vs plain; p50/p99 request latency",

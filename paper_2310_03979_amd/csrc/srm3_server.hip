@@ -3,9 +3,10 @@
 //
 // Requests wait in a FIFO until a slot is free and their workspace fits in
 // the server's device arena (admission by HBM footprint).  Each scheduling
-// step takes pair-sum work items round-robin from every active request --
-// enough to fill the GPU a couple of times over -- and runs them in one
-// persistent launch; a request admitted between steps joins the next one.  A
+// step takes pair-sum work items from the active requests -- those with the
+// least work left first (or round-robin), enough to fill the GPU a couple of
+// times over -- and runs them in one persistent launch; a request admitted
+// between steps joins the next one.  A
 // request whose items have all been issued gets its transforms and a
 // completion event; its slot and arena space are released when that event
 // has completed.  Per-step tables travel in one host-to-device copy from a
