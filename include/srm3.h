@@ -146,6 +146,29 @@ srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms);
  * 64 frequency columns x R kappa rows); the kernel is instantiated per R. */
 srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
 
+/* Pair-sum algorithm of a plan (used by srm3_generate and srm3_coefficients;
+ * batches and the server always use the direct form).
+ *   SRM3_ALGO_DIRECT     enumerates the unordered pairs of every line (the
+ *                        coefficient sum of Section 4.1 / 4.3 as written).
+ *   SRM3_ALGO_KAPPA_FFT  the same sum, reorganised: the weights depend on the
+ *                        frequency indices only, so the kappa part of the
+ *                        ordered pair sum is a linear convolution of phase
+ *                        columns; it runs as a DFT along kappa (length
+ *                        M >= 2 N_kappa - 1), a weighted frequency
+ *                        autoconvolution per kappa frequency, and the inverse
+ *                        DFT.  Same result up to rounding; O(M W^2) terms per
+ *                        realization instead of O(N_kappa^2 W^2).
+ * Switching to SRM3_ALGO_KAPPA_FFT builds its sheared weight table on the
+ * device (stream-ordered on hip_stream).  Errors: SRM3_E_INVALID (bad plan or
+ * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048, or one realization's
+ * transforms or the table above 4 GiB), SRM3_E_NOMEM, SRM3_E_DEVICE. */
+enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1 };
+srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream);
+
+/* Complex multiply-accumulate terms the plan's current pair-sum algorithm
+ * evaluates per realization (SRM3_ALGO_DIRECT: the pair terms). */
+srm3_status srm3_algorithm_terms(srm3_plan_t plan, double *terms);
+
 /* Per-kernel device time, measured with HIP events recorded on the launch
  * stream around every launch while profiling is on.  Kernel ids:
  * 0 phases, 1 pair sum, 2 assemble + t-transform, 3 x-transform. */

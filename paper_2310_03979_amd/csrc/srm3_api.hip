@@ -146,16 +146,29 @@ srm3_status event_pair(srm3_plan_t p, int kernel, hipStream_t st, bool begin)
     return SRM3_OK;
 }
 
-srm3_status ensure_workspace(srm3_plan_t p, int batch)
+srm3_status ensure_workspace(srm3_plan_t p, int batch, hipStream_t st)
 {
-    if (batch <= p->ws_batch) return SRM3_OK;
-    const size_t bytes = workspace_bytes(p->g, p->precision, batch);
-    hipError_t e = p->ws.alloc(bytes);
-    if (e != hipSuccess) {
-        p->ws_batch = 0;
-        return fail(SRM3_E_NOMEM, "workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    if (batch > p->ws_batch) {
+        const size_t bytes = workspace_bytes(p->g, p->precision, batch);
+        hipError_t e = p->ws.alloc(bytes);
+        if (e != hipSuccess) {
+            p->ws_batch = 0;
+            return fail(SRM3_E_NOMEM, "workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        p->ws_batch = batch;
     }
-    p->ws_batch = batch;
+    if (p->algo == SRM3_ALGO_KAPPA_FFT && batch > p->kws_batch) {
+        const size_t bytes = kfft_workspace_bytes(p->g, p->kg, p->precision, batch);
+        hipError_t e = p->kws.alloc(bytes);
+        if (e != hipSuccess) {
+            p->kws_batch = 0;
+            return fail(SRM3_E_NOMEM, "kappa-FFT workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        // the slack around the phase transforms is read (against zero weights)
+        // and never written: it must hold finite values, so clear it once
+        if ((e = launch_zero(p->kws.p, bytes, st)) != hipSuccess) return dev_err(e, "zero kernel");
+        p->kws_batch = batch;
+    }
     return SRM3_OK;
 }
 
@@ -179,8 +192,14 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
     if ((s = event_pair(p, 1, st, true))) return s;
-    e = launch_pairsum(p->g, p->precision, p->wtab.p, batch, ws, st);
-    if (e != hipSuccess) return dev_err(e, "pair-sum kernel");
+    if (p->algo == SRM3_ALGO_KAPPA_FFT) {
+        const KfftWorkspace kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
+        e = launch_kfft_pairsum(p->precision, p->g, p->kg, p->wsh.p, p->tw_k.p, batch, ws, kw, st);
+        if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
+    } else {
+        e = launch_pairsum(p->g, p->precision, p->wtab.p, batch, ws, st);
+        if (e != hipSuccess) return dev_err(e, "pair-sum kernel");
+    }
     if ((s = event_pair(p, 1, st, false))) return s;
     return SRM3_OK;
 }
@@ -423,6 +442,7 @@ srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes)
 {
     if (!plan || !bytes || batch < 0) return fail(SRM3_E_INVALID, "bad argument");
     *bytes = workspace_bytes(plan->g, plan->precision, batch);
+    if (plan->algo == SRM3_ALGO_KAPPA_FFT) *bytes += kfft_workspace_bytes(plan->g, plan->kg, plan->precision, batch);
     return SRM3_OK;
 }
 
@@ -440,14 +460,49 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows)
     return SRM3_OK;
 }
 
+srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!plan) return fail(SRM3_E_INVALID, "plan is NULL");
+    if (algorithm == SRM3_ALGO_DIRECT) {
+        plan->algo = SRM3_ALGO_DIRECT;
+        return SRM3_OK;
+    }
+    if (algorithm != SRM3_ALGO_KAPPA_FFT) return fail(SRM3_E_INVALID, "algorithm %d", algorithm);
+    if (plan->algo == SRM3_ALGO_KAPPA_FFT) return SRM3_OK;
+    const KfftGeom k = kfft_geometry(plan->g);
+    std::string why;
+    if (!kfft_supported(plan->g, k, plan->precision, &why))
+        return fail(SRM3_E_UNSUPPORTED, "kappa-FFT pair sum: %s", why.c_str());
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const size_t e2 = plan->precision == SRM3_FP64 ? 16 : 8;
+    hipError_t e = plan->wsh.alloc(static_cast<size_t>(k.wh_rows) * k.nca * e2);
+    if (e != hipSuccess) return fail(SRM3_E_NOMEM, "weight table hipMalloc: %s", hipGetErrorString(e));
+    if ((e = launch_wsh(plan->precision, plan->wtab.p, plan->g, k, plan->wsh.p, st)) != hipSuccess)
+        return dev_err(e, "sheared weight table kernel");
+    srm3_status s;
+    if ((s = upload(plan->tw_k, twiddles(k.M), plan->precision, st))) return s;
+    plan->kg = k;
+    plan->kws_batch = 0;
+    plan->algo = SRM3_ALGO_KAPPA_FFT;
+    return SRM3_OK;
+}
+
+srm3_status srm3_algorithm_terms(srm3_plan_t plan, double *terms)
+{
+    if (!plan || !terms) return fail(SRM3_E_INVALID, "bad argument");
+    *terms = plan->algo == SRM3_ALGO_KAPPA_FFT ? kfft_terms(plan->g, plan->kg) : plan->pair_terms;
+    return SRM3_OK;
+}
+
 srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *out_dev, void *hip_stream)
 {
     g_err[0] = 0;
     srm3_status s = check_batch(plan, seeds, batch, out_dev);
     if (s) return s;
     if (batch == 0) return SRM3_OK;
-    if ((s = ensure_workspace(plan, batch))) return s;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if ((s = ensure_workspace(plan, batch, st))) return s;
     const Workspace ws = carve_workspace(plan->g, plan->precision, batch, plan->ws.p);
     if ((s = run_front(plan, seeds, batch, ws, st))) return s;
     return run_back(plan, 0, nullptr, batch, ws, out_dev, st);
@@ -459,8 +514,8 @@ srm3_status srm3_coefficients(srm3_plan_t plan, const uint64_t *seeds, int32_t b
     srm3_status s = check_batch(plan, seeds, batch, C_dev);
     if (s) return s;
     if (batch == 0) return SRM3_OK;
-    if ((s = ensure_workspace(plan, batch))) return s;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if ((s = ensure_workspace(plan, batch, st))) return s;
     const Workspace ws = carve_workspace(plan->g, plan->precision, batch, plan->ws.p);
     if ((s = run_front(plan, seeds, batch, ws, st))) return s;
     hipError_t e = launch_assemble(plan->g, plan->precision, plan_amp(plan), plan->wtab.p, batch, ws, C_dev, st);
@@ -474,8 +529,8 @@ srm3_status srm3_transform(srm3_plan_t plan, const void *C_dev, int32_t batch, v
     srm3_status s = check_batch(plan, C_dev, batch, out_dev);
     if (s) return s;
     if (batch == 0) return SRM3_OK;
-    if ((s = ensure_workspace(plan, batch))) return s;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if ((s = ensure_workspace(plan, batch, st))) return s;
     const Workspace ws = carve_workspace(plan->g, plan->precision, batch, plan->ws.p);
     return run_back(plan, 1, C_dev, batch, ws, out_dev, st);
 }

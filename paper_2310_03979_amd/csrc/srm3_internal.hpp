@@ -110,6 +110,31 @@ hipError_t launch_wtable(int precision, int W, int b2_kind, const double *g2, co
 hipError_t launch_spectrum(int nk, int nw, double dk, double dw, double u_star, double z, double U, double lam,
                            double *S, hipStream_t st);
 
+// Pair sum through an FFT along kappa (see the kernels for the derivation).
+struct KfftGeom {
+    int M = 0;        // DFT length along kappa, power of two >= 2 n_kappa - 1
+    int nca = 0;      // output columns that a support pair reaches
+    int c_lo = 0;     // first of them (column index, k_omega + n_omega - 1)
+    int kw0 = 0;      // its k_omega
+    int wh_rows = 0;  // rows of the sheared weight table, zero rows included
+};
+struct KfftWorkspace {
+    void *Z = nullptr;   // [B][M][2W - 1] complex, inside allocated slack
+    void *Y = nullptr;   // [B][M][nca] complex
+};
+// Clear device memory with a kernel (stream-ordered, graph-safe); bytes is a
+// multiple of 16.
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+KfftGeom kfft_geometry(const Geometry &g);
+size_t kfft_workspace_bytes(const Geometry &g, const KfftGeom &k, int precision, int batch);
+KfftWorkspace carve_kfft(const Geometry &g, const KfftGeom &k, int precision, int batch, void *base);
+bool kfft_supported(const Geometry &g, const KfftGeom &k, int precision, std::string *why);
+hipError_t launch_wsh(int precision, const void *wt, const Geometry &g, const KfftGeom &k, void *wh, hipStream_t st);
+// tw: e^{+2 pi i n / M}, n < M
+hipError_t launch_kfft_pairsum(int precision, const Geometry &g, const KfftGeom &k, const void *wh, const void *tw,
+                               int batch, const Workspace &ws, const KfftWorkspace &kw, hipStream_t st);
+double kfft_terms(const Geometry &g, const KfftGeom &k);
+
 int pairsum_rows_per_wave(int nk, int precision);
 hipError_t prepare_transforms(int precision);
 
@@ -145,6 +170,11 @@ struct srm3_plan_s {
     int device = 0;
     srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
     int ws_batch = 0;
+    // pair-sum algorithm; the kappa-FFT form keeps its tables and workspace here
+    int algo = SRM3_ALGO_DIRECT;
+    srm3::KfftGeom kg{};
+    srm3::DevBuf wsh, tw_k, kws;
+    int kws_batch = 0;
     // profiling
     bool prof = false;
     struct Rec {

@@ -5,7 +5,9 @@
 //  tfft        : C_k = A_pure z_k + A_pair (T_k + diagonal fix), placed at bin
 //                (k_kappa, k_omega mod n_t), inverse DFT along t (Stockham, LDS)
 //  xfft        : inverse DFT along x over the n_kappa live rows, real part out
+#include <algorithm>
 #include <cstring>
+#include <string>
 
 #include "srm3_internal.hpp"
 
@@ -557,6 +559,14 @@ __global__ void fill_int_kernel(int *p, int n, int v)
     if (i < n) p[i] = v;
 }
 
+__global__ __launch_bounds__(256) void zero_words_kernel(uint4 *p, size_t n)
+{
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<size_t>(gridDim.x) * blockDim.x)
+        p[i] = z;
+}
+
 // ---------------------------------------------------------------------------
 // Stockham inverse DFT in LDS (radix-4 stages, one radix-2 stage when log2 N
 // is odd), for `nbatch` transforms of length N stored `ld` apart.  Every stage
@@ -805,6 +815,264 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
         const int mx = n / tc, col = n - mx * tc;
         out[static_cast<long>(mx) * g.nt + mt0 + col] = buf[col * ld + mx].x;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Pair sum through an FFT along kappa.
+//
+// For fixed frequencies (i_w, j_w) the kappa part of the ordered pair sum is a
+// linear convolution of two phase columns, so with Z[q][i_w] the length-M DFT
+// (M >= 2 N_kappa - 1, zero padded) of column i_w over kappa,
+//     ordered sum O[kk][kw] = (1/M) sum_q e^{+2 pi i q kk / M} Y[q][kw],
+//     Y[q][kw] = sum_{i_w} W(i_w, kw - i_w) Z[q][i_w] Z[q][kw - i_w],
+// and T = O / 2 as in the direct form.  Y pairs (i_w, j_w) and (j_w, i_w) give
+// the same term, so the sheared table Wh[i_w][kw] = f W(i_w, kw - i_w) with
+// f = 2 (i_w > j_w), 1 (i_w = j_w), 0 (i_w < j_w) sums each unordered
+// frequency pair once.  Work per realization: M x (2W - 1)^2 / 2 complex
+// terms against N_kappa^2 (2W - 1)^2 / 4 in the direct form.
+// ---------------------------------------------------------------------------
+
+// Column DFTs over the rows of a row-major array, one block per tc columns:
+// rows [0, in_rows) of columns col0 .. col0 + ncols - 1 are read (the rest of
+// the N inputs are zero), transformed and rows [0, out_rows) are written,
+// scaled, to columns ocol0 + c of the output.  `tw` is e^{+2 pi i n/N}; the
+// forward transform (e^{-2 pi i}) conjugates the input and the output of the
+// inverse one.
+struct ColfftArgs {
+    const void *in;
+    long in_bstride;    // elements between realizations
+    int in_ld, in_rows, col0;
+    void *out;
+    long out_bstride;
+    int out_ld, out_rows, ocol0;
+    int ncols, N, tc;
+    int forward;
+    const void *tw;
+    double scale;
+};
+
+template <typename T, int MAXB>
+__global__ __launch_bounds__(256) void colfft_kernel(ColfftArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    extern __shared__ unsigned char smem_raw[];
+    T2 *buf = reinterpret_cast<T2 *>(smem_raw);
+    const int b = blockIdx.y;
+    const int c0 = blockIdx.x * a.tc;
+    const int tc = min(a.tc, a.ncols - c0);
+    const T2 *in = static_cast<const T2 *>(a.in) + b * a.in_bstride;
+    for (int n = threadIdx.x; n < a.tc * a.N; n += blockDim.x) {
+        const int row = n / a.tc, col = n - row * a.tc;
+        T2 v;
+        v.x = T(0);
+        v.y = T(0);
+        if (row < a.in_rows && col < tc) v = in[static_cast<long>(row) * a.in_ld + a.col0 + c0 + col];
+        if (a.forward) v.y = -v.y;
+        buf[col * a.N + row] = v;
+    }
+    __syncthreads();
+    fft_lds<T, MAXB>(buf, a.N, a.N, a.tc, static_cast<const T2 *>(a.tw));
+    T2 *out = static_cast<T2 *>(a.out) + b * a.out_bstride;
+    const T sc = static_cast<T>(a.scale);
+    for (int n = threadIdx.x; n < a.out_rows * tc; n += blockDim.x) {
+        const int row = n / tc, col = n - row * tc;
+        T2 v = buf[col * a.N + row];
+        v.x *= sc;
+        v.y *= a.forward ? -sc : sc;
+        out[static_cast<long>(row) * a.out_ld + a.ocol0 + c0 + col] = v;
+    }
+}
+
+// Zero the pair sums of the output columns that no frequency pair reaches.
+template <typename T>
+__global__ __launch_bounds__(256) void zero_cols_kernel(typename vec<T>::v2 *tsum, int nk, int nc, int c_lo,
+                                                        int c_hi)
+{
+    const long per = static_cast<long>(nk) * nc;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= per) return;
+    const int c = static_cast<int>(idx % nc);
+    if (c >= c_lo && c <= c_hi) return;
+    typename vec<T>::v2 z;
+    z.x = T(0);
+    z.y = T(0);
+    tsum[static_cast<long>(blockIdx.y) * per + idx] = z;
+}
+
+// Sheared half table Wh[ic][cc] = f W(i_w, kw - i_w) over the active output
+// columns cc (kw = kw0 + cc), zero outside the support; `pad` rows of zeros
+// follow the table.
+template <typename T>
+__global__ __launch_bounds__(256) void wsh_kernel(const typename vec<T>::v2 *__restrict__ wt, int W, int nca,
+                                                  int kw0, int pad_rows, typename vec<T>::v2 *__restrict__ wh)
+{
+    const int ncw = 2 * W - 1;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= static_cast<long>(ncw + pad_rows) * nca) return;
+    const int ic = static_cast<int>(idx / nca), cc = static_cast<int>(idx - static_cast<long>(ic) * nca);
+    typename vec<T>::v2 v;
+    v.x = T(0);
+    v.y = T(0);
+    if (ic < ncw) {
+        const int iw = ic - (W - 1), jw = kw0 + cc - iw;
+        if (jw > -W && jw < W && iw >= jw) {
+            v = wt[static_cast<long>(ic) * ncw + (jw + W - 1)];
+            if (iw > jw) {
+                v.x *= T(2);
+                v.y *= T(2);
+            }
+        }
+    }
+    wh[idx] = v;
+}
+
+struct YpairArgs {
+    const void *Z;      // realization 0 of [B][M][ncw] phase DFTs, with kz_slack(nw) elements of
+                        // allocated slack before the first and after the last realization
+    void *Y;            // [B][M][nca]
+    const void *wh;     // [ncw + pad][nca] sheared half table
+    int M, W, nw, nca, kw0;
+    int wh_rows;        // rows of the sheared table including its zero rows
+    int batch, n_qtiles, n_cgroups, per_xcd;
+    int flush_blocks;
+};
+
+constexpr int kYRows = 4;     // DFT rows q per wave
+constexpr int kYCols = 4;     // consecutive output columns per lane
+constexpr int kZPadExtra = 64 * kYCols;
+__host__ __device__ constexpr long kz_slack(int nw) { return nw + kZPadExtra; }
+
+// Accumulate acc += W x (a b) with a = Z[q][i_w] (scalar registers) and
+// b = Z[q][kw - i_w] (per lane, a window along the lane's consecutive
+// outputs: stepping i_w by one shifts it by one element, so each step loads
+// one new element per row).
+template <typename T, int R, int S>
+__global__ __launch_bounds__(256) void ypair_kernel(YpairArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int bid = blockIdx.x;
+    const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
+    const int per_b = a.n_qtiles * a.n_cgroups;
+    if (work >= a.batch * per_b) return;
+    const int b = work / per_b;
+    const int rem = work - b * per_b;
+    const int qt = rem / a.n_cgroups;
+    const int cg = rem - qt * a.n_cgroups;
+    const int ct = cg * kWavesPerBlock + wave;
+    const int cc0 = ct * 64 * S;
+    if (cc0 >= a.nca) return;
+    const int W = a.W, ncw = 2 * W - 1, q0 = qt * R;
+    const long zb = static_cast<long>(b) * a.M * ncw;   // realization offset (elements)
+
+    const int kw_lo = a.kw0 + cc0;
+    const int kw_hi = a.kw0 + min(cc0 + 64 * S, a.nca) - 1;
+    const int iw_lo = max(-W + 1, (kw_lo + 1) >> 1);
+    const int iw_hi = min(W - 1, kw_hi + W - 1);
+    const int nblk = __builtin_amdgcn_readfirstlane(iw_hi >= iw_lo ? (iw_hi - iw_lo + S) / S : 0);
+    const int iw_top = iw_lo + nblk * S - 1;             // last step (steps past W - 1 meet zero rows)
+
+    // a operand: rows q0 + r of this realization (rows past M - 1, which a
+    // DFT shorter than R has, read row M - 1 and are not stored), constant
+    // address space
+    const T *Zu = uniform_ptr(static_cast<const T *>(a.Z) + 2 * zb);
+    const cptr<T> za = as_const(Zu);
+    // b operand: element e = (kw - i_w) + W - 1 of row q; byte offset
+    // = voff[r] + (iw_top - i_w) * sizeof(T2) >= 0 thanks to the slack
+    const long slack = kz_slack(a.nw);
+    const brsrc zbuf = make_brsrc(reinterpret_cast<const T2 *>(Zu) - slack,
+                                  static_cast<unsigned>((static_cast<long>(a.M) * ncw + 2 * slack) * sizeof(T2)));
+    unsigned voff[R];
+    const long base_l = static_cast<long>(cc0 + lane * S) + a.kw0 + W - 1 - iw_top + slack;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        voff[r] = static_cast<unsigned>((static_cast<long>(min(q0 + r, a.M - 1)) * ncw + base_l) * sizeof(T2));
+    // weights: row ic of the sheared table, the lane's S consecutive columns
+    const brsrc wbuf = make_brsrc(a.wh, static_cast<unsigned>(static_cast<long>(a.wh_rows) * a.nca * sizeof(T2)));
+    const unsigned wvoff = static_cast<unsigned>((cc0 + lane * S) * sizeof(T2));
+    const unsigned wrow = static_cast<unsigned>(a.nca * sizeof(T2));
+
+    T accr[R][S], acci[R][S], sumr[R][S], sumi[R][S];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < S; ++j) accr[r][j] = acci[r][j] = sumr[r][j] = sumi[r][j] = T(0);
+
+    // window bw[r][m], m in [0, 2S): element e0 + (m - S), where e0 is the
+    // lane's output-0 element at the block's first step.  Output j at block
+    // step s uses m = j - s + S; step s loads m = S - 1 - s (first used at
+    // step s + 1, or at the next block's first step for s = S - 1).
+    T2 bw[R][2 * S];
+    int iw = iw_lo;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int m = S; m < 2 * S; ++m)
+            bw[r][m] = bload(zbuf, voff[r], static_cast<unsigned>((iw_top - iw + m - S) * sizeof(T2)), T(0));
+    int since = 0;
+    for (int blk = 0; blk < nblk; ++blk) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int iws = iw + s;
+            const unsigned snext = static_cast<unsigned>(max(iw_top - iws - 1, 0)) * sizeof(T2);
+#pragma unroll
+            for (int r = 0; r < R; ++r) bw[r][S - 1 - s] = bload(zbuf, voff[r], snext, T(0));
+            const int ic = iws + W - 1;
+            T2 wj[S];
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+                wj[j] = bload(wbuf, wvoff + j * static_cast<unsigned>(sizeof(T2)), static_cast<unsigned>(ic) * wrow,
+                              T(0));
+            const int ica = min(ic, ncw - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const long ai = static_cast<long>(min(q0 + r, a.M - 1)) * ncw + ica;
+                const T ar = za[2 * ai], aim = za[2 * ai + 1];
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    const T2 bv = bw[r][j - s + S];
+                    // t = a b, acc += w t
+                    const T tr = fma_(ar, bv.x, -aim * bv.y);
+                    const T ti = fma_(ar, bv.y, aim * bv.x);
+                    accr[r][j] = fma_(wj[j].x, tr, accr[r][j]);
+                    accr[r][j] = fma_(-wj[j].y, ti, accr[r][j]);
+                    acci[r][j] = fma_(wj[j].x, ti, acci[r][j]);
+                    acci[r][j] = fma_(wj[j].y, tr, acci[r][j]);
+                }
+            }
+        }
+        iw += S;
+        // slide: the next block's values m in [S, 2S) are this block's m - S
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int m = S; m < 2 * S; ++m) bw[r][m] = bw[r][m - S];
+        if (++since >= a.flush_blocks) {
+            since = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    sumr[r][j] += accr[r][j];
+                    sumi[r][j] += acci[r][j];
+                    accr[r][j] = acci[r][j] = T(0);
+                }
+        }
+    }
+    T2 *Y = static_cast<T2 *>(a.Y) + static_cast<long>(b) * a.M * a.nca;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int cc = cc0 + lane * S + j;
+            if (cc < a.nca && q0 + r < a.M) {
+                T2 v;
+                v.x = sumr[r][j] + accr[r][j];
+                v.y = sumi[r][j] + acci[r][j];
+                Y[static_cast<long>(q0 + r) * a.nca + cc] = v;
+            }
+        }
 }
 
 // Pair weight table W[i][j] = sqrt(b2_raw(i, j)) exp(i beta(i, j)) over the
@@ -1120,6 +1388,193 @@ hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int bat
 {
     return precision == SRM3_FP64 ? xfft_t<double>(g, tw, batch, ws, out, out_b, st)
                                   : xfft_t<float>(g, tw, batch, ws, out, out_b, st);
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st)
+{
+    const size_t n = bytes / sizeof(uint4);
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    zero_words_kernel<<<dim3(static_cast<unsigned>(blocks)), 256, 0, st>>>(static_cast<uint4 *>(p), n);
+    return hipGetLastError();
+}
+
+// ---- pair sum through an FFT along kappa ----
+
+KfftGeom kfft_geometry(const Geometry &g)
+{
+    KfftGeom k{};
+    int M = 1;
+    while (M < 2 * g.nk - 1) M *= 2;
+    k.M = M;
+    // output frequencies that a pair of support frequencies reaches
+    const int kw_lo = std::max(-(g.nw - 1), -(2 * g.W - 2));
+    const int kw_hi = std::min(g.nw - 1, 2 * g.W - 2);
+    k.kw0 = kw_lo;
+    k.c_lo = kw_lo + g.nw - 1;
+    k.nca = kw_hi - kw_lo + 1;
+    // zero rows after the table: the S - 1 steps past the last support row and
+    // the ragged last column tile (< 64 S columns past a row's end)
+    k.wh_rows = g.ncw + kYCols + 1 + (64 * kYCols + k.nca - 1) / k.nca;
+    return k;
+}
+
+size_t kfft_workspace_bytes(const Geometry &g, const KfftGeom &k, int precision, int batch)
+{
+    const size_t e2 = precision == SRM3_FP64 ? 16 : 8;
+    auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    const size_t zel = static_cast<size_t>(batch) * k.M * g.ncw + 2 * static_cast<size_t>(kz_slack(g.nw));
+    return al(zel * e2) + al(static_cast<size_t>(batch) * k.M * k.nca * e2);
+}
+
+KfftWorkspace carve_kfft(const Geometry &g, const KfftGeom &k, int precision, int batch, void *base)
+{
+    const size_t e2 = precision == SRM3_FP64 ? 16 : 8;
+    auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    const size_t zel = static_cast<size_t>(batch) * k.M * g.ncw + 2 * static_cast<size_t>(kz_slack(g.nw));
+    KfftWorkspace w;
+    w.Z = static_cast<char *>(base) + kz_slack(g.nw) * e2;
+    w.Y = static_cast<char *>(base) + al(zel * e2);
+    return w;
+}
+
+bool kfft_supported(const Geometry &g, const KfftGeom &k, int precision, std::string *why)
+{
+    const size_t e2 = precision == SRM3_FP64 ? 16 : 8;
+    if (k.M > 4096) {
+        if (why) *why = "n_kappa above 2048";
+        return false;
+    }
+    if (static_cast<double>(k.wh_rows) * k.nca * e2 >= 4294967296.0 ||
+        (static_cast<double>(k.M) * g.ncw + 2.0 * kz_slack(g.nw)) * e2 >= 4294967296.0) {
+        if (why) *why = "weight table or phase transforms of one realization above 4 GiB";
+        return false;
+    }
+    return true;
+}
+
+template <typename T>
+static hipError_t wsh_t(const void *wt, const Geometry &g, const KfftGeom &k, void *wh, hipStream_t st)
+{
+    const long n = static_cast<long>(k.wh_rows) * k.nca;
+    wsh_kernel<T><<<dim3(static_cast<unsigned>((n + 255) / 256)), 256, 0, st>>>(
+        static_cast<const typename vec<T>::v2 *>(wt), g.W, k.nca, k.kw0, k.wh_rows - g.ncw,
+        static_cast<typename vec<T>::v2 *>(wh));
+    return hipGetLastError();
+}
+
+hipError_t launch_wsh(int precision, const void *wt, const Geometry &g, const KfftGeom &k, void *wh, hipStream_t st)
+{
+    return precision == SRM3_FP64 ? wsh_t<double>(wt, g, k, wh, st) : wsh_t<float>(wt, g, k, wh, st);
+}
+
+template <typename T>
+static hipError_t colfft_t(ColfftArgs a, int batch, hipStream_t st)
+{
+    using T2 = typename vec<T>::v2;
+    a.tc = std::max(1, static_cast<int>(32768 / (static_cast<long>(a.N) * sizeof(T2))));
+    const dim3 grid(static_cast<unsigned>((a.ncols + a.tc - 1) / a.tc), static_cast<unsigned>(batch));
+    colfft_kernel<T, 4><<<grid, 256, static_cast<size_t>(a.tc) * a.N * sizeof(T2), st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const void *wh, const void *tw_i, int batch,
+                                 const Workspace &ws, const KfftWorkspace &kw, hipStream_t st)
+{
+    using T2 = typename vec<T>::v2;
+    hipError_t e;
+    for (int b0 = 0; b0 < batch; b0 += 65535) {
+        const int nb = std::min(65535, batch - b0);
+        // forward DFT along kappa of the support columns
+        ColfftArgs f{};
+        f.in = static_cast<const T2 *>(ws.zrow) + static_cast<long>(b0) * g.nk * g.nc;
+        f.in_bstride = static_cast<long>(g.nk) * g.nc;
+        f.in_ld = g.nc;
+        f.in_rows = g.nk;
+        f.col0 = g.nw - g.W;
+        f.out = static_cast<T2 *>(kw.Z) + static_cast<long>(b0) * k.M * g.ncw;
+        f.out_bstride = static_cast<long>(k.M) * g.ncw;
+        f.out_ld = g.ncw;
+        f.out_rows = k.M;
+        f.ocol0 = 0;
+        f.ncols = g.ncw;
+        f.N = k.M;
+        f.forward = 1;
+        f.tw = tw_i;
+        f.scale = 1.0;
+        if ((e = colfft_t<T>(f, nb, st)) != hipSuccess) return e;
+    }
+    // weighted frequency autoconvolution per kappa frequency q
+    YpairArgs y{};
+    y.Z = kw.Z;
+    y.Y = kw.Y;
+    y.wh = wh;
+    y.M = k.M;
+    y.W = g.W;
+    y.nw = g.nw;
+    y.nca = k.nca;
+    y.kw0 = k.kw0;
+    y.wh_rows = k.wh_rows;
+    y.batch = batch;
+    y.n_qtiles = (k.M + kYRows - 1) / kYRows;
+    const int n_ctiles = (k.nca + 64 * kYCols - 1) / (64 * kYCols);
+    y.n_cgroups = (n_ctiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const long blocks = static_cast<long>(batch) * y.n_qtiles * y.n_cgroups;
+    y.per_xcd = static_cast<int>((blocks + kNumXcd - 1) / kNumXcd);
+    y.flush_blocks = std::max(1, 256 / kYCols);
+    ypair_kernel<T, kYRows, kYCols><<<dim3(static_cast<unsigned>(static_cast<long>(y.per_xcd) * kNumXcd)),
+                                      64 * kWavesPerBlock, 0, st>>>(y);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int b0 = 0; b0 < batch; b0 += 65535) {
+        const int nb = std::min(65535, batch - b0);
+        // inverse DFT along kappa, first n_kappa rows, halved: T = O / 2
+        ColfftArgs v{};
+        v.in = static_cast<const T2 *>(kw.Y) + static_cast<long>(b0) * k.M * k.nca;
+        v.in_bstride = static_cast<long>(k.M) * k.nca;
+        v.in_ld = k.nca;
+        v.in_rows = k.M;
+        v.col0 = 0;
+        v.out = static_cast<T2 *>(ws.tsum) + static_cast<long>(b0) * g.nk * g.nc;
+        v.out_bstride = static_cast<long>(g.nk) * g.nc;
+        v.out_ld = g.nc;
+        v.out_rows = g.nk;
+        v.ocol0 = k.c_lo;
+        v.ncols = k.nca;
+        v.N = k.M;
+        v.forward = 0;
+        v.tw = tw_i;
+        v.scale = 0.5 / k.M;
+        if ((e = colfft_t<T>(v, nb, st)) != hipSuccess) return e;
+        if (k.nca < g.nc) {
+            const long per = static_cast<long>(g.nk) * g.nc;
+            zero_cols_kernel<T><<<dim3(static_cast<unsigned>((per + 255) / 256), static_cast<unsigned>(nb)), 256, 0,
+                                  st>>>(static_cast<T2 *>(ws.tsum) + static_cast<long>(b0) * per, g.nk, g.nc,
+                                        k.c_lo, k.c_lo + k.nca - 1);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_kfft_pairsum(int precision, const Geometry &g, const KfftGeom &k, const void *wh, const void *tw,
+                               int batch, const Workspace &ws, const KfftWorkspace &kw, hipStream_t st)
+{
+    return precision == SRM3_FP64 ? kfft_pairsum_t<double>(g, k, wh, tw, batch, ws, kw, st)
+                                  : kfft_pairsum_t<float>(g, k, wh, tw, batch, ws, kw, st);
+}
+
+double kfft_terms(const Geometry &g, const KfftGeom &k)
+{
+    // complex terms of the frequency autoconvolution per realization: for each
+    // q, the unordered support pairs (i_w >= j_w) of every active output
+    double t = 0;
+    for (int kw = k.kw0; kw < k.kw0 + k.nca; ++kw) {
+        const int lo = std::max(-(g.W - 1), kw - (g.W - 1)), hi = std::min(g.W - 1, kw + (g.W - 1));
+        const int half_lo = std::max(lo, (kw + 1) >> 1);
+        if (hi >= half_lo) t += hi - half_lo + 1;
+    }
+    return t * k.M;
 }
 
 // Allow the transform kernels the 128 KB of LDS a length-16384 FP32 (8192

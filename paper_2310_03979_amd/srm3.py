@@ -95,6 +95,8 @@ def load():
     L.srm3_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
     L.srm3_pair_terms.argtypes = [vp, _dp]
     L.srm3_rows_per_wave.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.srm3_plan_set_algorithm.argtypes = [vp, ctypes.c_int32, vp]
+    L.srm3_algorithm_terms.argtypes = [vp, _dp]
     L.srm3_profile_enable.argtypes = [vp, ctypes.c_int32]
     L.srm3_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
     L.srm3_destroy.argtypes = [vp]
@@ -111,7 +113,8 @@ def load():
     L.srm3_batch_destroy.restype = None
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
     for f in ("srm3_plan", "srm3_generate", "srm3_coefficients", "srm3_transform",
-              "srm3_workspace_bytes", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_profile_enable",
+              "srm3_workspace_bytes", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
+              "srm3_algorithm_terms", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
               "srm3_batch_create", "srm3_batch_run", "srm3_batch_info", "srm3_generate_uneven"):
         getattr(L, f).restype = ctypes.c_int
@@ -289,6 +292,22 @@ def srm3_workspace_bytes(plan: Plan, batch: int) -> int:
 def srm3_pair_terms(plan: Plan) -> float:
     v = ctypes.c_double()
     _check(load().srm3_pair_terms(plan.handle, ctypes.byref(v)))
+    return float(v.value)
+
+
+SRM3_ALGO_DIRECT, SRM3_ALGO_KAPPA_FFT = 0, 1
+_ALGOS = {"direct": SRM3_ALGO_DIRECT, "kappa_fft": SRM3_ALGO_KAPPA_FFT}
+
+
+def srm3_plan_set_algorithm(plan: Plan, algorithm="direct", stream=None):
+    """Pair-sum algorithm of the plan: "direct" or "kappa_fft" (or the enum)."""
+    a = _ALGOS[algorithm] if isinstance(algorithm, str) else int(algorithm)
+    _check(load().srm3_plan_set_algorithm(plan.handle, a, _stream_ptr(stream)))
+
+
+def srm3_algorithm_terms(plan: Plan) -> float:
+    v = ctypes.c_double()
+    _check(load().srm3_algorithm_terms(plan.handle, ctypes.byref(v)))
     return float(v.value)
 
 
