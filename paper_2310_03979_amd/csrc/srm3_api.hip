@@ -164,9 +164,6 @@ srm3_status ensure_workspace(srm3_plan_t p, int batch, hipStream_t st)
             p->kws_batch = 0;
             return fail(SRM3_E_NOMEM, "kappa-FFT workspace hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
         }
-        // the slack around the phase transforms is read (against zero weights)
-        // and never written: it must hold finite values, so clear it once
-        if ((e = launch_zero(p->kws.p, bytes, st)) != hipSuccess) return dev_err(e, "zero kernel");
         p->kws_batch = batch;
     }
     return SRM3_OK;

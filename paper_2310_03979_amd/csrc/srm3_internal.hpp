@@ -119,12 +119,9 @@ struct KfftGeom {
     int wh_rows = 0;  // rows of the sheared weight table, zero rows included
 };
 struct KfftWorkspace {
-    void *Z = nullptr;   // [B][M][2W - 1] complex, inside allocated slack
+    void *Z = nullptr;   // [B][M][2W - 1] complex
     void *Y = nullptr;   // [B][M][nca] complex
 };
-// Clear device memory with a kernel (stream-ordered, graph-safe); bytes is a
-// multiple of 16.
-hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 KfftGeom kfft_geometry(const Geometry &g);
 size_t kfft_workspace_bytes(const Geometry &g, const KfftGeom &k, int precision, int batch);
 KfftWorkspace carve_kfft(const Geometry &g, const KfftGeom &k, int precision, int batch, void *base);

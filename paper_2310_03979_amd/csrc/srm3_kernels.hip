@@ -559,14 +559,6 @@ __global__ void fill_int_kernel(int *p, int n, int v)
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void zero_words_kernel(uint4 *p, size_t n)
-{
-    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += static_cast<size_t>(gridDim.x) * blockDim.x)
-        p[i] = z;
-}
-
 // ---------------------------------------------------------------------------
 // Stockham inverse DFT in LDS (radix-4 stages, one radix-2 stage when log2 N
 // is odd), for `nbatch` transforms of length N stored `ld` apart.  Every stage
@@ -927,31 +919,39 @@ __global__ __launch_bounds__(256) void wsh_kernel(const typename vec<T>::v2 *__r
 }
 
 struct YpairArgs {
-    const void *Z;      // realization 0 of [B][M][ncw] phase DFTs, with kz_slack(nw) elements of
-                        // allocated slack before the first and after the last realization
+    const void *Z;      // [B][M][ncw] phase DFTs along kappa
     void *Y;            // [B][M][nca]
-    const void *wh;     // [ncw + pad][nca] sheared half table
-    int M, W, nw, nca, kw0;
-    int wh_rows;        // rows of the sheared table including its zero rows
+    const void *wh;     // [wh_rows][nca] sheared half table, zero rows after row ncw - 1
+    int M, W, nca, kw0;
     int batch, n_qtiles, n_cgroups, per_xcd;
-    int flush_blocks;
 };
 
-constexpr int kYRows = 4;     // DFT rows q per wave
-constexpr int kYCols = 4;     // consecutive output columns per lane
-constexpr int kZPadExtra = 64 * kYCols;
-__host__ __device__ constexpr long kz_slack(int nw) { return nw + kZPadExtra; }
+// Staged form of the frequency autoconvolution.  A wave owns 64 consecutive
+// output columns (one per lane) and R DFT rows q, and walks the partner
+// frequencies i_w in chunks of C steps.  The b operand Z[q][kw - i_w] of lane
+// l at step i_w is element e = e0 + l - i_w of row q, so a chunk reads a
+// window of 64 + C - 1 elements per row; the window and the chunk's a
+// operands Z[q][i_w] (the same for all lanes) are staged in the wave's own
+// slice of LDS with coalesced global loads -- no barrier: the wave alone
+// writes and reads its slice.  The weight row W_h[i_w][.] is read from global
+// memory once per step for all R rows, two steps ahead.  Steps past the last
+// partner meet zero weights (zero rows after the table, or pairs outside the
+// support).  Per term: t = a b (4 ops), acc += w t (4 FMAs).
+constexpr int kY2Rows = 8;      // DFT rows per wave
+constexpr int kY2Chunk = 32;    // steps per staged window
+constexpr int kY2Unroll = 4;
 
-// Accumulate acc += W x (a b) with a = Z[q][i_w] (scalar registers) and
-// b = Z[q][kw - i_w] (per lane, a window along the lane's consecutive
-// outputs: stepping i_w by one shifts it by one element, so each step loads
-// one new element per row).
-template <typename T, int R, int S>
-__global__ __launch_bounds__(256) void ypair_kernel(YpairArgs a)
+template <typename T, int R, int C>
+__global__ __launch_bounds__(256) void ypair2_kernel(YpairArgs a)
 {
     using T2 = typename vec<T>::v2;
+    constexpr int LW = 64 + C;   // staged elements per row (64 + C - 1 used)
+    static_assert((R * LW) % 64 == 0 && (C * R) % 64 == 0 && C % kY2Unroll == 0, "staging shape");
+    extern __shared__ unsigned char smem_raw[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    T2 *ldsb = reinterpret_cast<T2 *>(smem_raw) + wave * (R * LW + C * R);
+    T2 *ldsa = ldsb + R * LW;
     const int bid = blockIdx.x;
     const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
     const int per_b = a.n_qtiles * a.n_cgroups;
@@ -960,119 +960,100 @@ __global__ __launch_bounds__(256) void ypair_kernel(YpairArgs a)
     const int rem = work - b * per_b;
     const int qt = rem / a.n_cgroups;
     const int cg = rem - qt * a.n_cgroups;
-    const int ct = cg * kWavesPerBlock + wave;
-    const int cc0 = ct * 64 * S;
+    const int cc0 = (cg * kWavesPerBlock + wave) * 64;
     if (cc0 >= a.nca) return;
     const int W = a.W, ncw = 2 * W - 1, q0 = qt * R;
-    const long zb = static_cast<long>(b) * a.M * ncw;   // realization offset (elements)
-
+    const T2 *Zb = static_cast<const T2 *>(a.Z) + static_cast<long>(b) * a.M * ncw;
     const int kw_lo = a.kw0 + cc0;
-    const int kw_hi = a.kw0 + min(cc0 + 64 * S, a.nca) - 1;
+    const int kw_hi = a.kw0 + min(cc0 + 64, a.nca) - 1;
     const int iw_lo = max(-W + 1, (kw_lo + 1) >> 1);
     const int iw_hi = min(W - 1, kw_hi + W - 1);
-    const int nblk = __builtin_amdgcn_readfirstlane(iw_hi >= iw_lo ? (iw_hi - iw_lo + S) / S : 0);
-    const int iw_top = iw_lo + nblk * S - 1;             // last step (steps past W - 1 meet zero rows)
+    const int nchunk = __builtin_amdgcn_readfirstlane(iw_hi >= iw_lo ? (iw_hi - iw_lo + C) / C : 0);
+    const gptr<T2> wcol = as_global(static_cast<const T2 *>(a.wh)) + cc0 + lane;
+    const long wstride = a.nca;
 
-    // a operand: rows q0 + r of this realization (rows past M - 1, which a
-    // DFT shorter than R has, read row M - 1 and are not stored), constant
-    // address space
-    const T *Zu = uniform_ptr(static_cast<const T *>(a.Z) + 2 * zb);
-    const cptr<T> za = as_const(Zu);
-    // b operand: element e = (kw - i_w) + W - 1 of row q; byte offset
-    // = voff[r] + (iw_top - i_w) * sizeof(T2) >= 0 thanks to the slack
-    const long slack = kz_slack(a.nw);
-    const brsrc zbuf = make_brsrc(reinterpret_cast<const T2 *>(Zu) - slack,
-                                  static_cast<unsigned>((static_cast<long>(a.M) * ncw + 2 * slack) * sizeof(T2)));
-    unsigned voff[R];
-    const long base_l = static_cast<long>(cc0 + lane * S) + a.kw0 + W - 1 - iw_top + slack;
+    T accr[R], acci[R], sumr[R], sumi[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        voff[r] = static_cast<unsigned>((static_cast<long>(min(q0 + r, a.M - 1)) * ncw + base_l) * sizeof(T2));
-    // weights: row ic of the sheared table, the lane's S consecutive columns
-    const brsrc wbuf = make_brsrc(a.wh, static_cast<unsigned>(static_cast<long>(a.wh_rows) * a.nca * sizeof(T2)));
-    const unsigned wvoff = static_cast<unsigned>((cc0 + lane * S) * sizeof(T2));
-    const unsigned wrow = static_cast<unsigned>(a.nca * sizeof(T2));
+    for (int r = 0; r < R; ++r) accr[r] = acci[r] = sumr[r] = sumi[r] = T(0);
 
-    T accr[R][S], acci[R][S], sumr[R][S], sumi[R][S];
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int iwc = iw_lo + ch * C;
+        // b window: lane l at chunk step s reads index l + C - 1 - s of row r
+        const int e_lo = kw_lo + W - 1 - (iwc + C - 1);
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+        for (int i = 0; i < R * LW / 64; ++i) {
+            const int idx = i * 64 + lane;
+            const int r = idx / LW, x = idx - r * LW;
+            const int e = e_lo + x;
+            T2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (e >= 0 && e < ncw) v = Zb[static_cast<long>(min(q0 + r, a.M - 1)) * ncw + e];
+            ldsb[r * LW + x] = v;
+        }
+        // a operands of the chunk, [s][r]
 #pragma unroll
-        for (int j = 0; j < S; ++j) accr[r][j] = acci[r][j] = sumr[r][j] = sumi[r][j] = T(0);
-
-    // window bw[r][m], m in [0, 2S): element e0 + (m - S), where e0 is the
-    // lane's output-0 element at the block's first step.  Output j at block
-    // step s uses m = j - s + S; step s loads m = S - 1 - s (first used at
-    // step s + 1, or at the next block's first step for s = S - 1).
-    T2 bw[R][2 * S];
-    int iw = iw_lo;
+        for (int i = 0; i < C * R / 64; ++i) {
+            const int idx = i * 64 + lane;
+            const int st = idx / R, r = idx - st * R;
+            const int ic = iwc + st + W - 1;
+            T2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (ic < ncw) v = Zb[static_cast<long>(min(q0 + r, a.M - 1)) * ncw + ic];
+            ldsa[st * R + r] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int ic0 = iwc + W - 1;
+        T2 w0 = wcol[static_cast<long>(ic0) * wstride];
+        T2 w1 = wcol[static_cast<long>(ic0 + 1) * wstride];
+        for (int s0 = 0; s0 < C; s0 += kY2Unroll) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+            for (int u = 0; u < kY2Unroll; ++u) {
+                const int s = s0 + u;
+                const T2 w2 = wcol[static_cast<long>(ic0 + s + 2) * wstride];
+                const int x = lane + C - 1 - s;
 #pragma unroll
-        for (int m = S; m < 2 * S; ++m)
-            bw[r][m] = bload(zbuf, voff[r], static_cast<unsigned>((iw_top - iw + m - S) * sizeof(T2)), T(0));
-    int since = 0;
-    for (int blk = 0; blk < nblk; ++blk) {
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int iws = iw + s;
-            const unsigned snext = static_cast<unsigned>(max(iw_top - iws - 1, 0)) * sizeof(T2);
-#pragma unroll
-            for (int r = 0; r < R; ++r) bw[r][S - 1 - s] = bload(zbuf, voff[r], snext, T(0));
-            const int ic = iws + W - 1;
-            T2 wj[S];
-#pragma unroll
-            for (int j = 0; j < S; ++j)
-                wj[j] = bload(wbuf, wvoff + j * static_cast<unsigned>(sizeof(T2)), static_cast<unsigned>(ic) * wrow,
-                              T(0));
-            const int ica = min(ic, ncw - 1);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const long ai = static_cast<long>(min(q0 + r, a.M - 1)) * ncw + ica;
-                const T ar = za[2 * ai], aim = za[2 * ai + 1];
-#pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    const T2 bv = bw[r][j - s + S];
-                    // t = a b, acc += w t
-                    const T tr = fma_(ar, bv.x, -aim * bv.y);
-                    const T ti = fma_(ar, bv.y, aim * bv.x);
-                    accr[r][j] = fma_(wj[j].x, tr, accr[r][j]);
-                    accr[r][j] = fma_(-wj[j].y, ti, accr[r][j]);
-                    acci[r][j] = fma_(wj[j].x, ti, acci[r][j]);
-                    acci[r][j] = fma_(wj[j].y, tr, acci[r][j]);
+                for (int r = 0; r < R; ++r) {
+                    const T2 av = ldsa[s * R + r];
+                    const T2 bv = ldsb[r * LW + x];
+                    const T tr = fma_(av.x, bv.x, -av.y * bv.y);
+                    const T ti = fma_(av.x, bv.y, av.y * bv.x);
+                    accr[r] = fma_(w0.x, tr, accr[r]);
+                    accr[r] = fma_(-w0.y, ti, accr[r]);
+                    acci[r] = fma_(w0.x, ti, acci[r]);
+                    acci[r] = fma_(w0.y, tr, acci[r]);
                 }
+                w0 = w1;
+                w1 = w2;
             }
         }
-        iw += S;
-        // slide: the next block's values m in [S, 2S) are this block's m - S
+        // the slice is rewritten by the next chunk only after these reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ch & 1) {
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int m = S; m < 2 * S; ++m) bw[r][m] = bw[r][m - S];
-        if (++since >= a.flush_blocks) {
-            since = 0;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int j = 0; j < S; ++j) {
-                    sumr[r][j] += accr[r][j];
-                    sumi[r][j] += acci[r][j];
-                    accr[r][j] = acci[r][j] = T(0);
-                }
+            for (int r = 0; r < R; ++r) {
+                sumr[r] += accr[r];
+                sumi[r] += acci[r];
+                accr[r] = acci[r] = T(0);
+            }
         }
     }
     T2 *Y = static_cast<T2 *>(a.Y) + static_cast<long>(b) * a.M * a.nca;
+    const int cc = cc0 + lane;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int j = 0; j < S; ++j) {
-            const int cc = cc0 + lane * S + j;
-            if (cc < a.nca && q0 + r < a.M) {
-                T2 v;
-                v.x = sumr[r][j] + accr[r][j];
-                v.y = sumi[r][j] + acci[r][j];
-                Y[static_cast<long>(q0 + r) * a.nca + cc] = v;
-            }
+    for (int r = 0; r < R; ++r) {
+        if (cc < a.nca && q0 + r < a.M) {
+            T2 v;
+            v.x = sumr[r] + accr[r];
+            v.y = sumi[r] + acci[r];
+            Y[static_cast<long>(q0 + r) * a.nca + cc] = v;
         }
+    }
 }
 
 // Pair weight table W[i][j] = sqrt(b2_raw(i, j)) exp(i beta(i, j)) over the
@@ -1390,15 +1371,6 @@ hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int bat
                                   : xfft_t<float>(g, tw, batch, ws, out, out_b, st);
 }
 
-hipError_t launch_zero(void *p, size_t bytes, hipStream_t st)
-{
-    const size_t n = bytes / sizeof(uint4);
-    if (n == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
-    zero_words_kernel<<<dim3(static_cast<unsigned>(blocks)), 256, 0, st>>>(static_cast<uint4 *>(p), n);
-    return hipGetLastError();
-}
-
 // ---- pair sum through an FFT along kappa ----
 
 KfftGeom kfft_geometry(const Geometry &g)
@@ -1413,9 +1385,10 @@ KfftGeom kfft_geometry(const Geometry &g)
     k.kw0 = kw_lo;
     k.c_lo = kw_lo + g.nw - 1;
     k.nca = kw_hi - kw_lo + 1;
-    // zero rows after the table: the S - 1 steps past the last support row and
-    // the ragged last column tile (< 64 S columns past a row's end)
-    k.wh_rows = g.ncw + kYCols + 1 + (64 * kYCols + k.nca - 1) / k.nca;
+    // zero rows after the table: the weight rows read up to C + 1 steps past
+    // the last partner, and the ragged last column tile (< 64 columns past a
+    // row's end)
+    k.wh_rows = g.ncw + kY2Chunk + 2 + (64 + k.nca - 1) / k.nca;
     return k;
 }
 
@@ -1423,31 +1396,24 @@ size_t kfft_workspace_bytes(const Geometry &g, const KfftGeom &k, int precision,
 {
     const size_t e2 = precision == SRM3_FP64 ? 16 : 8;
     auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-    const size_t zel = static_cast<size_t>(batch) * k.M * g.ncw + 2 * static_cast<size_t>(kz_slack(g.nw));
-    return al(zel * e2) + al(static_cast<size_t>(batch) * k.M * k.nca * e2);
+    return al(static_cast<size_t>(batch) * k.M * g.ncw * e2) + al(static_cast<size_t>(batch) * k.M * k.nca * e2);
 }
 
 KfftWorkspace carve_kfft(const Geometry &g, const KfftGeom &k, int precision, int batch, void *base)
 {
     const size_t e2 = precision == SRM3_FP64 ? 16 : 8;
     auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
-    const size_t zel = static_cast<size_t>(batch) * k.M * g.ncw + 2 * static_cast<size_t>(kz_slack(g.nw));
     KfftWorkspace w;
-    w.Z = static_cast<char *>(base) + kz_slack(g.nw) * e2;
-    w.Y = static_cast<char *>(base) + al(zel * e2);
+    w.Z = base;
+    w.Y = static_cast<char *>(base) + al(static_cast<size_t>(batch) * k.M * g.ncw * e2);
     return w;
 }
 
-bool kfft_supported(const Geometry &g, const KfftGeom &k, int precision, std::string *why)
+bool kfft_supported(const Geometry &, const KfftGeom &k, int, std::string *why)
 {
-    const size_t e2 = precision == SRM3_FP64 ? 16 : 8;
+    // one column transform of length M fits the column-DFT kernel's LDS
     if (k.M > 4096) {
         if (why) *why = "n_kappa above 2048";
-        return false;
-    }
-    if (static_cast<double>(k.wh_rows) * k.nca * e2 >= 4294967296.0 ||
-        (static_cast<double>(k.M) * g.ncw + 2.0 * kz_slack(g.nw)) * e2 >= 4294967296.0) {
-        if (why) *why = "weight table or phase transforms of one realization above 4 GiB";
         return false;
     }
     return true;
@@ -1512,19 +1478,18 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const voi
     y.wh = wh;
     y.M = k.M;
     y.W = g.W;
-    y.nw = g.nw;
     y.nca = k.nca;
     y.kw0 = k.kw0;
-    y.wh_rows = k.wh_rows;
     y.batch = batch;
-    y.n_qtiles = (k.M + kYRows - 1) / kYRows;
-    const int n_ctiles = (k.nca + 64 * kYCols - 1) / (64 * kYCols);
+    y.n_qtiles = (k.M + kY2Rows - 1) / kY2Rows;
+    const int n_ctiles = (k.nca + 63) / 64;
     y.n_cgroups = (n_ctiles + kWavesPerBlock - 1) / kWavesPerBlock;
     const long blocks = static_cast<long>(batch) * y.n_qtiles * y.n_cgroups;
     y.per_xcd = static_cast<int>((blocks + kNumXcd - 1) / kNumXcd);
-    y.flush_blocks = std::max(1, 256 / kYCols);
-    ypair_kernel<T, kYRows, kYCols><<<dim3(static_cast<unsigned>(static_cast<long>(y.per_xcd) * kNumXcd)),
-                                      64 * kWavesPerBlock, 0, st>>>(y);
+    const size_t lds = static_cast<size_t>(kWavesPerBlock) * (kY2Rows * (64 + kY2Chunk) + kY2Chunk * kY2Rows) *
+                       sizeof(T2);
+    ypair2_kernel<T, kY2Rows, kY2Chunk><<<dim3(static_cast<unsigned>(static_cast<long>(y.per_xcd) * kNumXcd)),
+                                         64 * kWavesPerBlock, lds, st>>>(y);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int b0 = 0; b0 < batch; b0 += 65535) {
         const int nb = std::min(65535, batch - b0);
