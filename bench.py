@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-kfft", action="store_true",
+                    help="skip the pair sum through an FFT along kappa (reported beside the direct form)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -149,7 +151,7 @@ def accuracy(torch, srm3, wl, plans, fields, sample):
     lines, ref = sample
     out = {"lines_compared": int(lines.size)}
     for name, plan in plans.items():
-        cdt = torch.complex128 if name == "fp64" else torch.complex64
+        cdt = torch.complex128 if name.startswith("fp64") else torch.complex64
         C = torch.empty((1,) + tuple(plan.coeff_shape), dtype=cdt, device="cuda")
         srm3.srm3_coefficients(plan, [int(wl.seeds()[0])], C)
         got = C.reshape(-1)[torch.as_tensor(lines, device="cuda")].to(torch.complex128).cpu().numpy()
@@ -418,6 +420,36 @@ def main():
         extra["fp64_pairsum_frac_of_fp64_peak"] = round(extra["fp64_pairsum_tflops"] / PEAK_FP64_TFLOPS, 4)
         log(f"[bench] batched fp64: {dt64 * 1e3:.2f} ms/step")
         torch.cuda.synchronize()
+
+    # ---- batched FP32 through the kappa-FFT pair sum (same field, own work count) ----
+    if not args.no_kfft:
+        plank = srm3.plan_from_workload(wl, "fp32")
+        srm3.srm3_plan_set_algorithm(plank, "kappa_fft")
+        outk = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+        for _ in range(max(1, args.warmup)):
+            srm3.srm3_generate(plank, seeds, outk)
+        torch.cuda.synchronize()
+        srm3.srm3_profile_enable(plank, True)
+        dtk = timed_steps(torch, lambda: srm3.srm3_generate(plank, seeds, outk), args.steps, 0)
+        pk = srm3.srm3_profile_read(plank)
+        srm3.srm3_profile_enable(plank, False)
+        kterms = srm3.srm3_algorithm_terms(plank)
+        ksum = pk["pairsum"][0] / max(1, pk["pairsum"][1])
+        ktf = FLOPS_PER_PAIR_TERM * kterms * B / (ksum * 1e-3) / 1e12
+        extra["kappa_fft"] = {
+            "grid_points_per_s": grid_points / dtk,
+            "ms_per_step": round(dtk * 1e3, 3),
+            "over_direct": round(dt / dtk, 3),
+            "terms_per_realization": kterms,
+            "pair_stage": {"bound": "alu", "kernels": "colfft_kernel (forward) + ypair2_kernel + colfft_kernel "
+                                                      "(inverse)", "avg_launch_ms": round(ksum, 4),
+                           "achieved": round(ktf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(ktf / PEAK_FP32_TFLOPS, 4), "flops_per_term": FLOPS_PER_PAIR_TERM},
+            "kernel_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in pk.items()},
+        }
+        plans["fp32_kappa_fft"] = plank
+        fields["fp32_kappa_fft"] = outk
+        log(f"[bench] kappa-FFT fp32: {dtk * 1e3:.2f} ms/step ({grid_points / dtk:.4g} grid points/s)")
 
     cpu = None
     if not args.no_cpu:
