@@ -923,7 +923,7 @@ struct YpairArgs {
     void *Y;            // [B][M][nca]
     const void *wh;     // [wh_rows][nca] sheared half table, zero rows after row ncw - 1
     int M, W, nca, kw0;
-    int batch, n_qtiles, n_cgroups, per_xcd;
+    int batch, n_qtiles, n_ctiles, per_xcd;
 };
 
 // Staged form of the frequency autoconvolution.  A wave owns 64 consecutive
@@ -952,16 +952,20 @@ __global__ __launch_bounds__(256) void ypair2_kernel(YpairArgs a)
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     T2 *ldsb = reinterpret_cast<T2 *>(smem_raw) + wave * (R * LW + C * R);
     T2 *ldsa = ldsb + R * LW;
+    // a block: one column tile, kWavesPerBlock consecutive q tiles (one per
+    // wave), so that its waves read the same weight rows at about the same time
     const int bid = blockIdx.x;
     const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
-    const int per_b = a.n_qtiles * a.n_cgroups;
+    const int n_qgroups = (a.n_qtiles + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per_b = n_qgroups * a.n_ctiles;
     if (work >= a.batch * per_b) return;
     const int b = work / per_b;
     const int rem = work - b * per_b;
-    const int qt = rem / a.n_cgroups;
-    const int cg = rem - qt * a.n_cgroups;
-    const int cc0 = (cg * kWavesPerBlock + wave) * 64;
-    if (cc0 >= a.nca) return;
+    const int qg = rem / a.n_ctiles;
+    const int ct = rem - qg * a.n_ctiles;
+    const int qt = qg * kWavesPerBlock + wave;
+    if (qt >= a.n_qtiles) return;
+    const int cc0 = ct * 64;
     const int W = a.W, ncw = 2 * W - 1, q0 = qt * R;
     const T2 *Zb = static_cast<const T2 *>(a.Z) + static_cast<long>(b) * a.M * ncw;
     const int kw_lo = a.kw0 + cc0;
@@ -1482,9 +1486,8 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const voi
     y.kw0 = k.kw0;
     y.batch = batch;
     y.n_qtiles = (k.M + kY2Rows - 1) / kY2Rows;
-    const int n_ctiles = (k.nca + 63) / 64;
-    y.n_cgroups = (n_ctiles + kWavesPerBlock - 1) / kWavesPerBlock;
-    const long blocks = static_cast<long>(batch) * y.n_qtiles * y.n_cgroups;
+    y.n_ctiles = (k.nca + 63) / 64;
+    const long blocks = static_cast<long>(batch) * ((y.n_qtiles + kWavesPerBlock - 1) / kWavesPerBlock) * y.n_ctiles;
     y.per_xcd = static_cast<int>((blocks + kNumXcd - 1) / kNumXcd);
     const size_t lds = static_cast<size_t>(kWavesPerBlock) * (kY2Rows * (64 + kY2Chunk) + kY2Chunk * kY2Rows) *
                        sizeof(T2);
