@@ -451,6 +451,15 @@ def main():
         fields["fp32_kappa_fft"] = outk
         log(f"[bench] kappa-FFT fp32: {dtk * 1e3:.2f} ms/step ({grid_points / dtk:.4g} grid points/s)")
 
+    # ---- the same grid with zero bicoherence: Gaussian (2nd-order) fast path ----
+    plang = srm3.srm3_plan(wl.grid_dict(), wl.spectrum(), None, "fp32")
+    outg = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+    dtg = timed_steps(torch, lambda: srm3.srm3_generate(plang, seeds, outg), args.steps, max(1, args.warmup))
+    extra["gaussian_fp32_grid_points_per_s"] = grid_points / dtg
+    extra["gaussian_fp32_ms_per_step"] = round(dtg * 1e3, 3)
+    del outg
+    log(f"[bench] zero bicoherence (2nd-order) fp32: {dtg * 1e3:.3f} ms/step")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")

@@ -70,7 +70,7 @@ srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_
 AmpRef plan_amp(srm3_plan_t p)
 {
     return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
-                  p->dk * p->dw, p->cap};
+                  p->dk * p->dw, p->cap, p->gaussian ? 0 : 1};
 }
 
 double max_sigma(double max_sig, double cap, double scale)
@@ -188,6 +188,7 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, ws, st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
+    if (p->gaussian) return SRM3_OK;   // zero bicoherence: the pair sums are not used
     if ((s = event_pair(p, 1, st, true))) return s;
     if (p->algo == SRM3_ALGO_KAPPA_FFT) {
         const KfftWorkspace kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
@@ -346,7 +347,8 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     p->dw = grid->d_omega;
     p->cap = bs.cap;
     p->max_sig = max_sig;
-    p->pair_terms = pair_terms;
+    p->gaussian = bs.kind == SRM3_BISPEC_NONE;
+    p->pair_terms = p->gaussian ? 0.0 : pair_terms;
     Geometry &g = p->g;
     g.nk = nk;
     g.nw = nw;

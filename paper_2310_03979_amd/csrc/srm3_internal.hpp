@@ -81,6 +81,7 @@ struct AmpRef {
     const double *const *S_b;
     double dkdw;
     double cap;
+    int pairs = 1;   // 0: zero bicoherence, the pair sums are not computed (Gaussian field)
 };
 
 // Kernel launchers (stream-ordered, return the launch status).
@@ -167,6 +168,7 @@ struct srm3_plan_s {
     int device = 0;
     srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
     int ws_batch = 0;
+    bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)
     // pair-sum algorithm; the kappa-FFT form keeps its tables and workspace here
     int algo = SRM3_ALGO_DIRECT;
     srm3::KfftGeom kg{};

@@ -665,6 +665,7 @@ struct AmpArgs {
     const double *const *S_b; // per realization spectrum, or null (plan's)
     double dkdw;
     double cap;
+    int pairs;                // 0: no pair sums (zero bicoherence)
 };
 
 struct TfftArgs {
@@ -690,9 +691,12 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     using T2 = typename vec<T>::v2;
     const long li = static_cast<long>(kk) * g.nc + c;
     const long bi = static_cast<long>(b) * g.nk * g.nc + li;
-    T2 t = tsum[bi];
+    T2 t;
+    t.x = T(0);
+    t.y = T(0);
+    if (amp.pairs) t = tsum[bi];
     const int kw = c - (g.nw - 1);
-    if (((kk | kw) & 1) == 0) {
+    if (amp.pairs && ((kk | kw) & 1) == 0) {
         const int hw = kw / 2;
         if (hw > -g.W && hw < g.W) {
             // half of the self pair {(kk/2, kw/2), (kk/2, kw/2)}
@@ -1307,7 +1311,7 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     a.cin = cin;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap};
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs};
     a.wtab = wtab;
     a.tw = tw;
     a.gout = ws.g;
@@ -1332,7 +1336,7 @@ static hipError_t assemble_t(const Geometry &g, const AmpRef &amp, const void *w
     a.g = g;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap};
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs};
     a.wtab = wtab;
     const long per = static_cast<long>(g.nk) * g.nc;
     assemble_kernel<T><<<dim3(static_cast<unsigned>((per + 255) / 256), batch), 256, 0, st>>>(

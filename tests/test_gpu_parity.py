@@ -254,3 +254,24 @@ def test_c2_full_size_sampled_lines(lib, oracle_mod):
         ref = P.coefficients(seed=int(seeds[r]), lines=lines)
         got = C[r].reshape(-1)[torch.as_tensor(lines, device="cuda")].cpu().numpy()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL["fp32"], r
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_bicoherence_is_the_gaussian_srm(lib, oracle_mod, precision):
+    """With no bicoherence the plan skips the pair sum (2nd-order SRM); the field
+    equals the oracle's with b = 0 and no pair terms are reported."""
+    torch = _torch()
+    for wl in (inp.C0, inp.small_grid(17, 40, batch=2, seed_base=55)):
+        print(f"[gpu] gaussian {wl.name} {precision}", flush=True)
+        plan = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), None, precision)
+        assert lib.srm3_pair_terms(plan) == 0
+        seeds = wl.seeds()
+        out = torch.empty((len(seeds), wl.n_x, wl.n_t), dtype=plan.real_dtype, device="cuda")
+        lib.srm3_generate(plan, seeds, out)
+        torch.cuda.synchronize()
+        u = out.double().cpu().numpy()
+        P = oracle_mod.Problem(wl.n_kappa, wl.n_omega, 1, wl.d_kappa, wl.d_omega, wl.spectrum(),
+                               np.zeros((1, 1)), oracle_mod.biphase(1, None), 0.0)
+        for r, s in enumerate(seeds):
+            ref = oracle_mod.field(P.coefficients(seed=int(s)), wl.n_x, wl.n_t)
+            assert _rel_l2(u[r], ref) <= TOL[precision]
