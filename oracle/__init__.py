@@ -12,6 +12,8 @@ over independent outputs).  This file only builds and marshals:
 * ``line_terms``      -- raw bicoherence sum, rescale factor, Sigma, pair count
 * ``coefficients``    -- C_k by explicit enumeration of the pair set P(k)
 * ``field`` / ``field_points`` / ``field_nested`` -- direct cosine sums
+* ``ProcessProblem``, ``process_phases``, ``process_biphase``,
+  ``process_field`` -- the 1-D stochastic process u(t) (Section 3)
 
 Every function cites the part of the paper it follows in the C source.
 """
@@ -53,6 +55,11 @@ class _Problem(ctypes.Structure):
                 ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double)]
 
 
+class _Process(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("W", ctypes.c_int), ("dw", ctypes.c_double),
+                ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -72,6 +79,13 @@ def lib():
         L.oracle_field_nested.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
         L.oracle_field_points.argtypes = [ctypes.c_int] * 4 + [_dp, ctypes.c_long, _ip, _ip, _dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_process_phases.argtypes = [ctypes.c_int, ctypes.c_uint64, _u32p]
+        L.oracle_process_biphase.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _u32p]
+        L.oracle_process_terms.argtypes = [ctypes.POINTER(_Process), ctypes.c_int, _dp, _dp, _dp, _lp]
+        L.oracle_process_terms.restype = ctypes.c_int
+        L.oracle_process_coefficients.argtypes = [ctypes.POINTER(_Process), _u32p, _dp]
+        L.oracle_process_coefficients.restype = ctypes.c_int
+        L.oracle_process_field.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
         _lib = L
     return _lib
 
@@ -199,3 +213,59 @@ def field_points(C: np.ndarray, n_x: int, n_t: int, mx, mt) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+# ---- the 1-D stochastic process u(t) (Section 3) ----
+
+def process_phases(n: int, seed: int) -> np.ndarray:
+    U = np.zeros(n, dtype=np.uint32)
+    lib().oracle_process_phases(n, ctypes.c_uint64(int(seed)), _ptr(U, _u32p))
+    return U
+
+
+def process_biphase(support_w: int, seed: Optional[int]) -> np.ndarray:
+    """Biphase over 0 <= i, j < W; ``seed=None`` gives beta == 0."""
+    B = np.zeros((support_w, support_w), dtype=np.uint32)
+    lib().oracle_process_biphase(support_w, 1 if seed is None else 0,
+                                 ctypes.c_uint64(0 if seed is None else int(seed)), _ptr(B, _u32p))
+    return B
+
+
+class ProcessProblem:
+    """Inputs of one process simulation: n one-sided frequencies, support W,
+    b2 and beta over 0 <= i, j < W."""
+
+    def __init__(self, n, support_w, d_omega, S, b2, beta, cap):
+        self.S = np.ascontiguousarray(S, dtype=np.float64)
+        self.b2 = np.ascontiguousarray(b2, dtype=np.float64)
+        self.beta = np.ascontiguousarray(beta, dtype=np.uint32)
+        assert self.S.shape == (n,) and 1 <= support_w <= n
+        assert self.b2.shape == (support_w, support_w) and self.beta.shape == (support_w, support_w)
+        self.n, self.W, self.d_omega, self.cap = n, support_w, d_omega, cap
+        self._c = _Process(n, support_w, d_omega, _ptr(self.S, _dp), _ptr(self.b2, _dp),
+                           _ptr(self.beta, _u32p), cap)
+
+    def terms(self, k: int):
+        sr, rho, sig = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        npairs = ctypes.c_long()
+        st = lib().oracle_process_terms(ctypes.byref(self._c), k, ctypes.byref(sr), ctypes.byref(rho),
+                                        ctypes.byref(sig), ctypes.byref(npairs))
+        return dict(status=st, sigma_raw=sr.value, rho=rho.value, sigma=sig.value, npairs=npairs.value)
+
+    def coefficients(self, seed: Optional[int] = None, U: Optional[np.ndarray] = None) -> np.ndarray:
+        if U is None:
+            U = process_phases(self.n, seed)
+        U = np.ascontiguousarray(U, dtype=np.uint32)
+        out = np.zeros((self.n, 2), dtype=np.float64)
+        st = lib().oracle_process_coefficients(ctypes.byref(self._c), _ptr(U, _u32p), _ptr(out, _dp))
+        if st != 0:
+            raise ValueError(f"oracle: pure spectrum not positive (status {st})")
+        return out[:, 0] + 1j * out[:, 1]
+
+
+def process_field(C: np.ndarray, n_t: int) -> np.ndarray:
+    """u(t_m) = sum_k Re[C_k exp(2 pi i k m / n_t)], direct cosine sum, [n_t]."""
+    buf = _cbuf(C)
+    u = np.zeros(n_t, dtype=np.float64)
+    lib().oracle_process_field(C.size, n_t, _ptr(buf, _dp), _ptr(u, _dp))
+    return u

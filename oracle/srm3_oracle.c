@@ -272,6 +272,110 @@ void oracle_field_nested(int nk, int nw, int nx, int nt, const double *C, double
     free(G); free(ct); free(st); free(cx); free(sx);
 }
 
+/* ------------------------------------------------------------------------ */
+/* 3rd-order SRM for a 1-D stochastic process u(t) (Section 3, the form of   */
+/* Shields and Kim), read as:                                                */
+/*  - Frequencies w_k = k dw, 0 <= k < N (one-sided).                        */
+/*  - Pairs: i + j = k with i >= j >= 0 and i, j < W, each unordered pair    */
+/*    once, the self pair i = j included (the printed index bounds are       */
+/*    garbled; the process has no difference interactions).                 */
+/*  - Phase of frequency k: Philox word 0, key = seed, counter (0, k, 0, 0); */
+/*    biphase beta(i, j): key = beta seed, counter (max, min, 1, 0).         */
+/*  - rho_k, b_p^2 = rho_k b2_raw, Sigma_k, pure part sqrt(1 - Sigma_k) as   */
+/*    for the wave (the pure-spectrum equation with b_p^2).                  */
+/*  - u(t_m) = 2 [ sum_k sqrt(S_p,k dw) cos(w_k t_m + phi_k)                 */
+/*             + sum_k sum_{i+j=k} sqrt(S_k dw) b_p cos(w_k t_m + phi_i      */
+/*               + phi_j + beta) ],  t_m = m dt, dw dt = 2 pi / NT.          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n, W;
+    double dw;
+    const double *S;        /* [n] one-sided power spectrum */
+    const double *b2;       /* [W][W] raw squared bicoherence, i, j >= 0 */
+    const uint32_t *beta;   /* [W][W] fixed-point biphase */
+    double cap;
+} oracle_process;
+
+void oracle_process_phases(int n, uint64_t seed, uint32_t *U)
+{
+    for (int k = 0; k < n; ++k) U[k] = philox_word0(0u, (uint32_t)k, 0u, seed);
+}
+
+void oracle_process_biphase(int W, int mode, uint64_t beta_seed, uint32_t *beta)
+{
+    for (int i = 0; i < W; ++i)
+        for (int j = 0; j < W; ++j) {
+            const int hi = i >= j ? i : j, lo = i >= j ? j : i;
+            beta[(size_t)i * W + j] = mode == 0 ? philox_word0((uint32_t)hi, (uint32_t)lo, 1u, beta_seed) : 0u;
+        }
+}
+
+/* Raw bicoherence sum over the pairs of frequency k, cap factor, Sigma and
+ * pair count; returns 2 if Sigma_k >= 1. */
+int oracle_process_terms(const oracle_process *p, int k, double *sigma_raw, double *rho, double *sigma,
+                         long *npairs)
+{
+    double sr = 0.0;
+    long cnt = 0;
+    for (int j = 0; 2 * j <= k; ++j) {
+        const int i = k - j;
+        if (i >= p->W) continue;
+        sr += p->b2[(size_t)i * p->W + j];
+        ++cnt;
+    }
+    double r = 1.0;
+    if (p->cap > 0.0 && sr > p->cap) r = p->cap / sr;
+    if (sigma_raw) *sigma_raw = sr;
+    if (rho) *rho = r;
+    if (sigma) *sigma = r * sr;
+    if (npairs) *npairs = cnt;
+    return (r * sr >= 1.0) ? 2 : 0;
+}
+
+/* Coefficients C_k = 2 sqrt(S_k dw) [sqrt(1 - Sigma_k) e^{i phi_k} + sum b_p
+ * e^{i(phi_i + phi_j + beta)}], interleaved re/im, [n]. */
+int oracle_process_coefficients(const oracle_process *p, const uint32_t *U, double *C)
+{
+    int status = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(max : status)
+    for (int k = 0; k < p->n; ++k) {
+        double rho, sigma;
+        const int st = oracle_process_terms(p, k, NULL, &rho, &sigma, NULL);
+        if (st) { status = st; C[2 * k] = NAN; C[2 * k + 1] = NAN; continue; }
+        const double amp = 2.0 * sqrt(p->S[k] * p->dw);
+        const double phik = TWO_PI * (double)U[k] / 4294967296.0;
+        double re = sqrt(1.0 - sigma) * cos(phik);
+        double im = sqrt(1.0 - sigma) * sin(phik);
+        for (int j = 0; 2 * j <= k; ++j) {
+            const int i = k - j;
+            if (i >= p->W) continue;
+            const size_t e = (size_t)i * p->W + j;
+            const double bp = sqrt(rho * p->b2[e]);
+            const uint32_t ang = U[i] + U[j] + p->beta[e];     /* exact mod 2^32 */
+            const double th = TWO_PI * (double)ang / 4294967296.0;
+            re += bp * cos(th);
+            im += bp * sin(th);
+        }
+        C[2 * k] = amp * re;
+        C[2 * k + 1] = amp * im;
+    }
+    return status;
+}
+
+/* u(t_m) = sum_k Re[C_k exp(2 pi i k m / nt)], direct cosine sum, [nt]. */
+void oracle_process_field(int n, int nt, const double *C, double *u)
+{
+#pragma omp parallel for schedule(static)
+    for (int m = 0; m < nt; ++m) {
+        double acc = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double th = TWO_PI * (double)posmod((long long)k * m, nt) / (double)nt;
+            acc += C[2 * k] * cos(th) - C[2 * k + 1] * sin(th);
+        }
+        u[m] = acc;
+    }
+}
+
 /* Threads the OpenMP runtime will use (for reporting). */
 int oracle_num_threads(void)
 {

@@ -236,3 +236,98 @@ def random_coefficients(n_kappa: int, n_omega: int, batch: int, seed: int) -> np
     rng = np.random.default_rng(seed)
     shape = (batch, n_kappa, 2 * n_omega - 1)
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex128)
+
+
+# --------------------------------------------------------------------------
+# The 1-D stochastic process u(t) (time only).  One-sided frequencies
+# w_k = k dw, 0 <= k < n; the Kaimal frequency spectrum of the wave recipe
+# (S(0) := 0) and the same exponential separable bicoherence over 0 <= i < W.
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class ProcessWorkload:
+    name: str
+    n: int
+    d_omega: float
+    n_t: int
+    support_w: int
+    batch: int
+    omega_u: float
+    cap: float = 0.9
+    beta_seed: int = BETA_SEED_DEFAULT
+    b2_scale: float = 0.3
+    U: float = 30.0
+    u_star: float = 1.5
+    z: float = 50.0
+    seed_base: int = 0
+
+    @property
+    def grid_points(self) -> int:
+        return self.n_t
+
+    def seeds(self, batch: Optional[int] = None) -> np.ndarray:
+        b = self.batch if batch is None else batch
+        return np.arange(b, dtype=np.uint64) + np.uint64(self.seed_base)
+
+    def spectrum(self) -> np.ndarray:
+        return kaimal_process(self.n, self.d_omega, U=self.U, u_star=self.u_star, z=self.z)
+
+    def g2(self) -> np.ndarray:
+        w = np.arange(self.support_w, dtype=np.float64) * self.d_omega
+        return math.sqrt(self.b2_scale) * np.exp(-w / (0.5 * self.omega_u))
+
+    def b2_dense(self) -> np.ndarray:
+        g = self.g2()
+        return np.outer(g, g)
+
+    def grid_dict(self) -> dict:
+        return dict(n_omega=self.n, d_omega=self.d_omega, n_t=self.n_t)
+
+    def with_(self, **kw) -> "ProcessWorkload":
+        return dataclasses.replace(self, **kw)
+
+
+def kaimal_process(n: int, d_omega: float, U: float = 30.0, u_star: float = 1.5,
+                   z: float = 50.0) -> np.ndarray:
+    """One-sided S_w(w_k), k = 0 .. n-1, with S(0) := 0."""
+    w = np.arange(n, dtype=np.float64) * d_omega
+    f = w / (2.0 * math.pi)
+    S = 200.0 * u_star ** 2 * (z / U) / (1.0 + 50.0 * f * z / U) ** (5.0 / 3.0)
+    S[0] = 0.0
+    return np.ascontiguousarray(S)
+
+
+def small_process(n: int, support_w: Optional[int] = None, batch: int = 1,
+                  n_t: Optional[int] = None, seed_base: int = 0, **kw) -> ProcessWorkload:
+    w = n if support_w is None else support_w
+    return ProcessWorkload(f"process_{n}_w{w}", n, 4 * math.pi / n,
+                           next_pow2(2 * n) if n_t is None else n_t, w, batch, 4 * math.pi,
+                           seed_base=seed_base, **kw)
+
+
+def _p1() -> ProcessWorkload:
+    n = 4096
+    return ProcessWorkload("p1_4096_b4096", n, 4 * math.pi / n, 2 * n, n, 4096, 4 * math.pi,
+                           seed_base=5000)
+
+
+P1 = _p1()
+
+
+def random_process_spectrum(n: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.uniform(0.1, 2.0, size=n))
+
+
+def random_b2_quadrant(support_w: int, seed: int, scale: float = 0.3) -> np.ndarray:
+    """Symmetric raw squared bicoherence over 0 <= i, j < W."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(0.0, scale, size=(support_w, support_w))
+    return np.ascontiguousarray(0.5 * (A + A.T))
+
+
+def random_beta_quadrant(support_w: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    A = rng.integers(0, 2 ** 32, size=(support_w, support_w), dtype=np.uint64)
+    A = np.triu(A) + np.triu(A, 1).T
+    return np.ascontiguousarray(A.astype(np.uint32))
