@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3", "c4"])
+    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3", "c4", "p1"])
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests per arrival rate in the serving workload (c4)")
     ap.add_argument("--batch", type=int, default=None)
@@ -236,6 +236,20 @@ def bench_uneven(args, torch, srm3):
         rec_plain = dict(plain_grid_points_per_s=points / dtp, plain_ms_per_batch=round(dtp * 1e3, 2),
                          batched_over_plain=round(dtp / dt, 3))
         log(f"[bench] plain: {dtp * 1e3:.1f} ms per batch")
+    # the same batch with every plan on the pair sum through a DFT along kappa
+    rec_k = None
+    if not args.no_kfft:
+        kplans = {}
+        for key, (wl, _) in plans.items():
+            kp = srm3.plan_from_workload(wl, "fp32")
+            srm3.srm3_plan_set_algorithm(kp, "kappa_fft")
+            kplans[key] = kp
+        kreqs = [dict(r, plan=kplans[(wl.n_kappa, wl.n_omega)]) for r, (wl, _, _) in zip(reqs, reqs_in)]
+        kbatch = srm3.Batch(kreqs, flags=srm3.SRM3_BATCH_GRAPH)
+        dtk = timed_steps(torch, lambda: kbatch.run(seeds), args.steps, max(1, args.warmup))
+        rec_k = {"grid_points_per_s": points / dtk, "ms_per_step": round(dtk * 1e3, 3),
+                 "over_direct_batch": round(dt / dtk, 3)}
+        log(f"[bench] kappa-DFT plans, graph: {dtk * 1e3:.1f} ms/step")
     rec = {
         "metric": "space-time grid points/sec, batched FP32 vs plain; p50/p99 request latency",
         "value": points / dt, "unit": "grid points/s", "n_gpus": 1, "steps": args.steps,
@@ -253,6 +267,8 @@ def bench_uneven(args, torch, srm3):
     }
     if rec_plain:
         rec.update(rec_plain)
+    if rec_k:
+        rec["kappa_fft"] = rec_k
     print(json.dumps(rec))
 
 
@@ -308,6 +324,29 @@ def bench_serve(args, torch, srm3):
     arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
     p9 = serve.replay(plain, reqs, arr, progress=prog)
     plain.destroy()
+    # the same requests with plans that use the pair sum through a DFT along kappa
+    kplans = {}
+    for g in grids:
+        wl = plans[g][0]
+        kp = srm3.plan_from_workload(wl, "fp32")
+        srm3.srm3_plan_set_algorithm(kp, "kappa_fft")
+        kplans[g] = kp
+    kreqs = [dict(r, plan=kplans[r["grid"]]) for r in reqs]
+    ksrv = srm3.Server("fp32", max_active=32, hbm_budget=budget)
+    serve.replay(ksrv, kreqs[:2], [0.0, 0.0])
+    ksat = serve.replay(ksrv, kreqs, [0.0] * n, progress=prog)
+    kthr = n / ksat["makespan"]
+    kout = {"saturated": dict(makespan_s=ksat["makespan"], requests_per_s=kthr,
+                              grid_points_per_s=points / ksat["makespan"])}
+    for f in (0.3, 0.6, 0.9):
+        arr = serve.poisson_arrivals(n, f * kthr, seed=42)
+        r = serve.replay(ksrv, kreqs, arr, progress=prog)
+        kout[f"rate_{f}"] = dict(rate_req_per_s=f * kthr, p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"],
+                                 makespan_s=r["makespan"])
+    ksrv.destroy()
+    out["kappa_fft"] = kout
+    log(f"[bench] kappa-DFT plans: saturated {ksat['makespan']:.3f} s ({kthr:.2f} req/s); rate 0.9 p50 "
+        f"{kout['rate_0.9']['p50_s']:.4f} s p99 {kout['rate_0.9']['p99_s']:.4f} s")
     out["plain_one_at_a_time"] = {
         "saturated_makespan_s": psat["makespan"], "saturated_grid_points_per_s": points / psat["makespan"],
         "rate_0.9_p50_s": p9["p50"], "rate_0.9_p99_s": p9["p99"]}
@@ -324,6 +363,92 @@ def bench_serve(args, torch, srm3):
                                f"shortest remaining work first)"},
         "serving": out, "roofline": None, "cpu_baseline": None,
     }
+    print(json.dumps(rec))
+
+
+def bench_process(args, torch, srm3):
+    """The 1-D process u(t) (Section 3): 4096 one-sided frequencies, full
+    bicoherence support, 8192 time points, 4096 realizations per step; the
+    pair sum is the frequency autoconvolution with the realizations as rows."""
+    wl = inp.P1
+    B = args.batch or wl.batch
+    seeds = wl.seeds(B)
+    points = B * wl.n_t
+    log(f"[bench] workload {wl.name} batch {B} steps {args.steps} warmup {args.warmup}")
+    plan = srm3.process_plan_from_workload(wl, "fp32")
+    out = torch.empty((B, 1, wl.n_t), dtype=torch.float32, device="cuda")
+    terms = srm3.srm3_algorithm_terms(plan)
+    for _ in range(args.warmup):
+        srm3.srm3_generate(plan, seeds, out)
+    torch.cuda.synchronize()
+    srm3.srm3_profile_enable(plan, True)
+    dt = timed_steps(torch, lambda: srm3.srm3_generate(plan, seeds, out), args.steps, 0)
+    prof = srm3.srm3_profile_read(plan)
+    srm3.srm3_profile_enable(plan, False)
+    ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
+    tf = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+    log(f"[bench] process fp32: {dt * 1e3:.3f} ms/step, kernels {prof}")
+    extra = {}
+    out1 = torch.empty((1, 1, wl.n_t), dtype=torch.float32, device="cuda")
+
+    def plain():
+        for sd in seeds:
+            srm3.srm3_generate(plan, [int(sd)], out1)
+    dtp = timed_steps(torch, plain, 1, 1)
+    extra["plain_fp32_samples_per_s"] = points / dtp
+    extra["batched_over_plain"] = round(dtp / dt, 3)
+    pland = srm3.process_plan_from_workload(wl, "fp32")
+    srm3.srm3_plan_set_algorithm(pland, "direct")
+    dtd = timed_steps(torch, lambda: srm3.srm3_generate(pland, seeds, out), args.steps, 1)
+    extra["direct_pair_sum_fp32_samples_per_s"] = points / dtd
+    extra["autoconvolution_over_direct"] = round(dtd / dt, 3)
+    plan64 = srm3.process_plan_from_workload(wl, "fp64")
+    out64 = torch.empty((B, 1, wl.n_t), dtype=torch.float64, device="cuda")
+    dt64 = timed_steps(torch, lambda: srm3.srm3_generate(plan64, seeds, out64), args.steps, 1)
+    extra["fp64_samples_per_s"] = points / dt64
+    log(f"[bench] plain {dtp * 1e3:.1f} ms, direct {dtd * 1e3:.2f} ms, fp64 {dt64 * 1e3:.2f} ms")
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        P = oracle.ProcessProblem(wl.n, wl.support_w, wl.d_omega, wl.spectrum(), wl.b2_dense(),
+                                  oracle.process_biphase(wl.support_w, wl.beta_seed), wl.cap)
+        t0 = time.perf_counter()
+        done, refs = 0, []
+        while time.perf_counter() - t0 < args.cpu_seconds and done < B:
+            Cr = P.coefficients(seed=int(seeds[done]))
+            oracle.process_field(Cr, wl.n_t)
+            refs.append(Cr)
+            done += 1
+        tcpu = time.perf_counter() - t0
+        cpu = {"value": done * wl.n_t / tcpu, "unit": "time samples/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"FP64 oracle: coefficients and direct cosine-sum field of "
+                                           f"realizations 0..{done - 1} of {wl.name} ({tcpu:.1f} s)"}
+        C = torch.empty((len(refs), 1, 2 * wl.n - 1), dtype=torch.complex64, device="cuda")
+        srm3.srm3_coefficients(plan, seeds[:len(refs)], C)
+        got = C[:, 0, wl.n - 1:].to(torch.complex128).cpu().numpy()
+        ref = np.stack(refs)
+        x = out.double() - out.double().mean()
+        extra["accuracy"] = {"realizations_compared": len(refs),
+                             "fp32_rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                             "fp32_skewness": float((x.pow(3).mean() / x.pow(2).mean().pow(1.5)).item())}
+        log(f"[bench] oracle {cpu['value']:.4g} samples/s; accuracy {extra['accuracy']}")
+    rec = {
+        "metric": "time samples/sec of the 1-D 3rd-order SRM process, batched FP32",
+        "value": points / dt, "unit": "time samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"1-D process: {wl.n} one-sided frequencies, support {wl.support_w}, "
+                               f"{wl.n_t} time points, {B} realizations per step (Kaimal spectrum, "
+                               f"separable exponential bicoherence capped at {wl.cap}, seeded biphase)"},
+        "roofline": {"bound": "alu", "kernel": "ypair2_kernel<float,8,32> (+ two length-1 column copies)",
+                     "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "pair_terms_per_launch": terms * B, "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
+                     "avg_launch_ms": round(ps_ms, 4), "pair_terms_per_s": terms * B / (ps_ms * 1e-3)},
+        "cpu_baseline": cpu,
+        "kernel_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()},
+    }
+    rec.update(extra)
     print(json.dumps(rec))
 
 
@@ -348,6 +473,9 @@ def main():
         return
     if args.workload == "c4":
         bench_serve(args, torch, srm3)
+        return
+    if args.workload == "p1":
+        bench_process(args, torch, srm3)
         return
     wl = inp.WORKLOADS[args.workload]
     B = args.batch or wl.batch

@@ -146,8 +146,8 @@ srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms);
  * 64 frequency columns x R kappa rows); the kernel is instantiated per R. */
 srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
 
-/* Pair-sum algorithm of a plan (used by srm3_generate and srm3_coefficients;
- * batches and the server always use the direct form).
+/* Pair-sum algorithm of a plan (used by every entry point that takes the plan:
+ * generation, coefficients, batches, the server).
  *   SRM3_ALGO_DIRECT     enumerates the unordered pairs of every line (the
  *                        coefficient sum of Section 4.1 / 4.3 as written).
  *   SRM3_ALGO_KAPPA_FFT  the same sum, reorganised: the weights depend on the
@@ -180,8 +180,37 @@ typedef struct {
 srm3_status srm3_profile_enable(srm3_plan_t plan, int32_t enable); /* clears the record */
 srm3_status srm3_profile_read(srm3_plan_t plan, srm3_profile *out); /* waits for the events */
 
+/* ---- the 1-D stochastic process u(t) (Section 3, the 3rd-order SRM of a
+ * process in the form of Shields and Kim) ----
+ * Frequencies w_k = k d_omega, 0 <= k < n_omega (one-sided); pairs {i, j} with
+ * i + j = k, i >= j >= 0, both < support_w, each once (self pair included);
+ *   C_k = 2 sqrt(S_k dw) [ sqrt(1 - Sigma_k) e^{i phi_k}
+ *                          + sum_{i+j=k} b_p e^{i(phi_i + phi_j + beta_p)} ],
+ *   u(m dt) = Re sum_k C_k exp(2 pi i k m / n_t),  dw dt = 2 pi / n_t.
+ * Cap, Sigma_k, the pure amplitude and the phase/biphase counters are those of
+ * the wave with k_kappa = 0 and k_omega = k.  A process plan is the wave's plan
+ * on one kappa line (d_kappa = 1, n_x = 1) with no spectrum at negative
+ * frequencies and no pair with a negative partner, and every plan entry point
+ * takes it: srm3_generate writes [b][n_t] (n_x = 1), srm3_coefficients
+ * [b][2 n_omega - 1] (column n_omega - 1 + k; the negative columns are zero).
+ * Its pair sum defaults to the frequency autoconvolution of
+ * SRM3_ALGO_KAPPA_FFT (a DFT of length 1 along kappa), with the realizations of
+ * a call as the rows of one launch; SRM3_ALGO_DIRECT also works. */
+typedef struct {
+    int32_t n_omega;   /* frequencies, >= 1 */
+    double d_omega;    /* > 0 */
+    int32_t n_t;       /* time points: power of two, 2 n_omega - 1 <= n_t <= 16384 (8192 for FP64) */
+} srm3_process_grid;
+
+/* S: host FP64 [n_omega] one-sided, finite, >= 0.  bispectrum (may be NULL)
+ * as for srm3_plan but over 0 <= i, j < support_w only: g2 [W], b2 [W][W],
+ * beta table [W][W] (symmetric).  Errors as for srm3_plan. */
+srm3_status srm3_process_plan(const srm3_process_grid *grid, const double *S, const srm3_bispectrum *bispectrum,
+                              int32_t precision, void *hip_stream, srm3_plan_t *out_plan);
+
 /* Replace the plan's spectrum (same grid and bicoherence table): host FP64
- * [n_kappa][2 n_omega - 1], validated like srm3_plan; synchronises the stream. */
+ * [n_kappa][2 n_omega - 1] (a process plan: [n_omega] one-sided), validated
+ * like srm3_plan; synchronises the stream. */
 srm3_status srm3_set_spectrum(srm3_plan_t plan, const srm3_spectrum *spectrum, void *hip_stream);
 
 /* Parameters of the wind-field spectrum of Section 5 (workload normalisation):
@@ -209,8 +238,9 @@ void srm3_destroy(srm3_plan_t plan);
  * spectrum) with its own seed, bicoherence scale and optionally its own
  * spectrum.  With b2_scale = c, b^2_raw -> c b^2_raw for this realization (the
  * per-line cap is applied after scaling).  S_dev (device FP64, may be NULL =
- * the plan's spectrum) must hold finite values >= 0 and stay valid while the
- * batch exists.  out_dev: [n_x][n_t] in the plan's precision. */
+ * the plan's spectrum) must hold finite values >= 0 in the line layout (a
+ * process plan: [2 n_omega - 1], zero at negative frequencies) and stay valid
+ * while the batch exists.  out_dev: [n_x][n_t] in the plan's precision. */
 typedef struct {
     srm3_plan_t plan;
     uint64_t seed;
@@ -230,9 +260,12 @@ enum {
 /* Prepare a batch of n requests sharing one precision (plans may differ).
  * Allocates one workspace slice per request and builds the work list: every
  * (request, row block, column group) item, ordered by request cost and cut
- * into eight queues, one per XCD.  Host arrays are copied; plans must
- * outlive the batch.  Fails with SRM3_E_PURE_NEGATIVE if a scaled request
- * would make some Sigma_k >= 1. */
+ * into eight queues, one per XCD.  Requests whose plan uses
+ * SRM3_ALGO_KAPPA_FFT run that pair sum per grid (all their realizations at
+ * once) instead; plans with zero bicoherence have no pair stage.  The plan's
+ * algorithm is read here: set it before creating the batch.  Host arrays are
+ * copied; plans must outlive the batch.  Fails with SRM3_E_PURE_NEGATIVE if a
+ * scaled request would make some Sigma_k >= 1. */
 srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags, void *hip_stream,
                               srm3_batch_t *out);
 /* Run the batch: phases of every request, one persistent pair-sum launch over
@@ -265,9 +298,11 @@ srm3_status srm3_generate_uneven(const srm3_request *reqs, int32_t n, void *hip_
  * round-robin; enough to fill the GPU twice and at least step_pair_terms pair
  * terms) in one persistent launch,
  * then the transforms of the requests whose work has all been issued.  A
- * request admitted between steps joins the next step, sharing the GPU with
- * the requests already running.  A request's result does not depend on what
- * it was batched with. */
+ * request whose plan uses SRM3_ALGO_KAPPA_FFT runs its pair sum (the DFT form,
+ * workspace from the arena) at admission within the step; a plan with zero
+ * bicoherence has no pair stage.  A request admitted between steps joins the
+ * next step, sharing the GPU with the requests already running.  A request's
+ * result does not depend on what it was batched with. */
 typedef struct srm3_server_s *srm3_server_t;
 
 enum {
@@ -292,8 +327,9 @@ typedef struct {
 srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, srm3_server_t *out);
 /* Queue a request.  If `spectrum` is given, the request's spectrum is
  * evaluated on the device at admission into its own arena space (req->S_dev
- * must then be NULL).  out_dev must stay valid until the ticket completes.
- * SRM3_E_NOMEM if the request could never fit the arena. */
+ * must then be NULL; SRM3_E_UNSUPPORTED for a process plan).  out_dev must
+ * stay valid until the ticket completes.  SRM3_E_NOMEM if the request could
+ * never fit the arena. */
 srm3_status srm3_server_submit(srm3_server_t srv, const srm3_request *req,
                                const srm3_kaimal_davenport *spectrum, int64_t *ticket);
 /* One scheduling iteration (non-blocking: does nothing while two steps are in flight). */

@@ -393,15 +393,96 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     return SRM3_OK;
 }
 
+srm3_status srm3_process_plan(const srm3_process_grid *grid, const double *S, const srm3_bispectrum *bispectrum,
+                              int32_t precision, void *hip_stream, srm3_plan_t *out_plan)
+{
+    g_err[0] = 0;
+    if (!out_plan) return fail(SRM3_E_INVALID, "out_plan is NULL");
+    *out_plan = nullptr;
+    if (!grid || !S) return fail(SRM3_E_INVALID, "grid/S is NULL");
+    const int n = grid->n_omega;
+    if (n < 1) return fail(SRM3_E_INVALID, "n_omega=%d must be >= 1", n);
+    // the wave with one kappa line (d_kappa = 1 leaves the amplitude 2 sqrt(S dw)),
+    // no spectrum at negative frequencies and no pair with a negative partner
+    srm3_grid wg{};
+    wg.n_kappa = 1;
+    wg.n_omega = n;
+    wg.d_kappa = 1.0;
+    wg.d_omega = grid->d_omega;
+    wg.n_x = 1;
+    wg.n_t = grid->n_t;
+    std::vector<double> Sw(2 * static_cast<size_t>(n) - 1, 0.0);
+    for (int k = 0; k < n; ++k) Sw[n - 1 + k] = S[k];
+    const srm3_spectrum spec{Sw.data()};
+    srm3_bispectrum wb{};
+    std::vector<double> g2w, b2w;
+    std::vector<uint32_t> betaw;
+    long long process_pairs = 0;
+    if (bispectrum && bispectrum->kind != SRM3_BISPEC_NONE) {
+        const srm3_bispectrum &q = *bispectrum;
+        const int W = q.support_w;
+        if (W < 1 || W > n) return fail(SRM3_E_INVALID, "support_w=%d must be in [1, n_omega=%d]", W, n);
+        const size_t nw2 = 2 * static_cast<size_t>(W) - 1;
+        wb = q;
+        if (q.kind == SRM3_BISPEC_SEPARABLE) {
+            if (!q.g2) return fail(SRM3_E_INVALID, "g2 is NULL");
+            g2w.assign(nw2, 0.0);
+            for (int i = 0; i < W; ++i) g2w[W - 1 + i] = q.g2[i];
+            wb.g2 = g2w.data();
+        } else if (q.kind == SRM3_BISPEC_DENSE) {
+            if (!q.b2) return fail(SRM3_E_INVALID, "b2 is NULL");
+            b2w.assign(nw2 * nw2, 0.0);
+            for (int i = 0; i < W; ++i)
+                for (int j = 0; j < W; ++j) b2w[(W - 1 + i) * nw2 + (W - 1 + j)] = q.b2[static_cast<size_t>(i) * W + j];
+            wb.b2 = b2w.data();
+        }
+        if (q.beta_mode == SRM3_BETA_TABLE && q.beta) {
+            betaw.assign(nw2 * nw2, 0u);
+            for (int i = 0; i < W; ++i)
+                for (int j = 0; j < W; ++j)
+                    betaw[(W - 1 + i) * nw2 + (W - 1 + j)] = q.beta[static_cast<size_t>(i) * W + j];
+            wb.beta = betaw.data();
+        }
+        // pairs i + j = k, i >= j >= 0, i < W, outputs k < n
+        for (int k = 0; k < n; ++k) process_pairs += std::max(0, k / 2 - std::max(0, k - W + 1) + 1);
+    } else if (bispectrum) {
+        wb = *bispectrum;
+    }
+    srm3_plan_t p = nullptr;
+    srm3_status s = srm3_plan(&wg, &spec, bispectrum ? &wb : nullptr, precision, hip_stream, &p);
+    if (s) return s;
+    p->process = true;
+    if (!p->gaussian) {
+        p->pair_terms = static_cast<double>(process_pairs);
+        if ((s = srm3_plan_set_algorithm(p, SRM3_ALGO_KAPPA_FFT, hip_stream))) {
+            srm3_destroy(p);
+            return s;
+        }
+    }
+    *out_plan = p;
+    return SRM3_OK;
+}
+
 srm3_status srm3_set_spectrum(srm3_plan_t plan, const srm3_spectrum *spectrum, void *hip_stream)
 {
     g_err[0] = 0;
     if (!plan || !spectrum || !spectrum->S) return fail(SRM3_E_INVALID, "plan/spectrum is NULL");
     const size_t n = static_cast<size_t>(plan->g.nk) * plan->g.nc;
-    srm3_status s = check_spectrum(spectrum->S, n);
+    const double *src = spectrum->S;
+    std::vector<double> Sw;
+    if (plan->process) {
+        // one-sided [n_omega] -> the line layout, zero at negative frequencies
+        const int nw = plan->g.nw;
+        srm3_status s = check_spectrum(spectrum->S, static_cast<size_t>(nw));
+        if (s) return s;
+        Sw.assign(n, 0.0);
+        for (int k = 0; k < nw; ++k) Sw[nw - 1 + k] = spectrum->S[k];
+        src = Sw.data();
+    }
+    srm3_status s = check_spectrum(src, n);
     if (s) return s;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    hipError_t e = hipMemcpyAsync(plan->S.p, spectrum->S, n * sizeof(double), hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(plan->S.p, src, n * sizeof(double), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return dev_err(e, "hipMemcpyAsync");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
@@ -469,7 +550,7 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
     }
     if (algorithm != SRM3_ALGO_KAPPA_FFT) return fail(SRM3_E_INVALID, "algorithm %d", algorithm);
     if (plan->algo == SRM3_ALGO_KAPPA_FFT) return SRM3_OK;
-    const KfftGeom k = kfft_geometry(plan->g);
+    const KfftGeom k = kfft_geometry(plan->g, plan->process);
     std::string why;
     if (!kfft_supported(plan->g, k, plan->precision, &why))
         return fail(SRM3_E_UNSUPPORTED, "kappa-FFT pair sum: %s", why.c_str());
@@ -581,6 +662,9 @@ struct srm3_batch_s {
         Geometry g;                    // with the batch's R
         size_t ws_off = 0;
         int first = 0;                 // offset of the group in the device arrays
+        int mode = 0;                  // 0: items of the persistent launch; 1: the plan's kappa-DFT
+                                       // pair sum over the group; 2: zero bicoherence, no pair sum
+        size_t kws_off = 0;            // kappa-DFT workspace of the group (mode 1)
     };
     std::vector<Group> groups;
     int R = 0;                         // rows per wave of the persistent launch
@@ -630,15 +714,23 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
     int first = 0;
     for (auto &gr : b->groups) {
         gr.g = gr.plan->g;
-        gr.g.R = rows_for(gr.g.nk, b->precision, R);
-        gr.g.nkp = ((gr.g.nk + gr.g.R - 1) / gr.g.R) * gr.g.R;
-        if (gr.g.R != R)
-            return fail(SRM3_E_UNSUPPORTED, "a %dx%d grid needs rows per wave %d != %d of the batch", gr.g.nk,
-                        gr.g.nw, gr.g.R, R);
+        gr.mode = gr.plan->gaussian ? 2 : (gr.plan->algo == SRM3_ALGO_KAPPA_FFT ? 1 : 0);
+        if (gr.mode == 0) {
+            gr.g.R = rows_for(gr.g.nk, b->precision, R);
+            gr.g.nkp = ((gr.g.nk + gr.g.R - 1) / gr.g.R) * gr.g.R;
+            if (gr.g.R != R)
+                return fail(SRM3_E_UNSUPPORTED, "a %dx%d grid needs rows per wave %d != %d of the batch", gr.g.nk,
+                            gr.g.nw, gr.g.R, R);
+        }
+        const int nb = static_cast<int>(gr.members.size());
         gr.ws_off = off;
         gr.first = first;
-        off += al(workspace_bytes(gr.g, b->precision, static_cast<int>(gr.members.size())));
-        first += static_cast<int>(gr.members.size());
+        off += al(workspace_bytes(gr.g, b->precision, nb));
+        if (gr.mode == 1) {
+            gr.kws_off = off;
+            off += al(kfft_workspace_bytes(gr.g, gr.plan->kg, b->precision, nb));
+        }
+        first += nb;
     }
     if (b->ws.n < off) {
         hipError_t e = b->ws.alloc(off);
@@ -661,6 +753,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
         const size_t plane3 = a_slots(b->precision) * gr.g.ncw * gr.g.nkp;
         const int nrb = gr.g.nkp / gr.g.R;
         const int ncg = ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
+        if (gr.mode != 0) continue;   // no items in the persistent launch
         for (size_t slot = 0; slot < gr.members.size(); ++slot) {
             const int d = gr.first + static_cast<int>(slot);
             fill_persistent_req(reqs.data() + rb * d, gr.g, static_cast<char *>(ws.zrow) + slot * lines * 2 * e,
@@ -722,10 +815,22 @@ srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
         if (e != hipSuccess) return dev_err(e, "phase kernel");
     }
     if (time_pairsum) (void)hipEventRecord(b->ev_a, st);
-    hipError_t e = launch_pairsum_persistent(b->precision, b->R, b->preq.p, b->pitem.p,
-                                             static_cast<const int *>(b->qbegin.p), static_cast<int *>(b->qnext.p),
-                                             b->n_cu * b->blocks_per_cu, st);
-    if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
+    hipError_t e;
+    for (auto &gr : b->groups) {
+        if (gr.mode != 1) continue;
+        const int nb = static_cast<int>(gr.members.size());
+        const Workspace ws = carve_workspace(gr.g, b->precision, nb, static_cast<char *>(b->ws.p) + gr.ws_off);
+        const KfftWorkspace kw = carve_kfft(gr.g, gr.plan->kg, b->precision, nb,
+                                            static_cast<char *>(b->ws.p) + gr.kws_off);
+        e = launch_kfft_pairsum(b->precision, gr.g, gr.plan->kg, gr.plan->wsh.p, gr.plan->tw_k.p, nb, ws, kw, st);
+        if (e != hipSuccess) return dev_err(e, "kappa-DFT pair-sum kernels");
+    }
+    if (b->n_items > 0) {
+        e = launch_pairsum_persistent(b->precision, b->R, b->preq.p, b->pitem.p,
+                                      static_cast<const int *>(b->qbegin.p), static_cast<int *>(b->qnext.p),
+                                      b->n_cu * b->blocks_per_cu, st);
+        if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
+    }
     if (time_pairsum) (void)hipEventRecord(b->ev_b, st);
     for (auto &gr : b->groups) {
         const int nb = static_cast<int>(gr.members.size());
@@ -855,9 +960,11 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         b->n_cu = prop.multiProcessorCount;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    // the largest rows per wave every grid of the batch supports
+    // the largest rows per wave every grid of the persistent launch supports
     int R = precision == SRM3_FP64 ? 8 : 16;
-    for (auto &gr : b->groups) R = std::min(R, rows_for(gr.plan->g.nk, precision, 0));
+    for (auto &gr : b->groups)
+        if (!gr.plan->gaussian && gr.plan->algo == SRM3_ALGO_DIRECT)
+            R = std::min(R, rows_for(gr.plan->g.nk, precision, 0));
     srm3_status s = batch_layout(b.get(), R, st);
     if (s) return s;
     for (auto &gr : b->groups) b->pair_terms += gr.plan->pair_terms * gr.members.size();

@@ -118,12 +118,13 @@ struct KfftGeom {
     int c_lo = 0;     // first of them (column index, k_omega + n_omega - 1)
     int kw0 = 0;      // its k_omega
     int wh_rows = 0;  // rows of the sheared weight table, zero rows included
+    int one_sided = 0;  // 1: outputs and partners at k_omega >= 0 only (the 1-D process)
 };
 struct KfftWorkspace {
     void *Z = nullptr;   // [B][M][2W - 1] complex
     void *Y = nullptr;   // [B][M][nca] complex
 };
-KfftGeom kfft_geometry(const Geometry &g);
+KfftGeom kfft_geometry(const Geometry &g, bool one_sided);
 size_t kfft_workspace_bytes(const Geometry &g, const KfftGeom &k, int precision, int batch);
 KfftWorkspace carve_kfft(const Geometry &g, const KfftGeom &k, int precision, int batch, void *base);
 bool kfft_supported(const Geometry &g, const KfftGeom &k, int precision, std::string *why);
@@ -169,6 +170,7 @@ struct srm3_plan_s {
     srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
     int ws_batch = 0;
     bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)
+    bool process = false;    // the 1-D process: one kappa line, one-sided spectrum and pairs
     // pair-sum algorithm; the kappa-FFT form keeps its tables and workspace here
     int algo = SRM3_ALGO_DIRECT;
     srm3::KfftGeom kg{};

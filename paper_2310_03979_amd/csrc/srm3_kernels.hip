@@ -928,6 +928,7 @@ struct YpairArgs {
     const void *wh;     // [wh_rows][nca] sheared half table, zero rows after row ncw - 1
     int M, W, nca, kw0;
     int batch, n_qtiles, n_ctiles, per_xcd;
+    int one_sided;      // partners i_w <= k_omega only (both partners >= 0)
 };
 
 // Staged form of the frequency autoconvolution.  A wave owns 64 consecutive
@@ -975,7 +976,7 @@ __global__ __launch_bounds__(256) void ypair2_kernel(YpairArgs a)
     const int kw_lo = a.kw0 + cc0;
     const int kw_hi = a.kw0 + min(cc0 + 64, a.nca) - 1;
     const int iw_lo = max(-W + 1, (kw_lo + 1) >> 1);
-    const int iw_hi = min(W - 1, kw_hi + W - 1);
+    const int iw_hi = min(W - 1, a.one_sided ? kw_hi : kw_hi + W - 1);
     const int nchunk = __builtin_amdgcn_readfirstlane(iw_hi >= iw_lo ? (iw_hi - iw_lo + C) / C : 0);
     const gptr<T2> wcol = as_global(static_cast<const T2 *>(a.wh)) + cc0 + lane;
     const long wstride = a.nca;
@@ -1381,14 +1382,15 @@ hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int bat
 
 // ---- pair sum through an FFT along kappa ----
 
-KfftGeom kfft_geometry(const Geometry &g)
+KfftGeom kfft_geometry(const Geometry &g, bool one_sided)
 {
     KfftGeom k{};
     int M = 1;
     while (M < 2 * g.nk - 1) M *= 2;
     k.M = M;
+    k.one_sided = one_sided ? 1 : 0;
     // output frequencies that a pair of support frequencies reaches
-    const int kw_lo = std::max(-(g.nw - 1), -(2 * g.W - 2));
+    const int kw_lo = one_sided ? 0 : std::max(-(g.nw - 1), -(2 * g.W - 2));
     const int kw_hi = std::min(g.nw - 1, 2 * g.W - 2);
     k.kw0 = kw_lo;
     k.c_lo = kw_lo + g.nw - 1;
@@ -1489,9 +1491,15 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const voi
     y.nca = k.nca;
     y.kw0 = k.kw0;
     y.batch = batch;
-    y.n_qtiles = (k.M + kY2Rows - 1) / kY2Rows;
+    y.one_sided = k.one_sided;
+    if (k.M == 1) {
+        // one kappa line: the realizations are the rows ([B][1][.] == [B][.])
+        y.M = batch;
+        y.batch = 1;
+    }
+    y.n_qtiles = (y.M + kY2Rows - 1) / kY2Rows;
     y.n_ctiles = (k.nca + 63) / 64;
-    const long blocks = static_cast<long>(batch) * ((y.n_qtiles + kWavesPerBlock - 1) / kWavesPerBlock) * y.n_ctiles;
+    const long blocks = static_cast<long>(y.batch) * ((y.n_qtiles + kWavesPerBlock - 1) / kWavesPerBlock) * y.n_ctiles;
     y.per_xcd = static_cast<int>((blocks + kNumXcd - 1) / kNumXcd);
     const size_t lds = static_cast<size_t>(kWavesPerBlock) * (kY2Rows * (64 + kY2Chunk) + kY2Chunk * kY2Rows) *
                        sizeof(T2);
@@ -1542,7 +1550,8 @@ double kfft_terms(const Geometry &g, const KfftGeom &k)
     // q, the unordered support pairs (i_w >= j_w) of every active output
     double t = 0;
     for (int kw = k.kw0; kw < k.kw0 + k.nca; ++kw) {
-        const int lo = std::max(-(g.W - 1), kw - (g.W - 1)), hi = std::min(g.W - 1, kw + (g.W - 1));
+        int lo = std::max(-(g.W - 1), kw - (g.W - 1)), hi = std::min(g.W - 1, kw + (g.W - 1));
+        if (k.one_sided) hi = std::min(hi, kw);   // both partners >= 0
         const int half_lo = std::max(lo, (kw + 1) >> 1);
         if (hi >= half_lo) t += hi - half_lo + 1;
     }

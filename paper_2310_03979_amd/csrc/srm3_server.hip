@@ -7,6 +7,9 @@
 // least work left first (or round-robin), enough to fill the GPU a couple of
 // times over -- and runs them in one persistent launch; a request admitted
 // between steps joins the next one.  A
+// request whose plan uses the pair sum through a DFT along kappa runs that
+// whole stage at admission, on the step's lane; a request with zero
+// bicoherence has no pair stage.  A
 // request whose items have all been issued gets its transforms and a
 // completion event; its slot and arena space are released when that event
 // has completed.  Per-step tables travel in one host-to-device copy from a
@@ -51,6 +54,9 @@ struct SReq {
     size_t off = 0, bytes = 0;      // arena slice: workspace [+ spectrum]
     int slot = -1;
     bool fresh = false;             // admitted, phases not yet launched
+    int mode = 0;                   // 0: pair-sum items in the persistent launch; 1: the plan's kappa-DFT
+                                    // pair sum, run at admission; 2: zero bicoherence, no pair sum
+    size_t kfft_off = 0;            // arena offset of the kappa-DFT workspace (mode 1)
     std::vector<Item> items;        // heaviest first
     size_t cursor = 0;
     double left = 0.0;              // cost of the items not yet issued
@@ -260,25 +266,37 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     if (spectrum && r.S_dev) return fail(SRM3_E_INVALID, "give either S_dev or spectrum parameters, not both");
     if (spectrum && (!(spectrum->U > 0) || !(spectrum->z > 0) || !(spectrum->lam > 0) || !(spectrum->u_star >= 0)))
         return fail(SRM3_E_INVALID, "bad spectrum parameters");
+    if (spectrum && r.plan->process)
+        return fail(SRM3_E_UNSUPPORTED, "the wind spectrum is a wave spectrum; a process request takes S_dev");
     std::unique_ptr<SReq> q(new (std::nothrow) SReq);
     if (!q) return fail(SRM3_E_NOMEM, "host allocation failed");
     q->r = r;
     q->own_spec = spectrum != nullptr;
     if (spectrum) q->spec = *spectrum;
     q->g = r.plan->g;
-    q->g.R = rows_for(q->g.nk, s->cfg.precision, s->R);
-    if (q->g.R != s->R) return fail(SRM3_E_UNSUPPORTED, "grids with n_kappa < %d are not served", s->R);
-    q->g.nkp = ((q->g.nk + q->g.R - 1) / q->g.R) * q->g.R;
+    q->mode = r.plan->gaussian ? 2 : (r.plan->algo == SRM3_ALGO_KAPPA_FFT ? 1 : 0);
+    if (q->mode == 0) {
+        q->g.R = rows_for(q->g.nk, s->cfg.precision, s->R);
+        if (q->g.R != s->R) return fail(SRM3_E_UNSUPPORTED, "grids with n_kappa < %d are not served", s->R);
+        q->g.nkp = ((q->g.nk + q->g.R - 1) / q->g.R) * q->g.R;
+    }
     q->bytes = request_bytes(s, q->g, q->own_spec);
+    if (q->mode == 1) {
+        q->kfft_off = q->bytes;
+        q->bytes += align256(kfft_workspace_bytes(q->g, r.plan->kg, s->cfg.precision, 1));
+    }
     if (q->bytes > s->arena.size)
         return fail(SRM3_E_NOMEM, "request needs %zu bytes, more than the server's budget %zu", q->bytes, s->arena.size);
-    const int nrb = q->g.nkp / q->g.R;
-    const int ncg = ((q->g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
-    for (int kb = nrb - 1; kb >= 0; --kb)
-        for (int cg = 0; cg < ncg; ++cg) q->items.push_back({kb, cg, item_cost(q->g, q->g.R, kb, cg)});
-    std::stable_sort(q->items.begin(), q->items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
-    for (const Item &it : q->items) q->left += it.cost;
-    if (static_cast<int>(q->items.size()) > s->max_items) return fail(SRM3_E_UNSUPPORTED, "grid too large");
+    if (q->mode == 0) {
+        const int nrb = q->g.nkp / q->g.R;
+        const int ncg = ((q->g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
+        for (int kb = nrb - 1; kb >= 0; --kb)
+            for (int cg = 0; cg < ncg; ++cg) q->items.push_back({kb, cg, item_cost(q->g, q->g.R, kb, cg)});
+        std::stable_sort(q->items.begin(), q->items.end(),
+                         [](const Item &a, const Item &b) { return a.cost > b.cost; });
+        for (const Item &it : q->items) q->left += it.cost;
+        if (static_cast<int>(q->items.size()) > s->max_items) return fail(SRM3_E_UNSUPPORTED, "grid too large");
+    }
     q->ticket = s->next_ticket++;
     *ticket = q->ticket;
     s->queue.push_back(q.release());
@@ -409,6 +427,13 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
             }
             e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, ws, st);
             if (e != hipSuccess) return dev_err(e, "phase kernel");
+            if (q->mode == 1) {
+                // the whole pair sum of this request, here on the lane
+                const srm3_plan_t p = q->r.plan;
+                const KfftWorkspace kw = carve_kfft(q->g, p->kg, s->cfg.precision, 1, base + q->kfft_off);
+                e = launch_kfft_pairsum(s->cfg.precision, q->g, p->kg, p->wsh.p, p->tw_k.p, 1, ws, kw, st);
+                if (e != hipSuccess) return dev_err(e, "kappa-DFT pair-sum kernels");
+            }
             q->fresh = false;
         }
         if ((e = hipEventRecord(s->ev_phases[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");

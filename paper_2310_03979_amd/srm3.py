@@ -50,6 +50,10 @@ class _Bispectrum(ctypes.Structure):
                 ("beta_mode", ctypes.c_int32), ("beta_seed", ctypes.c_uint64)]
 
 
+class _ProcessGrid(ctypes.Structure):
+    _fields_ = [("n_omega", ctypes.c_int32), ("d_omega", ctypes.c_double), ("n_t", ctypes.c_int32)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 4), ("launches", ctypes.c_int64 * 4)]
 
@@ -96,6 +100,8 @@ def load():
     L.srm3_pair_terms.argtypes = [vp, _dp]
     L.srm3_rows_per_wave.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.srm3_plan_set_algorithm.argtypes = [vp, ctypes.c_int32, vp]
+    L.srm3_process_plan.argtypes = [ctypes.POINTER(_ProcessGrid), _dp, ctypes.POINTER(_Bispectrum),
+                                    ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.srm3_algorithm_terms.argtypes = [vp, _dp]
     L.srm3_profile_enable.argtypes = [vp, ctypes.c_int32]
     L.srm3_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
@@ -112,7 +118,7 @@ def load():
     L.srm3_batch_destroy.argtypes = [vp]
     L.srm3_batch_destroy.restype = None
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
-    for f in ("srm3_plan", "srm3_generate", "srm3_coefficients", "srm3_transform",
+    for f in ("srm3_plan", "srm3_process_plan", "srm3_generate", "srm3_coefficients", "srm3_transform",
               "srm3_workspace_bytes", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
               "srm3_algorithm_terms", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
@@ -150,6 +156,7 @@ class Plan:
         self.grid = dict(grid)
         self.precision = precision
         self.support_w = support_w
+        self.process = False
 
     @property
     def handle(self):
@@ -185,6 +192,39 @@ def _precision(p) -> int:
     return int(p)
 
 
+def _bispectrum(bispectrum: Optional[dict], default_w: int):
+    """Marshal a bispectrum dict into the C struct; returns (struct or None, arrays to keep alive, W)."""
+    if bispectrum is None:
+        return None, [], 1
+    kinds = {"none": 0, "separable": 1, "dense": 2}
+    modes = {"seeded": 0, "zero": 1, "table": 2}
+    kind = bispectrum.get("kind", "separable")
+    kind = kinds[kind] if isinstance(kind, str) else int(kind)
+    mode = bispectrum.get("beta_mode", "seeded")
+    mode = modes[mode] if isinstance(mode, str) else int(mode)
+    W = int(bispectrum.get("support_w", default_w))
+    b = _Bispectrum()
+    b.kind = kind
+    b.support_w = W
+    b.cap = float(bispectrum.get("cap", 0.9))
+    b.beta_mode = mode
+    b.beta_seed = int(bispectrum.get("beta_seed", 0))
+    keep = []
+    if bispectrum.get("g2") is not None:
+        g2 = np.ascontiguousarray(bispectrum["g2"], dtype=np.float64)
+        keep.append(g2)
+        b.g2 = g2.ctypes.data_as(_dp)
+    if bispectrum.get("b2") is not None:
+        b2 = np.ascontiguousarray(bispectrum["b2"], dtype=np.float64)
+        keep.append(b2)
+        b.b2 = b2.ctypes.data_as(_dp)
+    if bispectrum.get("beta") is not None:
+        bt = np.ascontiguousarray(bispectrum["beta"], dtype=np.uint32)
+        keep.append(bt)
+        b.beta = bt.ctypes.data_as(_u32p)
+    return b, keep, W
+
+
 def srm3_plan(grid: dict, S: np.ndarray, bispectrum: Optional[dict] = None, precision="fp64",
               stream=None) -> Plan:
     """Build a plan.  ``grid``: n_kappa, n_omega, d_kappa, d_omega, n_x, n_t.
@@ -197,36 +237,9 @@ def srm3_plan(grid: dict, S: np.ndarray, bispectrum: Optional[dict] = None, prec
               float(grid["d_omega"]), int(grid["n_x"]), int(grid["n_t"]))
     S = np.ascontiguousarray(S, dtype=np.float64)
     spec = _Spectrum(S.ctypes.data_as(_dp))
-    keep = [S]
-    bp = None
-    W = 1
-    if bispectrum is not None:
-        kinds = {"none": 0, "separable": 1, "dense": 2}
-        modes = {"seeded": 0, "zero": 1, "table": 2}
-        kind = bispectrum.get("kind", "separable")
-        kind = kinds[kind] if isinstance(kind, str) else int(kind)
-        mode = bispectrum.get("beta_mode", "seeded")
-        mode = modes[mode] if isinstance(mode, str) else int(mode)
-        W = int(bispectrum.get("support_w", grid["n_omega"]))
-        b = _Bispectrum()
-        b.kind = kind
-        b.support_w = W
-        b.cap = float(bispectrum.get("cap", 0.9))
-        b.beta_mode = mode
-        b.beta_seed = int(bispectrum.get("beta_seed", 0))
-        if bispectrum.get("g2") is not None:
-            g2 = np.ascontiguousarray(bispectrum["g2"], dtype=np.float64)
-            keep.append(g2)
-            b.g2 = g2.ctypes.data_as(_dp)
-        if bispectrum.get("b2") is not None:
-            b2 = np.ascontiguousarray(bispectrum["b2"], dtype=np.float64)
-            keep.append(b2)
-            b.b2 = b2.ctypes.data_as(_dp)
-        if bispectrum.get("beta") is not None:
-            bt = np.ascontiguousarray(bispectrum["beta"], dtype=np.uint32)
-            keep.append(bt)
-            b.beta = bt.ctypes.data_as(_u32p)
-        bp = ctypes.byref(b)
+    b, keep, W = _bispectrum(bispectrum, int(grid["n_omega"]))
+    keep.append(S)
+    bp = ctypes.byref(b) if b is not None else None
     h = ctypes.c_void_p()
     _check(L.srm3_plan(ctypes.byref(g), ctypes.byref(spec), bp, _precision(precision),
                        _stream_ptr(stream), ctypes.byref(h)))
@@ -346,10 +359,45 @@ def plan_from_workload(wl, precision="fp64", beta_mode="seeded", stream=None, de
     return srm3_plan(wl.grid_dict(), wl.spectrum(), bis, precision, stream)
 
 
+def srm3_process_plan(grid: dict, S: np.ndarray, bispectrum: Optional[dict] = None, precision="fp64",
+                      stream=None) -> Plan:
+    """Plan for the 1-D process u(t): grid = dict(n_omega, d_omega, n_t), S one-sided
+    [n_omega], bispectrum tables over 0 <= i, j < support_w.  Fields are [B][1][n_t]."""
+    L = load()
+    g = _ProcessGrid(int(grid["n_omega"]), float(grid["d_omega"]), int(grid["n_t"]))
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    b, keep, W = _bispectrum(bispectrum, int(grid["n_omega"]))
+    keep.append(S)
+    h = ctypes.c_void_p()
+    _check(L.srm3_process_plan(ctypes.byref(g), S.ctypes.data_as(_dp),
+                               ctypes.byref(b) if b is not None else None, _precision(precision),
+                               _stream_ptr(stream), ctypes.byref(h)))
+    del keep
+    wave_grid = dict(n_kappa=1, n_omega=int(grid["n_omega"]), d_kappa=1.0, d_omega=float(grid["d_omega"]),
+                     n_x=1, n_t=int(grid["n_t"]))
+    p = Plan(h, wave_grid, _precision(precision), W)
+    p.process = True
+    return p
+
+
+def process_plan_from_workload(wl, precision="fp64", beta_mode="seeded", stream=None, dense=False,
+                               **overrides) -> Plan:
+    """Convenience: plan for a ``srm3_inputs.ProcessWorkload`` (separable bicoherence)."""
+    bis = dict(kind="dense" if dense else "separable", support_w=wl.support_w, cap=wl.cap,
+               beta_mode=beta_mode, beta_seed=wl.beta_seed)
+    if dense:
+        bis["b2"] = wl.b2_dense()
+    else:
+        bis["g2"] = wl.g2()
+    bis.update(overrides)
+    return srm3_process_plan(wl.grid_dict(), wl.spectrum(), bis, precision, stream)
+
+
 def srm3_set_spectrum(plan: Plan, S: np.ndarray, stream=None):
     S = np.ascontiguousarray(S, dtype=np.float64)
-    if S.shape != plan.coeff_shape:
-        raise ValueError(f"S shape {S.shape} != {plan.coeff_shape}")
+    want = (plan.grid["n_omega"],) if plan.process else plan.coeff_shape
+    if S.shape != want:
+        raise ValueError(f"S shape {S.shape} != {want}")
     spec = _Spectrum(S.ctypes.data_as(_dp))
     _check(load().srm3_set_spectrum(plan.handle, ctypes.byref(spec), _stream_ptr(stream)))
 

@@ -180,3 +180,46 @@ def test_batch_argument_errors(lib):
     with pytest.raises(lib.Srm3Error) as ei:
         lib.Batch([dict(plan=nocap, seed=1, out=_out(nocap), b2_scale=1e4)])
     assert ei.value.status == 2
+
+
+def test_batch_with_kappa_fft_and_gaussian_plans(lib, oracle_mod):
+    """Groups whose plans use the kappa-DFT pair sum, or have zero
+    bicoherence, share a batch (and its graph) with direct-form groups; every
+    realization equals its single generation, and the kappa-DFT ones match the
+    oracle."""
+    torch = _t()
+    plans = _plans(lib, "fp32")
+    kplans = []
+    for wl, _ in plans[:2]:
+        kp = lib.plan_from_workload(wl, "fp32")
+        lib.srm3_plan_set_algorithm(kp, "kappa_fft")
+        kplans.append((wl, kp))
+    gwl = _unit(inp.small_grid(24, 50))
+    gplan = lib.srm3_plan(gwl.grid_dict(), gwl.spectrum(), None, "fp32")
+    mix = plans[2:] + kplans + [(gwl, gplan)]
+    reqs, singles = [], []
+    for i in range(10):
+        wl, plan = mix[i % len(mix)]
+        seed = 70 + 3 * i
+        reqs.append(dict(plan=plan, seed=seed, out=_out(plan), wl=wl))
+        one = torch.empty((1,) + plan.field_shape, dtype=plan.real_dtype, device="cuda")
+        lib.srm3_generate(plan, [seed], one)
+        singles.append(one[0])
+    print("[gpu] mixed-algorithm batch", flush=True)
+    for flags in (0, lib.SRM3_BATCH_GRAPH):
+        b = lib.Batch([dict(plan=r["plan"], seed=r["seed"], out=r["out"]) for r in reqs], flags=flags)
+        for _ in range(2):
+            for r in reqs:
+                r["out"].zero_()
+            b.run()
+            torch.cuda.synchronize()
+            for r, s in zip(reqs, singles):
+                assert torch.equal(r["out"], s)
+    r = reqs[2]            # a kappa-DFT request
+    assert r["plan"] is kplans[0][1]
+    wl = r["wl"]
+    P = oracle_mod.Problem(wl.n_kappa, wl.n_omega, wl.support_w, wl.d_kappa, wl.d_omega, wl.spectrum(),
+                           wl.b2_dense(), oracle_mod.biphase(wl.support_w, wl.beta_seed), wl.cap)
+    ref = oracle_mod.field(P.coefficients(seed=r["seed"]), wl.n_x, wl.n_t)
+    got = r["out"].double().cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL["fp32"]

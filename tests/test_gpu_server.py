@@ -150,3 +150,40 @@ def test_requests_join_while_others_run(lib):
     assert overlap > 0
     for r in reqs:
         assert torch.equal(r["out"], _alone(lib, r))
+
+
+def test_kappa_fft_and_gaussian_requests_in_the_mix(lib, oracle_mod):
+    """Requests whose plans use the kappa-DFT pair sum, or have zero
+    bicoherence, share the server with direct-form requests: each result is
+    bitwise its result alone, and the kappa-DFT ones match the oracle."""
+    torch = _t()
+    plans, reqs = _setup(lib, 9, seed=21)
+    fast = {}
+    for nk, nw, W in GRIDS:
+        wl = inp.small_grid(nk, nw, support_w=W, b2_scale=1.0)
+        p = lib.plan_from_workload(wl, "fp32")
+        lib.srm3_plan_set_algorithm(p, "kappa_fft")
+        fast[(nk, nw)] = (wl, p)
+    gwl = inp.small_grid(32, 128)
+    gplan = lib.srm3_plan(gwl.grid_dict(), gwl.spectrum(), None, "fp32")
+    for i, r in enumerate(reqs):
+        if i % 3 == 1:
+            r["wl"], r["plan"] = fast[(r["wl"].n_kappa, r["wl"].n_omega)]
+        elif i % 3 == 2 and i < 6:
+            r["wl"], r["plan"] = gwl, gplan
+            r["out"] = torch.empty(gplan.field_shape, dtype=torch.float32, device="cuda")
+    srv = lib.srm3.Server("fp32", max_active=4, hbm_budget=2 << 30)
+    tickets = [srv.submit(r["plan"], r["seed"], r["out"], r["b2_scale"], spectrum=r["spectrum"]) for r in reqs]
+    done = _drain(srv)
+    torch.cuda.synchronize()
+    assert sorted(done) == sorted(tickets)
+    for r in reqs:
+        assert torch.equal(r["out"], _alone(lib, r))
+    r = reqs[1]
+    wl = r["wl"]
+    S = inp.kaimal_davenport_lines(wl.n_kappa, wl.n_omega, wl.d_kappa, wl.d_omega, U=r["spectrum"]["U"])
+    P = oracle_mod.Problem(wl.n_kappa, wl.n_omega, wl.support_w, wl.d_kappa, wl.d_omega, S,
+                           r["b2_scale"] * wl.b2_dense(), oracle_mod.biphase(wl.support_w, wl.beta_seed), wl.cap)
+    ref = oracle_mod.field(P.coefficients(seed=r["seed"]), wl.n_x, wl.n_t)
+    got = r["out"].double().cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 2e-5
