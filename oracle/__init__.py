@@ -20,6 +20,7 @@ Every function cites the part of the paper it follows in the C source.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional, Sequence
@@ -52,7 +53,9 @@ def build(force: bool = True) -> str:
 class _Problem(ctypes.Structure):
     _fields_ = [("nk", ctypes.c_int), ("nw", ctypes.c_int), ("W", ctypes.c_int),
                 ("dk", ctypes.c_double), ("dw", ctypes.c_double),
-                ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double)]
+                ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double),
+                ("line_c", _dp), ("line_r", _dp), ("mode", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("Sp", _dp)]
 
 
 class _Process(ctypes.Structure):
@@ -79,6 +82,8 @@ def lib():
         L.oracle_field_nested.argtypes = [ctypes.c_int] * 4 + [_dp, _dp]
         L.oracle_field_points.argtypes = [ctypes.c_int] * 4 + [_dp, ctypes.c_long, _ip, _ip, _dp]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_wind_solve.argtypes = [ctypes.POINTER(_Problem), _dp, ctypes.c_int, ctypes.c_double]
+        L.oracle_wind_solve.restype = ctypes.c_int
         L.oracle_process_phases.argtypes = [ctypes.c_int, ctypes.c_uint64, _u32p]
         L.oracle_process_biphase.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _u32p]
         L.oracle_process_terms.argtypes = [ctypes.POINTER(_Process), ctypes.c_int, _dp, _dp, _dp, _lp]
@@ -121,7 +126,8 @@ def biphase(support_w: int, seed: Optional[int]) -> np.ndarray:
 class Problem:
     """Inputs of one simulation (host FP64 arrays), kept alive for ctypes."""
 
-    def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, b2, beta, cap):
+    def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, b2, beta, cap,
+                 line_c=None, line_r=None):
         self.S = np.ascontiguousarray(S, dtype=np.float64)
         self.b2 = np.ascontiguousarray(b2, dtype=np.float64)
         self.beta = np.ascontiguousarray(beta, dtype=np.uint32)
@@ -131,8 +137,14 @@ class Problem:
         assert 1 <= support_w <= n_omega
         self.n_kappa, self.n_omega, self.W = n_kappa, n_omega, support_w
         self.d_kappa, self.d_omega, self.cap = d_kappa, d_omega, cap
+        self.line_c = None if line_c is None else np.ascontiguousarray(line_c, dtype=np.float64)
+        self.line_r = None if line_r is None else np.ascontiguousarray(line_r, dtype=np.float64)
+        for a in (self.line_c, self.line_r):
+            assert a is None or a.shape == (n_kappa, nc)
         self._c = _Problem(n_kappa, n_omega, support_w, d_kappa, d_omega,
-                           _ptr(self.S, _dp), _ptr(self.b2, _dp), _ptr(self.beta, _u32p), cap)
+                           _ptr(self.S, _dp), _ptr(self.b2, _dp), _ptr(self.beta, _u32p), cap,
+                           None if self.line_c is None else _ptr(self.line_c, _dp),
+                           None if self.line_r is None else _ptr(self.line_r, _dp), 0, 0.0, None)
 
     @classmethod
     def from_workload(cls, wl, beta_zero: bool = False, b2=None, beta=None, S=None,
@@ -173,6 +185,51 @@ class Problem:
             raise ValueError(f"oracle: pure spectrum not positive (status {st})")
         C = out[:, 0] + 1j * out[:, 1]
         return C.reshape(self.n_kappa, self.n_cols) if full else C
+
+
+class WindProblem(Problem):
+    """The wind bispectrum of Section 5 (scaled by alpha, beta = 0) through the
+    partial-bicoherence recursion of Section 4.1; ``solve()`` finds S_p."""
+
+    def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, alpha, cap):
+        W = support_w
+        super().__init__(n_kappa, n_omega, W, d_kappa, d_omega, S, np.zeros((2 * W - 1, 2 * W - 1)),
+                         np.zeros((2 * W - 1, 2 * W - 1), dtype=np.uint32), cap)
+        self.alpha = alpha
+        self._c.alpha = alpha
+        self.Sp = self.S.copy()
+        self.sweeps = None
+
+    def solve(self, max_iter: int = 500, tol: float = 1e-15) -> int:
+        it = lib().oracle_wind_solve(ctypes.byref(self._c), _ptr(self.Sp, _dp), max_iter, tol)
+        if it == -2:
+            raise ValueError("oracle: no admissible pure spectrum (Sigma >= 1)")
+        if it == -1:
+            raise ValueError("oracle: the recursion did not converge")
+        self.sweeps = it
+        return it
+
+    def _ensure(self):
+        if self.sweeps is None:
+            self.solve()
+
+    def line_terms(self, kk: int, kw: int):
+        self._ensure()
+        return super().line_terms(kk, kw)
+
+    def coefficients(self, *a, **kw):
+        self._ensure()
+        return super().coefficients(*a, **kw)
+
+    def bispectrum(self, ik, iw, jk, jw) -> float:
+        """|B| of the pair (Section 5, Eq. bispectrum, scaled), 0 where singular."""
+        kk, kw = ik + jk, iw + jw
+        if kk == 0 or kw == 0:
+            return 0.0
+        nw = self.n_omega
+        Si, Sj, Sk = self.S[ik, iw + nw - 1], self.S[jk, jw + nw - 1], self.S[kk, kw + nw - 1]
+        return self.alpha * 2.0 * math.sqrt(Si * Sj * Sk) / (
+            3.0 * math.sqrt(3.0 * abs(kw * self.d_omega) * kk * self.d_kappa))
 
 
 def _cbuf(C):

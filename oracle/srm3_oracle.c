@@ -104,7 +104,56 @@ typedef struct {
     const double *b2;       /* [2W-1][2W-1] raw squared bicoherence */
     const uint32_t *beta;   /* [2W-1][2W-1] fixed-point biphase */
     double cap;             /* > 0: per-line cap on sum b^2; <= 0: none */
+    /* kappa-dependent bicoherence (NULL / 0 = off):
+     *  line_c, line_r [nk][2nw-1]: b2_raw(i, j -> k) = c_k^2 r_i^2 r_j^2 b2(iw, jw);
+     *  mode 1: the wind bispectrum of Section 5 (Eq. bispectrum, scaled by
+     *  alpha, beta = 0) through the partial bicoherence of Section 4.1,
+     *  b_p^2 = |B|^2 dk dw / (S_p,i S_p,j S_k), with S_p from Sp [nk][2nw-1]. */
+    const double *line_c;
+    const double *line_r;
+    int mode;
+    double alpha;
+    const double *Sp;
 } oracle_problem;
+
+/* The wind bispectrum (Section 5, Eq. bispectrum) between lines i and j,
+ * scaled by alpha, with |omega_i + omega_j| under the root (the half-plane
+ * kappa >= 0 holds negative frequencies too; S is even in omega) and zero
+ * where it is singular (omega_k = 0 or kappa_k = 0). */
+static double wind_B(const oracle_problem *p, int ik, int iw, int jk, int jw)
+{
+    const int nc = 2 * p->nw - 1;
+    const int kk = ik + jk, kw = iw + jw;
+    if (kk == 0 || kw == 0) return 0.0;
+    const double Si = p->S[(size_t)ik * nc + iw + p->nw - 1];
+    const double Sj = p->S[(size_t)jk * nc + jw + p->nw - 1];
+    const double Sk = p->S[(size_t)kk * nc + kw + p->nw - 1];
+    const double wk = fabs((double)kw * p->dw), kap = (double)kk * p->dk;
+    return p->alpha * 2.0 * sqrt(Si * Sj * Sk) / (3.0 * sqrt(3.0 * wk * kap));
+}
+
+/* Squared bicoherence of the pair {i, j} before the per-line cap. */
+static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
+{
+    const int W = p->W, n = 2 * W - 1, nc = 2 * p->nw - 1;
+    const size_t li = (size_t)ik * nc + iw + p->nw - 1, lj = (size_t)jk * nc + jw + p->nw - 1;
+    const size_t lk = (size_t)(ik + jk) * nc + iw + jw + p->nw - 1;
+    if (p->mode == 1) {
+        const double B = wind_B(p, ik, iw, jk, jw);
+        if (B == 0.0) return 0.0;
+        return B * B * p->dk * p->dw / (p->Sp[li] * p->Sp[lj] * p->S[lk]);
+    }
+    double v = p->b2[(size_t)(iw + W - 1) * n + (jw + W - 1)];
+    if (p->line_c) v *= p->line_c[lk] * p->line_c[lk];
+    if (p->line_r) v *= p->line_r[li] * p->line_r[li] * p->line_r[lj] * p->line_r[lj];
+    return v;
+}
+
+static uint32_t pair_beta(const oracle_problem *p, int iw, int jw)
+{
+    const int W = p->W, n = 2 * W - 1;
+    return p->mode == 1 ? 0u : p->beta[(size_t)(iw + W - 1) * n + (jw + W - 1)];
+}
 
 /* Is the pair (i, j), i + j = k, the canonical member of its unordered pair? */
 static int canonical(int ik, int iw, int jk, int jw)
@@ -115,7 +164,7 @@ static int canonical(int ik, int iw, int jk, int jw)
 /* Enumerate P(k) and return the raw bicoherence sum and the pair count. */
 static double raw_sum(const oracle_problem *p, int kk, int kw, long *npairs)
 {
-    const int W = p->W, n = 2 * W - 1;
+    const int W = p->W;
     double s = 0.0;
     long cnt = 0;
     for (int ik = 0; ik <= kk; ++ik) {
@@ -124,7 +173,7 @@ static double raw_sum(const oracle_problem *p, int kk, int kw, long *npairs)
             const int jw = kw - iw;
             if (jw <= -W || jw >= W) continue;
             if (!canonical(ik, iw, jk, jw)) continue;
-            s += p->b2[(size_t)(iw + W - 1) * n + (jw + W - 1)];
+            s += pair_b2(p, ik, iw, jk, jw);
             ++cnt;
         }
     }
@@ -151,7 +200,7 @@ int oracle_line_terms(const oracle_problem *p, int kk, int kw, double *sigma_raw
 int oracle_coefficients(const oracle_problem *p, const uint32_t *U, long nlines,
                         const long *lines, double *C)
 {
-    const int nw = p->nw, nc = 2 * nw - 1, W = p->W, n = 2 * W - 1;
+    const int nw = p->nw, nc = 2 * nw - 1, W = p->W;
     int status = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(max : status)
     for (long q = 0; q < nlines; ++q) {
@@ -171,11 +220,10 @@ int oracle_coefficients(const oracle_problem *p, const uint32_t *U, long nlines,
                 const int jw = kw - iw;
                 if (jw <= -W || jw >= W) continue;
                 if (!canonical(ik, iw, jk, jw)) continue;
-                const size_t e = (size_t)(iw + W - 1) * n + (jw + W - 1);
-                const double bp = sqrt(rho * p->b2[e]);
+                const double bp = sqrt(rho * pair_b2(p, ik, iw, jk, jw));
                 const uint32_t ang = U[(size_t)ik * nc + (iw + nw - 1)]
                                    + U[(size_t)jk * nc + (jw + nw - 1)]
-                                   + p->beta[e];            /* exact mod 2^32 */
+                                   + pair_beta(p, iw, jw);  /* exact mod 2^32 */
                 const double th = TWO_PI * (double)ang / 4294967296.0;
                 re += bp * cos(th);
                 im += bp * sin(th);
@@ -185,6 +233,43 @@ int oracle_coefficients(const oracle_problem *p, const uint32_t *U, long nlines,
         C[2 * q + 1] = amp * im;
     }
     return status;
+}
+
+/* Partial-bicoherence recursion of Section 4.1 for the wind bispectrum: the
+ * pure spectrum S_p = S (1 - Sigma) enters the bicoherence of every pair that
+ * builds on a line, so S_p is the solution of a fixed point.  Plain Jacobi
+ * sweeps from S_p = S (Sigma = 0): each sweep recomputes every line's Sigma
+ * (cap applied) from the previous S_p by enumerating P(k).  Sigma grows
+ * monotonically and converges to the least solution.  Sp (in/out) is the
+ * problem's own array.  Returns the sweep count, or -2 if an uncapped Sigma
+ * reaches 1 (no admissible pure spectrum), -1 if not converged in max_iter. */
+int oracle_wind_solve(oracle_problem *p, double *Sp, int max_iter, double tol)
+{
+    const int nk = p->nk, nw = p->nw, nc = 2 * nw - 1;
+    const size_t nl = (size_t)nk * nc;
+    double *next = (double *)malloc(sizeof(double) * nl);
+    for (size_t l = 0; l < nl; ++l) Sp[l] = p->S[l];
+    p->mode = 1;
+    p->Sp = Sp;
+    int it;
+    for (it = 1; it <= max_iter; ++it) {
+        int bad = 0;
+        double diff = 0.0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(max : diff) reduction(| : bad)
+        for (long l = 0; l < (long)nl; ++l) {
+            const int kk = (int)(l / nc), kw = (int)(l % nc) - (nw - 1);
+            double sigma;
+            if (oracle_line_terms(p, kk, kw, NULL, NULL, &sigma, NULL)) { bad = 1; next[l] = 0.0; continue; }
+            next[l] = p->S[l] * (1.0 - sigma);
+            const double d = fabs(next[l] - Sp[l]) / (p->S[l] > 0.0 ? p->S[l] : 1.0);
+            if (d > diff) diff = d;
+        }
+        if (bad) { free(next); return -2; }
+        for (size_t l = 0; l < nl; ++l) Sp[l] = next[l];
+        if (diff <= tol) break;
+    }
+    free(next);
+    return it > max_iter ? -1 : it;
 }
 
 static long long posmod(long long a, long long m)
