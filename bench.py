@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3", "c4", "p1"])
+    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3", "c4", "p1", "bridge"])
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests per arrival rate in the serving workload (c4)")
     ap.add_argument("--batch", type=int, default=None)
@@ -452,6 +452,129 @@ def bench_process(args, torch, srm3):
     print(json.dumps(rec))
 
 
+def wind_theory(wl, c, r, sig):
+    """Closed-form variance and skewness of the field for line factors (c, r)
+    over a unit table: E[u^2] = 2 sum S dk dw and E[u^3] = 6 sum_k A_k
+    sqrt(rho_k) c_k (a * a)_k with A = a = sqrt(S dk dw) (the partner factors
+    A_i s_i r_i reduce to a_i), * the 2-D linear autoconvolution over the support."""
+    S = wl.spectrum()
+    nk, nw, W = wl.n_kappa, wl.n_omega, wl.support_w
+    c0 = nw - 1
+    a = np.sqrt(S * wl.d_kappa * wl.d_omega)[:, c0 - (W - 1):c0 + W]
+    y = (r ** 2)[:, c0 - (W - 1):c0 + W]
+    shape = (2 * nk, 4 * W)
+    conv_a = np.fft.ifft2(np.fft.fft2(a, s=shape) ** 2).real[:nk, :4 * W - 3]
+    conv_y = np.fft.ifft2(np.fft.fft2(y, s=shape) ** 2).real[:nk, :4 * W - 3]
+    m3 = 0.0
+    for kk in range(nk):
+        for kw in range(-min(nw - 1, 2 * W - 2), min(nw - 1, 2 * W - 2) + 1):
+            ck = c[kk, kw + c0]
+            if ck == 0.0:
+                continue
+            q = conv_y[kk, kw + 2 * W - 2]
+            if kk % 2 == 0 and kw % 2 == 0 and abs(kw // 2) < W:
+                q += y[kk // 2, kw // 2 + W - 1] ** 2
+            raw = ck * ck * 0.5 * q
+            rho = sig[kk, kw + c0] / raw if raw > 0 else 1.0
+            m3 += 6.0 * math.sqrt(S[kk, kw + c0] * wl.d_kappa * wl.d_omega) * math.sqrt(rho) * ck * \
+                conv_a[kk, kw + 2 * W - 2]
+    var = 2.0 * float(np.sum(S * wl.d_kappa * wl.d_omega))
+    return var, m3 / var ** 1.5
+
+
+def bench_bridge(args, torch, srm3):
+    """The bridge example of Section 5: 256 x 128 lines, 1024 x 2048 field, the
+    printed Kaimal/Davenport spectrum, the wind bispectrum through the
+    partial-bicoherence recursion (capped at 0.9 where no admissible pure
+    spectrum exists), 64 realizations per step; 2nd- and 3rd-order fields from
+    identical phases, their statistics and the closed-form values."""
+    wl = inp.bridge(batch=args.batch or 64)
+    B = wl.batch
+    seeds = wl.seeds()
+    points = B * wl.grid_points
+    S = wl.spectrum()
+    log(f"[bench] workload {wl.name} batch {B}")
+    t0 = time.perf_counter()
+    bis = dict(kind="wind", alpha=wl.alpha, cap=wl.cap, support_w=wl.support_w)
+    plan = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
+    plan_s = time.perf_counter() - t0
+    out = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+    dt = timed_steps(torch, lambda: srm3.srm3_generate(plan, seeds, out), args.steps, args.warmup)
+    terms = srm3.srm3_pair_terms(plan)
+    srm3.srm3_profile_enable(plan, True)
+    srm3.srm3_generate(plan, seeds, out)
+    prof = srm3.srm3_profile_read(plan)
+    srm3.srm3_profile_enable(plan, False)
+    ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
+    tf = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+    log(f"[bench] bridge direct fp32: {dt * 1e3:.2f} ms/step (plan {plan_s:.2f} s)")
+    kplan = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
+    srm3.srm3_plan_set_algorithm(kplan, "kappa_fft")
+    outk = torch.empty_like(out)
+    dtk = timed_steps(torch, lambda: srm3.srm3_generate(kplan, seeds, outk), args.steps, args.warmup)
+    gplan = srm3.srm3_plan(wl.grid_dict(), S, None, "fp32")
+    outg = torch.empty_like(out)
+    dtg = timed_steps(torch, lambda: srm3.srm3_generate(gplan, seeds, outg), args.steps, args.warmup)
+    log(f"[bench] bridge kappa-DFT {dtk * 1e3:.2f} ms, 2nd-order {dtg * 1e3:.2f} ms")
+
+    def moments(u):
+        x = u.double()
+        m = x.mean()
+        v = (x - m).pow(2).mean()
+        return {"mean": round(m.item(), 4), "variance": round(v.item(), 3),
+                "skewness": round(((x - m).pow(3).mean() / v.pow(1.5)).item(), 4)}
+    stats = {"third_order": moments(out), "second_order_same_phases": moments(outg)}
+    c, r, sig, sweeps = srm3.srm3_wind_factors(wl.grid_dict(), S, wl.alpha, wl.cap, wl.support_w)
+    var_th, skew_th = wind_theory(wl, c, r, sig)
+    stats["theory"] = {"variance": round(var_th, 3), "skewness": round(skew_th, 4)}
+    stats["lines_at_cap"] = float(np.mean(sig[S > 0] >= wl.cap - 1e-12))
+    stats["recursion_sweeps"] = sweeps
+    # the same bispectrum scaled so that the recursion needs no cap
+    wl2 = inp.bridge(alpha=0.1, cap=0.0, batch=B)
+    p2 = srm3.srm3_plan(wl2.grid_dict(), S, dict(kind="wind", alpha=0.1, cap=0.0, support_w=wl2.support_w), "fp32")
+    srm3.srm3_generate(p2, seeds, outk)
+    c2, r2, sig2, _ = srm3.srm3_wind_factors(wl2.grid_dict(), S, 0.1, 0.0, wl2.support_w)
+    v2, s2 = wind_theory(wl2, c2, r2, sig2)
+    stats["alpha_0.1_uncapped"] = {"sample": moments(outk), "theory": {"variance": round(v2, 3),
+                                                                       "skewness": round(s2, 4)}}
+    log(f"[bench] statistics {stats}")
+    extra = {}
+    if not args.no_cpu:
+        import oracle
+        W = wl.support_w
+        P = oracle.Problem(wl.n_kappa, wl.n_omega, W, wl.d_kappa, wl.d_omega, S, np.ones((2 * W - 1, 2 * W - 1)),
+                           oracle.biphase(W, None), wl.cap, line_c=c, line_r=r)
+        rng = np.random.default_rng(1)
+        lines = (rng.integers(0, wl.n_kappa, 256) * wl.n_cols + rng.integers(0, wl.n_cols, 256)).astype(np.int64)
+        t1 = time.perf_counter()
+        ref = P.coefficients(seed=int(seeds[0]), lines=lines)
+        tc = time.perf_counter() - t1
+        C = torch.empty((1,) + plan.coeff_shape, dtype=torch.complex64, device="cuda")
+        srm3.srm3_coefficients(plan, [int(seeds[0])], C)
+        got = C.reshape(-1)[torch.as_tensor(lines, device="cuda")].to(torch.complex128).cpu().numpy()
+        extra["accuracy"] = {"lines_compared": 256,
+                             "fp32_rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+        log(f"[bench] accuracy {extra['accuracy']} (oracle {tc:.1f} s for 256 lines)")
+    rec = {
+        "metric": "space-time grid points/sec of the bridge example (FP32), field statistics",
+        "value": points / dt, "unit": "grid points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"bridge example: {wl.n_kappa}x{wl.n_omega} lines, {wl.n_x}x{wl.n_t} field, "
+                               f"wind bispectrum alpha {wl.alpha} through the partial-bicoherence recursion, "
+                               f"cap {wl.cap}, {B} realizations"},
+        "roofline": {"bound": "alu", "kernel": "pairsum_kernel<float,8,true>", "achieved": round(tf, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None, "pair_terms_per_launch": terms * B, "avg_launch_ms": round(ps_ms, 4)},
+        "cpu_baseline": None,
+        "kappa_fft_grid_points_per_s": points / dtk, "kappa_fft_over_direct": round(dt / dtk, 3),
+        "second_order_grid_points_per_s": points / dtg, "plan_seconds": round(plan_s, 3),
+        "statistics": stats,
+    }
+    rec.update(extra)
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -476,6 +599,9 @@ def main():
         return
     if args.workload == "p1":
         bench_process(args, torch, srm3)
+        return
+    if args.workload == "bridge":
+        bench_bridge(args, torch, srm3)
         return
     wl = inp.WORKLOADS[args.workload]
     B = args.batch or wl.batch

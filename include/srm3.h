@@ -63,7 +63,9 @@ typedef enum { SRM3_FP64 = 0, SRM3_FP32 = 1 } srm3_precision;
 typedef enum {
     SRM3_BISPEC_NONE = 0,      /* b == 0: the 2nd-order (Gaussian) SRM of Section 3 */
     SRM3_BISPEC_SEPARABLE = 1, /* b^2_raw(i_w, j_w) = g2[i_w] * g2[j_w] */
-    SRM3_BISPEC_DENSE = 2      /* b^2_raw given as a full symmetric table */
+    SRM3_BISPEC_DENSE = 2,     /* b^2_raw given as a full symmetric table */
+    SRM3_BISPEC_WIND = 3       /* the wind bispectrum of Section 5 (Eq. bispectrum) times alpha, beta = 0,
+                                  through the partial bicoherence of Section 4.1 (see below) */
 } srm3_bispec_kind;
 
 typedef enum {
@@ -103,7 +105,36 @@ typedef struct {
                                 <= 0: no rescale */
     int32_t beta_mode;       /* srm3_beta_mode */
     uint64_t beta_seed;      /* BETA_SEEDED: Philox key */
+    /* kappa-dependent bicoherence through per-line factors (optional, host
+     * [n_kappa][2 n_omega - 1], NULL = 1): a pair {i, j} -> k has
+     * b^2_raw = line_c[k]^2 line_r[i]^2 line_r[j]^2 b^2_raw(i_w, j_w).
+     * line_c >= 0, line_r > 0, finite.  Not with SRM3_BISPEC_WIND. */
+    const double *line_c;
+    const double *line_r;
+    double alpha;            /* SRM3_BISPEC_WIND: scale of the bispectrum, > 0 */
 } srm3_bispectrum;
+
+/* SRM3_BISPEC_WIND.  B = alpha 2 sqrt(S_i S_j S_k) / (3 sqrt(3 |w_i + w_j| (kappa_i + kappa_j)))
+ * (Section 5; |.| since the kappa >= 0 half plane holds negative frequencies;
+ * zero where singular, k_kappa = 0 or k_omega = 0, or where an S is 0), and
+ * b_p = |B| sqrt(dk dw) / sqrt(S_p,i S_p,j S_k) with the pure spectrum
+ * S_p = S (1 - Sigma) (Section 4.1).  This factorises into line factors,
+ * c_k = alpha 2 / (3 sqrt 3) / sqrt(|k_omega| k_kappa) and r_i = sqrt(S_i / S_p,i),
+ * and Sigma solves a fixed point (Sigma_k = min(cap, c_k^2 sum_{P(k)} r_i^2 r_j^2)),
+ * found at plan time by sweeps from Sigma = 0 (each a 2-D FFT
+ * autoconvolution on the host).  support_w limits the pairs as usual; g2, b2
+ * and beta are ignored.  SRM3_E_PURE_NEGATIVE if no admissible pure spectrum
+ * exists without a cap.  The factors do not depend on the values of S (only on
+ * where it is zero), so srm3_set_spectrum and per-request spectra with the
+ * same zero lines keep them. */
+
+/* The line factors and Sigma that SRM3_BISPEC_WIND derives (host only, FP64,
+ * no device work): S host [n_kappa][2 n_omega - 1]; line_c, line_r, sigma:
+ * caller-owned host arrays of the same shape (sigma may be NULL); sweeps
+ * (may be NULL) receives the number of fixed-point sweeps.  Errors as for
+ * srm3_plan with that kind. */
+srm3_status srm3_wind_factors(const srm3_grid *grid, const double *S, double alpha, double cap, int32_t support_w,
+                              double *line_c, double *line_r, double *sigma, int32_t *sweeps);
 
 /* Build a plan: validates every input, computes on the host in FP64 the
  * per-line raw bicoherence sums, the cap factor rho_k, Sigma_k and the two

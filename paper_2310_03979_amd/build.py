@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsrm3.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["srm3_kernels.hip", "srm3_api.hip", "srm3_server.hip"]
+SOURCES = ["srm3_kernels.hip", "srm3_api.hip", "srm3_server.hip", "srm3_lines.hip"]
 
 ARCH = os.environ.get("SRM3_OFFLOAD_ARCH", "gfx950")
 

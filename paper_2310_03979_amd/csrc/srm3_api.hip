@@ -70,7 +70,8 @@ srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_
 AmpRef plan_amp(srm3_plan_t p)
 {
     return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
-                  p->dk * p->dw, p->cap, p->gaussian ? 0 : 1};
+                  p->dk * p->dw, p->cap, p->gaussian ? 0 : 1, static_cast<const double *>(p->lc.p),
+                  static_cast<const double *>(p->lr.p)};
 }
 
 double max_sigma(double max_sig, double cap, double scale)
@@ -185,7 +186,7 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
 {
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
-    hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, ws, st);
+    hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, ws, static_cast<const double *>(p->lr.p), st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
     if (p->gaussian) return SRM3_OK;   // zero bicoherence: the pair sums are not used
@@ -258,12 +259,39 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     none.kind = SRM3_BISPEC_NONE;
     none.support_w = 1;
     none.beta_mode = SRM3_BETA_ZERO;
-    const srm3_bispectrum &bs = bispectrum ? *bispectrum : none;
+    srm3_bispectrum bs = bispectrum ? *bispectrum : none;
     const int W = bs.kind == SRM3_BISPEC_NONE ? (bs.support_w >= 1 ? bs.support_w : 1) : bs.support_w;
     if (W < 1 || W > nw) return fail(SRM3_E_INVALID, "support_w=%d must be in [1, n_omega=%d]", W, nw);
     const int ncw = 2 * W - 1;
-    if (bs.kind != SRM3_BISPEC_NONE && bs.kind != SRM3_BISPEC_SEPARABLE && bs.kind != SRM3_BISPEC_DENSE)
+    if (bs.kind != SRM3_BISPEC_NONE && bs.kind != SRM3_BISPEC_SEPARABLE && bs.kind != SRM3_BISPEC_DENSE &&
+        bs.kind != SRM3_BISPEC_WIND)
         return fail(SRM3_E_INVALID, "bispectrum kind %d", bs.kind);
+    if (bs.kind == SRM3_BISPEC_NONE) bs.line_c = bs.line_r = nullptr;
+    const size_t nlines0 = static_cast<size_t>(nk) * nc;
+    std::vector<double> wind_c, wind_r;
+    const std::vector<double> ones(static_cast<size_t>(ncw), 1.0);
+    if (bs.kind == SRM3_BISPEC_WIND) {
+        // the wind bispectrum becomes line factors over a unit separable table
+        if (bs.line_c || bs.line_r) return fail(SRM3_E_INVALID, "line factors are derived for the wind bispectrum");
+        if (!(bs.alpha > 0) || !std::isfinite(bs.alpha)) return fail(SRM3_E_INVALID, "alpha must be finite and > 0");
+        if (!(bs.cap < 1.0)) return fail(SRM3_E_INVALID, "cap must be < 1");
+        srm3_status sw = check_spectrum(spectrum->S, nlines0);
+        if (sw) return sw;
+        if ((sw = wind_factors(nk, nw, W, spectrum->S, bs.alpha, bs.cap, wind_c, wind_r, nullptr, nullptr))) return sw;
+        bs.kind = SRM3_BISPEC_SEPARABLE;
+        bs.g2 = ones.data();
+        bs.beta_mode = SRM3_BETA_ZERO;
+        bs.line_c = wind_c.data();
+        bs.line_r = wind_r.data();
+    } else {
+        for (const double *f : {bs.line_c, bs.line_r}) {
+            if (!f) continue;
+            for (size_t l = 0; l < nlines0; ++l)
+                if (!(f[l] >= 0) || !std::isfinite(f[l]) || (f == bs.line_r && !(f[l] > 0)))
+                    return fail(SRM3_E_INVALID, "line factor [%zu] must be finite (line_c >= 0, line_r > 0)", l);
+        }
+    }
+    const bool factors = bs.line_c || bs.line_r;
     if (bs.kind == SRM3_BISPEC_SEPARABLE && !bs.g2) return fail(SRM3_E_INVALID, "g2 is NULL");
     if (bs.kind == SRM3_BISPEC_DENSE && !bs.b2) return fail(SRM3_E_INVALID, "b2 is NULL");
     if (bs.beta_mode != SRM3_BETA_SEEDED && bs.beta_mode != SRM3_BETA_ZERO && bs.beta_mode != SRM3_BETA_TABLE)
@@ -336,6 +364,23 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
             sig[static_cast<size_t>(kk) * nc + c] = v;
             max_sig = std::max(max_sig, v);
         }
+    if (factors) {
+        // kappa-dependent bicoherence: weighted 2-D autoconvolution of r^2 on the host
+        if (bs.kind == SRM3_BISPEC_DENSE) {
+            int Mk = 1;
+            while (Mk < 2 * nk - 1) Mk *= 2;
+            if (static_cast<double>(Mk) * (4.0 * W - 3) * ncw > 4e9)
+                return fail(SRM3_E_UNSUPPORTED, "line factors with a dense table: grid too large for the plan-time sums");
+        }
+        std::vector<double> Q;
+        line_pair_sums(nk, nw, W, bs.line_r, bs.kind, bs.g2, bs.b2, Q);
+        max_sig = 0.0;
+        for (size_t l = 0; l < nlines; ++l) {
+            const double c = bs.line_c ? bs.line_c[l] : 1.0;
+            sig[l] = c * c * Q[l];
+            max_sig = std::max(max_sig, sig[l]);
+        }
+    }
     if (max_sigma(max_sig, bs.cap, 1.0) >= 1.0)
         return fail(SRM3_E_PURE_NEGATIVE, "a line has sum of b^2 = %.6g >= 1: pure spectrum not positive",
                     max_sigma(max_sig, bs.cap, 1.0));
@@ -387,9 +432,36 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     }
     if ((s = upload_bytes(p->S, S, nlines * sizeof(double), st))) return s;
     if ((s = upload_bytes(p->sig, sig.data(), nlines * sizeof(double), st))) return s;
+    if (bs.line_c && (s = upload_bytes(p->lc, bs.line_c, nlines * sizeof(double), st))) return s;
+    if (bs.line_r && (s = upload_bytes(p->lr, bs.line_r, nlines * sizeof(double), st))) return s;
     if ((s = upload(p->tw_t, twiddles(nt), precision, st))) return s;
     if ((s = upload(p->tw_x, twiddles(nx), precision, st))) return s;
     *out_plan = p.release();
+    return SRM3_OK;
+}
+
+srm3_status srm3_wind_factors(const srm3_grid *grid, const double *S, double alpha, double cap, int32_t support_w,
+                              double *line_c, double *line_r, double *sigma, int32_t *sweeps)
+{
+    g_err[0] = 0;
+    if (!grid || !S || !line_c || !line_r) return fail(SRM3_E_INVALID, "NULL argument");
+    const int nk = grid->n_kappa, nw = grid->n_omega;
+    if (nk < 1 || nw < 1) return fail(SRM3_E_INVALID, "n_kappa=%d n_omega=%d must be >= 1", nk, nw);
+    if (support_w < 1 || support_w > nw) return fail(SRM3_E_INVALID, "support_w=%d must be in [1, n_omega]", support_w);
+    if (!(alpha > 0) || !std::isfinite(alpha)) return fail(SRM3_E_INVALID, "alpha must be finite and > 0");
+    if (!(cap < 1.0) || !std::isfinite(cap)) return fail(SRM3_E_INVALID, "cap must be < 1");
+    const size_t nl = static_cast<size_t>(nk) * (2 * nw - 1);
+    srm3_status s = check_spectrum(S, nl);
+    if (s) return s;
+    std::vector<double> c, r;
+    int it = 0;
+    if ((s = wind_factors(nk, nw, support_w, S, alpha, cap, c, r, &it, nullptr))) return s;
+    for (size_t l = 0; l < nl; ++l) {
+        line_c[l] = c[l];
+        line_r[l] = r[l];
+        if (sigma) sigma[l] = r[l] > 0.0 ? 1.0 - 1.0 / (r[l] * r[l]) : 0.0;
+    }
+    if (sweeps) *sweeps = it;
     return SRM3_OK;
 }
 
@@ -418,6 +490,8 @@ srm3_status srm3_process_plan(const srm3_process_grid *grid, const double *S, co
     std::vector<double> g2w, b2w;
     std::vector<uint32_t> betaw;
     long long process_pairs = 0;
+    if (bispectrum && (bispectrum->kind == SRM3_BISPEC_WIND || bispectrum->line_c || bispectrum->line_r))
+        return fail(SRM3_E_UNSUPPORTED, "process plans take frequency-only bicoherence");
     if (bispectrum && bispectrum->kind != SRM3_BISPEC_NONE) {
         const srm3_bispectrum &q = *bispectrum;
         const int W = q.support_w;
@@ -811,7 +885,8 @@ srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
         const Workspace ws = carve_workspace(gr.g, b->precision, static_cast<int>(gr.members.size()),
                                              static_cast<char *>(b->ws.p) + gr.ws_off);
         hipError_t e = launch_phases(gr.g, b->precision, nullptr, static_cast<const uint64_t *>(b->seeds.p) + gr.first,
-                                     static_cast<int>(gr.members.size()), ws, st);
+                                     static_cast<int>(gr.members.size()), ws,
+                                     static_cast<const double *>(gr.plan->lr.p), st);
         if (e != hipSuccess) return dev_err(e, "phase kernel");
     }
     if (time_pairsum) (void)hipEventRecord(b->ev_a, st);

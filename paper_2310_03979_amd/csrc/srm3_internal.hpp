@@ -82,11 +82,13 @@ struct AmpRef {
     double dkdw;
     double cap;
     int pairs = 1;   // 0: zero bicoherence, the pair sums are not computed (Gaussian field)
+    const double *lc = nullptr;   // per-line pair factor c_k (NULL = 1)
+    const double *lr = nullptr;   // per-line phase factor r_k (NULL = 1); the pure part divides it out
 };
 
 // Kernel launchers (stream-ordered, return the launch status).
 hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, const uint64_t *seeds_dev,
-                         int batch, const Workspace &ws, hipStream_t st);
+                         int batch, const Workspace &ws, const double *lr, hipStream_t st);
 hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
                           const Workspace &ws, hipStream_t st);
 // Persistent pair sum over a device work list (all requests share R).
@@ -149,6 +151,15 @@ struct DevBuf {
     hipError_t alloc(size_t bytes);
 };
 
+// Kappa-dependent bicoherence (plan time, host FP64).  Per-line raw pair sums
+// Q_k = sum_{P(k)} r_i^2 r_j^2 b2(i_w, j_w) (r may be NULL = 1; b2 separable
+// from g2 or dense), and the line factors of the wind bispectrum through the
+// partial-bicoherence recursion.
+void line_pair_sums(int nk, int nw, int W, const double *r, int kind, const double *g2, const double *b2,
+                    std::vector<double> &Q);
+srm3_status wind_factors(int nk, int nw, int W, const double *S, double alpha, double cap, std::vector<double> &c,
+                         std::vector<double> &r, int *sweeps, double *max_sig);
+
 srm3_status fail(srm3_status s, const char *fmt, ...);
 srm3_status dev_err(hipError_t e, const char *what);
 srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_t st);
@@ -168,6 +179,7 @@ struct srm3_plan_s {
     double pair_terms = 0;
     int device = 0;
     srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
+    srm3::DevBuf lc, lr;     // per-line bicoherence factors (kappa-dependent bispectra), FP64, or empty
     int ws_batch = 0;
     bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)
     bool process = false;    // the 1-D process: one kappa line, one-sided spectrum and pairs

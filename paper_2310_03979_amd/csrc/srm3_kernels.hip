@@ -152,7 +152,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
                                                     int b0, Geometry g,
                                                     typename vec<T>::v2 *__restrict__ zrow,
-                                                    T *__restrict__ zcol)
+                                                    T *__restrict__ zcol, const double *__restrict__ lr)
 {
     const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
     const int bl = blockIdx.y;
@@ -167,6 +167,12 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
         const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
         sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
+        if (lr) {
+            // per-line bicoherence factor r_k carried by the phase factor
+            const double rk = lr[static_cast<long>(kk) * g.nc + c];
+            s *= rk;
+            co *= rk;
+        }
         typename vec<T>::v2 v;
         v.x = static_cast<T>(co);
         v.y = static_cast<T>(s);
@@ -666,6 +672,8 @@ struct AmpArgs {
     double dkdw;
     double cap;
     int pairs;                // 0: no pair sums (zero bicoherence)
+    const double *lc;         // per-line pair factor c_k, or null (1)
+    const double *lr;         // per-line phase factor r_k carried by zrow, or null (1)
 };
 
 struct TfftArgs {
@@ -713,8 +721,16 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     const double sraw = sc * amp.sig[li];
     const double rho = (amp.cap > 0.0 && sraw > amp.cap) ? amp.cap / sraw : 1.0;
     const double base = Sp[li] * amp.dkdw;
-    const T p = static_cast<T>(2.0 * sqrt(base * (1.0 - rho * sraw)));
-    const T q = static_cast<T>(2.0 * sqrt(base * rho * sc));
+    double pd = 2.0 * sqrt(base * (1.0 - rho * sraw));
+    double qd = 2.0 * sqrt(base * rho * sc);
+    if (amp.lc) qd *= amp.lc[li];
+    if (amp.lr) {
+        // zrow carries r_k; the pure part takes the bare phase factor
+        const double rk = amp.lr[li];
+        pd = rk > 0.0 ? pd / rk : 0.0;
+    }
+    const T p = static_cast<T>(pd);
+    const T q = static_cast<T>(qd);
     const T2 z = zrow[bi];
     T2 C;
     C.x = fma_(p, z.x, q * t.x);
@@ -1174,7 +1190,7 @@ Workspace carve_workspace(const Geometry &g, int precision, int batch, void *bas
 
 template <typename T>
 static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint64_t *seeds_dev, int batch,
-                           const Workspace &ws, hipStream_t st)
+                           const Workspace &ws, const double *lr, hipStream_t st)
 {
     const long per = static_cast<long>(g.nkp) * g.nc;
     const unsigned gx = static_cast<unsigned>((per + 255) / 256);
@@ -1185,7 +1201,7 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
         phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
                                                        static_cast<typename vec<T>::v2 *>(ws.zrow),
-                                                       static_cast<T *>(ws.zcol));
+                                                       static_cast<T *>(ws.zcol), lr);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1193,10 +1209,10 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
 }
 
 hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds, const uint64_t *seeds_dev,
-                         int batch, const Workspace &ws, hipStream_t st)
+                         int batch, const Workspace &ws, const double *lr, hipStream_t st)
 {
-    return precision == SRM3_FP64 ? phases_t<double>(g, seeds, seeds_dev, batch, ws, st)
-                                  : phases_t<float>(g, seeds, seeds_dev, batch, ws, st);
+    return precision == SRM3_FP64 ? phases_t<double>(g, seeds, seeds_dev, batch, ws, lr, st)
+                                  : phases_t<float>(g, seeds, seeds_dev, batch, ws, lr, st);
 }
 
 template <typename T, int R, bool COMP>
@@ -1312,7 +1328,7 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     a.cin = cin;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs};
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr};
     a.wtab = wtab;
     a.tw = tw;
     a.gout = ws.g;
@@ -1337,7 +1353,7 @@ static hipError_t assemble_t(const Geometry &g, const AmpRef &amp, const void *w
     a.g = g;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs};
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr};
     a.wtab = wtab;
     const long per = static_cast<long>(g.nk) * g.nc;
     assemble_kernel<T><<<dim3(static_cast<unsigned>((per + 255) / 256), batch), 256, 0, st>>>(

@@ -425,7 +425,8 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
                                     q->spec.lam, const_cast<double *>(s->hdr[q->slot].S), st);
                 if (e != hipSuccess) return dev_err(e, "spectrum kernel");
             }
-            e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, ws, st);
+            e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, ws,
+                              static_cast<const double *>(q->r.plan->lr.p), st);
             if (e != hipSuccess) return dev_err(e, "phase kernel");
             if (q->mode == 1) {
                 // the whole pair sum of this request, here on the lane

@@ -47,7 +47,8 @@ class _Spectrum(ctypes.Structure):
 class _Bispectrum(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("g2", _dp), ("b2", _dp), ("beta", _u32p),
                 ("support_w", ctypes.c_int32), ("cap", ctypes.c_double),
-                ("beta_mode", ctypes.c_int32), ("beta_seed", ctypes.c_uint64)]
+                ("beta_mode", ctypes.c_int32), ("beta_seed", ctypes.c_uint64),
+                ("line_c", _dp), ("line_r", _dp), ("alpha", ctypes.c_double)]
 
 
 class _ProcessGrid(ctypes.Structure):
@@ -100,6 +101,8 @@ def load():
     L.srm3_pair_terms.argtypes = [vp, _dp]
     L.srm3_rows_per_wave.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.srm3_plan_set_algorithm.argtypes = [vp, ctypes.c_int32, vp]
+    L.srm3_wind_factors.argtypes = [ctypes.POINTER(_Grid), _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                    _dp, _dp, _dp, ctypes.POINTER(ctypes.c_int32)]
     L.srm3_process_plan.argtypes = [ctypes.POINTER(_ProcessGrid), _dp, ctypes.POINTER(_Bispectrum),
                                     ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.srm3_algorithm_terms.argtypes = [vp, _dp]
@@ -118,7 +121,7 @@ def load():
     L.srm3_batch_destroy.argtypes = [vp]
     L.srm3_batch_destroy.restype = None
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
-    for f in ("srm3_plan", "srm3_process_plan", "srm3_generate", "srm3_coefficients", "srm3_transform",
+    for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_generate", "srm3_coefficients", "srm3_transform",
               "srm3_workspace_bytes", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
               "srm3_algorithm_terms", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
@@ -196,7 +199,7 @@ def _bispectrum(bispectrum: Optional[dict], default_w: int):
     """Marshal a bispectrum dict into the C struct; returns (struct or None, arrays to keep alive, W)."""
     if bispectrum is None:
         return None, [], 1
-    kinds = {"none": 0, "separable": 1, "dense": 2}
+    kinds = {"none": 0, "separable": 1, "dense": 2, "wind": 3}
     modes = {"seeded": 0, "zero": 1, "table": 2}
     kind = bispectrum.get("kind", "separable")
     kind = kinds[kind] if isinstance(kind, str) else int(kind)
@@ -222,6 +225,12 @@ def _bispectrum(bispectrum: Optional[dict], default_w: int):
         bt = np.ascontiguousarray(bispectrum["beta"], dtype=np.uint32)
         keep.append(bt)
         b.beta = bt.ctypes.data_as(_u32p)
+    for name in ("line_c", "line_r"):
+        if bispectrum.get(name) is not None:
+            f = np.ascontiguousarray(bispectrum[name], dtype=np.float64)
+            keep.append(f)
+            setattr(b, name, f.ctypes.data_as(_dp))
+    b.alpha = float(bispectrum.get("alpha", 0.0))
     return b, keep, W
 
 
@@ -378,6 +387,22 @@ def srm3_process_plan(grid: dict, S: np.ndarray, bispectrum: Optional[dict] = No
     p = Plan(h, wave_grid, _precision(precision), W)
     p.process = True
     return p
+
+
+def srm3_wind_factors(grid: dict, S: np.ndarray, alpha: float, cap: float = 0.0, support_w: Optional[int] = None):
+    """Line factors (c, r), Sigma and sweep count of the wind bispectrum
+    (host computation; no GPU needed)."""
+    L = load()
+    g = _Grid(int(grid["n_kappa"]), int(grid["n_omega"]), float(grid["d_kappa"]),
+              float(grid["d_omega"]), int(grid.get("n_x", 1)), int(grid.get("n_t", 1)))
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    c, r, sig = np.zeros_like(S), np.zeros_like(S), np.zeros_like(S)
+    it = ctypes.c_int32()
+    W = int(grid["n_omega"]) if support_w is None else int(support_w)
+    _check(L.srm3_wind_factors(ctypes.byref(g), S.ctypes.data_as(_dp), float(alpha), float(cap), W,
+                               c.ctypes.data_as(_dp), r.ctypes.data_as(_dp), sig.ctypes.data_as(_dp),
+                               ctypes.byref(it)))
+    return c, r, sig, int(it.value)
 
 
 def process_plan_from_workload(wl, precision="fp64", beta_mode="seeded", stream=None, dense=False,

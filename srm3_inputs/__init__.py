@@ -53,6 +53,8 @@ class Workload:
     z: float = 50.0
     lam: float = 10.0
     seed_base: int = 0
+    spectrum_form: str = "workload"     # "paper": the printed closed form of Section 5
+    alpha: float = 0.0                  # > 0: the wind bispectrum of Section 5, scaled
 
     @property
     def n_cols(self) -> int:
@@ -71,6 +73,9 @@ class Workload:
         return np.arange(b, dtype=np.uint64) + np.uint64(self.seed_base)
 
     def spectrum(self) -> np.ndarray:
+        if self.spectrum_form == "paper":
+            return kaimal_davenport_paper(self.n_kappa, self.n_omega, self.d_kappa, self.d_omega,
+                                          U=self.U, u_star=self.u_star, z=self.z, lam=self.lam)
         return kaimal_davenport_lines(self.n_kappa, self.n_omega, self.d_kappa,
                                       self.d_omega, U=self.U, u_star=self.u_star,
                                       z=self.z, lam=self.lam)
@@ -110,6 +115,37 @@ def kaimal_davenport_lines(n_kappa: int, n_omega: int, d_kappa: float, d_omega: 
     S = s_w[None, :] * gam
     S[:, kw == 0] = 0.0
     return np.ascontiguousarray(S)
+
+
+def kaimal_davenport_paper(n_kappa: int, n_omega: int, d_kappa: float, d_omega: float,
+                           U: float = 40.0, u_star: float = 0.4 * 40.0 / math.log(50.0 / 0.03),
+                           z: float = 50.0, lam: float = 10.0) -> np.ndarray:
+    """The closed form printed in Section 5 for the bridge example, on the line
+    grid with |omega| (S is even in omega) and S(., 0) := 0:
+    S = (1/2)(200/2pi) u*^2 (z/U) / [1 + 50 w z/(2 pi U)]^(5/3) * a / (kappa^2 + a^2),
+    a = lam w / (pi U), u* = k U / ln(z / z0) with k = 0.4, z0 = 0.03."""
+    kw = np.arange(-(n_omega - 1), n_omega, dtype=np.float64)
+    w = np.abs(kw) * d_omega
+    kap = np.arange(n_kappa, dtype=np.float64) * d_kappa
+    s_w = 0.5 * 200.0 / (2.0 * math.pi) * u_star ** 2 * (z / U) / (1.0 + 50.0 * w * z / (2.0 * math.pi * U)) ** (5.0 / 3.0)
+    a = lam * w / (math.pi * U)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        S = s_w[None, :] * a[None, :] / (kap[:, None] ** 2 + a[None, :] ** 2)
+    S[:, kw == 0] = 0.0
+    return np.ascontiguousarray(S)
+
+
+def bridge(alpha: float = 1.0, cap: float = 0.9, batch: int = 16) -> Workload:
+    """The long-span bridge example of Section 5: L = 628 m, dk = 2 pi / L,
+    w_u = pi with dw = w_u / (N_w - 1), N_w = 128, N_kappa = 256, N_x = 1024,
+    N_t = 2048, the printed Kaimal/Davenport closed form (U = 40 m/s, z = 50 m,
+    z0 = 0.03, lam = 10), the wind bispectrum scaled by alpha, full support."""
+    nk, nw = 256, 128
+    L = 628.0
+    return Workload(f"bridge_alpha{alpha:g}_cap{cap:g}", nk, nw, 2.0 * math.pi / L, math.pi / (nw - 1),
+                    1024, 2048, nw, batch, math.pi, cap=cap, U=40.0,
+                    u_star=0.4 * 40.0 / math.log(50.0 / 0.03), z=50.0, lam=10.0, seed_base=7000,
+                    spectrum_form="paper", alpha=alpha)
 
 
 def exp_bicoherence_g2(support_w: int, d_omega: float, omega_u: float,
