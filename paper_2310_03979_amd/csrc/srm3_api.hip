@@ -186,7 +186,9 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
 {
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
-    hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, ws, static_cast<const double *>(p->lr.p), st);
+    Workspace wp = ws;
+    if (p->gaussian || p->algo == SRM3_ALGO_KAPPA_FFT) wp.zcol = nullptr;   // no a operand planes needed
+    hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, wp, static_cast<const double *>(p->lr.p), st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
     if (p->gaussian) return SRM3_OK;   // zero bicoherence: the pair sums are not used
@@ -208,9 +210,12 @@ srm3_status run_back(srm3_plan_t p, int mode, const void *cin, int32_t batch, co
 {
     srm3_status s;
     if ((s = event_pair(p, 2, st, true))) return s;
-    hipError_t e = launch_tfft(p->g, p->precision, mode, cin, plan_amp(p), p->wtab.p, p->tw_t.p, batch, ws, st);
+    const bool direct_out = p->g.nx == 1 && p->g.nk == 1;   // the x-transform is the real part
+    hipError_t e = launch_tfft(p->g, p->precision, mode, cin, plan_amp(p), p->wtab.p, p->tw_t.p, batch, ws, st,
+                               direct_out ? out : nullptr);
     if (e != hipSuccess) return dev_err(e, "t-transform kernel");
     if ((s = event_pair(p, 2, st, false))) return s;
+    if (direct_out) return SRM3_OK;
     if ((s = event_pair(p, 3, st, true))) return s;
     e = launch_xfft(p->g, p->precision, p->tw_x.p, batch, ws, out, nullptr, st);
     if (e != hipSuccess) return dev_err(e, "x-transform kernel");
@@ -882,8 +887,9 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
 srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
 {
     for (auto &gr : b->groups) {
-        const Workspace ws = carve_workspace(gr.g, b->precision, static_cast<int>(gr.members.size()),
-                                             static_cast<char *>(b->ws.p) + gr.ws_off);
+        Workspace ws = carve_workspace(gr.g, b->precision, static_cast<int>(gr.members.size()),
+                                       static_cast<char *>(b->ws.p) + gr.ws_off);
+        if (gr.mode != 0) ws.zcol = nullptr;   // no a operand planes needed
         hipError_t e = launch_phases(gr.g, b->precision, nullptr, static_cast<const uint64_t *>(b->seeds.p) + gr.first,
                                      static_cast<int>(gr.members.size()), ws,
                                      static_cast<const double *>(gr.plan->lr.p), st);

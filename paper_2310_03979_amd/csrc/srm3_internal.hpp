@@ -102,8 +102,11 @@ void fill_persistent_item(void *dst, int req, int kb, int cg);
 int waves_per_block();
 constexpr int kXcds = 8;
 // mode 0: assemble C from pair sums and phases; mode 1: read C from `cin`.
+// rout (n_x == n_kappa == 1 only, else ignored): write the real field [B][n_t]
+// directly; the x-transform is then skipped.
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
-                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st);
+                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st,
+                       void *rout = nullptr);
 hipError_t launch_assemble(const Geometry &g, int precision, const AmpRef &amp, const void *wtab, int batch,
                            const Workspace &ws, void *cout, hipStream_t st);
 hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int batch, const Workspace &ws,

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
     }
     const int ic = c - (g.nw - g.W);
-    if (ic >= 0 && ic < g.ncw) {
+    if (zcol && ic >= 0 && ic < g.ncw) {   // zcol null: no direct-form pair sum follows
         using L = ALayout<T>;
         const long plane = L::plane(g);
         T *zc = zcol + static_cast<long>(b) * L::NS * g.ncw * g.nkp +
@@ -686,6 +686,7 @@ struct TfftArgs {
     const void *wtab;     // [ncw][ncw]
     const void *tw;       // [nt]
     void *gout;           // [B][nk][nt]
+    void *rout;           // n_x == 1 only, or null: the field itself, [B][nt] real (no x-transform)
 };
 
 // Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
@@ -768,6 +769,12 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
     }
     __syncthreads();
     fft_lds<T, MAXB>(buf, g.nt, g.nt, 1, static_cast<const T2 *>(a.tw));
+    if (a.rout) {
+        // one kappa line and one x point: the x-transform is the real part
+        T *u = static_cast<T *>(a.rout) + static_cast<long>(row) * g.nt;
+        for (int n = threadIdx.x; n < g.nt; n += blockDim.x) u[n] = buf[n].x;
+        return;
+    }
     T2 *gout = static_cast<T2 *>(a.gout) + static_cast<long>(row) * g.nt;
     for (int n = threadIdx.x; n < g.nt; n += blockDim.x) gout[n] = buf[n];
 }
@@ -1320,9 +1327,10 @@ int waves_per_block() { return kWavesPerBlock; }
 
 template <typename T>
 static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const AmpRef &amp, const void *wtab,
-                         const void *tw, int batch, const Workspace &ws, hipStream_t st)
+                         const void *tw, int batch, const Workspace &ws, void *rout, hipStream_t st)
 {
     TfftArgs a;
+    a.rout = (g.nx == 1 && g.nk == 1) ? rout : nullptr;
     a.g = g;
     a.mode = mode;
     a.cin = cin;
@@ -1339,10 +1347,10 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
 }
 
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
-                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st)
+                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st, void *rout)
 {
-    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, amp, wtab, tw, batch, ws, st)
-                                  : tfft_t<float>(g, mode, cin, amp, wtab, tw, batch, ws, st);
+    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, amp, wtab, tw, batch, ws, rout, st)
+                                  : tfft_t<float>(g, mode, cin, amp, wtab, tw, batch, ws, rout, st);
 }
 
 template <typename T>

@@ -425,7 +425,9 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
                                     q->spec.lam, const_cast<double *>(s->hdr[q->slot].S), st);
                 if (e != hipSuccess) return dev_err(e, "spectrum kernel");
             }
-            e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, ws,
+            Workspace wp = ws;
+            if (q->mode != 0) wp.zcol = nullptr;   // no a operand planes needed
+            e = launch_phases(q->g, s->cfg.precision, nullptr, &hdr_dev[q->slot].seed, 1, wp,
                               static_cast<const double *>(q->r.plan->lr.p), st);
             if (e != hipSuccess) return dev_err(e, "phase kernel");
             if (q->mode == 1) {
