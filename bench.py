@@ -512,10 +512,13 @@ def bench_bridge(args, torch, srm3):
     srm3.srm3_plan_set_algorithm(kplan, "kappa_fft")
     outk = torch.empty_like(out)
     dtk = timed_steps(torch, lambda: srm3.srm3_generate(kplan, seeds, outk), args.steps, args.warmup)
+    fplan = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
+    srm3.srm3_plan_set_algorithm(fplan, "fft2d")
+    dtf = timed_steps(torch, lambda: srm3.srm3_generate(fplan, seeds, outk), args.steps, args.warmup)
     gplan = srm3.srm3_plan(wl.grid_dict(), S, None, "fp32")
     outg = torch.empty_like(out)
     dtg = timed_steps(torch, lambda: srm3.srm3_generate(gplan, seeds, outg), args.steps, args.warmup)
-    log(f"[bench] bridge kappa-DFT {dtk * 1e3:.2f} ms, 2nd-order {dtg * 1e3:.2f} ms")
+    log(f"[bench] bridge kappa-DFT {dtk * 1e3:.2f} ms, 2-D FFT {dtf * 1e3:.2f} ms, 2nd-order {dtg * 1e3:.2f} ms")
 
     def moments(u):
         x = u.double()
@@ -568,6 +571,7 @@ def bench_bridge(args, torch, srm3):
                      "traffic": None, "pair_terms_per_launch": terms * B, "avg_launch_ms": round(ps_ms, 4)},
         "cpu_baseline": None,
         "kappa_fft_grid_points_per_s": points / dtk, "kappa_fft_over_direct": round(dt / dtk, 3),
+        "fft2d_grid_points_per_s": points / dtf, "fft2d_over_direct": round(dt / dtf, 3),
         "second_order_grid_points_per_s": points / dtg, "plan_seconds": round(plan_s, 3),
         "statistics": stats,
     }

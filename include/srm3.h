@@ -189,11 +189,19 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  *                        autoconvolution per kappa frequency, and the inverse
  *                        DFT.  Same result up to rounding; O(M W^2) terms per
  *                        realization instead of O(N_kappa^2 W^2).
+ *   SRM3_ALGO_FFT2D      for rank-one weights only (separable b^2 and
+ *                        beta = 0, e.g. SRM3_BISPEC_WIND): W = g_i g_j, so the
+ *                        whole pair sum is a 2-D linear autoconvolution of
+ *                        g z: the DFT along kappa, then per kappa frequency a
+ *                        forward FFT of length L >= 2(2W - 1) - 1 along the
+ *                        frequency, a squaring and the inverse FFT, then the
+ *                        inverse DFT along kappa.  Same result up to rounding;
+ *                        O(M L log L) work per realization.
  * Switching to SRM3_ALGO_KAPPA_FFT builds its sheared weight table on the
  * device (stream-ordered on hip_stream).  Errors: SRM3_E_INVALID (bad plan or
- * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048, or one realization's
- * transforms or the table above 4 GiB), SRM3_E_NOMEM, SRM3_E_DEVICE. */
-enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1 };
+ * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048; SRM3_ALGO_FFT2D: weights
+ * not rank-one, or L above 16384, 8192 in FP64), SRM3_E_NOMEM, SRM3_E_DEVICE. */
+enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1, SRM3_ALGO_FFT2D = 2 };
 srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream);
 
 /* Complex multiply-accumulate terms the plan's current pair-sum algorithm

@@ -67,6 +67,18 @@ srm3_status upload_bytes(DevBuf &buf, const void *data, size_t bytes, hipStream_
     return SRM3_OK;
 }
 
+KfftTables plan_ktab(srm3_plan_t p)
+{
+    KfftTables t;
+    t.wh = p->wsh.p;
+    t.tw_k = p->tw_k.p;
+    if (p->kg.L > 0) {
+        t.gw = p->gw.p;
+        t.tw_l = p->tw_l.p;
+    }
+    return t;
+}
+
 AmpRef plan_amp(srm3_plan_t p)
 {
     return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
@@ -158,7 +170,7 @@ srm3_status ensure_workspace(srm3_plan_t p, int batch, hipStream_t st)
         }
         p->ws_batch = batch;
     }
-    if (p->algo == SRM3_ALGO_KAPPA_FFT && batch > p->kws_batch) {
+    if (p->algo != SRM3_ALGO_DIRECT && batch > p->kws_batch) {
         const size_t bytes = kfft_workspace_bytes(p->g, p->kg, p->precision, batch);
         hipError_t e = p->kws.alloc(bytes);
         if (e != hipSuccess) {
@@ -187,15 +199,15 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
     Workspace wp = ws;
-    if (p->gaussian || p->algo == SRM3_ALGO_KAPPA_FFT) wp.zcol = nullptr;   // no a operand planes needed
+    if (p->gaussian || p->algo != SRM3_ALGO_DIRECT) wp.zcol = nullptr;   // no a operand planes needed
     hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, wp, static_cast<const double *>(p->lr.p), st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
     if (p->gaussian) return SRM3_OK;   // zero bicoherence: the pair sums are not used
     if ((s = event_pair(p, 1, st, true))) return s;
-    if (p->algo == SRM3_ALGO_KAPPA_FFT) {
+    if (p->algo != SRM3_ALGO_DIRECT) {
         const KfftWorkspace kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
-        e = launch_kfft_pairsum(p->precision, p->g, p->kg, p->wsh.p, p->tw_k.p, batch, ws, kw, st);
+        e = launch_kfft_pairsum(p->precision, p->g, p->kg, plan_ktab(p), batch, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
     } else {
         e = launch_pairsum(p->g, p->precision, p->wtab.p, batch, ws, st);
@@ -398,6 +410,8 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     p->cap = bs.cap;
     p->max_sig = max_sig;
     p->gaussian = bs.kind == SRM3_BISPEC_NONE;
+    if (bs.kind == SRM3_BISPEC_SEPARABLE && bs.beta_mode == SRM3_BETA_ZERO)
+        p->g2_host.assign(bs.g2, bs.g2 + ncw);   // rank-one weights: the 2-D FFT pair sum applies
     p->pair_terms = p->gaussian ? 0.0 : pair_terms;
     Geometry &g = p->g;
     g.nk = nk;
@@ -601,7 +615,7 @@ srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes)
 {
     if (!plan || !bytes || batch < 0) return fail(SRM3_E_INVALID, "bad argument");
     *bytes = workspace_bytes(plan->g, plan->precision, batch);
-    if (plan->algo == SRM3_ALGO_KAPPA_FFT) *bytes += kfft_workspace_bytes(plan->g, plan->kg, plan->precision, batch);
+    if (plan->algo != SRM3_ALGO_DIRECT) *bytes += kfft_workspace_bytes(plan->g, plan->kg, plan->precision, batch);
     return SRM3_OK;
 }
 
@@ -627,30 +641,45 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
         plan->algo = SRM3_ALGO_DIRECT;
         return SRM3_OK;
     }
-    if (algorithm != SRM3_ALGO_KAPPA_FFT) return fail(SRM3_E_INVALID, "algorithm %d", algorithm);
-    if (plan->algo == SRM3_ALGO_KAPPA_FFT) return SRM3_OK;
-    const KfftGeom k = kfft_geometry(plan->g, plan->process);
+    if (algorithm != SRM3_ALGO_KAPPA_FFT && algorithm != SRM3_ALGO_FFT2D)
+        return fail(SRM3_E_INVALID, "algorithm %d", algorithm);
+    if (plan->algo == algorithm) return SRM3_OK;
+    KfftGeom k = kfft_geometry(plan->g, plan->process);
     std::string why;
     if (!kfft_supported(plan->g, k, plan->precision, &why))
         return fail(SRM3_E_UNSUPPORTED, "kappa-FFT pair sum: %s", why.c_str());
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const size_t e2 = plan->precision == SRM3_FP64 ? 16 : 8;
-    hipError_t e = plan->wsh.alloc(static_cast<size_t>(k.wh_rows) * k.nca * e2);
-    if (e != hipSuccess) return fail(SRM3_E_NOMEM, "weight table hipMalloc: %s", hipGetErrorString(e));
-    if ((e = launch_wsh(plan->precision, plan->wtab.p, plan->g, k, plan->wsh.p, st)) != hipSuccess)
-        return dev_err(e, "sheared weight table kernel");
     srm3_status s;
+    if (algorithm == SRM3_ALGO_FFT2D) {
+        if (plan->g2_host.empty())
+            return fail(SRM3_E_UNSUPPORTED, "the 2-D FFT pair sum needs rank-one weights (separable b^2, beta = 0)");
+        int L = 1;
+        while (L < 2 * plan->g.ncw - 1) L *= 2;
+        const int lmax = plan->precision == SRM3_FP64 ? 8192 : 16384;   // one row transform in 128 KB of LDS
+        if (L > lmax) return fail(SRM3_E_UNSUPPORTED, "2-D FFT pair sum: frequency transform %d above %d", L, lmax);
+        k.L = L;
+        std::vector<double> g(plan->g2_host.size());
+        for (size_t i = 0; i < g.size(); ++i) g[i] = std::sqrt(plan->g2_host[i]);
+        if ((s = upload(plan->gw, g, plan->precision, st))) return s;
+        if ((s = upload(plan->tw_l, twiddles(L), plan->precision, st))) return s;
+    } else {
+        const size_t e2 = plan->precision == SRM3_FP64 ? 16 : 8;
+        hipError_t e = plan->wsh.alloc(static_cast<size_t>(k.wh_rows) * k.nca * e2);
+        if (e != hipSuccess) return fail(SRM3_E_NOMEM, "weight table hipMalloc: %s", hipGetErrorString(e));
+        if ((e = launch_wsh(plan->precision, plan->wtab.p, plan->g, k, plan->wsh.p, st)) != hipSuccess)
+            return dev_err(e, "sheared weight table kernel");
+    }
     if ((s = upload(plan->tw_k, twiddles(k.M), plan->precision, st))) return s;
     plan->kg = k;
     plan->kws_batch = 0;
-    plan->algo = SRM3_ALGO_KAPPA_FFT;
+    plan->algo = algorithm;
     return SRM3_OK;
 }
 
 srm3_status srm3_algorithm_terms(srm3_plan_t plan, double *terms)
 {
     if (!plan || !terms) return fail(SRM3_E_INVALID, "bad argument");
-    *terms = plan->algo == SRM3_ALGO_KAPPA_FFT ? kfft_terms(plan->g, plan->kg) : plan->pair_terms;
+    *terms = plan->algo != SRM3_ALGO_DIRECT ? kfft_terms(plan->g, plan->kg) : plan->pair_terms;
     return SRM3_OK;
 }
 
@@ -793,7 +822,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
     int first = 0;
     for (auto &gr : b->groups) {
         gr.g = gr.plan->g;
-        gr.mode = gr.plan->gaussian ? 2 : (gr.plan->algo == SRM3_ALGO_KAPPA_FFT ? 1 : 0);
+        gr.mode = gr.plan->gaussian ? 2 : (gr.plan->algo != SRM3_ALGO_DIRECT ? 1 : 0);
         if (gr.mode == 0) {
             gr.g.R = rows_for(gr.g.nk, b->precision, R);
             gr.g.nkp = ((gr.g.nk + gr.g.R - 1) / gr.g.R) * gr.g.R;
@@ -903,7 +932,7 @@ srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
         const Workspace ws = carve_workspace(gr.g, b->precision, nb, static_cast<char *>(b->ws.p) + gr.ws_off);
         const KfftWorkspace kw = carve_kfft(gr.g, gr.plan->kg, b->precision, nb,
                                             static_cast<char *>(b->ws.p) + gr.kws_off);
-        e = launch_kfft_pairsum(b->precision, gr.g, gr.plan->kg, gr.plan->wsh.p, gr.plan->tw_k.p, nb, ws, kw, st);
+        e = launch_kfft_pairsum(b->precision, gr.g, gr.plan->kg, plan_ktab(gr.plan), nb, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-DFT pair-sum kernels");
     }
     if (b->n_items > 0) {

@@ -124,6 +124,16 @@ struct KfftGeom {
     int kw0 = 0;      // its k_omega
     int wh_rows = 0;  // rows of the sheared weight table, zero rows included
     int one_sided = 0;  // 1: outputs and partners at k_omega >= 0 only (the 1-D process)
+    int L = 0;          // > 0: rank-one weights, the frequency autoconvolution runs as FFTs of length L
+};
+// Device tables of the kappa-DFT pair sum: the sheared half weight table and
+// kappa twiddles; for rank-one weights W = g_i g_j instead the factor g [2W-1]
+// and the twiddles of the length-L frequency transform.
+struct KfftTables {
+    const void *wh = nullptr;
+    const void *tw_k = nullptr;
+    const void *gw = nullptr;
+    const void *tw_l = nullptr;
 };
 struct KfftWorkspace {
     void *Z = nullptr;   // [B][M][2W - 1] complex
@@ -135,8 +145,8 @@ KfftWorkspace carve_kfft(const Geometry &g, const KfftGeom &k, int precision, in
 bool kfft_supported(const Geometry &g, const KfftGeom &k, int precision, std::string *why);
 hipError_t launch_wsh(int precision, const void *wt, const Geometry &g, const KfftGeom &k, void *wh, hipStream_t st);
 // tw: e^{+2 pi i n / M}, n < M
-hipError_t launch_kfft_pairsum(int precision, const Geometry &g, const KfftGeom &k, const void *wh, const void *tw,
-                               int batch, const Workspace &ws, const KfftWorkspace &kw, hipStream_t st);
+hipError_t launch_kfft_pairsum(int precision, const Geometry &g, const KfftGeom &k, const KfftTables &t, int batch,
+                               const Workspace &ws, const KfftWorkspace &kw, hipStream_t st);
 double kfft_terms(const Geometry &g, const KfftGeom &k);
 
 int pairsum_rows_per_wave(int nk, int precision);
@@ -190,6 +200,8 @@ struct srm3_plan_s {
     int algo = SRM3_ALGO_DIRECT;
     srm3::KfftGeom kg{};
     srm3::DevBuf wsh, tw_k, kws;
+    srm3::DevBuf gw, tw_l;   // rank-one weights (SRM3_ALGO_FFT2D): sqrt(g2) and length-L twiddles
+    std::vector<double> g2_host;   // separable factor of a plan with beta == 0, else empty
     int kws_batch = 0;
     // profiling
     bool prof = false;
@@ -203,4 +215,5 @@ struct srm3_plan_s {
 
 namespace srm3 {
 AmpRef plan_amp(srm3_plan_t p);
+KfftTables plan_ktab(srm3_plan_t p);
 }  // namespace srm3

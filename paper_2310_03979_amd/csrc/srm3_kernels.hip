@@ -918,6 +918,63 @@ __global__ __launch_bounds__(256) void zero_cols_kernel(typename vec<T>::v2 *tsu
     tsum[static_cast<long>(blockIdx.y) * per + idx] = z;
 }
 
+// Rank-one weights W(i_w, j_w) = g_i g_j (separable bicoherence, beta = 0):
+// the weighted frequency autoconvolution of a DFT row is a plain linear
+// autoconvolution of y = g Z, done as a forward FFT of length L >= 2(2W-1) - 1,
+// a squaring and an inverse FFT, all in LDS (one block per row).  The forward
+// transform is the inverse one on the conjugate; F(y)^2 = conj(conj(F(y))^2).
+// Output column cc holds k_w = kw0 + cc, i.e. index k_w + 2W - 2 of the
+// convolution, scaled by 1/L.
+struct RowconvArgs {
+    const void *Z;      // [rows][2W - 1] phase DFTs along kappa
+    void *Y;            // [rows][nca]
+    const void *gw;     // [2W - 1] g = sqrt(g2), path precision
+    const void *tw;     // [L] exp(+2 pi i n / L)
+    int W, nca, kw0, L;
+};
+
+template <typename T, int MAXB>
+__global__ __launch_bounds__(1024) void rowconv_kernel(RowconvArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    extern __shared__ unsigned char smem_raw[];
+    T2 *buf = reinterpret_cast<T2 *>(smem_raw);
+    const int ncw = 2 * a.W - 1;
+    const long row = blockIdx.x;
+    const T2 *z = static_cast<const T2 *>(a.Z) + row * ncw;
+    const T *gw = static_cast<const T *>(a.gw);
+    for (int n = threadIdx.x; n < a.L; n += blockDim.x) {
+        T2 v;
+        v.x = T(0);
+        v.y = T(0);
+        if (n < ncw) {
+            const T2 x = z[n];
+            v.x = gw[n] * x.x;
+            v.y = -gw[n] * x.y;
+        }
+        buf[n] = v;
+    }
+    __syncthreads();
+    fft_lds<T, MAXB>(buf, a.L, a.L, 1, static_cast<const T2 *>(a.tw));
+    for (int n = threadIdx.x; n < a.L; n += blockDim.x) {
+        const T2 f = buf[n];
+        T2 v;
+        v.x = f.x * f.x - f.y * f.y;
+        v.y = T(-2) * f.x * f.y;
+        buf[n] = v;
+    }
+    __syncthreads();
+    fft_lds<T, MAXB>(buf, a.L, a.L, 1, static_cast<const T2 *>(a.tw));
+    T2 *y = static_cast<T2 *>(a.Y) + row * a.nca;
+    const T sc = T(1) / static_cast<T>(a.L);
+    for (int cc = threadIdx.x; cc < a.nca; cc += blockDim.x) {
+        T2 v = buf[a.kw0 + cc + 2 * a.W - 2];
+        v.x *= sc;
+        v.y *= sc;
+        y[cc] = v;
+    }
+}
+
 // Sheared half table Wh[ic][cc] = f W(i_w, kw - i_w) over the active output
 // columns cc (kw = kw0 + cc), zero outside the support; `pad` rows of zeros
 // follow the table.
@@ -1479,9 +1536,10 @@ static hipError_t colfft_t(ColfftArgs a, int batch, hipStream_t st)
 }
 
 template <typename T>
-static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const void *wh, const void *tw_i, int batch,
+static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const KfftTables &tab, int batch,
                                  const Workspace &ws, const KfftWorkspace &kw, hipStream_t st)
 {
+    const void *wh = tab.wh, *tw_i = tab.tw_k;
     using T2 = typename vec<T>::v2;
     hipError_t e;
     for (int b0 = 0; b0 < batch; b0 += 65535) {
@@ -1505,6 +1563,29 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const voi
         f.scale = 1.0;
         if ((e = colfft_t<T>(f, nb, st)) != hipSuccess) return e;
     }
+    if (k.L > 0) {
+        // rank-one weights: FFT autoconvolution of every (realization, q) row
+        RowconvArgs r{};
+        r.Z = kw.Z;
+        r.Y = kw.Y;
+        r.gw = tab.gw;
+        r.tw = tab.tw_l;
+        r.W = g.W;
+        r.nca = k.nca;
+        r.kw0 = k.kw0;
+        r.L = k.L;
+        const long rows = static_cast<long>(batch) * k.M;
+        const int thr = fft_threads(k.L / 2);
+        const size_t lds = static_cast<size_t>(k.L) * sizeof(T2);
+        for (long r0 = 0; r0 < rows; r0 += 1L << 30) {
+            const long nr = std::min(rows - r0, 1L << 30);
+            RowconvArgs rr = r;
+            rr.Z = static_cast<const T2 *>(kw.Z) + r0 * g.ncw;
+            rr.Y = static_cast<T2 *>(kw.Y) + r0 * k.nca;
+            rowconv_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(nr)), thr, lds, st>>>(rr);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    } else {
     // weighted frequency autoconvolution per kappa frequency q
     YpairArgs y{};
     y.Z = kw.Z;
@@ -1530,6 +1611,7 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const voi
     ypair2_kernel<T, kY2Rows, kY2Chunk><<<dim3(static_cast<unsigned>(static_cast<long>(y.per_xcd) * kNumXcd)),
                                          64 * kWavesPerBlock, lds, st>>>(y);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     for (int b0 = 0; b0 < batch; b0 += 65535) {
         const int nb = std::min(65535, batch - b0);
         // inverse DFT along kappa, first n_kappa rows, halved: T = O / 2
@@ -1561,15 +1643,21 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const voi
     return hipSuccess;
 }
 
-hipError_t launch_kfft_pairsum(int precision, const Geometry &g, const KfftGeom &k, const void *wh, const void *tw,
-                               int batch, const Workspace &ws, const KfftWorkspace &kw, hipStream_t st)
+hipError_t launch_kfft_pairsum(int precision, const Geometry &g, const KfftGeom &k, const KfftTables &t, int batch,
+                               const Workspace &ws, const KfftWorkspace &kw, hipStream_t st)
 {
-    return precision == SRM3_FP64 ? kfft_pairsum_t<double>(g, k, wh, tw, batch, ws, kw, st)
-                                  : kfft_pairsum_t<float>(g, k, wh, tw, batch, ws, kw, st);
+    return precision == SRM3_FP64 ? kfft_pairsum_t<double>(g, k, t, batch, ws, kw, st)
+                                  : kfft_pairsum_t<float>(g, k, t, batch, ws, kw, st);
 }
 
 double kfft_terms(const Geometry &g, const KfftGeom &k)
 {
+    if (k.L > 0) {
+        // two length-L transforms (L/2 log2 L butterflies each) and L squarings per row
+        int lg = 0;
+        while ((1 << lg) < k.L) ++lg;
+        return static_cast<double>(k.M) * (static_cast<double>(k.L) * lg + k.L);
+    }
     // complex terms of the frequency autoconvolution per realization: for each
     // q, the unordered support pairs (i_w >= j_w) of every active output
     double t = 0;
@@ -1591,6 +1679,9 @@ static hipError_t prepare_t()
     const int lds = 131072;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T, kFftMaxB>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rowconv_kernel<T, kFftMaxB>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T, kFftMaxB>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);

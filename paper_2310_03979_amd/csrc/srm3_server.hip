@@ -274,7 +274,7 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     q->own_spec = spectrum != nullptr;
     if (spectrum) q->spec = *spectrum;
     q->g = r.plan->g;
-    q->mode = r.plan->gaussian ? 2 : (r.plan->algo == SRM3_ALGO_KAPPA_FFT ? 1 : 0);
+    q->mode = r.plan->gaussian ? 2 : (r.plan->algo != SRM3_ALGO_DIRECT ? 1 : 0);
     if (q->mode == 0) {
         q->g.R = rows_for(q->g.nk, s->cfg.precision, s->R);
         if (q->g.R != s->R) return fail(SRM3_E_UNSUPPORTED, "grids with n_kappa < %d are not served", s->R);
@@ -434,7 +434,7 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
                 // the whole pair sum of this request, here on the lane
                 const srm3_plan_t p = q->r.plan;
                 const KfftWorkspace kw = carve_kfft(q->g, p->kg, s->cfg.precision, 1, base + q->kfft_off);
-                e = launch_kfft_pairsum(s->cfg.precision, q->g, p->kg, p->wsh.p, p->tw_k.p, 1, ws, kw, st);
+                e = launch_kfft_pairsum(s->cfg.precision, q->g, p->kg, plan_ktab(p), 1, ws, kw, st);
                 if (e != hipSuccess) return dev_err(e, "kappa-DFT pair-sum kernels");
             }
             q->fresh = false;
