@@ -12,6 +12,8 @@ over independent outputs).  This file only builds and marshals:
 * ``line_terms``      -- raw bicoherence sum, rescale factor, Sigma, pair count
 * ``coefficients``    -- C_k by explicit enumeration of the pair set P(k)
 * ``field`` / ``field_points`` / ``field_nested`` -- direct cosine sums
+* ``WindProblem``, ``ProductProblem`` -- kappa-dependent bispectra through the
+  partial-bicoherence recursion (Section 4.1, Section 5)
 * ``ProcessProblem``, ``process_phases``, ``process_biphase``,
   ``process_field`` -- the 1-D stochastic process u(t) (Section 3)
 
@@ -55,7 +57,7 @@ class _Problem(ctypes.Structure):
                 ("dk", ctypes.c_double), ("dw", ctypes.c_double),
                 ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double),
                 ("line_c", _dp), ("line_r", _dp), ("mode", ctypes.c_int), ("alpha", ctypes.c_double),
-                ("Sp", _dp)]
+                ("Sp", _dp), ("F", _dp), ("G", _dp), ("H", _dp)]
 
 
 class _Process(ctypes.Structure):
@@ -230,6 +232,33 @@ class WindProblem(Problem):
         Si, Sj, Sk = self.S[ik, iw + nw - 1], self.S[jk, jw + nw - 1], self.S[kk, kw + nw - 1]
         return self.alpha * 2.0 * math.sqrt(Si * Sj * Sk) / (
             3.0 * math.sqrt(3.0 * abs(kw * self.d_omega) * kk * self.d_kappa))
+
+
+class ProductProblem(WindProblem):
+    """A prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w)
+    (complex; H may be None = 1) through the partial-bicoherence recursion of
+    Section 4.1, with beta = atan2(Im B, Re B); ``solve()`` finds S_p."""
+
+    def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, F, G, H, cap):
+        super().__init__(n_kappa, n_omega, support_w, d_kappa, d_omega, S, 0.0, cap)
+        nc, nwc = 2 * n_omega - 1, 2 * support_w - 1
+        self.F = _cbuf(np.asarray(F).reshape(n_kappa, nc))
+        self.G = _cbuf(np.asarray(G).reshape(n_kappa, nc))
+        self.H = None if H is None else _cbuf(np.asarray(H).reshape(nwc, nwc))
+        self._c.mode = 2
+        self._c.F = _ptr(self.F, _dp)
+        self._c.G = _ptr(self.G, _dp)
+        self._c.H = None if self.H is None else _ptr(self.H, _dp)
+
+    def bispectrum_c(self, ik, iw, jk, jw) -> complex:
+        nw, W = self.n_omega, self.W
+        F = self.F[ik + jk, iw + jw + nw - 1]
+        G1, G2 = self.G[ik, iw + nw - 1], self.G[jk, jw + nw - 1]
+        B = complex(F[0], F[1]) * complex(G1[0], G1[1]) * complex(G2[0], G2[1])
+        if self.H is not None:
+            h = self.H[iw + W - 1, jw + W - 1]
+            B *= complex(h[0], h[1])
+        return B
 
 
 def _cbuf(C):

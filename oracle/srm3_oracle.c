@@ -108,13 +108,37 @@ typedef struct {
      *  line_c, line_r [nk][2nw-1]: b2_raw(i, j -> k) = c_k^2 r_i^2 r_j^2 b2(iw, jw);
      *  mode 1: the wind bispectrum of Section 5 (Eq. bispectrum, scaled by
      *  alpha, beta = 0) through the partial bicoherence of Section 4.1,
-     *  b_p^2 = |B|^2 dk dw / (S_p,i S_p,j S_k), with S_p from Sp [nk][2nw-1]. */
+     *  b_p^2 = |B|^2 dk dw / (S_p,i S_p,j S_k), with S_p from Sp [nk][2nw-1].
+     *  mode 2: a prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w)
+     *  (complex, interleaved re/im; H may be NULL = 1) through the same partial
+     *  bicoherence, with beta = atan2(Im B, Re B). */
     const double *line_c;
     const double *line_r;
     int mode;
     double alpha;
     const double *Sp;
+    const double *F;        /* mode 2: [nk][2nw-1] complex */
+    const double *G;        /* mode 2: [nk][2nw-1] complex */
+    const double *H;        /* mode 2: [2W-1][2W-1] complex, or NULL */
 } oracle_problem;
+
+/* The prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w). */
+static void product_B(const oracle_problem *p, int ik, int iw, int jk, int jw, double *re, double *im)
+{
+    const int nc = 2 * p->nw - 1, W = p->W, n = 2 * W - 1;
+    const size_t li = (size_t)ik * nc + iw + p->nw - 1, lj = (size_t)jk * nc + jw + p->nw - 1;
+    const size_t lk = (size_t)(ik + jk) * nc + iw + jw + p->nw - 1;
+    double r = p->F[2 * lk], m = p->F[2 * lk + 1];
+    double t;
+    t = r * p->G[2 * li] - m * p->G[2 * li + 1]; m = r * p->G[2 * li + 1] + m * p->G[2 * li]; r = t;
+    t = r * p->G[2 * lj] - m * p->G[2 * lj + 1]; m = r * p->G[2 * lj + 1] + m * p->G[2 * lj]; r = t;
+    if (p->H) {
+        const size_t e = (size_t)(iw + W - 1) * n + (jw + W - 1);
+        t = r * p->H[2 * e] - m * p->H[2 * e + 1]; m = r * p->H[2 * e + 1] + m * p->H[2 * e]; r = t;
+    }
+    *re = r;
+    *im = m;
+}
 
 /* The wind bispectrum (Section 5, Eq. bispectrum) between lines i and j,
  * scaled by alpha, with |omega_i + omega_j| under the root (the half-plane
@@ -143,6 +167,13 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
         if (B == 0.0) return 0.0;
         return B * B * p->dk * p->dw / (p->Sp[li] * p->Sp[lj] * p->S[lk]);
     }
+    if (p->mode == 2) {
+        double re, im;
+        product_B(p, ik, iw, jk, jw, &re, &im);
+        const double B2 = re * re + im * im;
+        if (B2 == 0.0 || p->S[lk] <= 0.0 || p->Sp[li] <= 0.0 || p->Sp[lj] <= 0.0) return 0.0;
+        return B2 * p->dk * p->dw / (p->Sp[li] * p->Sp[lj] * p->S[lk]);
+    }
     double v = p->b2[(size_t)(iw + W - 1) * n + (jw + W - 1)];
     if (p->line_c) v *= p->line_c[lk] * p->line_c[lk];
     if (p->line_r) v *= p->line_r[li] * p->line_r[li] * p->line_r[lj] * p->line_r[lj];
@@ -152,7 +183,16 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
 static uint32_t pair_beta(const oracle_problem *p, int iw, int jw)
 {
     const int W = p->W, n = 2 * W - 1;
-    return p->mode == 1 ? 0u : p->beta[(size_t)(iw + W - 1) * n + (jw + W - 1)];
+    return p->mode != 0 ? 0u : p->beta[(size_t)(iw + W - 1) * n + (jw + W - 1)];
+}
+
+/* Biphase of a prescribed product bispectrum, in radians. */
+static double pair_beta_rad(const oracle_problem *p, int ik, int iw, int jk, int jw)
+{
+    if (p->mode != 2) return 0.0;
+    double re, im;
+    product_B(p, ik, iw, jk, jw, &re, &im);
+    return atan2(im, re);
 }
 
 /* Is the pair (i, j), i + j = k, the canonical member of its unordered pair? */
@@ -224,7 +264,7 @@ int oracle_coefficients(const oracle_problem *p, const uint32_t *U, long nlines,
                 const uint32_t ang = U[(size_t)ik * nc + (iw + nw - 1)]
                                    + U[(size_t)jk * nc + (jw + nw - 1)]
                                    + pair_beta(p, iw, jw);  /* exact mod 2^32 */
-                const double th = TWO_PI * (double)ang / 4294967296.0;
+                const double th = TWO_PI * (double)ang / 4294967296.0 + pair_beta_rad(p, ik, iw, jk, jw);
                 re += bp * cos(th);
                 im += bp * sin(th);
             }
@@ -249,7 +289,7 @@ int oracle_wind_solve(oracle_problem *p, double *Sp, int max_iter, double tol)
     const size_t nl = (size_t)nk * nc;
     double *next = (double *)malloc(sizeof(double) * nl);
     for (size_t l = 0; l < nl; ++l) Sp[l] = p->S[l];
-    p->mode = 1;
+    if (p->mode != 2) p->mode = 1;   /* mode 2: the caller's product bispectrum */
     p->Sp = Sp;
     int it;
     for (it = 1; it <= max_iter; ++it) {

@@ -189,3 +189,88 @@ def test_wind_third_moment_is_the_bispectrum_integral(oracle_mod):
     assert abs(X2.mean() - var) <= 4.5 * se2
     assert abs(X3.mean() - m3) <= 4.5 * se3
     assert abs(m3 - m3_wrong) >= 10 * se3        # the test can tell S_p from S
+
+
+def _product(oracle_mod, nk, nw, W, seed, scale, cap=0.0, with_h=True):
+    rng = np.random.default_rng(seed)
+    S = inp.random_spectrum(nk, nw, seed=seed)
+    shape = (nk, 2 * nw - 1)
+    F = scale * (rng.uniform(0.2, 1.0, shape) * np.exp(1j * rng.uniform(0, 2 * np.pi, shape)))
+    G = np.sqrt(S) * rng.uniform(0.5, 1.0, shape) * np.exp(1j * rng.uniform(0, 2 * np.pi, shape))
+    H = None
+    if with_h:
+        A = rng.uniform(0.3, 1.0, (2 * W - 1, 2 * W - 1)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (2 * W - 1, 2 * W - 1)))
+        H = 0.5 * (A + A.T)
+    return oracle_mod.ProductProblem(nk, nw, W, 0.5, 0.4, S, F, G, H, cap)
+
+
+def test_product_bispectrum_reduces_to_wind(oracle_mod):
+    """The wind bispectrum is the product form with F_k = alpha 2 sqrt(S_k) /
+    (3 sqrt(3 |w_k| kappa_k)), G = sqrt(S), H = 1."""
+    nk, nw, W = 5, 6, 6
+    Wd = _wind(oracle_mod, nk=nk, nw=nw, W=W, alpha=0.5)
+    Wd.solve()
+    S = Wd.S
+    kk = np.arange(nk)[:, None]
+    kw = np.abs(np.arange(-(nw - 1), nw))[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = 0.5 * 2.0 * np.sqrt(S) / (3.0 * np.sqrt(3.0 * kw * Wd.d_omega * kk * Wd.d_kappa))
+    F[~np.isfinite(F)] = 0.0
+    P = oracle_mod.ProductProblem(nk, nw, W, Wd.d_kappa, Wd.d_omega, S, F + 0j, np.sqrt(S) + 0j, None, 0.0)
+    P.solve()
+    assert np.max(np.abs(P.Sp - Wd.Sp)) <= 1e-14 * np.max(S)
+    a, b = P.coefficients(seed=8), Wd.coefficients(seed=8)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(a))
+
+
+def test_product_solution_in_another_order(oracle_mod):
+    P = _product(oracle_mod, 4, 4, 4, seed=5, scale=0.4)
+    P.solve()
+    nk, nw, W = P.n_kappa, P.n_omega, P.W
+    c0 = nw - 1
+    Sp = P.S.copy()
+    dkdw = P.d_kappa * P.d_omega
+    for kk in range(nk):
+        for _ in range(500):
+            new = Sp[kk].copy()
+            for kw in range(-(nw - 1), nw):
+                tot = 0.0
+                for ik, iw, jk, jw in _pairs(nk, nw, W, kk, kw):
+                    B = P.bispectrum_c(ik, iw, jk, jw)
+                    if P.S[kk, kw + c0] > 0 and Sp[ik, iw + c0] > 0 and Sp[jk, jw + c0] > 0:
+                        tot += abs(B) ** 2 * dkdw / (Sp[ik, iw + c0] * Sp[jk, jw + c0] * P.S[kk, kw + c0])
+                new[kw + c0] = P.S[kk, kw + c0] * (1.0 - tot)
+            done = np.max(np.abs(new - Sp[kk])) <= 1e-16 * np.max(P.S)
+            Sp[kk] = new
+            if done:
+                break
+    assert np.max(np.abs(Sp - P.Sp)) <= 1e-13 * np.max(P.S)
+
+
+def test_product_third_moment_is_the_bispectrum_integral(oracle_mod):
+    """With a complex prescribed B the biphase is atan2(Im B, Re B), and the
+    third moment is 6 sum_k sum_{P(k)} c_p Re(B_p) (dk dw)^2."""
+    nk, nw, nx, nt = 3, 4, 4, 8
+    P = _product(oracle_mod, nk, nw, nw, seed=21, scale=0.9)
+    P.solve()
+    dkdw = P.d_kappa * P.d_omega
+    m3, m3_nophase = 0.0, 0.0
+    for kk in range(nk):
+        for kw in range(-(nw - 1), nw):
+            if P.S[kk, kw + nw - 1] <= 0:
+                continue
+            for ik, iw, jk, jw in _pairs(nk, nw, P.W, kk, kw):
+                if P.S[ik, iw + nw - 1] <= 0 or P.S[jk, jw + nw - 1] <= 0:
+                    continue
+                B = P.bispectrum_c(ik, iw, jk, jw)
+                c = 1.0 if (ik == jk and iw == jw) else 2.0
+                m3 += 6.0 * c * B.real * dkdw ** 2
+                m3_nophase += 6.0 * c * abs(B) * dkdw ** 2
+    R = 20000
+    X3 = np.zeros(R)
+    for r in range(R):
+        u = oracle_mod.field(P.coefficients(seed=3000 + r), nx, nt)
+        X3[r] = np.mean(u ** 3)
+    se3 = X3.std(ddof=1) / math.sqrt(R)
+    assert abs(X3.mean() - m3) <= 4.5 * se3
+    assert abs(m3 - m3_nophase) >= 10 * se3       # the biphase matters at this size
