@@ -64,8 +64,10 @@ typedef enum {
     SRM3_BISPEC_NONE = 0,      /* b == 0: the 2nd-order (Gaussian) SRM of Section 3 */
     SRM3_BISPEC_SEPARABLE = 1, /* b^2_raw(i_w, j_w) = g2[i_w] * g2[j_w] */
     SRM3_BISPEC_DENSE = 2,     /* b^2_raw given as a full symmetric table */
-    SRM3_BISPEC_WIND = 3       /* the wind bispectrum of Section 5 (Eq. bispectrum) times alpha, beta = 0,
+    SRM3_BISPEC_WIND = 3,      /* the wind bispectrum of Section 5 (Eq. bispectrum) times alpha, beta = 0,
                                   through the partial bicoherence of Section 4.1 (see below) */
+    SRM3_BISPEC_PRODUCT = 4    /* a prescribed bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w) through the
+                                  partial bicoherence, beta = atan2(Im B, Re B) (see below) */
 } srm3_bispec_kind;
 
 typedef enum {
@@ -112,7 +114,25 @@ typedef struct {
     const double *line_c;
     const double *line_r;
     double alpha;            /* SRM3_BISPEC_WIND: scale of the bispectrum, > 0 */
+    /* SRM3_BISPEC_PRODUCT: host complex arrays (interleaved re, im): F and G
+     * [n_kappa][2 n_omega - 1], H [2W-1][2W-1] symmetric (NULL = 1). */
+    const double *prod_f;
+    const double *prod_g;
+    const double *prod_h;
 } srm3_bispectrum;
+
+/* SRM3_BISPEC_PRODUCT.  A prescribed bispectrum of product form
+ * B(i, j) = F_k G_i G_j H(i_w, j_w), k = i + j (complex), enters as in
+ * Section 4.1: b_p = |B| sqrt(dk dw) / sqrt(S_p,i S_p,j S_k) and
+ * beta_p = atan2(Im B, Re B), with S_p = S (1 - Sigma) solved as for
+ * SRM3_BISPEC_WIND (least fixed point, optional cap).  Equivalently
+ * b_p e^{i beta_p} = c_k rho_i rho_j H(i_w, j_w) with the complex line factors
+ * c_k = F_k sqrt(dk dw / S_k) and rho_i = G_i / sqrt(S_p,i) (zero where S is
+ * zero); the library applies rho to the phase factors, c to a line's pair
+ * sum and H as the weight table.  The wind bispectrum is the case
+ * F_k = alpha 2 sqrt(S_k) / (3 sqrt(3 |w_k| kappa_k)), G = sqrt(S), H = 1.
+ * support_w limits the pairs; g2, b2, beta and alpha are ignored.  Plan-time
+ * sums: 2-D FFTs when H is NULL, else O(M (4W-3)(2W-1)) per sweep. */
 
 /* SRM3_BISPEC_WIND.  B = alpha 2 sqrt(S_i S_j S_k) / (3 sqrt(3 |w_i + w_j| (kappa_i + kappa_j)))
  * (Section 5; |.| since the kappa >= 0 half plane holds negative frequencies;
@@ -135,6 +155,13 @@ typedef struct {
  * srm3_plan with that kind. */
 srm3_status srm3_wind_factors(const srm3_grid *grid, const double *S, double alpha, double cap, int32_t support_w,
                               double *line_c, double *line_r, double *sigma, int32_t *sweeps);
+
+/* The complex line factors c and rho (interleaved, [n_kappa][2 n_omega - 1][2])
+ * and Sigma that SRM3_BISPEC_PRODUCT derives (host only, FP64); F, G, H as in
+ * srm3_bispectrum.  Errors as for srm3_plan with that kind. */
+srm3_status srm3_product_factors(const srm3_grid *grid, const double *S, const double *F, const double *G,
+                                 const double *H, int32_t support_w, double cap, double *line_c, double *line_rho,
+                                 double *sigma, int32_t *sweeps);
 
 /* Build a plan: validates every input, computes on the host in FP64 the
  * per-line raw bicoherence sums, the cap factor rho_k, Sigma_k and the two

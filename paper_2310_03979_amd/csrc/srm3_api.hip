@@ -281,25 +281,62 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (W < 1 || W > nw) return fail(SRM3_E_INVALID, "support_w=%d must be in [1, n_omega=%d]", W, nw);
     const int ncw = 2 * W - 1;
     if (bs.kind != SRM3_BISPEC_NONE && bs.kind != SRM3_BISPEC_SEPARABLE && bs.kind != SRM3_BISPEC_DENSE &&
-        bs.kind != SRM3_BISPEC_WIND)
+        bs.kind != SRM3_BISPEC_WIND && bs.kind != SRM3_BISPEC_PRODUCT)
         return fail(SRM3_E_INVALID, "bispectrum kind %d", bs.kind);
     if (bs.kind == SRM3_BISPEC_NONE) bs.line_c = bs.line_r = nullptr;
     const size_t nlines0 = static_cast<size_t>(nk) * nc;
-    std::vector<double> wind_c, wind_r;
+    // complex per-line factors c (pair sum) and rho (phase factor), interleaved
+    std::vector<double> lcx, lrx, hw2, hcx;
     const std::vector<double> ones(static_cast<size_t>(ncw), 1.0);
-    if (bs.kind == SRM3_BISPEC_WIND) {
-        // the wind bispectrum becomes line factors over a unit separable table
-        if (bs.line_c || bs.line_r) return fail(SRM3_E_INVALID, "line factors are derived for the wind bispectrum");
-        if (!(bs.alpha > 0) || !std::isfinite(bs.alpha)) return fail(SRM3_E_INVALID, "alpha must be finite and > 0");
-        if (!(bs.cap < 1.0)) return fail(SRM3_E_INVALID, "cap must be < 1");
+    auto real_to_complex = [&](const double *f, std::vector<double> &out) {
+        out.assign(2 * nlines0, 0.0);
+        for (size_t l = 0; l < nlines0; ++l) out[2 * l] = f[l];
+    };
+    if (bs.kind == SRM3_BISPEC_WIND || bs.kind == SRM3_BISPEC_PRODUCT) {
+        if (bs.line_c || bs.line_r) return fail(SRM3_E_INVALID, "line factors are derived from the bispectrum");
+        if (!(bs.cap < 1.0) || !std::isfinite(bs.cap)) return fail(SRM3_E_INVALID, "cap must be < 1");
         srm3_status sw = check_spectrum(spectrum->S, nlines0);
         if (sw) return sw;
-        if ((sw = wind_factors(nk, nw, W, spectrum->S, bs.alpha, bs.cap, wind_c, wind_r, nullptr, nullptr))) return sw;
-        bs.kind = SRM3_BISPEC_SEPARABLE;
-        bs.g2 = ones.data();
+        if (bs.kind == SRM3_BISPEC_WIND) {
+            // the wind bispectrum becomes real line factors over a unit separable table
+            if (!(bs.alpha > 0) || !std::isfinite(bs.alpha)) return fail(SRM3_E_INVALID, "alpha must be finite and > 0");
+            std::vector<double> c, r;
+            if ((sw = wind_factors(nk, nw, W, spectrum->S, bs.alpha, bs.cap, c, r, nullptr, nullptr))) return sw;
+            real_to_complex(c.data(), lcx);
+            real_to_complex(r.data(), lrx);
+        } else {
+            // a prescribed product bispectrum: complex line factors, H as the weight table
+            if (!bs.prod_f || !bs.prod_g) return fail(SRM3_E_INVALID, "prod_f / prod_g is NULL");
+            for (size_t l = 0; l < 2 * nlines0; ++l)
+                if (!std::isfinite(bs.prod_f[l]) || !std::isfinite(bs.prod_g[l]))
+                    return fail(SRM3_E_INVALID, "F and G must be finite");
+            if (bs.prod_h) {
+                const size_t n2 = static_cast<size_t>(ncw) * ncw;
+                for (int i = 0; i < ncw; ++i)
+                    for (int j = 0; j < ncw; ++j) {
+                        const size_t a = 2 * (static_cast<size_t>(i) * ncw + j), b = 2 * (static_cast<size_t>(j) * ncw + i);
+                        if (!std::isfinite(bs.prod_h[a]) || !std::isfinite(bs.prod_h[a + 1]))
+                            return fail(SRM3_E_INVALID, "H must be finite");
+                        if (bs.prod_h[a] != bs.prod_h[b] || bs.prod_h[a + 1] != bs.prod_h[b + 1])
+                            return fail(SRM3_E_INVALID, "H is not symmetric at [%d][%d]", i, j);
+                    }
+                hw2.resize(n2);
+                for (size_t e = 0; e < n2; ++e)
+                    hw2[e] = bs.prod_h[2 * e] * bs.prod_h[2 * e] + bs.prod_h[2 * e + 1] * bs.prod_h[2 * e + 1];
+                hcx.assign(bs.prod_h, bs.prod_h + 2 * n2);
+            }
+            if ((sw = product_factors(nk, nw, W, spectrum->S, bs.prod_f, bs.prod_g, bs.prod_h, grid->d_kappa,
+                                      grid->d_omega, bs.cap, lcx, lrx, nullptr, nullptr)))
+                return sw;
+        }
+        if (bs.kind == SRM3_BISPEC_PRODUCT && bs.prod_h) {
+            bs.kind = SRM3_BISPEC_DENSE;      // |H|^2 for the plan-time sums; H itself is the weight table
+            bs.b2 = hw2.data();
+        } else {
+            bs.kind = SRM3_BISPEC_SEPARABLE;
+            bs.g2 = ones.data();
+        }
         bs.beta_mode = SRM3_BETA_ZERO;
-        bs.line_c = wind_c.data();
-        bs.line_r = wind_r.data();
     } else {
         for (const double *f : {bs.line_c, bs.line_r}) {
             if (!f) continue;
@@ -307,8 +344,10 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
                 if (!(f[l] >= 0) || !std::isfinite(f[l]) || (f == bs.line_r && !(f[l] > 0)))
                     return fail(SRM3_E_INVALID, "line factor [%zu] must be finite (line_c >= 0, line_r > 0)", l);
         }
+        if (bs.line_c) real_to_complex(bs.line_c, lcx);
+        if (bs.line_r) real_to_complex(bs.line_r, lrx);
     }
-    const bool factors = bs.line_c || bs.line_r;
+    const bool factors = !lcx.empty() || !lrx.empty();
     if (bs.kind == SRM3_BISPEC_SEPARABLE && !bs.g2) return fail(SRM3_E_INVALID, "g2 is NULL");
     if (bs.kind == SRM3_BISPEC_DENSE && !bs.b2) return fail(SRM3_E_INVALID, "b2 is NULL");
     if (bs.beta_mode != SRM3_BETA_SEEDED && bs.beta_mode != SRM3_BETA_ZERO && bs.beta_mode != SRM3_BETA_TABLE)
@@ -389,12 +428,16 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
             if (static_cast<double>(Mk) * (4.0 * W - 3) * ncw > 4e9)
                 return fail(SRM3_E_UNSUPPORTED, "line factors with a dense table: grid too large for the plan-time sums");
         }
-        std::vector<double> Q;
-        line_pair_sums(nk, nw, W, bs.line_r, bs.kind, bs.g2, bs.b2, Q);
+        std::vector<double> Q, rmag;
+        if (!lrx.empty()) {
+            rmag.resize(nlines);
+            for (size_t l = 0; l < nlines; ++l) rmag[l] = std::hypot(lrx[2 * l], lrx[2 * l + 1]);
+        }
+        line_pair_sums(nk, nw, W, rmag.empty() ? nullptr : rmag.data(), bs.kind, bs.g2, bs.b2, Q);
         max_sig = 0.0;
         for (size_t l = 0; l < nlines; ++l) {
-            const double c = bs.line_c ? bs.line_c[l] : 1.0;
-            sig[l] = c * c * Q[l];
+            const double c2 = lcx.empty() ? 1.0 : lcx[2 * l] * lcx[2 * l] + lcx[2 * l + 1] * lcx[2 * l + 1];
+            sig[l] = c2 * Q[l];
             max_sig = std::max(max_sig, sig[l]);
         }
     }
@@ -451,8 +494,9 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     }
     if ((s = upload_bytes(p->S, S, nlines * sizeof(double), st))) return s;
     if ((s = upload_bytes(p->sig, sig.data(), nlines * sizeof(double), st))) return s;
-    if (bs.line_c && (s = upload_bytes(p->lc, bs.line_c, nlines * sizeof(double), st))) return s;
-    if (bs.line_r && (s = upload_bytes(p->lr, bs.line_r, nlines * sizeof(double), st))) return s;
+    if (!lcx.empty() && (s = upload_bytes(p->lc, lcx.data(), lcx.size() * sizeof(double), st))) return s;
+    if (!lrx.empty() && (s = upload_bytes(p->lr, lrx.data(), lrx.size() * sizeof(double), st))) return s;
+    if (!hcx.empty() && (s = upload(p->wtab, hcx, precision, st))) return s;   // the prescribed H as the weights
     if ((s = upload(p->tw_t, twiddles(nt), precision, st))) return s;
     if ((s = upload(p->tw_x, twiddles(nx), precision, st))) return s;
     *out_plan = p.release();
@@ -484,6 +528,35 @@ srm3_status srm3_wind_factors(const srm3_grid *grid, const double *S, double alp
     return SRM3_OK;
 }
 
+srm3_status srm3_product_factors(const srm3_grid *grid, const double *S, const double *F, const double *G,
+                                 const double *H, int32_t support_w, double cap, double *line_c, double *line_rho,
+                                 double *sigma, int32_t *sweeps)
+{
+    g_err[0] = 0;
+    if (!grid || !S || !F || !G || !line_c || !line_rho) return fail(SRM3_E_INVALID, "NULL argument");
+    const int nk = grid->n_kappa, nw = grid->n_omega;
+    if (nk < 1 || nw < 1) return fail(SRM3_E_INVALID, "n_kappa=%d n_omega=%d must be >= 1", nk, nw);
+    if (support_w < 1 || support_w > nw) return fail(SRM3_E_INVALID, "support_w=%d must be in [1, n_omega]", support_w);
+    if (!(grid->d_kappa > 0) || !(grid->d_omega > 0)) return fail(SRM3_E_INVALID, "d_kappa/d_omega must be > 0");
+    if (!(cap < 1.0) || !std::isfinite(cap)) return fail(SRM3_E_INVALID, "cap must be < 1");
+    const size_t nl = static_cast<size_t>(nk) * (2 * nw - 1);
+    srm3_status s = check_spectrum(S, nl);
+    if (s) return s;
+    std::vector<double> c, rho, sig;
+    int it = 0;
+    if ((s = product_factors(nk, nw, support_w, S, F, G, H, grid->d_kappa, grid->d_omega, cap, c, rho, &it, nullptr,
+                             &sig)))
+        return s;
+    for (size_t l = 0; l < 2 * nl; ++l) {
+        line_c[l] = c[l];
+        line_rho[l] = rho[l];
+    }
+    if (sigma)
+        for (size_t l = 0; l < nl; ++l) sigma[l] = sig[l];
+    if (sweeps) *sweeps = it;
+    return SRM3_OK;
+}
+
 srm3_status srm3_process_plan(const srm3_process_grid *grid, const double *S, const srm3_bispectrum *bispectrum,
                               int32_t precision, void *hip_stream, srm3_plan_t *out_plan)
 {
@@ -509,7 +582,8 @@ srm3_status srm3_process_plan(const srm3_process_grid *grid, const double *S, co
     std::vector<double> g2w, b2w;
     std::vector<uint32_t> betaw;
     long long process_pairs = 0;
-    if (bispectrum && (bispectrum->kind == SRM3_BISPEC_WIND || bispectrum->line_c || bispectrum->line_r))
+    if (bispectrum && (bispectrum->kind == SRM3_BISPEC_WIND || bispectrum->kind == SRM3_BISPEC_PRODUCT ||
+                       bispectrum->line_c || bispectrum->line_r))
         return fail(SRM3_E_UNSUPPORTED, "process plans take frequency-only bicoherence");
     if (bispectrum && bispectrum->kind != SRM3_BISPEC_NONE) {
         const srm3_bispectrum &q = *bispectrum;

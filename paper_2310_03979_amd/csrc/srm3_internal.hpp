@@ -44,7 +44,7 @@ template <> struct vec<double> { using v2 = double2; using v4 = double4; };
 // 3 interleaved values padded to 4 in FP64
 inline size_t a_slots(int precision) { return precision == SRM3_FP64 ? 4 : 3; }
 
-constexpr int kMaxSeedsPerLaunch = 32;
+constexpr int kMaxSeedsPerLaunch = 256;   // 2 KB of kernel arguments
 struct SeedChunk {
     uint64_t s[kMaxSeedsPerLaunch];
 };
@@ -82,8 +82,9 @@ struct AmpRef {
     double dkdw;
     double cap;
     int pairs = 1;   // 0: zero bicoherence, the pair sums are not computed (Gaussian field)
-    const double *lc = nullptr;   // per-line pair factor c_k (NULL = 1)
-    const double *lr = nullptr;   // per-line phase factor r_k (NULL = 1); the pure part divides it out
+    const double *lc = nullptr;   // per-line complex pair factor c_k, interleaved (NULL = 1)
+    const double *lr = nullptr;   // per-line complex phase factor rho_k, interleaved (NULL = 1);
+                                  // the pure part divides it out
 };
 
 // Kernel launchers (stream-ordered, return the launch status).
@@ -172,6 +173,10 @@ void line_pair_sums(int nk, int nw, int W, const double *r, int kind, const doub
                     std::vector<double> &Q);
 srm3_status wind_factors(int nk, int nw, int W, const double *S, double alpha, double cap, std::vector<double> &c,
                          std::vector<double> &r, int *sweeps, double *max_sig);
+srm3_status product_factors(int nk, int nw, int W, const double *S, const double *F, const double *G,
+                            const double *H, double dk, double dw, double cap, std::vector<double> &c,
+                            std::vector<double> &rho, int *sweeps, double *max_sig,
+                            std::vector<double> *sigma_out = nullptr);
 
 srm3_status fail(srm3_status s, const char *fmt, ...);
 srm3_status dev_err(hipError_t e, const char *what);
@@ -192,7 +197,7 @@ struct srm3_plan_s {
     double pair_terms = 0;
     int device = 0;
     srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
-    srm3::DevBuf lc, lr;     // per-line bicoherence factors (kappa-dependent bispectra), FP64, or empty
+    srm3::DevBuf lc, lr;     // per-line complex bicoherence factors c, rho (interleaved FP64), or empty
     int ws_batch = 0;
     bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)
     bool process = false;    // the 1-D process: one kappa line, one-sided spectrum and pairs

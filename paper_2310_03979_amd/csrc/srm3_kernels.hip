@@ -168,10 +168,12 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
         sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
         if (lr) {
-            // per-line bicoherence factor r_k carried by the phase factor
-            const double rk = lr[static_cast<long>(kk) * g.nc + c];
-            s *= rk;
-            co *= rk;
+            // per-line complex bicoherence factor rho_k carried by the phase factor
+            const long l = static_cast<long>(kk) * g.nc + c;
+            const double xr = lr[2 * l], xi = lr[2 * l + 1];
+            const double cr = co * xr - s * xi, ci = co * xi + s * xr;
+            co = cr;
+            s = ci;
         }
         typename vec<T>::v2 v;
         v.x = static_cast<T>(co);
@@ -672,8 +674,8 @@ struct AmpArgs {
     double dkdw;
     double cap;
     int pairs;                // 0: no pair sums (zero bicoherence)
-    const double *lc;         // per-line pair factor c_k, or null (1)
-    const double *lr;         // per-line phase factor r_k carried by zrow, or null (1)
+    const double *lc;         // per-line complex pair factor c_k (interleaved), or null (1)
+    const double *lr;         // per-line complex factor rho_k carried by zrow (interleaved), or null (1)
 };
 
 struct TfftArgs {
@@ -722,20 +724,33 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     const double sraw = sc * amp.sig[li];
     const double rho = (amp.cap > 0.0 && sraw > amp.cap) ? amp.cap / sraw : 1.0;
     const double base = Sp[li] * amp.dkdw;
-    double pd = 2.0 * sqrt(base * (1.0 - rho * sraw));
-    double qd = 2.0 * sqrt(base * rho * sc);
-    if (amp.lc) qd *= amp.lc[li];
-    if (amp.lr) {
-        // zrow carries r_k; the pure part takes the bare phase factor
-        const double rk = amp.lr[li];
-        pd = rk > 0.0 ? pd / rk : 0.0;
-    }
-    const T p = static_cast<T>(pd);
-    const T q = static_cast<T>(qd);
+    const double pd = 2.0 * sqrt(base * (1.0 - rho * sraw));
+    const double qd = 2.0 * sqrt(base * rho * sc);
     const T2 z = zrow[bi];
     T2 C;
-    C.x = fma_(p, z.x, q * t.x);
-    C.y = fma_(p, z.y, q * t.y);
+    if (!amp.lc && !amp.lr) {
+        const T p = static_cast<T>(pd);
+        const T q = static_cast<T>(qd);
+        C.x = fma_(p, z.x, q * t.x);
+        C.y = fma_(p, z.y, q * t.y);
+        return C;
+    }
+    // complex line factors: pair part times c_k; zrow carries rho_k, which the
+    // pure part divides out (its bare phase factor)
+    double qr = qd, qi = 0.0, pr = pd, pi = 0.0;
+    if (amp.lc) {
+        qr = qd * amp.lc[2 * li];
+        qi = qd * amp.lc[2 * li + 1];
+    }
+    if (amp.lr) {
+        const double xr = amp.lr[2 * li], xi = amp.lr[2 * li + 1];
+        const double m2 = xr * xr + xi * xi;
+        pr = m2 > 0.0 ? pd * xr / m2 : 0.0;
+        pi = m2 > 0.0 ? -pd * xi / m2 : 0.0;
+    }
+    const T Pr = static_cast<T>(pr), Pi = static_cast<T>(pi), Qr = static_cast<T>(qr), Qi = static_cast<T>(qi);
+    C.x = Pr * z.x - Pi * z.y + Qr * t.x - Qi * t.y;
+    C.y = Pr * z.y + Pi * z.x + Qr * t.y + Qi * t.x;
     return C;
 }
 
@@ -1258,8 +1273,10 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
 {
     const long per = static_cast<long>(g.nkp) * g.nc;
     const unsigned gx = static_cast<unsigned>((per + 255) / 256);
-    for (int b0 = 0; b0 < batch; b0 += kMaxSeedsPerLaunch) {
-        const int nb = std::min(kMaxSeedsPerLaunch, batch - b0);
+    // seeds travel as kernel arguments in chunks, or are read from the device
+    const int chunk = seeds_dev ? 65535 : kMaxSeedsPerLaunch;
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
         SeedChunk sc{};
         if (!seeds_dev)
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];

@@ -149,7 +149,7 @@ srm3_status wind_factors(int nk, int nw, int W, const double *S, double alpha, d
     std::vector<double> sigma(nl, 0.0), Q;
     const std::vector<double> ones(2 * W - 1, 1.0);
     int it = 0;
-    double ms = 0.0;
+    double ms = 0.0, last_diff = 1.0;
     for (it = 1; it <= 1000; ++it) {
         for (size_t l = 0; l < nl; ++l) r[l] = S[l] > 0.0 ? 1.0 / std::sqrt(1.0 - sigma[l]) : 0.0;
         line_pair_sums(nk, nw, W, r.data(), SRM3_BISPEC_SEPARABLE, ones.data(), nullptr, Q);
@@ -167,12 +167,89 @@ srm3_status wind_factors(int nk, int nw, int W, const double *S, double alpha, d
             sigma[l] = s;
             ms = std::max(ms, s);
         }
-        if (diff <= 1e-15) break;
+        // converged, or settled at the rounding floor of the FFT sums
+        if (diff <= 1e-14 || (diff <= 1e-12 && diff >= last_diff)) break;
+        last_diff = diff;
     }
     if (it > 1000) return fail(SRM3_E_UNSUPPORTED, "wind bispectrum: the recursion did not converge");
     for (size_t l = 0; l < nl; ++l) r[l] = S[l] > 0.0 ? 1.0 / std::sqrt(1.0 - sigma[l]) : 0.0;
     if (sweeps) *sweeps = it;
     if (max_sig) *max_sig = ms;
+    return SRM3_OK;
+}
+
+}  // namespace srm3
+
+namespace srm3 {
+
+// Prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w): complex line
+// factors c_k = F_k sqrt(dk dw / S_k), rho_i = G_i / sqrt(S_i (1 - Sigma_i)),
+// Sigma_k = min(cap, |c_k|^2 sum_{P(k)} |rho_i|^2 |rho_j|^2 |H|^2) by the same
+// monotone sweeps as the wind bispectrum.  c, rho: interleaved complex.
+srm3_status product_factors(int nk, int nw, int W, const double *S, const double *F, const double *G,
+                            const double *H, double dk, double dw, double cap, std::vector<double> &c,
+                            std::vector<double> &rho, int *sweeps, double *max_sig, std::vector<double> *sigma_out)
+{
+    const int nc = 2 * nw - 1, ncw = 2 * W - 1;
+    const size_t nl = static_cast<size_t>(nk) * nc;
+    c.assign(2 * nl, 0.0);
+    rho.assign(2 * nl, 0.0);
+    for (size_t l = 0; l < nl; ++l)
+        if (S[l] > 0.0) {
+            const double f = std::sqrt(dk * dw / S[l]);
+            c[2 * l] = F[2 * l] * f;
+            c[2 * l + 1] = F[2 * l + 1] * f;
+        }
+    std::vector<double> h2;
+    const std::vector<double> ones(ncw, 1.0);
+    if (H) {
+        h2.resize(static_cast<size_t>(ncw) * ncw);
+        for (size_t e = 0; e < h2.size(); ++e) h2[e] = H[2 * e] * H[2 * e] + H[2 * e + 1] * H[2 * e + 1];
+    }
+    std::vector<double> sigma(nl, 0.0), mag(nl, 0.0), Q;
+    int it = 0;
+    double ms = 0.0, last_diff = 1.0;
+    auto set_rho = [&]() {
+        for (size_t l = 0; l < nl; ++l) {
+            if (S[l] > 0.0) {
+                const double f = 1.0 / std::sqrt(S[l] * (1.0 - sigma[l]));
+                rho[2 * l] = G[2 * l] * f;
+                rho[2 * l + 1] = G[2 * l + 1] * f;
+            } else {
+                rho[2 * l] = rho[2 * l + 1] = 0.0;
+            }
+            mag[l] = std::hypot(rho[2 * l], rho[2 * l + 1]);
+        }
+    };
+    for (it = 1; it <= 1000; ++it) {
+        set_rho();
+        if (H)
+            line_pair_sums(nk, nw, W, mag.data(), SRM3_BISPEC_DENSE, nullptr, h2.data(), Q);
+        else
+            line_pair_sums(nk, nw, W, mag.data(), SRM3_BISPEC_SEPARABLE, ones.data(), nullptr, Q);
+        double diff = 0.0;
+        ms = 0.0;
+        for (size_t l = 0; l < nl; ++l) {
+            double s = (c[2 * l] * c[2 * l] + c[2 * l + 1] * c[2 * l + 1]) * Q[l];
+            if (S[l] <= 0.0) s = 0.0;
+            if (cap > 0.0) s = std::min(s, cap);
+            if (!(s < 1.0))
+                return fail(SRM3_E_PURE_NEGATIVE,
+                            "product bispectrum: the partial-bicoherence recursion has no admissible pure spectrum "
+                            "(Sigma reaches 1); give a cap < 1 or a smaller bispectrum");
+            diff = std::max(diff, std::fabs(s - sigma[l]));
+            sigma[l] = s;
+            ms = std::max(ms, s);
+        }
+        // converged, or settled at the rounding floor of the FFT sums
+        if (diff <= 1e-14 || (diff <= 1e-12 && diff >= last_diff)) break;
+        last_diff = diff;
+    }
+    if (it > 1000) return fail(SRM3_E_UNSUPPORTED, "product bispectrum: the recursion did not converge");
+    set_rho();
+    if (sweeps) *sweeps = it;
+    if (max_sig) *max_sig = ms;
+    if (sigma_out) *sigma_out = sigma;
     return SRM3_OK;
 }
 

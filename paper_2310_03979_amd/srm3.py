@@ -48,7 +48,8 @@ class _Bispectrum(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("g2", _dp), ("b2", _dp), ("beta", _u32p),
                 ("support_w", ctypes.c_int32), ("cap", ctypes.c_double),
                 ("beta_mode", ctypes.c_int32), ("beta_seed", ctypes.c_uint64),
-                ("line_c", _dp), ("line_r", _dp), ("alpha", ctypes.c_double)]
+                ("line_c", _dp), ("line_r", _dp), ("alpha", ctypes.c_double),
+                ("prod_f", _dp), ("prod_g", _dp), ("prod_h", _dp)]
 
 
 class _ProcessGrid(ctypes.Structure):
@@ -103,6 +104,8 @@ def load():
     L.srm3_plan_set_algorithm.argtypes = [vp, ctypes.c_int32, vp]
     L.srm3_wind_factors.argtypes = [ctypes.POINTER(_Grid), _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                     _dp, _dp, _dp, ctypes.POINTER(ctypes.c_int32)]
+    L.srm3_product_factors.argtypes = [ctypes.POINTER(_Grid), _dp, _dp, _dp, _dp, ctypes.c_int32, ctypes.c_double,
+                                       _dp, _dp, _dp, ctypes.POINTER(ctypes.c_int32)]
     L.srm3_process_plan.argtypes = [ctypes.POINTER(_ProcessGrid), _dp, ctypes.POINTER(_Bispectrum),
                                     ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.srm3_algorithm_terms.argtypes = [vp, _dp]
@@ -121,7 +124,7 @@ def load():
     L.srm3_batch_destroy.argtypes = [vp]
     L.srm3_batch_destroy.restype = None
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
-    for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_generate", "srm3_coefficients", "srm3_transform",
+    for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_product_factors", "srm3_generate", "srm3_coefficients", "srm3_transform",
               "srm3_workspace_bytes", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
               "srm3_algorithm_terms", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
@@ -199,7 +202,7 @@ def _bispectrum(bispectrum: Optional[dict], default_w: int):
     """Marshal a bispectrum dict into the C struct; returns (struct or None, arrays to keep alive, W)."""
     if bispectrum is None:
         return None, [], 1
-    kinds = {"none": 0, "separable": 1, "dense": 2, "wind": 3}
+    kinds = {"none": 0, "separable": 1, "dense": 2, "wind": 3, "product": 4}
     modes = {"seeded": 0, "zero": 1, "table": 2}
     kind = bispectrum.get("kind", "separable")
     kind = kinds[kind] if isinstance(kind, str) else int(kind)
@@ -231,7 +234,18 @@ def _bispectrum(bispectrum: Optional[dict], default_w: int):
             keep.append(f)
             setattr(b, name, f.ctypes.data_as(_dp))
     b.alpha = float(bispectrum.get("alpha", 0.0))
+    for key, field in (("F", "prod_f"), ("G", "prod_g"), ("H", "prod_h")):
+        if bispectrum.get(key) is not None:
+            f = _complex_buf(bispectrum[key])
+            keep.append(f)
+            setattr(b, field, f.ctypes.data_as(_dp))
     return b, keep, W
+
+
+def _complex_buf(a) -> np.ndarray:
+    """Complex array -> contiguous interleaved (re, im) float64."""
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
 
 
 def srm3_plan(grid: dict, S: np.ndarray, bispectrum: Optional[dict] = None, precision="fp64",
@@ -403,6 +417,28 @@ def srm3_wind_factors(grid: dict, S: np.ndarray, alpha: float, cap: float = 0.0,
                                c.ctypes.data_as(_dp), r.ctypes.data_as(_dp), sig.ctypes.data_as(_dp),
                                ctypes.byref(it)))
     return c, r, sig, int(it.value)
+
+
+def srm3_product_factors(grid: dict, S: np.ndarray, F, G, H=None, support_w: Optional[int] = None,
+                         cap: float = 0.0):
+    """Complex line factors (c, rho), Sigma and sweep count of a prescribed
+    product bispectrum (host computation; no GPU needed)."""
+    L = load()
+    g = _Grid(int(grid["n_kappa"]), int(grid["n_omega"]), float(grid["d_kappa"]),
+              float(grid["d_omega"]), int(grid.get("n_x", 1)), int(grid.get("n_t", 1)))
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    Fb, Gb = _complex_buf(F), _complex_buf(G)
+    Hb = None if H is None else _complex_buf(H)
+    c = np.zeros(S.shape + (2,))
+    rho = np.zeros(S.shape + (2,))
+    sig = np.zeros_like(S)
+    it = ctypes.c_int32()
+    W = int(grid["n_omega"]) if support_w is None else int(support_w)
+    _check(L.srm3_product_factors(ctypes.byref(g), S.ctypes.data_as(_dp), Fb.ctypes.data_as(_dp),
+                                  Gb.ctypes.data_as(_dp), None if Hb is None else Hb.ctypes.data_as(_dp), W,
+                                  float(cap), c.ctypes.data_as(_dp), rho.ctypes.data_as(_dp),
+                                  sig.ctypes.data_as(_dp), ctypes.byref(it)))
+    return c[..., 0] + 1j * c[..., 1], rho[..., 0] + 1j * rho[..., 1], sig, int(it.value)
 
 
 def process_plan_from_workload(wl, precision="fp64", beta_mode="seeded", stream=None, dense=False,

@@ -217,3 +217,44 @@ def test_wind_plans_in_batches_and_the_server(lib):
     assert sorted(done) == sorted(tickets)
     for r, s in zip(reqs, singles):
         assert torch.equal(r["out"], s)
+
+
+PRODUCT_CASES = [
+    # nk, nw, W, nx, nt, scale, cap, with_h
+    (6, 10, 10, 8, 32, 0.4, 0.0, True),
+    (16, 24, 12, 32, 64, 2.0, 0.7, True),
+    (9, 12, 12, 16, 32, 0.5, 0.0, False),
+]
+
+
+@pytest.mark.parametrize("algorithm", ["direct", "kappa_fft", "fft2d"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", PRODUCT_CASES, ids=[f"{c[0]}x{c[1]}w{c[2]}_s{c[5]}_cap{c[6]}_H{c[7]}" for c in PRODUCT_CASES])
+def test_product_bispectrum_matches_oracle(lib, oracle_mod, case, precision, algorithm):
+    """A prescribed complex bispectrum B = F_k G_i G_j H(i_w, j_w) through the
+    partial-bicoherence recursion, beta = atan2(Im B, Re B)."""
+    nk, nw, W, nx, nt, scale, cap, with_h = case
+    if algorithm == "fft2d" and with_h:
+        pytest.skip("the 2-D FFT pair sum needs rank-one weights (H = 1)")
+    print(f"[gpu] product {case} {precision} {algorithm}", flush=True)
+    rng = np.random.default_rng(nk * nw)
+    S = inp.random_spectrum(nk, nw, seed=nk * nw)
+    F = scale * rng.uniform(0.2, 1.0, S.shape) * np.exp(1j * rng.uniform(0, 2 * np.pi, S.shape))
+    G = np.sqrt(S) * rng.uniform(0.5, 1.0, S.shape) * np.exp(1j * rng.uniform(0, 2 * np.pi, S.shape))
+    H = None
+    if with_h:
+        A = rng.uniform(0.3, 1.0, (2 * W - 1, 2 * W - 1)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (2 * W - 1, 2 * W - 1)))
+        H = 0.5 * (A + A.T)
+    dk, dw = 0.5, 0.4
+    grid = dict(n_kappa=nk, n_omega=nw, d_kappa=dk, d_omega=dw, n_x=nx, n_t=nt)
+    bis = dict(kind="product", F=F, G=G, H=H, cap=cap, support_w=W)
+    plan = lib.srm3_plan(grid, S, bis, precision)
+    lib.srm3_plan_set_algorithm(plan, algorithm)
+    P = oracle_mod.ProductProblem(nk, nw, W, dk, dw, S, F, G, H, cap)
+    P.solve()
+    seeds = [21, 22]
+    C, u = _run(lib, plan, nx, nt, seeds)
+    for i, s in enumerate(seeds):
+        Cref = P.coefficients(seed=s)
+        assert _rel(C[i], Cref) <= TOL[precision], i
+        assert _rel(u[i], oracle_mod.field(Cref, nx, nt)) <= TOL[precision], i

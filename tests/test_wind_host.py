@@ -64,3 +64,36 @@ def test_wind_errors(lib):
     assert ei.value.status == 1
     c, r, sig, _ = lib.srm3_wind_factors(grid, S, 50.0, 0.6, 4)   # the cap makes it admissible
     assert sig.max() <= 0.6 + 1e-15
+
+
+def _product_inputs(nk, nw, W, seed, scale):
+    rng = np.random.default_rng(seed)
+    S = inp.random_spectrum(nk, nw, seed=seed)
+    shape = S.shape
+    F = scale * rng.uniform(0.2, 1.0, shape) * np.exp(1j * rng.uniform(0, 2 * np.pi, shape))
+    G = np.sqrt(S) * rng.uniform(0.5, 1.0, shape) * np.exp(1j * rng.uniform(0, 2 * np.pi, shape))
+    A = rng.uniform(0.3, 1.0, (2 * W - 1, 2 * W - 1)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (2 * W - 1, 2 * W - 1)))
+    return S, F, G, 0.5 * (A + A.T)
+
+
+@pytest.mark.parametrize("with_h", [True, False])
+@pytest.mark.parametrize("case", [(4, 5, 5, 0.4, 0.0), (6, 8, 5, 2.0, 0.5), (3, 7, 7, 0.6, 0.0),
+                                  (16, 24, 12, 2.0, 0.7)],   # sweeps settle at the rounding floor of the sums
+                         ids=str)
+def test_product_factors_match_oracle_recursion(lib, oracle_mod, case, with_h):
+    nk, nw, W, scale, cap = case
+    S, F, G, H = _product_inputs(nk, nw, W, nk * nw, scale)
+    if not with_h:
+        H = None
+    grid = dict(n_kappa=nk, n_omega=nw, d_kappa=0.5, d_omega=0.4)
+    c, rho, sig, sweeps = lib.srm3_product_factors(grid, S, F, G, H, W, cap)
+    P = oracle_mod.ProductProblem(nk, nw, W, 0.5, 0.4, S, F, G, H, cap)
+    P.solve()
+    pos = S > 0
+    sig_ref = np.where(pos, 1.0 - P.Sp / np.where(pos, S, 1.0), 0.0)
+    assert np.max(np.abs(sig - sig_ref)) <= 1e-13
+    c_ref = np.where(pos, F * np.sqrt(0.5 * 0.4 / np.where(pos, S, 1.0)), 0.0)
+    assert np.max(np.abs(c - c_ref)) <= 1e-13 * np.max(np.abs(c_ref))
+    rho_ref = np.where(pos, G / np.sqrt(np.where(pos, P.Sp, 1.0)), 0.0)
+    assert np.max(np.abs(rho - rho_ref)) <= 1e-12 * np.max(np.abs(rho_ref))
+    assert sweeps >= 1
