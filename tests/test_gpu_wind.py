@@ -223,7 +223,7 @@ PRODUCT_CASES = [
     # nk, nw, W, nx, nt, scale, cap, with_h
     (6, 10, 10, 8, 32, 0.4, 0.0, True),
     (16, 24, 12, 32, 64, 2.0, 0.7, True),
-    (9, 12, 12, 16, 32, 0.5, 0.0, False),
+    (9, 12, 12, 16, 32, 0.25, 0.0, False),
 ]
 
 
