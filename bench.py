@@ -709,6 +709,22 @@ def main():
         fields["fp32_kappa_fft"] = outk
         log(f"[bench] kappa-FFT fp32: {dtk * 1e3:.2f} ms/step ({grid_points / dtk:.4g} grid points/s)")
 
+    # ---- a bispectrum generated per 4-index pair inside the kernel (no table) ----
+    if not args.no_kfft:
+        bh = 4
+        planh = srm3.srm3_plan(wl.grid_dict(), wl.spectrum(), dict(kind="hashed", alpha=1e-4, beta_seed=wl.beta_seed,
+                                                                   cap=wl.cap, support_w=wl.support_w), "fp32")
+        outh = torch.empty((bh, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+        srm3.srm3_profile_enable(planh, True)
+        dth = timed_steps(torch, lambda: srm3.srm3_generate(planh, seeds[:bh], outh), 1, 1)
+        ph = srm3.srm3_profile_read(planh)
+        hms = ph["pairsum"][0] / max(1, ph["pairsum"][1])
+        extra["hashed_bispectrum"] = {"realizations": bh, "ms_per_step": round(dth * 1e3, 3),
+                                      "grid_points_per_s": bh * wl.grid_points / dth,
+                                      "pair_terms_per_s": terms * bh / (hms * 1e-3)}
+        del outh
+        log(f"[bench] hashed bispectrum fp32: {dth * 1e3:.1f} ms per {bh} realizations")
+
     # ---- the same grid with zero bicoherence: Gaussian (2nd-order) fast path ----
     plang = srm3.srm3_plan(wl.grid_dict(), wl.spectrum(), None, "fp32")
     outg = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")

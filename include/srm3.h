@@ -66,8 +66,10 @@ typedef enum {
     SRM3_BISPEC_DENSE = 2,     /* b^2_raw given as a full symmetric table */
     SRM3_BISPEC_WIND = 3,      /* the wind bispectrum of Section 5 (Eq. bispectrum) times alpha, beta = 0,
                                   through the partial bicoherence of Section 4.1 (see below) */
-    SRM3_BISPEC_PRODUCT = 4    /* a prescribed bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w) through the
+    SRM3_BISPEC_PRODUCT = 4,   /* a prescribed bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w) through the
                                   partial bicoherence, beta = atan2(Im B, Re B) (see below) */
+    SRM3_BISPEC_HASHED = 5     /* b^2_raw and beta of every 4-index pair generated inside the kernel
+                                  from a counter-based hash, no table (see below) */
 } srm3_bispec_kind;
 
 typedef enum {
@@ -147,6 +149,16 @@ typedef struct {
  * exists without a cap.  The factors do not depend on the values of S (only on
  * where it is zero), so srm3_set_spectrum and per-request spectra with the
  * same zero lines keep them. */
+
+/* SRM3_BISPEC_HASHED.  A bispectrum that depends on all four indices of a
+ * pair, generated just in time: for the canonical member (i, j) of an
+ * unordered pair (i_kappa > j_kappa, or equal and i_w >= j_w), Philox4x32-10
+ * with key = beta_seed and counter (i_kappa, (uint32)i_w, j_kappa, (uint32)j_w)
+ * gives b^2_raw = alpha * word0 / 2^32 and beta = 2 pi word1 / 2^32.  The
+ * per-line raw sums are computed on the device when the plan is built
+ * (O(pairs)), then the cap applies as usual.  Direct pair sum only (the
+ * weights depend on kappa); not in batches or the server (SRM3_E_UNSUPPORTED);
+ * g2, b2, beta tables and line factors are ignored. */
 
 /* The line factors and Sigma that SRM3_BISPEC_WIND derives (host only, FP64,
  * no device work): S host [n_kappa][2 n_omega - 1]; line_c, line_r, sigma:

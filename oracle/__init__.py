@@ -57,7 +57,7 @@ class _Problem(ctypes.Structure):
                 ("dk", ctypes.c_double), ("dw", ctypes.c_double),
                 ("S", _dp), ("b2", _dp), ("beta", _u32p), ("cap", ctypes.c_double),
                 ("line_c", _dp), ("line_r", _dp), ("mode", ctypes.c_int), ("alpha", ctypes.c_double),
-                ("Sp", _dp), ("F", _dp), ("G", _dp), ("H", _dp)]
+                ("Sp", _dp), ("F", _dp), ("G", _dp), ("H", _dp), ("hash_key", ctypes.c_uint64)]
 
 
 class _Process(ctypes.Structure):
@@ -259,6 +259,20 @@ class ProductProblem(WindProblem):
             h = self.H[iw + W - 1, jw + W - 1]
             B *= complex(h[0], h[1])
         return B
+
+
+class HashedProblem(Problem):
+    """A bispectrum drawn per 4-index pair: for the canonical member (i, j) of
+    an unordered pair, Philox4x32-10 (key ``key``, counter (i_kappa, i_w,
+    j_kappa, j_w)) gives b2_raw = scale * U / 2^32 and beta = 2 pi V / 2^32."""
+
+    def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, scale, key, cap):
+        W = support_w
+        super().__init__(n_kappa, n_omega, W, d_kappa, d_omega, S, np.zeros((2 * W - 1, 2 * W - 1)),
+                         np.zeros((2 * W - 1, 2 * W - 1), dtype=np.uint32), cap)
+        self._c.mode = 3
+        self._c.alpha = scale
+        self._c.hash_key = int(key)
 
 
 def _cbuf(C):

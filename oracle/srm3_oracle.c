@@ -120,7 +120,20 @@ typedef struct {
     const double *F;        /* mode 2: [nk][2nw-1] complex */
     const double *G;        /* mode 2: [nk][2nw-1] complex */
     const double *H;        /* mode 2: [2W-1][2W-1] complex, or NULL */
+    uint64_t hash_key;      /* mode 3: a bispectrum drawn per 4-index pair, b2_raw = alpha U, beta = V */
 } oracle_problem;
+
+/* Mode 3: the two uniform words of the canonical pair (i, j): Philox4x32-10,
+ * key = hash_key, counter (i_kappa, i_w, j_kappa, j_w). */
+static void pair_words(const oracle_problem *p, int ik, int iw, int jk, int jw, uint32_t *u, uint32_t *v)
+{
+    const uint32_t ctr[4] = {(uint32_t)ik, (uint32_t)(int32_t)iw, (uint32_t)jk, (uint32_t)(int32_t)jw};
+    const uint32_t key[2] = {(uint32_t)(p->hash_key & 0xffffffffu), (uint32_t)(p->hash_key >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    *u = out[0];
+    *v = out[1];
+}
 
 /* The prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w). */
 static void product_B(const oracle_problem *p, int ik, int iw, int jk, int jw, double *re, double *im)
@@ -167,6 +180,11 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
         if (B == 0.0) return 0.0;
         return B * B * p->dk * p->dw / (p->Sp[li] * p->Sp[lj] * p->S[lk]);
     }
+    if (p->mode == 3) {
+        uint32_t u, v;
+        pair_words(p, ik, iw, jk, jw, &u, &v);
+        return p->alpha * (double)u / 4294967296.0;
+    }
     if (p->mode == 2) {
         double re, im;
         product_B(p, ik, iw, jk, jw, &re, &im);
@@ -180,9 +198,14 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
     return v;
 }
 
-static uint32_t pair_beta(const oracle_problem *p, int iw, int jw)
+static uint32_t pair_beta(const oracle_problem *p, int ik, int iw, int jk, int jw)
 {
     const int W = p->W, n = 2 * W - 1;
+    if (p->mode == 3) {
+        uint32_t u, v;
+        pair_words(p, ik, iw, jk, jw, &u, &v);
+        return v;
+    }
     return p->mode != 0 ? 0u : p->beta[(size_t)(iw + W - 1) * n + (jw + W - 1)];
 }
 
@@ -263,7 +286,7 @@ int oracle_coefficients(const oracle_problem *p, const uint32_t *U, long nlines,
                 const double bp = sqrt(rho * pair_b2(p, ik, iw, jk, jw));
                 const uint32_t ang = U[(size_t)ik * nc + (iw + nw - 1)]
                                    + U[(size_t)jk * nc + (jw + nw - 1)]
-                                   + pair_beta(p, iw, jw);  /* exact mod 2^32 */
+                                   + pair_beta(p, ik, iw, jk, jw);  /* exact mod 2^32 */
                 const double th = TWO_PI * (double)ang / 4294967296.0 + pair_beta_rad(p, ik, iw, jk, jw);
                 re += bp * cos(th);
                 im += bp * sin(th);

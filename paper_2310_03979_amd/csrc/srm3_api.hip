@@ -82,7 +82,7 @@ KfftTables plan_ktab(srm3_plan_t p)
 AmpRef plan_amp(srm3_plan_t p)
 {
     return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
-                  p->dk * p->dw, p->cap, p->gaussian ? 0 : 1, static_cast<const double *>(p->lc.p),
+                  p->dk * p->dw, p->cap, p->gaussian ? 0 : (p->hashed ? 2 : 1), static_cast<const double *>(p->lc.p),
                   static_cast<const double *>(p->lr.p)};
 }
 
@@ -199,13 +199,16 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
     Workspace wp = ws;
-    if (p->gaussian || p->algo != SRM3_ALGO_DIRECT) wp.zcol = nullptr;   // no a operand planes needed
+    if (p->gaussian || p->hashed || p->algo != SRM3_ALGO_DIRECT) wp.zcol = nullptr;   // no a operand planes needed
     hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, wp, static_cast<const double *>(p->lr.p), st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
     if (p->gaussian) return SRM3_OK;   // zero bicoherence: the pair sums are not used
     if ((s = event_pair(p, 1, st, true))) return s;
-    if (p->algo != SRM3_ALGO_DIRECT) {
+    if (p->hashed) {
+        e = launch_pairsum_hash(p->g, p->precision, p->hash_key, p->hash_scale, batch, &ws, nullptr, st);
+        if (e != hipSuccess) return dev_err(e, "hashed pair-sum kernel");
+    } else if (p->algo != SRM3_ALGO_DIRECT) {
         const KfftWorkspace kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
         e = launch_kfft_pairsum(p->precision, p->g, p->kg, plan_ktab(p), batch, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
@@ -281,8 +284,18 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (W < 1 || W > nw) return fail(SRM3_E_INVALID, "support_w=%d must be in [1, n_omega=%d]", W, nw);
     const int ncw = 2 * W - 1;
     if (bs.kind != SRM3_BISPEC_NONE && bs.kind != SRM3_BISPEC_SEPARABLE && bs.kind != SRM3_BISPEC_DENSE &&
-        bs.kind != SRM3_BISPEC_WIND && bs.kind != SRM3_BISPEC_PRODUCT)
+        bs.kind != SRM3_BISPEC_WIND && bs.kind != SRM3_BISPEC_PRODUCT && bs.kind != SRM3_BISPEC_HASHED)
         return fail(SRM3_E_INVALID, "bispectrum kind %d", bs.kind);
+    const bool hashed = bs.kind == SRM3_BISPEC_HASHED;
+    const uint64_t hash_key = bs.beta_seed;
+    const double hash_scale = bs.alpha;
+    if (hashed) {
+        // generated per pair in the kernel; the unit table only serves the pair count
+        if (bs.line_c || bs.line_r) return fail(SRM3_E_INVALID, "line factors do not apply to a hashed bispectrum");
+        if (!(bs.alpha > 0) || !std::isfinite(bs.alpha)) return fail(SRM3_E_INVALID, "alpha (scale) must be finite and > 0");
+        bs.kind = SRM3_BISPEC_SEPARABLE;
+        bs.beta_mode = SRM3_BETA_ZERO;
+    }
     if (bs.kind == SRM3_BISPEC_NONE) bs.line_c = bs.line_r = nullptr;
     const size_t nlines0 = static_cast<size_t>(nk) * nc;
     // complex per-line factors c (pair sum) and rho (phase factor), interleaved
@@ -347,6 +360,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
         if (bs.line_c) real_to_complex(bs.line_c, lcx);
         if (bs.line_r) real_to_complex(bs.line_r, lrx);
     }
+    if (hashed) bs.g2 = ones.data();
     const bool factors = !lcx.empty() || !lrx.empty();
     if (bs.kind == SRM3_BISPEC_SEPARABLE && !bs.g2) return fail(SRM3_E_INVALID, "g2 is NULL");
     if (bs.kind == SRM3_BISPEC_DENSE && !bs.b2) return fail(SRM3_E_INVALID, "b2 is NULL");
@@ -441,7 +455,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
             max_sig = std::max(max_sig, sig[l]);
         }
     }
-    if (max_sigma(max_sig, bs.cap, 1.0) >= 1.0)
+    if (!hashed && max_sigma(max_sig, bs.cap, 1.0) >= 1.0)
         return fail(SRM3_E_PURE_NEGATIVE, "a line has sum of b^2 = %.6g >= 1: pure spectrum not positive",
                     max_sigma(max_sig, bs.cap, 1.0));
 
@@ -456,6 +470,9 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (bs.kind == SRM3_BISPEC_SEPARABLE && bs.beta_mode == SRM3_BETA_ZERO)
         p->g2_host.assign(bs.g2, bs.g2 + ncw);   // rank-one weights: the 2-D FFT pair sum applies
     p->pair_terms = p->gaussian ? 0.0 : pair_terms;
+    p->hashed = hashed;
+    p->hash_key = hash_key;
+    p->hash_scale = hash_scale;
     Geometry &g = p->g;
     g.nk = nk;
     g.nw = nw;
@@ -499,6 +516,19 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (!hcx.empty() && (s = upload(p->wtab, hcx, precision, st))) return s;   // the prescribed H as the weights
     if ((s = upload(p->tw_t, twiddles(nt), precision, st))) return s;
     if ((s = upload(p->tw_x, twiddles(nx), precision, st))) return s;
+    if (hashed) {
+        // per-line raw sums of the generated bicoherence, on the device, then the cap check
+        e = launch_pairsum_hash(g, precision, hash_key, hash_scale, 1, nullptr, static_cast<double *>(p->sig.p), st);
+        if (e != hipSuccess) return dev_err(e, "hashed bispectrum sums");
+        if ((e = hipMemcpyAsync(sig.data(), p->sig.p, nlines * sizeof(double), hipMemcpyDeviceToHost, st)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(st)) != hipSuccess)
+            return dev_err(e, "copy of the raw sums");
+        p->max_sig = *std::max_element(sig.begin(), sig.end());
+        if (max_sigma(p->max_sig, bs.cap, 1.0) >= 1.0)
+            return fail(SRM3_E_PURE_NEGATIVE, "a line has sum of b^2 = %.6g >= 1: pure spectrum not positive",
+                        max_sigma(p->max_sig, bs.cap, 1.0));
+    }
     *out_plan = p.release();
     return SRM3_OK;
 }
@@ -583,6 +613,7 @@ srm3_status srm3_process_plan(const srm3_process_grid *grid, const double *S, co
     std::vector<uint32_t> betaw;
     long long process_pairs = 0;
     if (bispectrum && (bispectrum->kind == SRM3_BISPEC_WIND || bispectrum->kind == SRM3_BISPEC_PRODUCT ||
+                       bispectrum->kind == SRM3_BISPEC_HASHED ||
                        bispectrum->line_c || bispectrum->line_r))
         return fail(SRM3_E_UNSUPPORTED, "process plans take frequency-only bicoherence");
     if (bispectrum && bispectrum->kind != SRM3_BISPEC_NONE) {
@@ -717,6 +748,8 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
     }
     if (algorithm != SRM3_ALGO_KAPPA_FFT && algorithm != SRM3_ALGO_FFT2D)
         return fail(SRM3_E_INVALID, "algorithm %d", algorithm);
+    if (plan->hashed)
+        return fail(SRM3_E_UNSUPPORTED, "a bispectrum generated per pair has kappa-dependent weights: direct form only");
     if (plan->algo == algorithm) return SRM3_OK;
     KfftGeom k = kfft_geometry(plan->g, plan->process);
     std::string why;
@@ -1116,6 +1149,8 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
     for (int i = 0; i < n; ++i) {
         const srm3_request &r = reqs[i];
         if (!r.plan || !r.out_dev) return fail(SRM3_E_INVALID, "request %d: NULL plan or output", i);
+        if (r.plan->hashed)
+            return fail(SRM3_E_UNSUPPORTED, "request %d: bispectra generated per pair run through srm3_generate", i);
         if (r.plan->precision != precision)
             return fail(SRM3_E_INVALID, "request %d: all requests of a batch share one precision", i);
         if (!(r.b2_scale > 0) || !std::isfinite(r.b2_scale))

@@ -37,6 +37,28 @@ __host__ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint3
     return c0;
 }
 
+// The first two output words of the same generator.
+__host__ __device__ inline void philox_words01(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key,
+                                               uint32_t *w0, uint32_t *w1)
+{
+    uint32_t k0 = static_cast<uint32_t>(key), k1 = static_cast<uint32_t>(key >> 32);
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    *w0 = c0;
+    *w1 = c1;
+}
+
 template <typename T> struct vec;
 template <> struct vec<float> { using v2 = float2; using v4 = float4; };
 template <> struct vec<double> { using v2 = double2; using v4 = double4; };
@@ -81,7 +103,8 @@ struct AmpRef {
     const double *const *S_b;
     double dkdw;
     double cap;
-    int pairs = 1;   // 0: zero bicoherence, the pair sums are not computed (Gaussian field)
+    int pairs = 1;   // 0: zero bicoherence, the pair sums are not computed (Gaussian field);
+                     // 2: the pair sums hold the whole self pair (hashed bispectra)
     const double *lc = nullptr;   // per-line complex pair factor c_k, interleaved (NULL = 1)
     const double *lr = nullptr;   // per-line complex phase factor rho_k, interleaved (NULL = 1);
                                   // the pure part divides it out
@@ -92,6 +115,10 @@ hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds
                          int batch, const Workspace &ws, const double *lr, hipStream_t st);
 hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
                           const Workspace &ws, hipStream_t st);
+// Bispectrum generated per pair inside the kernel (hashed b^2 and beta).  With
+// ws == nullptr it writes the per-line raw sums sum b^2_raw to sig (FP64).
+hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, double scale, int batch,
+                               const Workspace *ws, double *sig, hipStream_t st);
 // Persistent pair sum over a device work list (all requests share R).
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
                                      int *q_next, int nblocks, hipStream_t st);
@@ -201,6 +228,9 @@ struct srm3_plan_s {
     int ws_batch = 0;
     bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)
     bool process = false;    // the 1-D process: one kappa line, one-sided spectrum and pairs
+    bool hashed = false;     // bispectrum generated per pair in the kernel (SRM3_BISPEC_HASHED)
+    uint64_t hash_key = 0;
+    double hash_scale = 0;
     // pair-sum algorithm; the kappa-FFT form keeps its tables and workspace here
     int algo = SRM3_ALGO_DIRECT;
     srm3::KfftGeom kg{};

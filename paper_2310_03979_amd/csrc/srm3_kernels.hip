@@ -707,7 +707,7 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     t.y = T(0);
     if (amp.pairs) t = tsum[bi];
     const int kw = c - (g.nw - 1);
-    if (amp.pairs && ((kk | kw) & 1) == 0) {
+    if (amp.pairs == 1 && ((kk | kw) & 1) == 0) {
         const int hw = kw / 2;
         if (hw > -g.W && hw < g.W) {
             // half of the self pair {(kk/2, kw/2), (kk/2, kw/2)}
@@ -931,6 +931,71 @@ __global__ __launch_bounds__(256) void zero_cols_kernel(typename vec<T>::v2 *tsu
     z.x = T(0);
     z.y = T(0);
     tsum[static_cast<long>(blockIdx.y) * per + idx] = z;
+}
+
+// Bispectrum generated per pair inside the kernel, no table: for the
+// canonical member (i, j) of an unordered pair (i_kappa > j_kappa, or equal
+// and i_w >= j_w), Philox4x32-10 with key `key` and counter
+// (i_kappa, i_w, j_kappa, j_w) gives b^2_raw = scale * word0 / 2^32 and
+// beta = 2 pi word1 / 2^32.  One thread per output line loops over its pairs
+// (self pair in full) and sums in FP64.  Without phases (zrow null) it sums
+// b^2_raw per line (plan time); else it writes the unscaled pair sum
+// sum sqrt(b^2_raw) e^{i(phi_i + phi_j + beta)}.
+struct HashPairArgs {
+    Geometry g;
+    uint64_t key;
+    double scale;
+    const void *zrow;   // [B][nk][nc] phase factors, or null
+    void *tsum;         // [B][nk][nc] complex out
+    double *sig;        // [nk][nc] out when zrow is null
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void pairsum_hash_kernel(HashPairArgs a)
+{
+    using T2 = typename vec<T>::v2;
+    const Geometry &g = a.g;
+    const long per = static_cast<long>(g.nk) * g.nc;
+    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= per) return;
+    const int kk = static_cast<int>(idx / g.nc);
+    const int kw = static_cast<int>(idx - static_cast<long>(kk) * g.nc) - (g.nw - 1);
+    const T2 *z = a.zrow ? static_cast<const T2 *>(a.zrow) + static_cast<long>(blockIdx.y) * per : nullptr;
+    const int W = g.W;
+    const int lo0 = max(-(W - 1), kw - (W - 1)), hi = min(W - 1, kw + (W - 1));
+    double sr = 0.0, si = 0.0, s2 = 0.0;
+    for (int ik = (kk + 1) >> 1; ik <= kk; ++ik) {
+        const int jk = kk - ik;
+        const int lo = ik == jk ? max(lo0, (kw + 1) >> 1) : lo0;
+        for (int iw = lo; iw <= hi; ++iw) {
+            const int jw = kw - iw;
+            uint32_t w0, w1;
+            philox_words01(static_cast<uint32_t>(ik), static_cast<uint32_t>(iw), static_cast<uint32_t>(jk),
+                           static_cast<uint32_t>(jw), a.key, &w0, &w1);
+            const double b2 = a.scale * static_cast<double>(w0) * (1.0 / 4294967296.0);
+            if (!z) {
+                s2 += b2;
+                continue;
+            }
+            const T2 zi = z[static_cast<long>(ik) * g.nc + iw + g.nw - 1];
+            const T2 zj = z[static_cast<long>(jk) * g.nc + jw + g.nw - 1];
+            const double tr = static_cast<double>(zi.x) * zj.x - static_cast<double>(zi.y) * zj.y;
+            const double ti = static_cast<double>(zi.x) * zj.y + static_cast<double>(zi.y) * zj.x;
+            double sb, cb;
+            sincospi(static_cast<double>(w1) * (1.0 / 2147483648.0), &sb, &cb);
+            const double bp = sqrt(b2);
+            sr += bp * (tr * cb - ti * sb);
+            si += bp * (tr * sb + ti * cb);
+        }
+    }
+    if (!z) {
+        a.sig[idx] = s2;
+        return;
+    }
+    T2 v;
+    v.x = static_cast<T>(sr);
+    v.y = static_cast<T>(si);
+    static_cast<T2 *>(a.tsum)[static_cast<long>(blockIdx.y) * per + idx] = v;
 }
 
 // Rank-one weights W(i_w, j_w) = g_i g_j (separable bicoherence, beta = 0):
@@ -1336,6 +1401,40 @@ hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, in
     case 16: return pairsum_t<float, 16, true>(g, wtab, batch, ws, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <typename T>
+static hipError_t pairsum_hash_t(const Geometry &g, uint64_t key, double scale, int batch, const Workspace *ws,
+                                 double *sig, hipStream_t st)
+{
+    HashPairArgs a{};
+    a.g = g;
+    a.key = key;
+    a.scale = scale;
+    a.zrow = ws ? ws->zrow : nullptr;
+    a.tsum = ws ? ws->tsum : nullptr;
+    a.sig = sig;
+    const long per = static_cast<long>(g.nk) * g.nc;
+    const unsigned gx = static_cast<unsigned>((per + 255) / 256);
+    hipError_t e = hipSuccess;
+    for (int b0 = 0; b0 < (ws ? batch : 1); b0 += 65535) {
+        const int nb = ws ? std::min(65535, batch - b0) : 1;
+        HashPairArgs c = a;
+        if (ws) {
+            c.zrow = static_cast<const typename vec<T>::v2 *>(ws->zrow) + static_cast<long>(b0) * per;
+            c.tsum = static_cast<typename vec<T>::v2 *>(ws->tsum) + static_cast<long>(b0) * per;
+        }
+        pairsum_hash_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(c);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return e;
+}
+
+hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, double scale, int batch,
+                               const Workspace *ws, double *sig, hipStream_t st)
+{
+    return precision == SRM3_FP64 ? pairsum_hash_t<double>(g, key, scale, batch, ws, sig, st)
+                                  : pairsum_hash_t<float>(g, key, scale, batch, ws, sig, st);
 }
 
 template <typename T, int R, bool COMP>

@@ -202,7 +202,7 @@ def _bispectrum(bispectrum: Optional[dict], default_w: int):
     """Marshal a bispectrum dict into the C struct; returns (struct or None, arrays to keep alive, W)."""
     if bispectrum is None:
         return None, [], 1
-    kinds = {"none": 0, "separable": 1, "dense": 2, "wind": 3, "product": 4}
+    kinds = {"none": 0, "separable": 1, "dense": 2, "wind": 3, "product": 4, "hashed": 5}
     modes = {"seeded": 0, "zero": 1, "table": 2}
     kind = bispectrum.get("kind", "separable")
     kind = kinds[kind] if isinstance(kind, str) else int(kind)

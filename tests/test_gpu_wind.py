@@ -258,3 +258,66 @@ def test_product_bispectrum_matches_oracle(lib, oracle_mod, case, precision, alg
         Cref = P.coefficients(seed=s)
         assert _rel(C[i], Cref) <= TOL[precision], i
         assert _rel(u[i], oracle_mod.field(Cref, nx, nt)) <= TOL[precision], i
+
+
+HASH_CASES = [
+    # nk, nw, W, nx, nt, scale, cap
+    (6, 10, 10, 8, 32, 0.02, 0.5),
+    (13, 20, 9, 32, 64, 0.01, 0.0),
+    (1, 8, 8, 1, 16, 0.05, 0.0),
+    (24, 40, 40, 64, 128, 0.004, 0.9),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", HASH_CASES, ids=[f"{c[0]}x{c[1]}w{c[2]}_cap{c[6]}" for c in HASH_CASES])
+def test_hashed_bispectrum_matches_oracle(lib, oracle_mod, case, precision):
+    """b and beta generated per 4-index pair inside the kernel."""
+    nk, nw, W, nx, nt, scale, cap = case
+    print(f"[gpu] hashed {case} {precision}", flush=True)
+    S = inp.random_spectrum(nk, nw, seed=nk + nw)
+    grid = dict(n_kappa=nk, n_omega=nw, d_kappa=0.3, d_omega=0.2, n_x=nx, n_t=nt)
+    key = 0x1234ABCD5678
+    plan = lib.srm3_plan(grid, S, dict(kind="hashed", alpha=scale, beta_seed=key, cap=cap, support_w=W), precision)
+    P = oracle_mod.HashedProblem(nk, nw, W, 0.3, 0.2, S, scale, key, cap)
+    seeds = [31, 32]
+    C, u = _run(lib, plan, nx, nt, seeds)
+    for i, s in enumerate(seeds):
+        Cref = P.coefficients(seed=s)
+        assert _rel(C[i], Cref) <= TOL[precision], i
+        assert _rel(u[i], oracle_mod.field(Cref, nx, nt)) <= TOL[precision], i
+    one = _run(lib, plan, nx, nt, [seeds[1]])[0]
+    assert np.array_equal(one[0], C[1])
+
+
+def test_hashed_full_size_sampled_lines_and_errors(lib, oracle_mod):
+    torch = _torch()
+    wl = inp.C1.with_(batch=1)
+    print("[gpu] hashed c1", flush=True)
+    S = wl.spectrum()
+    key = 77
+    bis = dict(kind="hashed", alpha=1e-4, beta_seed=key, cap=0.9, support_w=wl.support_w)
+    plan = lib.srm3_plan(wl.grid_dict(), S, bis, "fp32")
+    C = torch.empty((1,) + plan.coeff_shape, dtype=torch.complex64, device="cuda")
+    lib.srm3_coefficients(plan, wl.seeds(), C)
+    torch.cuda.synchronize()
+    P = oracle_mod.HashedProblem(wl.n_kappa, wl.n_omega, wl.support_w, wl.d_kappa, wl.d_omega, S, 1e-4, key, 0.9)
+    rng = np.random.default_rng(12)
+    kk = np.concatenate([[wl.n_kappa - 1, 0], rng.integers(0, wl.n_kappa, 30)])
+    cc = np.concatenate([[wl.n_omega - 1, 0], rng.integers(0, wl.n_cols, 30)])
+    lines = (kk * wl.n_cols + cc).astype(np.int64)
+    ref = P.coefficients(seed=int(wl.seeds()[0]), lines=lines)
+    got = C[0].reshape(-1)[torch.as_tensor(lines, device="cuda")].to(torch.complex128).cpu().numpy()
+    assert _rel(got, ref) <= TOL["fp32"]
+    for algo in ("kappa_fft", "fft2d"):
+        with pytest.raises(lib.Srm3Error) as ei:
+            lib.srm3_plan_set_algorithm(plan, algo)
+        assert ei.value.status == 5
+    out = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.Batch([dict(plan=plan, seed=1, out=out)])
+    assert ei.value.status == 5
+    srv = lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 30)
+    with pytest.raises(lib.Srm3Error) as ei:
+        srv.submit(plan, 1, out)
+    assert ei.value.status == 5

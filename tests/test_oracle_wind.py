@@ -274,3 +274,34 @@ def test_product_third_moment_is_the_bispectrum_integral(oracle_mod):
     se3 = X3.std(ddof=1) / math.sqrt(R)
     assert abs(X3.mean() - m3) <= 4.5 * se3
     assert abs(m3 - m3_nophase) >= 10 * se3       # the biphase matters at this size
+
+
+def test_hashed_bispectrum_brute_force(oracle_mod):
+    """A bispectrum drawn per 4-index pair: the pair sum written out in Python
+    with the generator called per canonical pair (b2_raw = scale U / 2^32,
+    beta = 2 pi V / 2^32), cap included."""
+    nk, nw, W, scale, key, cap = 4, 5, 4, 0.05, 0xABCDEF12345, 0.3
+    S = inp.random_spectrum(nk, nw, seed=9)
+    P = oracle_mod.HashedProblem(nk, nw, W, 0.3, 0.2, S, scale, key, cap)
+    U = oracle_mod.phases(nk, nw, 42)
+    C = P.coefficients(U=U)
+    phi = TWO_PI * U.astype(np.float64) / 2.0 ** 32
+    kw0 = [key & 0xFFFFFFFF, key >> 32]
+    c0 = nw - 1
+    b2_seen = {}
+    for kk in range(nk):
+        for kw in range(-(nw - 1), nw):
+            prs = list(_pairs(nk, nw, W, kk, kw))
+            words = [oracle_mod.philox4x32_10([ik, iw & 0xFFFFFFFF, jk, jw & 0xFFFFFFFF], kw0) for ik, iw, jk, jw in prs]
+            b2 = [scale * float(w[0]) / 2.0 ** 32 for w in words]
+            for (ik, iw, jk, jw), v in zip(prs, b2):
+                b2_seen.setdefault((iw, jw), set()).add(round(v, 15))
+            tot = sum(b2)
+            rho = cap / tot if tot > cap else 1.0
+            acc = math.sqrt(1.0 - rho * tot) * np.exp(1j * phi[kk, kw + c0])
+            for (ik, iw, jk, jw), v, w in zip(prs, b2, words):
+                acc += math.sqrt(rho * v) * np.exp(1j * (phi[ik, iw + c0] + phi[jk, jw + c0] + TWO_PI * float(w[1]) / 2.0 ** 32))
+            ref = 2.0 * math.sqrt(S[kk, kw + c0] * 0.3 * 0.2) * acc
+            assert abs(C[kk, kw + c0] - ref) <= 1e-12 * max(1.0, abs(ref))
+    # the same frequency pair takes different values at different wavenumbers
+    assert max(len(v) for v in b2_seen.values()) > 1
