@@ -339,9 +339,11 @@ enum {
  * Allocates one workspace slice per request and builds the work list: every
  * (request, row block, column group) item, ordered by request cost and cut
  * into eight queues, one per XCD.  Requests whose plan uses
- * SRM3_ALGO_KAPPA_FFT run that pair sum per grid (all their realizations at
- * once) instead; plans with zero bicoherence have no pair stage.  The plan's
- * algorithm is read here: set it before creating the batch.  Host arrays are
+ * SRM3_ALGO_KAPPA_FFT or SRM3_ALGO_FFT2D run that pair sum per grid (all their
+ * realizations at once) instead; plans with zero bicoherence have no pair
+ * stage.  The plan's
+ * algorithm is read here: set it before creating the batch (plans with
+ * SRM3_BISPEC_HASHED are refused, SRM3_E_UNSUPPORTED).  Host arrays are
  * copied; plans must outlive the batch.  Fails with SRM3_E_PURE_NEGATIVE if a
  * scaled request would make some Sigma_k >= 1. */
 srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags, void *hip_stream,
@@ -405,9 +407,11 @@ typedef struct {
 srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, srm3_server_t *out);
 /* Queue a request.  If `spectrum` is given, the request's spectrum is
  * evaluated on the device at admission into its own arena space (req->S_dev
- * must then be NULL; SRM3_E_UNSUPPORTED for a process plan).  out_dev must
- * stay valid until the ticket completes.  SRM3_E_NOMEM if the request could
- * never fit the arena. */
+ * must then be NULL; SRM3_E_UNSUPPORTED for a process plan).  The plan's
+ * pair-sum algorithm is read here; the plan must not change algorithm while
+ * the request is in flight.  Plans with SRM3_BISPEC_HASHED are refused
+ * (SRM3_E_UNSUPPORTED).  out_dev must stay valid until the ticket completes.
+ * SRM3_E_NOMEM if the request could never fit the arena. */
 srm3_status srm3_server_submit(srm3_server_t srv, const srm3_request *req,
                                const srm3_kaimal_davenport *spectrum, int64_t *ticket);
 /* One scheduling iteration (non-blocking: does nothing while two steps are in flight). */
