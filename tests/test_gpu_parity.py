@@ -196,7 +196,7 @@ def test_c1_full_size_sampled_lines(lib, oracle_mod, precision):
     C = _gpu_coeffs(lib, plan, seeds)
     P = _oracle_problem(oracle_mod, wl, bis, b2)
     for r in (0, 31, 63):
-        lines = _sample_lines(wl, 48, r)
+        lines = _sample_lines(wl, 4096 if r == 0 else 48, r)   # split parity on 4096 random lines
         ref = P.coefficients(seed=int(seeds[r]), lines=lines)
         got = C[r].reshape(-1)[torch.as_tensor(lines, device="cuda")].cpu().numpy()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL[precision], r
@@ -250,7 +250,7 @@ def test_c2_full_size_sampled_lines(lib, oracle_mod):
     C = _gpu_coeffs(lib, plan, seeds)
     P = _oracle_problem(oracle_mod, wl, bis, b2)
     for r in (0, 15):
-        lines = _sample_lines(wl, 24, 100 + r)
+        lines = _sample_lines(wl, 4096 if r == 0 else 24, 100 + r)
         ref = P.coefficients(seed=int(seeds[r]), lines=lines)
         got = C[r].reshape(-1)[torch.as_tensor(lines, device="cuda")].cpu().numpy()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= TOL["fp32"], r
