@@ -540,6 +540,28 @@ def bench_bridge(args, torch, srm3):
     v2, s2 = wind_theory(wl2, c2, r2, sig2)
     stats["alpha_0.1_uncapped"] = {"sample": moments(outk), "theory": {"variance": round(v2, 3),
                                                                        "skewness": round(s2, 4)}}
+
+    # the statistics experiment of Section 5: 1000 realizations of both orders
+    # from identical phases (2-D FFT pair sum), moments pooled over all points
+    def pooled(plan_, n_real, first_seed):
+        acc = torch.zeros(4, dtype=torch.float64, device="cuda")
+        for r0 in range(0, n_real, B):
+            nb = min(B, n_real - r0)
+            sd = np.arange(first_seed + r0, first_seed + r0 + nb, dtype=np.uint64)
+            srm3.srm3_generate(plan_, sd, outk[:nb])
+            x = outk[:nb].double()
+            acc += torch.stack([x.sum(), x.pow(2).sum(), x.pow(3).sum(), torch.tensor(float(x.numel()),
+                                                                                      device="cuda")])
+        s1, s2_, s3, n = acc.tolist()
+        m = s1 / n
+        v = s2_ / n - m * m
+        return {"mean": round(m, 4), "variance": round(v, 3),
+                "skewness": round((s3 / n - 3 * m * v - m ** 3) / v ** 1.5, 4)}
+    t1 = time.perf_counter()
+    stats["1000_realizations"] = {"third_order": pooled(fplan, 1000, 10000),
+                                  "second_order_same_phases": pooled(gplan, 1000, 10000),
+                                  "theory": stats["theory"]}
+    stats["1000_realizations"]["seconds"] = round(time.perf_counter() - t1, 3)
     log(f"[bench] statistics {stats}")
     extra = {}
     if not args.no_cpu:
