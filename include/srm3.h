@@ -134,7 +134,9 @@ typedef struct {
  * sum and H as the weight table.  The wind bispectrum is the case
  * F_k = alpha 2 sqrt(S_k) / (3 sqrt(3 |w_k| kappa_k)), G = sqrt(S), H = 1.
  * support_w limits the pairs; g2, b2, beta and alpha are ignored.  Plan-time
- * sums: 2-D FFTs when H is NULL, else O(M (4W-3)(2W-1)) per sweep. */
+ * sums: 2-D FFTs when H is NULL, else O(M (4W-3)(2W-1)) per sweep.  The
+ * factors depend on S, so such a plan keeps its spectrum: srm3_set_spectrum
+ * and per-request spectra (batches, server) return SRM3_E_UNSUPPORTED. */
 
 /* SRM3_BISPEC_WIND.  B = alpha 2 sqrt(S_i S_j S_k) / (3 sqrt(3 |w_i + w_j| (kappa_i + kappa_j)))
  * (Section 5; |.| since the kappa >= 0 half plane holds negative frequencies;

@@ -471,6 +471,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
         p->g2_host.assign(bs.g2, bs.g2 + ncw);   // rank-one weights: the 2-D FFT pair sum applies
     p->pair_terms = p->gaussian ? 0.0 : pair_terms;
     p->hashed = hashed;
+    p->fixed_spectrum = bispectrum && bispectrum->kind == SRM3_BISPEC_PRODUCT;
     p->hash_key = hash_key;
     p->hash_scale = hash_scale;
     Geometry &g = p->g;
@@ -665,6 +666,8 @@ srm3_status srm3_set_spectrum(srm3_plan_t plan, const srm3_spectrum *spectrum, v
 {
     g_err[0] = 0;
     if (!plan || !spectrum || !spectrum->S) return fail(SRM3_E_INVALID, "plan/spectrum is NULL");
+    if (plan->fixed_spectrum)
+        return fail(SRM3_E_UNSUPPORTED, "a product bispectrum's line factors were derived from the plan's spectrum");
     const size_t n = static_cast<size_t>(plan->g.nk) * plan->g.nc;
     const double *src = spectrum->S;
     std::vector<double> Sw;
@@ -1151,6 +1154,8 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
         if (!r.plan || !r.out_dev) return fail(SRM3_E_INVALID, "request %d: NULL plan or output", i);
         if (r.plan->hashed)
             return fail(SRM3_E_UNSUPPORTED, "request %d: bispectra generated per pair run through srm3_generate", i);
+        if (r.plan->fixed_spectrum && r.S_dev)
+            return fail(SRM3_E_UNSUPPORTED, "request %d: a product bispectrum's plan keeps its own spectrum", i);
         if (r.plan->precision != precision)
             return fail(SRM3_E_INVALID, "request %d: all requests of a batch share one precision", i);
         if (!(r.b2_scale > 0) || !std::isfinite(r.b2_scale))

@@ -229,6 +229,7 @@ struct srm3_plan_s {
     bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)
     bool process = false;    // the 1-D process: one kappa line, one-sided spectrum and pairs
     bool hashed = false;     // bispectrum generated per pair in the kernel (SRM3_BISPEC_HASHED)
+    bool fixed_spectrum = false;   // line factors derived from S (SRM3_BISPEC_PRODUCT): S may not change
     uint64_t hash_key = 0;
     double hash_scale = 0;
     // pair-sum algorithm; the kappa-FFT form keeps its tables and workspace here

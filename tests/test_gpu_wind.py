@@ -321,3 +321,29 @@ def test_hashed_full_size_sampled_lines_and_errors(lib, oracle_mod):
     with pytest.raises(lib.Srm3Error) as ei:
         srv.submit(plan, 1, out)
     assert ei.value.status == 5
+
+
+def test_product_plan_keeps_its_spectrum(lib):
+    torch = _torch()
+    nk, nw, W = 6, 10, 10
+    rng = np.random.default_rng(2)
+    S = inp.random_spectrum(nk, nw, seed=2)
+    F = 0.3 * rng.uniform(0.2, 1.0, S.shape) + 0j
+    G = np.sqrt(S) + 0j
+    grid = dict(n_kappa=nk, n_omega=nw, d_kappa=0.5, d_omega=0.4, n_x=8, n_t=32)
+    plan = lib.srm3_plan(grid, S, dict(kind="product", F=F, G=G, cap=0.0, support_w=W), "fp32")
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.srm3_set_spectrum(plan, S)
+    assert ei.value.status == 5
+    out = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
+    Sd = torch.as_tensor(S, device="cuda")
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.Batch([dict(plan=plan, seed=1, out=out, S=Sd)])
+    assert ei.value.status == 5
+    srv = lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 28)
+    with pytest.raises(lib.Srm3Error) as ei:
+        srv.submit(plan, 1, out, spectrum=dict(U=30.0))
+    assert ei.value.status == 5
+    b = lib.Batch([dict(plan=plan, seed=1, out=out)])        # its own spectrum is fine
+    b.run()
+    torch.cuda.synchronize()
