@@ -604,7 +604,7 @@ def bench_bridge(args, torch, srm3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: srm3 runs on one GPU; --gpus {args.gpus} is not supported "
               "(realizations are independent and would shard across GPUs with no communication)",
               file=sys.stderr)
         sys.exit(2)

@@ -55,7 +55,7 @@ typedef enum {
     SRM3_E_PURE_NEGATIVE = 2,  /* some line has Sigma_k >= 1: pure spectrum not positive (Section 5) */
     SRM3_E_NOMEM = 3,          /* device or host allocation failed */
     SRM3_E_DEVICE = 4,         /* a HIP runtime call or kernel launch failed */
-    SRM3_E_UNSUPPORTED = 5     /* valid but outside this build's limits (see srm3_plan) */
+    SRM3_E_UNSUPPORTED = 5     /* valid but outside the library's limits (see srm3_plan) */
 } srm3_status;
 
 typedef enum { SRM3_FP64 = 0, SRM3_FP32 = 1 } srm3_precision;

@@ -271,7 +271,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
                     nk, nc);
     const int tmax = precision == SRM3_FP64 ? 8192 : 16384;   // one transform fits 128 KB of LDS
     if (nt > tmax || nx > tmax)
-        return fail(SRM3_E_UNSUPPORTED, "n_t=%d / n_x=%d above this build's limit %d", nt, nx, tmax);
+        return fail(SRM3_E_UNSUPPORTED, "n_t=%d / n_x=%d above the library's limit %d", nt, nx, tmax);
     if (static_cast<long long>(nk) * nc > (1LL << 30)) return fail(SRM3_E_UNSUPPORTED, "line grid too large");
 
     // ---- bicoherence description ----

@@ -1,9 +1,9 @@
-"""Serving driver: replays an arrival schedule against a ``Server`` and
+"""Arrival replay: replays an arrival schedule against a ``Server`` and
 reports per-request latency and throughput.
 
 Arrivals are given as offsets in seconds; a request is submitted when the
 wall clock passes its arrival time, the server is stepped continuously, and a
-request's latency runs from its arrival time to the moment the driver sees
+request's latency runs from its arrival time to the moment the replay loop sees
 its completion (polled, ~0.2 ms resolution).
 """
 from __future__ import annotations
