@@ -331,7 +331,7 @@ def test_product_plan_keeps_its_spectrum(lib):
     F = 0.3 * rng.uniform(0.2, 1.0, S.shape) + 0j
     G = np.sqrt(S) + 0j
     grid = dict(n_kappa=nk, n_omega=nw, d_kappa=0.5, d_omega=0.4, n_x=8, n_t=32)
-    plan = lib.srm3_plan(grid, S, dict(kind="product", F=F, G=G, cap=0.0, support_w=W), "fp32")
+    plan = lib.srm3_plan(grid, S, dict(kind="product", F=F, G=G, cap=0.5, support_w=W), "fp32")
     with pytest.raises(lib.Srm3Error) as ei:
         lib.srm3_set_spectrum(plan, S)
     assert ei.value.status == 5
