@@ -145,6 +145,22 @@ def counter_traffic(wl):
         return None
 
 
+def counter_valu(wl):
+    """VALU issue fraction of the pair-sum launch from the same committed
+    counter summary (SQ_INSTS_VALU x 4 cycles over the 1024 SIMDs and the
+    kernel's cycles), under the same source-hash condition, else None."""
+    if counter_traffic(wl) is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"pairsum_{wl.name}_counters.md")
+    for line in open(path):
+        if line.startswith("* VALU issue") and "**" in line:
+            try:
+                return float(line.split("**")[1].split("%")[0]) / 100.0
+            except ValueError:
+                return None
+    return None
+
+
 def accuracy(torch, srm3, wl, plans, fields, sample):
     """Relative L2 of the GPU coefficients of realization 0 against the FP64
     oracle on the sampled lines, and the sample skewness of each path's fields."""
@@ -663,11 +679,14 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
         "traffic": counter_traffic(wl) if B == wl.batch else None,
+        "valu_issue_frac": counter_valu(wl) if B == wl.batch else None,
         "pair_terms_per_launch": terms * B,
         "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
         "avg_launch_ms": round(ps_ms, 4),
         "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
     }
+    if roofline["traffic"]:
+        roofline["hbm_GB_per_s"] = round(roofline["traffic"] / (ps_ms * 1e-3) / 1e9, 1)
     kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()}
 
     extra = {}
