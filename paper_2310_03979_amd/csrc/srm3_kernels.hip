@@ -689,6 +689,7 @@ struct TfftArgs {
     const void *tw;       // [nt]
     void *gout;           // [B][nk][nt]
     void *rout;           // n_x == 1 only, or null: the field itself, [B][nt] real (no x-transform)
+    int tw_lds;           // 1: the twiddles are copied to LDS after the row
 };
 
 // Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
@@ -769,6 +770,10 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         zero.y = T(0);
         buf[n] = zero;
     }
+    T2 *twl = buf + g.nt;
+    const bool twin = a.tw_lds;
+    if (twin)
+        for (int n = threadIdx.x; n < g.nt; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
     __syncthreads();
     for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
         const int kw = c - (g.nw - 1);
@@ -783,7 +788,7 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         buf[bin] = C;
     }
     __syncthreads();
-    fft_lds<T, MAXB>(buf, g.nt, g.nt, 1, static_cast<const T2 *>(a.tw));
+    fft_lds<T, MAXB>(buf, g.nt, g.nt, 1, twin ? twl : static_cast<const T2 *>(a.tw));
     if (a.rout) {
         // one kappa line and one x point: the x-transform is the real part
         T *u = static_cast<T *>(a.rout) + static_cast<long>(row) * g.nt;
@@ -817,6 +822,7 @@ struct XfftArgs {
     const void *tw;      // [nx]
     void *out;           // [B][nx][nt] real
     void *const *out_b;  // per realization output, or null (out + b * nx * nt)
+    int tw_lds;          // 1: the twiddles are copied to LDS after the tile (low-latency stage reads)
 };
 
 template <typename T, int MAXB>
@@ -836,6 +842,10 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
         zero.y = T(0);
         buf[n] = zero;
     }
+    T2 *twl = buf + tc * ld;
+    const bool twin = a.tw_lds;
+    if (twin)
+        for (int n = threadIdx.x; n < g.nx; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
     __syncthreads();
     const T2 *gin = static_cast<const T2 *>(a.gin) + static_cast<long>(b) * g.nk * g.nt;
     for (int n = threadIdx.x; n < tc * g.nk; n += blockDim.x) {
@@ -843,7 +853,7 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
         buf[col * ld + kk] = gin[static_cast<long>(kk) * g.nt + mt0 + col];
     }
     __syncthreads();
-    fft_lds<T, MAXB>(buf, g.nx, ld, tc, static_cast<const T2 *>(a.tw));
+    fft_lds<T, MAXB>(buf, g.nx, ld, tc, twin ? twl : static_cast<const T2 *>(a.tw));
     T *out = a.out_b ? static_cast<T *>(a.out_b[b]) : static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
     for (int n = threadIdx.x; n < tc * g.nx; n += blockDim.x) {
         const int mx = n / tc, col = n - mx * tc;
@@ -883,6 +893,7 @@ struct ColfftArgs {
     int forward;
     const void *tw;
     double scale;
+    int tw_lds;         // 1: the twiddles are copied to LDS after the tile
 };
 
 template <typename T, int MAXB>
@@ -904,8 +915,11 @@ __global__ __launch_bounds__(256) void colfft_kernel(ColfftArgs a)
         if (a.forward) v.y = -v.y;
         buf[col * a.N + row] = v;
     }
+    T2 *twl = buf + a.tc * a.N;
+    if (a.tw_lds)
+        for (int n = threadIdx.x; n < a.N; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
     __syncthreads();
-    fft_lds<T, MAXB>(buf, a.N, a.N, a.tc, static_cast<const T2 *>(a.tw));
+    fft_lds<T, MAXB>(buf, a.N, a.N, a.tc, a.tw_lds ? twl : static_cast<const T2 *>(a.tw));
     T2 *out = static_cast<T2 *>(a.out) + b * a.out_bstride;
     const T sc = static_cast<T>(a.scale);
     for (int n = threadIdx.x; n < a.out_rows * tc; n += blockDim.x) {
@@ -1011,6 +1025,7 @@ struct RowconvArgs {
     const void *gw;     // [2W - 1] g = sqrt(g2), path precision
     const void *tw;     // [L] exp(+2 pi i n / L)
     int W, nca, kw0, L;
+    int tw_lds;         // 1: the twiddles are copied to LDS after the row
 };
 
 template <typename T, int MAXB>
@@ -1034,8 +1049,12 @@ __global__ __launch_bounds__(1024) void rowconv_kernel(RowconvArgs a)
         }
         buf[n] = v;
     }
+    T2 *twl = buf + a.L;
+    if (a.tw_lds)
+        for (int n = threadIdx.x; n < a.L; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
+    const T2 *tw = a.tw_lds ? twl : static_cast<const T2 *>(a.tw);
     __syncthreads();
-    fft_lds<T, MAXB>(buf, a.L, a.L, 1, static_cast<const T2 *>(a.tw));
+    fft_lds<T, MAXB>(buf, a.L, a.L, 1, tw);
     for (int n = threadIdx.x; n < a.L; n += blockDim.x) {
         const T2 f = buf[n];
         T2 v;
@@ -1044,7 +1063,7 @@ __global__ __launch_bounds__(1024) void rowconv_kernel(RowconvArgs a)
         buf[n] = v;
     }
     __syncthreads();
-    fft_lds<T, MAXB>(buf, a.L, a.L, 1, static_cast<const T2 *>(a.tw));
+    fft_lds<T, MAXB>(buf, a.L, a.L, 1, tw);
     T2 *y = static_cast<T2 *>(a.Y) + row * a.nca;
     const T sc = T(1) / static_cast<T>(a.L);
     for (int cc = threadIdx.x; cc < a.nca; cc += blockDim.x) {
@@ -1514,7 +1533,9 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     a.tw = tw;
     a.gout = ws.g;
     const int thr = fft_threads(g.nt / 2);
-    const size_t lds = static_cast<size_t>(g.nt) * sizeof(typename vec<T>::v2);
+    size_t lds = static_cast<size_t>(g.nt) * sizeof(typename vec<T>::v2);
+    a.tw_lds = 2 * lds <= 131072 ? 1 : 0;
+    if (a.tw_lds) lds *= 2;
     tfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(batch * g.nk)), thr, lds, st>>>(a);
     return hipGetLastError();
 }
@@ -1565,7 +1586,9 @@ static hipError_t xfft_t(const Geometry &g, const void *tw, int batch, const Wor
     a.out = out;
     a.out_b = out_b;
     const int thr = fft_threads(tc * g.nx / 2);
-    const size_t lds = tc * col_bytes;
+    size_t lds = tc * col_bytes;
+    a.tw_lds = lds + col_bytes <= 131072 ? 1 : 0;
+    if (a.tw_lds) lds += col_bytes;
     xfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(g.nt / tc), batch), thr, lds, st>>>(a);
     return hipGetLastError();
 }
@@ -1647,7 +1670,10 @@ static hipError_t colfft_t(ColfftArgs a, int batch, hipStream_t st)
     using T2 = typename vec<T>::v2;
     a.tc = std::max(1, static_cast<int>(32768 / (static_cast<long>(a.N) * sizeof(T2))));
     const dim3 grid(static_cast<unsigned>((a.ncols + a.tc - 1) / a.tc), static_cast<unsigned>(batch));
-    colfft_kernel<T, 4><<<grid, 256, static_cast<size_t>(a.tc) * a.N * sizeof(T2), st>>>(a);
+    size_t lds = static_cast<size_t>(a.tc) * a.N * sizeof(T2);
+    a.tw_lds = lds + a.N * sizeof(T2) <= 131072 ? 1 : 0;
+    if (a.tw_lds) lds += a.N * sizeof(T2);
+    colfft_kernel<T, 4><<<grid, 256, lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -1692,7 +1718,9 @@ static hipError_t kfft_pairsum_t(const Geometry &g, const KfftGeom &k, const Kff
         r.L = k.L;
         const long rows = static_cast<long>(batch) * k.M;
         const int thr = fft_threads(k.L / 2);
-        const size_t lds = static_cast<size_t>(k.L) * sizeof(T2);
+        size_t lds = static_cast<size_t>(k.L) * sizeof(T2);
+        r.tw_lds = 2 * lds <= 131072 ? 1 : 0;
+        if (r.tw_lds) lds *= 2;
         for (long r0 = 0; r0 < rows; r0 += 1L << 30) {
             const long nr = std::min(rows - r0, 1L << 30);
             RowconvArgs rr = r;
@@ -1797,6 +1825,9 @@ static hipError_t prepare_t()
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rowconv_kernel<T, kFftMaxB>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&colfft_kernel<T, kFftMaxB>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T, kFftMaxB>),
