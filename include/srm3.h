@@ -238,15 +238,26 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  *                        frequency, a squaring and the inverse FFT, then the
  *                        inverse DFT along kappa.  Same result up to rounding;
  *                        O(M L log L) work per realization.
+ *   SRM3_ALGO_MFMA       the direct form's unordered pairs (same terms), FP32
+ *                        plans only, on the matrix cores: for each kappa split
+ *                        the sum over the partner frequency is a dense product
+ *                        of a block of phase rows with a block of weighted
+ *                        phases, evaluated with 16x16x4 FP32 MFMAs.  Same
+ *                        result up to rounding.  Runs through srm3_generate,
+ *                        srm3_coefficients and srm3_transform; batches and the
+ *                        server refuse such plans (SRM3_E_UNSUPPORTED).
  * Switching to SRM3_ALGO_KAPPA_FFT builds its sheared weight table on the
  * device (stream-ordered on hip_stream).  Errors: SRM3_E_INVALID (bad plan or
  * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048; SRM3_ALGO_FFT2D: weights
- * not rank-one, or L above 16384, 8192 in FP64), SRM3_E_NOMEM, SRM3_E_DEVICE. */
-enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1, SRM3_ALGO_FFT2D = 2 };
+ * not rank-one, or L above 16384, 8192 in FP64; SRM3_ALGO_MFMA: an FP64 plan),
+ * SRM3_E_NOMEM, SRM3_E_DEVICE.  A bispectrum generated per pair
+ * (SRM3_BISPEC_HASHED) takes SRM3_ALGO_DIRECT only. */
+enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1, SRM3_ALGO_FFT2D = 2, SRM3_ALGO_MFMA = 3 };
 srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream);
 
 /* Complex multiply-accumulate terms the plan's current pair-sum algorithm
- * evaluates per realization (SRM3_ALGO_DIRECT: the pair terms). */
+ * evaluates per realization (SRM3_ALGO_DIRECT and SRM3_ALGO_MFMA: the pair
+ * terms). */
 srm3_status srm3_algorithm_terms(srm3_plan_t plan, double *terms);
 
 /* Per-kernel device time, measured with HIP events recorded on the launch

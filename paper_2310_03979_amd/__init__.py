@@ -3,7 +3,7 @@
 The generator itself is the HIP library ``libsrm3.so`` (see ``include/srm3.h``);
 this package only builds it and marshals arguments to it.
 """
-from .srm3 import (SRM3_ALGO_DIRECT, SRM3_ALGO_FFT2D, SRM3_ALGO_KAPPA_FFT, SRM3_BATCH_AUTOTUNE, SRM3_BATCH_GRAPH,  # noqa: F401
+from .srm3 import (SRM3_ALGO_DIRECT, SRM3_ALGO_FFT2D, SRM3_ALGO_KAPPA_FFT, SRM3_ALGO_MFMA, SRM3_BATCH_AUTOTUNE, SRM3_BATCH_GRAPH,  # noqa: F401
                    SRM3_FP32, SRM3_FP64,
                    Batch, Plan, Server, Srm3Error, load, plan_from_workload, process_plan_from_workload,
                    srm3_batch_create, srm3_process_plan, srm3_wind_factors, srm3_product_factors,

@@ -159,6 +159,9 @@ srm3_status event_pair(srm3_plan_t p, int kernel, hipStream_t st, bool begin)
     return SRM3_OK;
 }
 
+// The pair-sum algorithms that go through a DFT along kappa (own workspace and tables).
+bool kfft_family(int algo) { return algo == SRM3_ALGO_KAPPA_FFT || algo == SRM3_ALGO_FFT2D; }
+
 srm3_status ensure_workspace(srm3_plan_t p, int batch, hipStream_t st)
 {
     if (batch > p->ws_batch) {
@@ -170,7 +173,7 @@ srm3_status ensure_workspace(srm3_plan_t p, int batch, hipStream_t st)
         }
         p->ws_batch = batch;
     }
-    if (p->algo != SRM3_ALGO_DIRECT && batch > p->kws_batch) {
+    if (kfft_family(p->algo) && batch > p->kws_batch) {
         const size_t bytes = kfft_workspace_bytes(p->g, p->kg, p->precision, batch);
         hipError_t e = p->kws.alloc(bytes);
         if (e != hipSuccess) {
@@ -199,7 +202,7 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
     Workspace wp = ws;
-    if (p->gaussian || p->hashed || p->algo != SRM3_ALGO_DIRECT) wp.zcol = nullptr;   // no a operand planes needed
+    if (p->gaussian || p->hashed || kfft_family(p->algo)) wp.zcol = nullptr;   // no a operand planes needed
     hipError_t e = launch_phases(p->g, p->precision, seeds, nullptr, batch, wp, static_cast<const double *>(p->lr.p), st);
     if (e != hipSuccess) return dev_err(e, "phase kernel");
     if ((s = event_pair(p, 0, st, false))) return s;
@@ -208,10 +211,13 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     if (p->hashed) {
         e = launch_pairsum_hash(p->g, p->precision, p->hash_key, p->hash_scale, batch, &ws, nullptr, st);
         if (e != hipSuccess) return dev_err(e, "hashed pair-sum kernel");
-    } else if (p->algo != SRM3_ALGO_DIRECT) {
+    } else if (kfft_family(p->algo)) {
         const KfftWorkspace kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
         e = launch_kfft_pairsum(p->precision, p->g, p->kg, plan_ktab(p), batch, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
+    } else if (p->algo == SRM3_ALGO_MFMA) {
+        e = launch_pairsum_mfma(p->g, p->wtab.p, batch, ws, st);
+        if (e != hipSuccess) return dev_err(e, "matrix-core pair-sum kernel");
     } else {
         e = launch_pairsum(p->g, p->precision, p->wtab.p, batch, ws, st);
         if (e != hipSuccess) return dev_err(e, "pair-sum kernel");
@@ -723,7 +729,7 @@ srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes)
 {
     if (!plan || !bytes || batch < 0) return fail(SRM3_E_INVALID, "bad argument");
     *bytes = workspace_bytes(plan->g, plan->precision, batch);
-    if (plan->algo != SRM3_ALGO_DIRECT) *bytes += kfft_workspace_bytes(plan->g, plan->kg, plan->precision, batch);
+    if (kfft_family(plan->algo)) *bytes += kfft_workspace_bytes(plan->g, plan->kg, plan->precision, batch);
     return SRM3_OK;
 }
 
@@ -749,10 +755,15 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
         plan->algo = SRM3_ALGO_DIRECT;
         return SRM3_OK;
     }
-    if (algorithm != SRM3_ALGO_KAPPA_FFT && algorithm != SRM3_ALGO_FFT2D)
+    if (algorithm != SRM3_ALGO_KAPPA_FFT && algorithm != SRM3_ALGO_FFT2D && algorithm != SRM3_ALGO_MFMA)
         return fail(SRM3_E_INVALID, "algorithm %d", algorithm);
     if (plan->hashed)
         return fail(SRM3_E_UNSUPPORTED, "a bispectrum generated per pair has kappa-dependent weights: direct form only");
+    if (algorithm == SRM3_ALGO_MFMA) {
+        if (plan->precision != SRM3_FP32) return fail(SRM3_E_UNSUPPORTED, "the matrix-core pair sum is FP32 only");
+        plan->algo = SRM3_ALGO_MFMA;
+        return SRM3_OK;
+    }
     if (plan->algo == algorithm) return SRM3_OK;
     KfftGeom k = kfft_geometry(plan->g, plan->process);
     std::string why;
@@ -789,7 +800,7 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
 srm3_status srm3_algorithm_terms(srm3_plan_t plan, double *terms)
 {
     if (!plan || !terms) return fail(SRM3_E_INVALID, "bad argument");
-    *terms = plan->algo != SRM3_ALGO_DIRECT ? kfft_terms(plan->g, plan->kg) : plan->pair_terms;
+    *terms = kfft_family(plan->algo) ? kfft_terms(plan->g, plan->kg) : plan->pair_terms;
     return SRM3_OK;
 }
 
@@ -1154,6 +1165,8 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
         if (!r.plan || !r.out_dev) return fail(SRM3_E_INVALID, "request %d: NULL plan or output", i);
         if (r.plan->hashed)
             return fail(SRM3_E_UNSUPPORTED, "request %d: bispectra generated per pair run through srm3_generate", i);
+        if (r.plan->algo == SRM3_ALGO_MFMA)
+            return fail(SRM3_E_UNSUPPORTED, "request %d: matrix-core pair sums run through srm3_generate", i);
         if (r.plan->fixed_spectrum && r.S_dev)
             return fail(SRM3_E_UNSUPPORTED, "request %d: a product bispectrum's plan keeps its own spectrum", i);
         if (r.plan->precision != precision)

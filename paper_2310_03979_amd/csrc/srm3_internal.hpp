@@ -115,6 +115,10 @@ hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds
                          int batch, const Workspace &ws, const double *lr, hipStream_t st);
 hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
                           const Workspace &ws, hipStream_t st);
+// The same pair sum (FP32 only) on the matrix cores: dense products over the
+// partner frequency for each kappa split.
+hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, const Workspace &ws,
+                               hipStream_t st);
 // Bispectrum generated per pair inside the kernel (hashed b^2 and beta).  With
 // ws == nullptr it writes the per-line raw sums sum b^2_raw to sig (FP64).
 hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, double scale, int batch,

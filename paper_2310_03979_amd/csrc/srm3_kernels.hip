@@ -120,6 +120,11 @@ __device__ __forceinline__ double2 bload(brsrc r, unsigned voff, unsigned soff, 
     __builtin_memcpy(&d, &v, sizeof(d));
     return d;
 }
+__device__ __forceinline__ float bload32(brsrc r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff),
+                                                                          static_cast<int>(soff), 0));
+}
 #else
 struct brsrc {
     const void *p;
@@ -127,6 +132,7 @@ struct brsrc {
 __device__ inline brsrc make_brsrc(const void *p, unsigned) { return brsrc{p}; }
 __device__ inline float2 bload(brsrc, unsigned, unsigned, float) { return float2{}; }
 __device__ inline double2 bload(brsrc, unsigned, unsigned, double) { return double2{}; }
+__device__ inline float bload32(brsrc, unsigned, unsigned) { return 0.0f; }
 #endif
 
 // Layout of the a operand (re, re + im, im - re) of support column ic, row kk:
@@ -496,6 +502,226 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
                              static_cast<const T *>(a.zcol) + b * ALayout<T>::NS * plane,
                              static_cast<const T2 *>(a.wtab), static_cast<T2 *>(a.tout) + b * lines, kb, ct,
                              a.flush_terms);
+}
+
+// ---------------------------------------------------------------------------
+// Pair sum on the matrix cores (FP32).
+//
+// Grouped by the kappa split jk instead of the partner column, the sum of the
+// vector kernel reads
+//     T[kk][kw] = sum_jk f(kk, jk) sum_iw A_jk[kk][iw] B_jk[iw][kw],
+//     A_jk[kk][iw] = z[kk - jk][iw],   B_jk[iw][kw] = W(iw, kw - iw) z[jk][kw - iw],
+// with f = 1 for 2 jk < kk, 1/2 for 2 jk == kk, 0 above.  For fixed jk the iw
+// sum is a dense product of a block of phase rows (A, rows kk) and a block of
+// weighted phases (B) that every output row shares, so it runs as 16x16x4
+// FP32 MFMAs with iw as the reduction index: one B element is formed per
+// (jk, 4 partner columns, 16 output columns) and used by all the rows of the
+// wave's tile.  Complex products take three real products, with A stored as
+// (re, re + im, im - re) (the a planes of the phase kernel) and B as
+// (re + im, im, re):
+//     P1 += A_re (B_re + B_im),  P2 += (A_re + A_im) B_im,  P3 += (A_im - A_re) B_re,
+//     Re T = P1 - P2,  Im T = P1 + P3.
+// The sums are flushed into error-free (two-sum) accumulators every few
+// hundred steps.  A wave owns RT x CT tiles of 16 x 16 outputs; partner
+// columns are stepped 4 at a time (outer loop, weights kept in registers),
+// kappa splits one at a time (inner loop).  Operand layouts of
+// v_mfma_f32_16x16x4_f32 (lane l, i = l % 16, q = l / 16): A[i][q], B[q][i]
+// in, D[4 q + e][i] (e = 0..3) out.
+// ---------------------------------------------------------------------------
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+struct MfmaArgs {
+    const void *zrow;   // [B][nk][nc] float2
+    const void *zcol;   // [B][3][ncw][nkp] float planes (re, re + im, im - re)
+    const void *wtab;   // [ncw][ncw] float2
+    void *tout;         // [B][nk][nc] float2
+    Geometry g;
+    int batch;
+    int n_rg;           // row groups of 16 RT rows
+    int n_cg;           // column groups: kWavesPerBlock waves of 16 CT columns
+    int per_xcd;        // > 0: XCD-blocked order, 0: interleaved
+    int flush_steps;    // kappa steps between two-sum flushes
+};
+
+constexpr int kMfmaFlushSteps = 256;   // 1024 products per accumulator element
+
+template <int RT, int CT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_mfma_kernel(MfmaArgs a)
+{
+    const Geometry &g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int bid = blockIdx.x;
+    int b, rg, cg;
+    if (a.per_xcd > 0) {
+        const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
+        const int per_b = a.n_rg * a.n_cg;
+        if (work >= a.batch * per_b) return;
+        b = work / per_b;
+        const int rem = work - b * per_b;
+        rg = a.n_rg - 1 - rem / a.n_cg;
+        cg = rem - (rem / a.n_cg) * a.n_cg;
+    } else {
+        const int per_rg = a.batch * a.n_cg;
+        rg = a.n_rg - 1 - bid / per_rg;
+        const int rem = bid - (bid / per_rg) * per_rg;
+        b = rem / a.n_cg;
+        cg = rem - b * a.n_cg;
+    }
+    const int c0 = (cg * kWavesPerBlock + wave) * 16 * CT;   // first output column of the wave
+    if (c0 >= g.nc) return;
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lq = lane >> 4;
+    const int K0 = rg * 16 * RT;
+    const int Wm1 = g.W - 1;
+    const int kw_lo = c0 - (g.nw - 1);
+    const int kw_hi = min(c0 + 16 * CT - 1, g.nc - 1) - (g.nw - 1);
+    const int iw_lo = max(-Wm1, kw_lo - Wm1);
+    const int iw_hi = min(Wm1, kw_hi + Wm1);
+    const int kk_max = min(K0 + 16 * RT - 1, g.nk - 1);
+    const int jk_end = kk_max / 2;   // last kappa split any row of the wave uses
+    const int jb = K0 / 2;           // splits below jb are at full weight for every row
+
+    const long lines = static_cast<long>(g.nk) * g.nc;
+    const long plane = static_cast<long>(g.ncw) * g.nkp;
+    const float2 *zrow_b = static_cast<const float2 *>(a.zrow) + b * lines;
+    const float *zcol_b = static_cast<const float *>(a.zcol) + b * 3 * plane;
+    const float2 *wtab = static_cast<const float2 *>(a.wtab);
+    float2 *tout_b = static_cast<float2 *>(a.tout) + b * lines;
+    // reads outside a realization's arrays (negative rows of the a planes)
+    // return zero; every such value meets a zero weight or a zero f
+    const brsrc za = make_brsrc(zcol_b, static_cast<unsigned>(3 * plane * sizeof(float)));
+    const unsigned row_bytes = static_cast<unsigned>(g.nc * sizeof(float2));
+    const brsrc zb = make_brsrc(zrow_b, static_cast<unsigned>(lines * sizeof(float2)));
+    const unsigned plane_bytes = static_cast<unsigned>(plane * sizeof(float));
+
+    mf4 P1[RT][CT], P2[RT][CT], P3[RT][CT];
+    float sre[RT][CT][4], cre[RT][CT][4], sim[RT][CT][4], cim[RT][CT][4];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            P1[r][c] = P2[r][c] = P3[r][c] = mf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sre[r][c][e] = cre[r][c][e] = sim[r][c][e] = cim[r][c][e] = 0.f;
+        }
+    auto flush = [&]() {
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    two_sum(sre[r][c][e], cre[r][c][e], P1[r][c][e] - P2[r][c][e]);
+                    two_sum(sim[r][c][e], cim[r][c][e], P1[r][c][e] + P3[r][c][e]);
+                }
+                P1[r][c] = P2[r][c] = P3[r][c] = mf4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+
+    // Partner step iw0 (4 columns): the lane's a-plane byte offset (row shift
+    // excluded), its b column offsets and weights.
+    auto setup = [&](int s0, int &ab, unsigned (&bo)[CT], float2 (&w)[CT]) {
+        const int iw = s0 + lq;
+        const int ic = min(iw + Wm1, g.ncw - 1);
+        ab = (ic * g.nkp + K0 + li) * static_cast<int>(sizeof(float));
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int col = c0 + 16 * c + li;
+            const int jw = col - (g.nw - 1) - iw;
+            const bool ok = col < g.nc && iw <= Wm1 && jw > -g.W && jw < g.W;
+            w[c] = make_float2(0.f, 0.f);
+            if (ok) w[c] = wtab[static_cast<long>(iw + Wm1) * g.ncw + (jw + Wm1)];
+            bo[c] = ok ? static_cast<unsigned>(jw + g.nw - 1) * static_cast<unsigned>(sizeof(float2)) : 0u;
+        }
+    };
+    float2 zn[CT];
+    float an[RT][3];
+    auto load_step = [&](int ab, const unsigned (&bo)[CT], int jk) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) zn[c] = bload(zb, bo[c], static_cast<unsigned>(jk) * row_bytes, 0.f);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            // rows a tile does not use are harmless: they meet f = 0 or are
+            // skipped; offsets before the planes read zero
+            const unsigned off = static_cast<unsigned>(ab + (16 * r - jk) * static_cast<int>(sizeof(float)));
+            an[r][0] = bload32(za, off, 0u);
+            an[r][1] = bload32(za, off, plane_bytes);
+            an[r][2] = bload32(za, off, 2 * plane_bytes);
+        }
+    };
+
+    int since = 0;
+    for (int iw0 = iw_lo; iw0 <= iw_hi; iw0 += 4) {
+        int abase;
+        unsigned boff[CT];
+        float2 wc[CT];
+        setup(iw0, abase, boff, wc);
+        load_step(abase, boff, 0);
+        // one kappa split: operands of the next split are requested first
+        // (past the last split they read zeros or unused rows)
+        auto split = [&](int jk, bool tail) {
+            float2 zc[CT];
+            float ac[RT][3];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) zc[c] = zn[c];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                ac[r][0] = an[r][0];
+                ac[r][1] = an[r][1];
+                ac[r][2] = an[r][2];
+            }
+            load_step(abase, boff, jk + 1);
+            float bs[CT], bi[CT], br[CT];
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                const float Br = fma_(wc[c].x, zc[c].x, -wc[c].y * zc[c].y);
+                const float Bi = fma_(wc[c].x, zc[c].y, wc[c].y * zc[c].x);
+                bs[c] = Br + Bi;
+                bi[c] = Bi;
+                br[c] = Br;
+            }
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                if (tail && 2 * jk > K0 + 16 * r + 15) continue;   // no row of this tile uses the split
+                float x0 = ac[r][0], x1 = ac[r][1], x2 = ac[r][2];
+                if (tail) {
+                    const int kk = K0 + 16 * r + li;
+                    const float f = 2 * jk < kk ? 1.f : (2 * jk == kk ? 0.5f : 0.f);
+                    x0 *= f;
+                    x1 *= f;
+                    x2 *= f;
+                }
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    P1[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, bs[c], P1[r][c], 0, 0, 0);
+                    P2[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, bi[c], P2[r][c], 0, 0, 0);
+                    P3[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x2, br[c], P3[r][c], 0, 0, 0);
+                }
+            }
+        };
+        int jk = 0;
+        for (; jk < jb; ++jk) split(jk, false);      // every row of the wave at full weight
+        for (; jk <= jk_end; ++jk) split(jk, true);
+        since += jk_end + 1;
+        if (since >= a.flush_steps) {
+            flush();
+            since = 0;
+        }
+    }
+    flush();
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int col = c0 + 16 * c + li;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kk = K0 + 16 * r + 4 * lq + e;
+                if (kk < g.nk && col < g.nc)
+                    tout_b[static_cast<long>(kk) * g.nc + col] =
+                        make_float2(sre[r][c][e] + cre[r][c][e], sim[r][c][e] + cim[r][c][e]);
+            }
+        }
 }
 
 // Persistent pair sum over an uneven work list.  Work items (request, row
@@ -1420,6 +1646,28 @@ hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, in
     case 16: return pairsum_t<float, 16, true>(g, wtab, batch, ws, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, const Workspace &ws,
+                               hipStream_t st)
+{
+    constexpr int RT = 2, CT = 2;
+    MfmaArgs a;
+    a.zrow = ws.zrow;
+    a.zcol = ws.zcol;
+    a.wtab = wtab;
+    a.tout = ws.tsum;
+    a.g = g;
+    a.batch = batch;
+    a.n_rg = (g.nk + 16 * RT - 1) / (16 * RT);
+    const int n_ct = (g.nc + 16 * CT - 1) / (16 * CT);
+    a.n_cg = (n_ct + kWavesPerBlock - 1) / kWavesPerBlock;
+    a.flush_steps = kMfmaFlushSteps;
+    const long work = static_cast<long>(a.n_rg) * batch * a.n_cg;
+    a.per_xcd = batch >= kNumXcd ? static_cast<int>((work + kNumXcd - 1) / kNumXcd) : 0;
+    const long blocks = a.per_xcd > 0 ? static_cast<long>(a.per_xcd) * kNumXcd : work;
+    pairsum_mfma_kernel<RT, CT><<<dim3(static_cast<unsigned>(blocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    return hipGetLastError();
 }
 
 template <typename T>

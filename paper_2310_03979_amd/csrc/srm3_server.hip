@@ -267,6 +267,8 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     if (spectrum && (!(spectrum->U > 0) || !(spectrum->z > 0) || !(spectrum->lam > 0) || !(spectrum->u_star >= 0)))
         return fail(SRM3_E_INVALID, "bad spectrum parameters");
     if (r.plan->hashed) return fail(SRM3_E_UNSUPPORTED, "bispectra generated per pair run through srm3_generate");
+    if (r.plan->algo == SRM3_ALGO_MFMA)
+        return fail(SRM3_E_UNSUPPORTED, "matrix-core pair sums run through srm3_generate");
     if (r.plan->fixed_spectrum && (r.S_dev || spectrum))
         return fail(SRM3_E_UNSUPPORTED, "a product bispectrum's plan keeps its own spectrum");
     if (spectrum && r.plan->process)

@@ -331,12 +331,13 @@ def srm3_pair_terms(plan: Plan) -> float:
     return float(v.value)
 
 
-SRM3_ALGO_DIRECT, SRM3_ALGO_KAPPA_FFT, SRM3_ALGO_FFT2D = 0, 1, 2
-_ALGOS = {"direct": SRM3_ALGO_DIRECT, "kappa_fft": SRM3_ALGO_KAPPA_FFT, "fft2d": SRM3_ALGO_FFT2D}
+SRM3_ALGO_DIRECT, SRM3_ALGO_KAPPA_FFT, SRM3_ALGO_FFT2D, SRM3_ALGO_MFMA = 0, 1, 2, 3
+_ALGOS = {"direct": SRM3_ALGO_DIRECT, "kappa_fft": SRM3_ALGO_KAPPA_FFT, "fft2d": SRM3_ALGO_FFT2D,
+          "mfma": SRM3_ALGO_MFMA}
 
 
 def srm3_plan_set_algorithm(plan: Plan, algorithm="direct", stream=None):
-    """Pair-sum algorithm of the plan: "direct", "kappa_fft" or "fft2d" (or the enum)."""
+    """Pair-sum algorithm of the plan: "direct", "kappa_fft", "fft2d" or "mfma" (or the enum)."""
     a = _ALGOS[algorithm] if isinstance(algorithm, str) else int(algorithm)
     _check(load().srm3_plan_set_algorithm(plan.handle, a, _stream_ptr(stream)))
 

@@ -1,0 +1,210 @@
+"""The direct-form pair sum on the matrix cores (SRM3_ALGO_MFMA, FP32) against
+the FP64 oracle through the C-ABI, FP32 <= 2e-5 relative L2: small, ragged and
+degenerate grids with every bispectrum form, the 256x1024 and 512x8192 grids at
+full batch on sampled lines, agreement with the vector kernel, batch
+invariance, a process plan, a wind plan with line factors, and errors."""
+import numpy as np
+import pytest
+
+import srm3_inputs as inp
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2310_03979_amd as p
+    p.load()
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _bispec(wl, kind, beta_mode, seed=5):
+    b = dict(kind=kind, support_w=wl.support_w, cap=wl.cap, beta_mode=beta_mode, beta_seed=wl.beta_seed)
+    if kind == "separable":
+        b["g2"] = wl.g2()
+        b2 = wl.b2_dense()
+    else:
+        b2 = inp.random_b2_dense(wl.support_w, seed, scale=0.3)
+        b["b2"] = b2
+    if beta_mode == "table":
+        b["beta"] = inp.random_beta_table(wl.support_w, seed + 1)
+    return b, b2
+
+
+def _problem(oracle_mod, wl, bis, b2):
+    if bis.get("beta_mode") == "table":
+        beta = bis["beta"]
+    elif bis.get("beta_mode") == "zero":
+        beta = oracle_mod.biphase(wl.support_w, None)
+    else:
+        beta = oracle_mod.biphase(wl.support_w, wl.beta_seed)
+    return oracle_mod.Problem(wl.n_kappa, wl.n_omega, wl.support_w, wl.d_kappa, wl.d_omega,
+                              wl.spectrum(), b2, beta, bis["cap"])
+
+
+def _plan(lib, wl, bis):
+    plan = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), bis, "fp32")
+    lib.srm3_plan_set_algorithm(plan, "mfma")
+    return plan
+
+
+def _coeffs(lib, plan, seeds):
+    torch = _torch()
+    C = torch.empty((len(seeds),) + plan.coeff_shape, dtype=torch.complex64, device="cuda")
+    lib.srm3_coefficients(plan, seeds, C)
+    torch.cuda.synchronize()
+    return C
+
+
+def _field(lib, plan, nx, nt, seeds):
+    torch = _torch()
+    out = torch.empty((len(seeds), nx, nt), dtype=torch.float32, device="cuda")
+    lib.srm3_generate(plan, seeds, out)
+    torch.cuda.synchronize()
+    return out
+
+
+SMALL = [
+    # nk, nw, W, nx, nt, kind, beta_mode
+    (32, 64, 64, 64, 128, "separable", "seeded"),   # one row group, several column tiles
+    (5, 40, 40, 16, 128, "dense", "table"),         # rows below one 16-row tile
+    (24, 70, 33, 64, 256, "dense", "seeded"),       # truncated support, ragged column tile
+    (17, 9, 9, 64, 32, "separable", "zero"),        # odd rows, beta == 0
+    (1, 8, 8, 2, 16, "separable", "seeded"),        # a single kappa row (every split is the half one)
+    (3, 5, 1, 8, 16, "dense", "seeded"),            # support of one frequency
+    (2, 1, 1, 4, 1, "separable", "seeded"),         # only the omega = 0 lines
+    (70, 33, 17, 256, 128, "dense", "table"),       # three row groups, the last ragged
+    (40, 300, 300, 128, 1024, "separable", "seeded"),   # many partner steps, two row groups
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}w{c[2]}_{c[5]}_{c[6]}" for c in SMALL])
+def test_small_grids_match_oracle(lib, oracle_mod, case):
+    nk, nw, W, nx, nt, kind, beta_mode = case
+    wl = inp.small_grid(nk, nw, support_w=W, n_x=nx, n_t=nt, batch=3, seed_base=71)
+    print(f"[gpu] mfma {case}", flush=True)
+    bis, b2 = _bispec(wl, kind, beta_mode)
+    plan = _plan(lib, wl, bis)
+    C = _coeffs(lib, plan, wl.seeds()).to(_torch().complex128).cpu().numpy()
+    u = _field(lib, plan, nx, nt, wl.seeds()).double().cpu().numpy()
+    P = _problem(oracle_mod, wl, bis, b2)
+    for r, s in enumerate(wl.seeds()):
+        Cref = P.coefficients(seed=int(s))
+        ref = oracle_mod.field(Cref, nx, nt)
+        if np.linalg.norm(ref) == 0:
+            assert np.all(C[r] == 0) and np.all(u[r] == 0)
+            continue
+        assert _rel(C[r], Cref) <= TOL, r
+        assert _rel(u[r], ref) <= TOL, r
+
+
+def test_agrees_with_vector_kernel_and_is_batch_invariant(lib):
+    torch = _torch()
+    wl = inp.small_grid(64, 200, support_w=150, batch=6, seed_base=300)
+    bis, _ = _bispec(wl, "separable", "seeded")
+    vec = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), bis, "fp32")
+    mat = _plan(lib, wl, bis)
+    seeds = wl.seeds()
+    a = _coeffs(lib, vec, seeds).to(torch.complex128)
+    b = _coeffs(lib, mat, seeds).to(torch.complex128)
+    rel = ((a - b).abs().pow(2).sum() / a.abs().pow(2).sum()).sqrt().item()
+    assert rel <= 2e-6
+    one = _coeffs(lib, mat, [int(seeds[4])])
+    assert torch.equal(one[0].to(torch.complex128), b[4])
+    again = _coeffs(lib, mat, seeds).to(torch.complex128)
+    assert torch.equal(again, b)
+    assert lib.srm3_algorithm_terms(mat) == lib.srm3_pair_terms(mat)
+    # switching back gives the vector result again, bitwise
+    lib.srm3_plan_set_algorithm(mat, "direct")
+    assert torch.equal(_coeffs(lib, mat, seeds).to(torch.complex128), a)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_full_size_sampled_lines(lib, oracle_mod, name):
+    """The 256x1024 grid at its full batch of 64 and the 512x8192 grid (support
+    2048) at batch 16: sampled lines of the first and last realization."""
+    torch = _torch()
+    wl = inp.WORKLOADS[name]
+    print(f"[gpu] mfma {name} batch {wl.batch}", flush=True)
+    bis, b2 = _bispec(wl, "separable", "seeded")
+    plan = _plan(lib, wl, bis)
+    seeds = wl.seeds()
+    C = _coeffs(lib, plan, seeds)
+    P = _problem(oracle_mod, wl, bis, b2)
+    rng = np.random.default_rng(12)
+    W = wl.support_w
+    for r in (0, wl.batch - 1):
+        kk = np.concatenate([[0, 1, wl.n_kappa - 1, wl.n_kappa - 2], rng.integers(0, wl.n_kappa, 20)])
+        c = (wl.n_omega - 1) + rng.integers(-(2 * W - 2), 2 * W - 1, 24)
+        c = np.clip(c, 0, wl.n_cols - 1)
+        lines = (kk * wl.n_cols + c).astype(np.int64)
+        ref = P.coefficients(seed=int(seeds[r]), lines=lines)
+        got = C[r].reshape(-1)[torch.as_tensor(lines, device="cuda")].to(torch.complex128).cpu().numpy()
+        assert _rel(got, ref) <= TOL, r
+
+
+def test_process_and_wind_plans(lib, oracle_mod):
+    # the 1-D process: one kappa row, one-sided spectrum
+    wl = inp.small_process(300, support_w=200, batch=4, seed_base=6)
+    bis = dict(kind="separable", g2=wl.g2(), support_w=wl.support_w, cap=wl.cap, beta_mode="seeded",
+               beta_seed=wl.beta_seed)
+    plan = lib.srm3_process_plan(wl.grid_dict(), wl.spectrum(), bis, "fp32")
+    lib.srm3_plan_set_algorithm(plan, "mfma")
+    P = oracle_mod.ProcessProblem(wl.n, wl.support_w, wl.d_omega, wl.spectrum(), wl.b2_dense(),
+                                  oracle_mod.process_biphase(wl.support_w, wl.beta_seed), wl.cap)
+    C = _coeffs(lib, plan, wl.seeds()).to(_torch().complex128).cpu().numpy()[:, 0, :]
+    u = _field(lib, plan, 1, wl.n_t, wl.seeds()).double().cpu().numpy()[:, 0, :]
+    for r, s in enumerate(wl.seeds()):
+        Cref = P.coefficients(seed=int(s))
+        assert _rel(C[r, wl.n - 1:], Cref) <= TOL, r
+        assert _rel(u[r], oracle_mod.process_field(Cref, wl.n_t)) <= TOL, r
+    # the wind bispectrum (kappa-dependent line factors applied at assembly)
+    nk, nw, W, nx, nt = 16, 24, 12, 32, 64
+    dk, dw = 0.05, 0.1
+    S = inp.kaimal_davenport_paper(nk, nw, dk, dw)
+    grid = dict(n_kappa=nk, n_omega=nw, d_kappa=dk, d_omega=dw, n_x=nx, n_t=nt)
+    wp = lib.srm3_plan(grid, S, dict(kind="wind", alpha=1.0, cap=0.8, support_w=W), "fp32")
+    lib.srm3_plan_set_algorithm(wp, "mfma")
+    Pw = oracle_mod.WindProblem(nk, nw, W, dk, dw, S, 1.0, 0.8)
+    Pw.solve()
+    Cw = _coeffs(lib, wp, [3, 4]).to(_torch().complex128).cpu().numpy()
+    for i, s in enumerate([3, 4]):
+        assert _rel(Cw[i], Pw.coefficients(seed=s)) <= TOL
+
+
+def test_errors(lib):
+    torch = _torch()
+    wl = inp.small_grid(8, 16)
+    bis, _ = _bispec(wl, "separable", "seeded")
+    p64 = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), bis, "fp64")
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.srm3_plan_set_algorithm(p64, "mfma")
+    assert ei.value.status == 5
+    hashed = lib.srm3_plan(wl.grid_dict(), wl.spectrum(),
+                           dict(kind="hashed", alpha=0.5, support_w=wl.support_w, cap=0.9, beta_seed=3), "fp32")
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.srm3_plan_set_algorithm(hashed, "mfma")
+    assert ei.value.status == 5
+    plan = _plan(lib, wl, bis)
+    out = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.Batch([dict(plan=plan, seed=1, out=out)])
+    assert ei.value.status == 5
+    srv = lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 28)
+    with pytest.raises(lib.Srm3Error) as ei:
+        srv.submit(plan, 1, out)
+    assert ei.value.status == 5
