@@ -587,11 +587,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     const float *zcol_b = static_cast<const float *>(a.zcol) + b * 3 * plane;
     const float2 *wtab = static_cast<const float2 *>(a.wtab);
     float2 *tout_b = static_cast<float2 *>(a.tout) + b * lines;
-    // reads outside a realization's arrays (negative rows of the a planes)
-    // return zero; every such value meets a zero weight or a zero f
-    const brsrc za = make_brsrc(zcol_b, static_cast<unsigned>(3 * plane * sizeof(float)));
+    // b rows through a buffer resource (uniform row offset, per-lane column).
+    // The a planes' resource starts `shift` rows before them: per-lane offsets
+    // stay fixed for a partner step and the split moves the uniform offset
+    // (shift - jk rows, never negative).  Reads of rows a split does not use
+    // stay inside the plan's workspace (the phase rows precede the a planes)
+    // and meet a zero f, a skipped tile or a discarded output row.
     const unsigned row_bytes = static_cast<unsigned>(g.nc * sizeof(float2));
     const brsrc zb = make_brsrc(zrow_b, static_cast<unsigned>(lines * sizeof(float2)));
+    const int shift = jk_end + 2;
+    const brsrc za = make_brsrc(reinterpret_cast<const char *>(zcol_b) - static_cast<long>(shift) * sizeof(float),
+                                static_cast<unsigned>((3 * plane + shift + 64) * sizeof(float)));
     const unsigned plane_bytes = static_cast<unsigned>(plane * sizeof(float));
 
     mf4 P1[RT][CT], P2[RT][CT], P3[RT][CT];
@@ -618,12 +624,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
             }
     };
 
-    // Partner step iw0 (4 columns): the lane's a-plane byte offset (row shift
-    // excluded), its b column offsets and weights.
-    auto setup = [&](int s0, int &ab, unsigned (&bo)[CT], float2 (&w)[CT]) {
+    // Partner step iw0 (4 columns): the lane's a-plane byte offset (row
+    // K0 + li of column ic, plane 0), its b column offsets and weights.
+    auto setup = [&](int s0, unsigned &ao, unsigned (&bo)[CT], float2 (&w)[CT]) {
         const int iw = s0 + lq;
         const int ic = min(iw + Wm1, g.ncw - 1);
-        ab = (ic * g.nkp + K0 + li) * static_cast<int>(sizeof(float));
+        ao = static_cast<unsigned>(ic * g.nkp + K0 + li) * static_cast<unsigned>(sizeof(float));
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int col = c0 + 16 * c + li;
@@ -634,74 +640,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
             bo[c] = ok ? static_cast<unsigned>(jw + g.nw - 1) * static_cast<unsigned>(sizeof(float2)) : 0u;
         }
     };
-    float2 zn[CT];
-    float an[RT][3];
-    auto load_step = [&](int ab, const unsigned (&bo)[CT], int jk) {
+    // operands of split jk: b phases per column tile, a planes per row tile
+    auto load_split = [&](float2 (&zs)[CT], float (&as)[RT][3], unsigned ao, const unsigned (&bo)[CT], int jk) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c) zn[c] = bload(zb, bo[c], static_cast<unsigned>(jk) * row_bytes, 0.f);
+        for (int c = 0; c < CT; ++c) zs[c] = bload(zb, bo[c], static_cast<unsigned>(jk) * row_bytes, 0.f);
+        const unsigned so = static_cast<unsigned>(shift - jk) * static_cast<unsigned>(sizeof(float));
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-            // rows a tile does not use are harmless: they meet f = 0 or are
-            // skipped; offsets before the planes read zero
-            const unsigned off = static_cast<unsigned>(ab + (16 * r - jk) * static_cast<int>(sizeof(float)));
-            an[r][0] = bload32(za, off, 0u);
-            an[r][1] = bload32(za, off, plane_bytes);
-            an[r][2] = bload32(za, off, 2 * plane_bytes);
+            const unsigned o = ao + 64u * r;
+            as[r][0] = bload32(za, o, so);
+            as[r][1] = bload32(za, o + plane_bytes, so);
+            as[r][2] = bload32(za, o + 2 * plane_bytes, so);
+        }
+    };
+    auto split = [&](int jk, bool tail, const unsigned (&bo)[CT], const float2 (&wc)[CT], const float2 (&zc)[CT],
+                     const float (&ac)[RT][3]) {
+        float bs[CT], bi[CT], br[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const float Br = fma_(wc[c].x, zc[c].x, -wc[c].y * zc[c].y);
+            const float Bi = fma_(wc[c].x, zc[c].y, wc[c].y * zc[c].x);
+            bs[c] = Br + Bi;
+            bi[c] = Bi;
+            br[c] = Br;
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            if (tail && 2 * jk > K0 + 16 * r + 15) continue;   // no row of this tile uses the split
+            float x0 = ac[r][0], x1 = ac[r][1], x2 = ac[r][2];
+            if (tail) {
+                const int kk = K0 + 16 * r + li;
+                const float f = 2 * jk < kk ? 1.f : (2 * jk == kk ? 0.5f : 0.f);
+                x0 *= f;
+                x1 *= f;
+                x2 *= f;
+            }
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                P1[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, bs[c], P1[r][c], 0, 0, 0);
+                P2[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, bi[c], P2[r][c], 0, 0, 0);
+                P3[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x2, br[c], P3[r][c], 0, 0, 0);
+            }
         }
     };
 
     int since = 0;
     for (int iw0 = iw_lo; iw0 <= iw_hi; iw0 += 4) {
-        int abase;
+        unsigned ao;
         unsigned boff[CT];
         float2 wc[CT];
-        setup(iw0, abase, boff, wc);
-        load_step(abase, boff, 0);
-        // one kappa split: operands of the next split are requested first
-        // (past the last split they read zeros or unused rows)
-        auto split = [&](int jk, bool tail) {
-            float2 zc[CT];
-            float ac[RT][3];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) zc[c] = zn[c];
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                ac[r][0] = an[r][0];
-                ac[r][1] = an[r][1];
-                ac[r][2] = an[r][2];
-            }
-            load_step(abase, boff, jk + 1);
-            float bs[CT], bi[CT], br[CT];
-#pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                const float Br = fma_(wc[c].x, zc[c].x, -wc[c].y * zc[c].y);
-                const float Bi = fma_(wc[c].x, zc[c].y, wc[c].y * zc[c].x);
-                bs[c] = Br + Bi;
-                bi[c] = Bi;
-                br[c] = Br;
-            }
-#pragma unroll
-            for (int r = 0; r < RT; ++r) {
-                if (tail && 2 * jk > K0 + 16 * r + 15) continue;   // no row of this tile uses the split
-                float x0 = ac[r][0], x1 = ac[r][1], x2 = ac[r][2];
-                if (tail) {
-                    const int kk = K0 + 16 * r + li;
-                    const float f = 2 * jk < kk ? 1.f : (2 * jk == kk ? 0.5f : 0.f);
-                    x0 *= f;
-                    x1 *= f;
-                    x2 *= f;
-                }
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    P1[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, bs[c], P1[r][c], 0, 0, 0);
-                    P2[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, bi[c], P2[r][c], 0, 0, 0);
-                    P3[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x2, br[c], P3[r][c], 0, 0, 0);
-                }
-            }
+        setup(iw0, ao, boff, wc);
+        // two operand sets: even splits in set 0, odd ones in set 1; each
+        // split first requests the next split's operands (the scheduling
+        // barrier keeps those loads ahead of this split's MFMAs; past the
+        // last split they read unused rows)
+        float2 z0[CT], z1[CT];
+        float a0[RT][3], a1[RT][3];
+        load_split(z0, a0, ao, boff, 0);
+        auto pair = [&](int jk, bool tail, bool both) {
+            load_split(z1, a1, ao, boff, jk + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            split(jk, tail, boff, wc, z0, a0);
+            if (!both) return;
+            load_split(z0, a0, ao, boff, jk + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            split(jk + 1, tail, boff, wc, z1, a1);
         };
+        // jb = K0 / 2 is even: the bulk ends on a set-0 split
         int jk = 0;
-        for (; jk < jb; ++jk) split(jk, false);      // every row of the wave at full weight
-        for (; jk <= jk_end; ++jk) split(jk, true);
+        for (; jk < jb; jk += 2) pair(jk, false, true);      // every row of the wave at full weight
+        for (; jk + 1 <= jk_end; jk += 2) pair(jk, true, true);
+        if (jk <= jk_end) pair(jk, true, false);
         since += jk_end + 1;
         if (since >= a.flush_steps) {
             flush();
