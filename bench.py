@@ -8,8 +8,10 @@ path): phases, pair sums, coefficients and the 2-D inverse DFT, with the plan
 
 * plain   -- the same realizations, one non-batched call per realization
 * fp64    -- the batched FP64 path
-* roofline -- the pair-sum kernel (the dominant kernel), timed with HIP events
-              recorded by the library on its launch stream during the timed steps
+* vector_pairsum -- the FP32 step with the pair sum on the vector ALUs
+* roofline -- the pair-sum kernel (the dominant kernel: on the matrix cores by
+              default), timed with HIP events recorded by the library on its
+              launch stream during the timed steps
 * cpu_baseline -- the FP64 oracle on this host, on a bounded sample
 
 Prints ONE JSON line.
@@ -31,9 +33,11 @@ sys.path.insert(0, ROOT)
 import srm3_inputs as inp  # noqa: E402
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
+PEAK_FP32_MFMA_TFLOPS = 157.3 # MI355X dense FP32 matrix (published)
 PEAK_FP64_TFLOPS = 78.6       # MI355X vector FP64 (published)
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR_TERM = 14      # complex product z_i z_j (6) x W (6) + accumulate (2)
+MFMA_FLOPS_PER_PAIR_TERM = 6  # the matrix cores' share: three real products (Gauss form), each a multiply-add
 
 
 def log(*a):
@@ -52,6 +56,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pair-kernel", default="mfma", choices=["mfma", "vector"],
+                    help="FP32 pair sum of the measured step: matrix cores or vector ALUs")
     ap.add_argument("--no-kfft", action="store_true",
                     help="skip the pair sum through an FFT along kappa (reported beside the direct form)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -121,13 +127,18 @@ def cpu_baseline(wl, target_s):
     }, (np.concatenate(sample_lines), np.concatenate(sample_C))
 
 
-def counter_traffic(wl):
+def counter_path(wl, kernel="vector"):
+    stem = "pairsum_mfma" if kernel == "mfma" else "pairsum"
+    return os.path.join(ROOT, "profiles", f"{stem}_{wl.name}_counters.md")
+
+
+def counter_traffic(wl, kernel="vector"):
     """HBM bytes per pair-sum launch from the committed rocprofv3 counter
     summary of this workload (FETCH_SIZE and WRITE_SIZE passes, each scaled by
     the reading of a plain device copy), or None when the kernel source has
     changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"pairsum_{wl.name}_counters.md")
+    path = counter_path(wl, kernel)
     src = os.path.join(ROOT, "paper_2310_03979_amd", "csrc", "srm3_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -145,15 +156,16 @@ def counter_traffic(wl):
         return None
 
 
-def counter_valu(wl):
-    """VALU issue fraction of the pair-sum launch from the same committed
-    counter summary (SQ_INSTS_VALU x 4 cycles over the 1024 SIMDs and the
-    kernel's cycles), under the same source-hash condition, else None."""
-    if counter_traffic(wl) is None:
+def counter_valu(wl, kernel="vector", key="* VALU issue"):
+    """VALU issue fraction (vector kernel: SQ_INSTS_VALU x 4 cycles over the
+    1024 SIMDs and the kernel's cycles) or matrix-core busy fraction (key
+    "* MFMA busy": SQ_VALU_MFMA_BUSY_CYCLES over the SIMDs' cycles) of the
+    pair-sum launch from the same committed counter summary, under the same
+    source-hash condition, else None."""
+    if counter_traffic(wl, kernel) is None:
         return None
-    path = os.path.join(ROOT, "profiles", f"pairsum_{wl.name}_counters.md")
-    for line in open(path):
-        if line.startswith("* VALU issue") and "**" in line:
+    for line in open(counter_path(wl, kernel)):
+        if line.startswith(key) and "**" in line:
             try:
                 return float(line.split("**")[1].split("%")[0]) / 100.0
             except ValueError:
@@ -652,6 +664,9 @@ def main():
     log(f"[bench] workload {wl.name} batch {B} steps {args.steps} warmup {args.warmup}")
 
     plan32 = srm3.plan_from_workload(wl, "fp32")
+    mfma = args.pair_kernel == "mfma"
+    if mfma:
+        srm3.srm3_plan_set_algorithm(plan32, "mfma")
     out32 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
     terms = srm3.srm3_pair_terms(plan32)
 
@@ -670,21 +685,41 @@ def main():
     log(f"[bench] batched fp32: {dt * 1e3:.2f} ms/step, kernels {prof}")
 
     ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
-    achieved_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
-    roofline = {
-        "bound": "alu",
-        "kernel": f"pairsum_kernel<float,{srm3.srm3_rows_per_wave(plan32)},true>",
-        "achieved": round(achieved_tflops, 3),
-        "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-        "traffic": counter_traffic(wl) if B == wl.batch else None,
-        "valu_issue_frac": counter_valu(wl) if B == wl.batch else None,
-        "pair_terms_per_launch": terms * B,
-        "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
-        "avg_launch_ms": round(ps_ms, 4),
-        "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
-    }
+    kname = "mfma" if mfma else "vector"
+    full = B == wl.batch
+    if mfma:
+        achieved_tflops = MFMA_FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+        roofline = {
+            "bound": "mfma",
+            "kernel": "pairsum_mfma_kernel<2,2> (v_mfma_f32_16x16x4_f32)",
+            "achieved": round(achieved_tflops, 3),
+            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tflops / PEAK_FP32_MFMA_TFLOPS, 4),
+            "traffic": counter_traffic(wl, kname) if full else None,
+            "mfma_busy_frac": counter_valu(wl, kname, "* MFMA busy") if full else None,
+            "pair_terms_per_launch": terms * B,
+            "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
+            "complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12, 3),
+            "avg_launch_ms": round(ps_ms, 4),
+            "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
+        }
+    else:
+        achieved_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+        roofline = {
+            "bound": "alu",
+            "kernel": f"pairsum_kernel<float,{srm3.srm3_rows_per_wave(plan32)},true>",
+            "achieved": round(achieved_tflops, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+            "traffic": counter_traffic(wl, kname) if full else None,
+            "valu_issue_frac": counter_valu(wl, kname) if full else None,
+            "pair_terms_per_launch": terms * B,
+            "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
+            "avg_launch_ms": round(ps_ms, 4),
+            "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
+        }
     if roofline["traffic"]:
         roofline["hbm_GB_per_s"] = round(roofline["traffic"] / (ps_ms * 1e-3) / 1e9, 1)
     kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()}
@@ -702,9 +737,33 @@ def main():
         extra["plain_fp32_ms_per_batch"] = round(dtp * 1e3, 3)
         extra["batched_over_plain"] = round(dtp / dt, 3)
         log(f"[bench] plain fp32: {dtp * 1e3:.2f} ms per {B} realizations")
-    # ---- batched FP64 ----
     plans = {"fp32": plan32}
     fields = {"fp32": out32}
+    # ---- the other FP32 pair-sum kernel (vector ALUs, or the matrix cores) ----
+    if not args.no_plain:
+        other = "vector" if mfma else "mfma"
+        planv = srm3.plan_from_workload(wl, "fp32")
+        if other == "mfma":
+            srm3.srm3_plan_set_algorithm(planv, "mfma")
+        outv = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+        srm3.srm3_profile_enable(planv, True)
+        dtv = timed_steps(torch, lambda: srm3.srm3_generate(planv, seeds, outv), 1, 1)
+        pv = srm3.srm3_profile_read(planv)
+        srm3.srm3_profile_enable(planv, False)
+        vms = pv["pairsum"][0] / max(1, pv["pairsum"][1])
+        vtf = FLOPS_PER_PAIR_TERM * terms * B / (vms * 1e-3) / 1e12
+        leg = {"grid_points_per_s": grid_points / dtv, "ms_per_step": round(dtv * 1e3, 3),
+               "pairsum_avg_launch_ms": round(vms, 4), "pair_terms_per_s": terms * B / (vms * 1e-3),
+               "complex_form_tflops": round(vtf, 3)}
+        if other == "vector":
+            leg.update({"kernel": f"pairsum_kernel<float,{srm3.srm3_rows_per_wave(planv)},true>", "bound": "alu",
+                        "frac_of_fp32_vector_peak": round(vtf / PEAK_FP32_TFLOPS, 4),
+                        "valu_issue_frac": counter_valu(wl, "vector") if full else None})
+        extra[f"{other}_pairsum"] = leg
+        plans[f"fp32_{other}"] = planv
+        fields[f"fp32_{other}"] = outv
+        log(f"[bench] batched fp32, {other} pair sum: {dtv * 1e3:.2f} ms/step")
+    # ---- batched FP64 ----
     if not args.no_fp64 and wl.n_t <= 8192:
         plan64 = srm3.plan_from_workload(wl, "fp64")
         out64 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float64, device="cuda")
@@ -798,7 +857,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.n_kappa}x{wl.n_omega} lines, {wl.n_x}x{wl.n_t} field, "
                                f"batch {B}, bicoherence support {wl.support_w}",
-                   "global_batch": B, "precision": "fp32 fixed-point phases, compensated pair sums"},
+                   "global_batch": B, "precision": "fp32 fixed-point phases, compensated pair sums",
+                   "pair_kernel": "matrix cores (FP32 MFMA)" if mfma else "vector ALUs"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_avg_ms": kernel_ms,
