@@ -244,8 +244,11 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  *                        of a block of phase rows with a block of weighted
  *                        phases, evaluated with 16x16x4 FP32 MFMAs.  Same
  *                        result up to rounding.  Runs through srm3_generate,
- *                        srm3_coefficients and srm3_transform; batches and the
- *                        server refuse such plans (SRM3_E_UNSUPPORTED).
+ *                        srm3_coefficients, srm3_transform and uneven batches
+ *                        (whose persistent launch then takes matrix-core work
+ *                        items: a batch's direct-form plans must be all
+ *                        SRM3_ALGO_DIRECT or all SRM3_ALGO_MFMA); the server
+ *                        refuses such plans (SRM3_E_UNSUPPORTED).
  * Switching to SRM3_ALGO_KAPPA_FFT builds its sheared weight table on the
  * device (stream-ordered on hip_stream).  Errors: SRM3_E_INVALID (bad plan or
  * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048; SRM3_ALGO_FFT2D: weights
@@ -354,7 +357,10 @@ enum {
  * into eight queues, one per XCD.  Requests whose plan uses
  * SRM3_ALGO_KAPPA_FFT or SRM3_ALGO_FFT2D run that pair sum per grid (all their
  * realizations at once) instead; plans with zero bicoherence have no pair
- * stage.  The plan's
+ * stage.  Plans with SRM3_ALGO_MFMA put matrix-core items (32 kappa rows x
+ * 128 frequencies) into the persistent launch; a batch whose direct-form
+ * plans mix SRM3_ALGO_DIRECT and SRM3_ALGO_MFMA is refused
+ * (SRM3_E_UNSUPPORTED).  The plan's
  * algorithm is read here: set it before creating the batch (plans with
  * SRM3_BISPEC_HASHED are refused, SRM3_E_UNSUPPORTED).  Host arrays are
  * copied; plans must outlive the batch.  Fails with SRM3_E_PURE_NEGATIVE if a

@@ -897,6 +897,7 @@ struct srm3_batch_s {
     };
     std::vector<Group> groups;
     int R = 0;                         // rows per wave of the persistent launch
+    bool mfma = false;                 // its items are those of the matrix-core pair sum
     int blocks_per_cu = 2;
     int n_cu = 256;
     DevBuf ws, seeds, scales, sptr, outs, preq, pitem, qbegin, qnext;
@@ -934,6 +935,23 @@ double item_cost_impl(const Geometry &g, int R, int kb, int cg)
     return static_cast<double>(kb * R / 2 + R / 2) * widest;
 }
 
+// Relative cost of a matrix-core item (row group kb, column group cg): its
+// kappa splits times the widest partner range of its waves' column tiles.
+double mfma_item_cost(const Geometry &g, int kb, int cg)
+{
+    const int rows = mfma_rows_per_group(), cols = mfma_cols_per_group(), wcols = cols / waves_per_block();
+    int widest = 0;
+    for (int c0 = cg * cols; c0 < std::min(g.nc, (cg + 1) * cols); c0 += wcols) {
+        const int kw_lo = c0 - (g.nw - 1);
+        const int kw_hi = std::min(c0 + wcols - 1, g.nc - 1) - (g.nw - 1);
+        const int lo = std::max(-(g.W - 1), kw_lo - (g.W - 1));
+        const int hi = std::min(g.W - 1, kw_hi + (g.W - 1));
+        widest = std::max(widest, hi - lo + 1);
+    }
+    const int kk_max = std::min(kb * rows + rows - 1, g.nk - 1);
+    return static_cast<double>(kk_max / 2 + 1) * widest;
+}
+
 // (Re)build layouts and work queues for rows-per-wave R and grid size.
 srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
 {
@@ -943,7 +961,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
     int first = 0;
     for (auto &gr : b->groups) {
         gr.g = gr.plan->g;
-        gr.mode = gr.plan->gaussian ? 2 : (gr.plan->algo != SRM3_ALGO_DIRECT ? 1 : 0);
+        gr.mode = gr.plan->gaussian ? 2 : (kfft_family(gr.plan->algo) ? 1 : 0);
         if (gr.mode == 0) {
             gr.g.R = rows_for(gr.g.nk, b->precision, R);
             gr.g.nkp = ((gr.g.nk + gr.g.R - 1) / gr.g.R) * gr.g.R;
@@ -980,8 +998,9 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
                                              static_cast<char *>(b->ws.p) + gr.ws_off);
         const size_t lines = static_cast<size_t>(gr.g.nk) * gr.g.nc;
         const size_t plane3 = a_slots(b->precision) * gr.g.ncw * gr.g.nkp;
-        const int nrb = gr.g.nkp / gr.g.R;
-        const int ncg = ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
+        const int nrb = b->mfma ? (gr.g.nk + mfma_rows_per_group() - 1) / mfma_rows_per_group() : gr.g.nkp / gr.g.R;
+        const int ncg = b->mfma ? (gr.g.nc + mfma_cols_per_group() - 1) / mfma_cols_per_group()
+                                : ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
         if (gr.mode != 0) continue;   // no items in the persistent launch
         for (size_t slot = 0; slot < gr.members.size(); ++slot) {
             const int d = gr.first + static_cast<int>(slot);
@@ -990,7 +1009,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
                                 static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
             for (int kb = nrb - 1; kb >= 0; --kb)
                 for (int cg = 0; cg < ncg; ++cg) {
-                    const double c = item_cost_impl(gr.g, gr.g.R, kb, cg);
+                    const double c = b->mfma ? mfma_item_cost(gr.g, kb, cg) : item_cost_impl(gr.g, gr.g.R, kb, cg);
                     per_req[d].push_back({d, kb, cg, c});
                     req_cost[d] += c;
                 }
@@ -1059,7 +1078,7 @@ srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
     if (b->n_items > 0) {
         e = launch_pairsum_persistent(b->precision, b->R, b->preq.p, b->pitem.p,
                                       static_cast<const int *>(b->qbegin.p), static_cast<int *>(b->qnext.p),
-                                      b->n_cu * b->blocks_per_cu, st);
+                                      b->n_cu * b->blocks_per_cu, st, b->mfma);
         if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
     }
     if (time_pairsum) (void)hipEventRecord(b->ev_b, st);
@@ -1112,7 +1131,7 @@ std::string batch_signature(srm3_batch_t b)
         count[k.str()] += static_cast<int>(gr.members.size());
     }
     std::ostringstream o;
-    o << (b->precision == SRM3_FP64 ? "fp64" : "fp32") << ";cu" << b->n_cu;
+    o << (b->precision == SRM3_FP64 ? "fp64" : "fp32") << (b->mfma ? ";mfma" : "") << ";cu" << b->n_cu;
     for (auto &kv : count) o << ';' << kv.first << '*' << kv.second;
     return o.str();
 }
@@ -1160,13 +1179,17 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
     *out = nullptr;
     if (!reqs || n <= 0) return fail(SRM3_E_INVALID, "no requests");
     const int precision = reqs[0].plan ? reqs[0].plan->precision : -1;
+    bool has_mfma = false, has_vector = false;
     for (int i = 0; i < n; ++i) {
         const srm3_request &r = reqs[i];
         if (!r.plan || !r.out_dev) return fail(SRM3_E_INVALID, "request %d: NULL plan or output", i);
         if (r.plan->hashed)
             return fail(SRM3_E_UNSUPPORTED, "request %d: bispectra generated per pair run through srm3_generate", i);
-        if (r.plan->algo == SRM3_ALGO_MFMA)
-            return fail(SRM3_E_UNSUPPORTED, "request %d: matrix-core pair sums run through srm3_generate", i);
+        if (r.plan->algo == SRM3_ALGO_MFMA && !r.plan->gaussian) has_mfma = true;
+        if (r.plan->algo == SRM3_ALGO_DIRECT && !r.plan->gaussian) has_vector = true;
+        if (has_mfma && has_vector)
+            return fail(SRM3_E_UNSUPPORTED,
+                        "request %d: a batch's direct-form plans use one pair-sum kernel (all vector or all matrix-core)", i);
         if (r.plan->fixed_spectrum && r.S_dev)
             return fail(SRM3_E_UNSUPPORTED, "request %d: a product bispectrum's plan keeps its own spectrum", i);
         if (r.plan->precision != precision)
@@ -1181,6 +1204,8 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
     b->precision = precision;
     b->n = n;
     b->flags = flags;
+    b->mfma = has_mfma;
+    if (has_mfma) b->blocks_per_cu = 3;   // the matrix-core kernel runs 3 waves per SIMD
     b->req.assign(reqs, reqs + n);
     std::map<srm3_plan_t, int> gi;
     for (int i = 0; i < n; ++i) {
@@ -1200,7 +1225,7 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
     // the largest rows per wave every grid of the persistent launch supports
     int R = precision == SRM3_FP64 ? 8 : 16;
     for (auto &gr : b->groups)
-        if (!gr.plan->gaussian && gr.plan->algo == SRM3_ALGO_DIRECT)
+        if (!gr.plan->gaussian && !kfft_family(gr.plan->algo))
             R = std::min(R, rows_for(gr.plan->g.nk, precision, 0));
     srm3_status s = batch_layout(b.get(), R, st);
     if (s) return s;
@@ -1261,7 +1286,7 @@ static srm3_status batch_autotune(srm3_batch_t b, hipStream_t st)
     for (int r : {Rmax, Rmax / 2}) {
         if (r < 2) continue;
         if (r != t->R && (s = batch_layout(t, r, st))) break;
-        for (int c : {1, 2, 4}) {
+        for (int c : {1, 2, 3, 4}) {
             t->blocks_per_cu = c;
             float ms = 0.f;
             const int reps = (r == Rmax && c == 1) ? 2 : 1;   // the first launch also warms up

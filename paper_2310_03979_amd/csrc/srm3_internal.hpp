@@ -124,8 +124,12 @@ hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, c
 hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, double scale, int batch,
                                const Workspace *ws, double *sig, hipStream_t st);
 // Persistent pair sum over a device work list (all requests share R).
+// mfma: items of the matrix-core pair sum (FP32; see mfma_rows_per_group).
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
-                                     int *q_next, int nblocks, hipStream_t st);
+                                     int *q_next, int nblocks, hipStream_t st, bool mfma = false);
+// Output rows and columns of one matrix-core work item (a block of waves).
+int mfma_rows_per_group();
+int mfma_cols_per_group();
 size_t persistent_req_bytes();
 size_t persistent_item_bytes();
 void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const void *zcol, void *tsum,

@@ -545,30 +545,13 @@ struct MfmaArgs {
 
 constexpr int kMfmaFlushSteps = 256;   // 1024 products per accumulator element
 
+// One wave's RT x CT tiles of one realization: output rows from K0 = 16 RT rg,
+// columns c0 .. c0 + 16 CT - 1.
 template <int RT, int CT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_mfma_kernel(MfmaArgs a)
+__device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__restrict__ zrow_b,
+                                          const float *__restrict__ zcol_b, const float2 *__restrict__ wtab,
+                                          float2 *__restrict__ tout_b, int rg, int c0, int flush_steps)
 {
-    const Geometry &g = a.g;
-    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
-    const int bid = blockIdx.x;
-    int b, rg, cg;
-    if (a.per_xcd > 0) {
-        const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
-        const int per_b = a.n_rg * a.n_cg;
-        if (work >= a.batch * per_b) return;
-        b = work / per_b;
-        const int rem = work - b * per_b;
-        rg = a.n_rg - 1 - rem / a.n_cg;
-        cg = rem - (rem / a.n_cg) * a.n_cg;
-    } else {
-        const int per_rg = a.batch * a.n_cg;
-        rg = a.n_rg - 1 - bid / per_rg;
-        const int rem = bid - (bid / per_rg) * per_rg;
-        b = rem / a.n_cg;
-        cg = rem - b * a.n_cg;
-    }
-    const int c0 = (cg * kWavesPerBlock + wave) * 16 * CT;   // first output column of the wave
-    if (c0 >= g.nc) return;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
     const int K0 = rg * 16 * RT;
@@ -583,10 +566,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
 
     const long lines = static_cast<long>(g.nk) * g.nc;
     const long plane = static_cast<long>(g.ncw) * g.nkp;
-    const float2 *zrow_b = static_cast<const float2 *>(a.zrow) + b * lines;
-    const float *zcol_b = static_cast<const float *>(a.zcol) + b * 3 * plane;
-    const float2 *wtab = static_cast<const float2 *>(a.wtab);
-    float2 *tout_b = static_cast<float2 *>(a.tout) + b * lines;
     // b rows through a buffer resource (uniform row offset, per-lane column).
     // The a planes' resource starts `shift` rows before them: per-lane offsets
     // stay fixed for a partner step and the split moves the uniform offset
@@ -712,7 +691,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
         for (; jk + 1 <= jk_end; jk += 2) pair(jk, true, true);
         if (jk <= jk_end) pair(jk, true, false);
         since += jk_end + 1;
-        if (since >= a.flush_steps) {
+        if (since >= flush_steps) {
             flush();
             since = 0;
         }
@@ -731,6 +710,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
                         make_float2(sre[r][c][e] + cre[r][c][e], sim[r][c][e] + cim[r][c][e]);
             }
         }
+}
+
+template <int RT, int CT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_mfma_kernel(MfmaArgs a)
+{
+    const Geometry &g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int bid = blockIdx.x;
+    int b, rg, cg;
+    if (a.per_xcd > 0) {
+        const int work = (bid % kNumXcd) * a.per_xcd + bid / kNumXcd;
+        const int per_b = a.n_rg * a.n_cg;
+        if (work >= a.batch * per_b) return;
+        b = work / per_b;
+        const int rem = work - b * per_b;
+        rg = a.n_rg - 1 - rem / a.n_cg;
+        cg = rem - (rem / a.n_cg) * a.n_cg;
+    } else {
+        const int per_rg = a.batch * a.n_cg;
+        rg = a.n_rg - 1 - bid / per_rg;
+        const int rem = bid - (bid / per_rg) * per_rg;
+        b = rem / a.n_cg;
+        cg = rem - b * a.n_cg;
+    }
+    const int c0 = (cg * kWavesPerBlock + wave) * 16 * CT;   // first output column of the wave
+    if (c0 >= g.nc) return;
+    const long lines = static_cast<long>(g.nk) * g.nc;
+    const long plane = static_cast<long>(g.ncw) * g.nkp;
+    mfma_tile<RT, CT>(g, static_cast<const float2 *>(a.zrow) + b * lines,
+                      static_cast<const float *>(a.zcol) + b * 3 * plane, static_cast<const float2 *>(a.wtab),
+                      static_cast<float2 *>(a.tout) + b * lines, rg, c0, a.flush_steps);
 }
 
 // Persistent pair sum over an uneven work list.  Work items (request, row
@@ -793,6 +803,44 @@ __global__ __launch_bounds__(256) void pairsum_persistent(PersistArgs a)
                                      static_cast<const T *>(rq.zcol),
                                      static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, ct,
                                      a.flush_terms);
+    }
+}
+
+// The same queues with matrix-core items: (request, row group of 16 kMfmaRT
+// rows, column group of kWavesPerBlock x 16 kMfmaCT columns), FP32 only.
+constexpr int kMfmaRT = 2, kMfmaCT = 2;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_persistent_mfma(PersistArgs a)
+{
+    __shared__ int s_item;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int home = blockIdx.x % kNumXcd;
+    int tries = 0;   // meaningful in thread 0 only
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (tries < kNumXcd) {
+                const int q = (home + tries) % kNumXcd;
+                const int i = a.q_begin[q] + atomicAdd(&a.q_next[q], 1);
+                if (i < a.q_begin[q + 1]) {
+                    it = i;
+                    break;
+                }
+                ++tries;
+            }
+            s_item = it;
+        }
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it < 0) break;
+        const PItem w = a.items[it];
+        const PReq rq = a.reqs[w.req];
+        const int c0 = (w.cg * kWavesPerBlock + wave) * 16 * kMfmaCT;
+        if (c0 < rq.g.nc)
+            mfma_tile<kMfmaRT, kMfmaCT>(rq.g, static_cast<const float2 *>(rq.zrow), static_cast<const float *>(rq.zcol),
+                                        static_cast<const float2 *>(rq.wtab), static_cast<float2 *>(rq.tsum), w.kb, c0,
+                                        kMfmaFlushSteps);
     }
 }
 
@@ -1660,7 +1708,7 @@ hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, in
 hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, const Workspace &ws,
                                hipStream_t st)
 {
-    constexpr int RT = 2, CT = 2;
+    constexpr int RT = kMfmaRT, CT = kMfmaCT;
     MfmaArgs a;
     a.zrow = ws.zrow;
     a.zcol = ws.zcol;
@@ -1715,7 +1763,7 @@ hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, d
 
 template <typename T, int R, bool COMP>
 static hipError_t persistent_t(const void *reqs, const void *items, const int *q_begin, int *q_next, int nblocks,
-                               hipStream_t st)
+                               hipStream_t st, bool mfma = false)
 {
     fill_int_kernel<<<1, 64, 0, st>>>(q_next, kNumXcd, 0);
     hipError_t e = hipGetLastError();
@@ -1726,13 +1774,20 @@ static hipError_t persistent_t(const void *reqs, const void *items, const int *q
     a.q_begin = q_begin;
     a.q_next = q_next;
     a.flush_terms = kFlushTerms;
-    pairsum_persistent<T, R, COMP><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    if (mfma)
+        pairsum_persistent_mfma<<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    else
+        pairsum_persistent<T, R, COMP><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
-                                     int *q_next, int nblocks, hipStream_t st)
+                                     int *q_next, int nblocks, hipStream_t st, bool mfma)
 {
+    if (mfma) {
+        if (precision != SRM3_FP32) return hipErrorInvalidValue;
+        return persistent_t<float, 2, true>(reqs, items, q_begin, q_next, nblocks, st, true);
+    }
     if (precision == SRM3_FP64) {
         switch (R) {
         case 2: return persistent_t<double, 2, false>(reqs, items, q_begin, q_next, nblocks, st);
@@ -1751,6 +1806,8 @@ hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, con
 }
 
 size_t persistent_req_bytes() { return sizeof(PReq); }
+int mfma_rows_per_group() { return 16 * kMfmaRT; }
+int mfma_cols_per_group() { return 16 * kMfmaCT * kWavesPerBlock; }
 size_t persistent_item_bytes() { return sizeof(PItem); }
 
 void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const void *zcol, void *tsum,

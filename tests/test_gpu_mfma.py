@@ -2,7 +2,9 @@
 the FP64 oracle through the C-ABI, FP32 <= 2e-5 relative L2: small, ragged and
 degenerate grids with every bispectrum form, the 256x1024 and 512x8192 grids at
 full batch on sampled lines, agreement with the vector kernel, batch
-invariance, a process plan, a wind plan with line factors, and errors."""
+invariance, uneven batches (matrix-core items in the persistent launch) equal
+to single generation, a process plan, a wind plan with line factors, and
+errors."""
 import numpy as np
 import pytest
 
@@ -201,10 +203,52 @@ def test_errors(lib):
     assert ei.value.status == 5
     plan = _plan(lib, wl, bis)
     out = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
-    with pytest.raises(lib.Srm3Error) as ei:
-        lib.Batch([dict(plan=plan, seed=1, out=out)])
+    vec = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), bis, "fp32")
+    out2 = torch.empty(plan.field_shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.Srm3Error) as ei:      # one pair-sum kernel per batch
+        lib.Batch([dict(plan=plan, seed=1, out=out), dict(plan=vec, seed=2, out=out2)])
     assert ei.value.status == 5
     srv = lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 28)
     with pytest.raises(lib.Srm3Error) as ei:
         srv.submit(plan, 1, out)
     assert ei.value.status == 5
+
+
+@pytest.mark.parametrize("flags", ["plain", "graph_autotune"])
+def test_uneven_batch_equals_single_generation(lib, flags, monkeypatch, tmp_path):
+    """Mixed grids (ragged rows and columns, truncated support, a Gaussian
+    plan and a kappa-DFT plan beside them) in one batch: each realization
+    equals its single generation bitwise, over two runs."""
+    torch = _torch()
+    monkeypatch.setenv("SRM3_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    grids = [(40, 300, 300), (5, 40, 40), (70, 33, 17), (24, 70, 33), (1, 8, 8)]
+    plans = []
+    for nk, nw, W in grids:
+        wl = inp.small_grid(nk, nw, support_w=W)
+        bis, _ = _bispec(wl, "separable", "seeded")
+        plans.append(_plan(lib, wl, bis))
+    wg = inp.small_grid(16, 32)
+    plans.append(lib.srm3_plan(wg.grid_dict(), wg.spectrum(), None, "fp32"))          # zero bicoherence
+    wk = inp.small_grid(16, 40)
+    pk = lib.plan_from_workload(wk, "fp32")
+    lib.srm3_plan_set_algorithm(pk, "kappa_fft")
+    plans.append(pk)
+    reqs, singles = [], []
+    for i in range(11):
+        plan = plans[i % len(plans)]
+        seed = 700 + 3 * i
+        one = torch.empty((1,) + plan.field_shape, dtype=torch.float32, device="cuda")
+        lib.srm3_generate(plan, [seed], one)
+        singles.append(one[0])
+        reqs.append(dict(plan=plan, seed=seed, out=torch.empty(plan.field_shape, dtype=torch.float32,
+                                                                device="cuda")))
+    print(f"[gpu] mfma uneven batch {flags}", flush=True)
+    fl = 0 if flags == "plain" else lib.SRM3_BATCH_GRAPH | lib.SRM3_BATCH_AUTOTUNE
+    b = lib.Batch(reqs, flags=fl)
+    for _ in range(2):
+        for r in reqs:
+            r["out"].zero_()
+        b.run()
+        torch.cuda.synchronize()
+        for r, s in zip(reqs, singles):
+            assert torch.equal(r["out"], s)
