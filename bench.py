@@ -218,11 +218,14 @@ def bench_uneven(args, torch, srm3):
     persistent pair-sum launch, autotuned and replayed as a hipGraph, vs the
     plain form (one non-persistent, non-graph call per realization)."""
     reqs_in = inp.uneven_requests()
+    mfma = args.pair_kernel == "mfma"
     plans = {}
     for wl, c, seed in reqs_in:
         key = (wl.n_kappa, wl.n_omega)
         if key not in plans:
             plans[key] = (wl, srm3.plan_from_workload(wl, "fp32"))
+            if mfma:
+                srm3.srm3_plan_set_algorithm(plans[key][1], "mfma")
     reqs = []
     for wl, c, seed in reqs_in:
         plan = plans[(wl.n_kappa, wl.n_omega)][1]
@@ -251,7 +254,8 @@ def bench_uneven(args, torch, srm3):
     dinfo = direct.info()
     terms = info["pair_terms"]
     ps_ms = dinfo["pairsum_ms"]
-    achieved = FLOPS_PER_PAIR_TERM * terms / (ps_ms * 1e-3) / 1e12
+    fpt = MFMA_FLOPS_PER_PAIR_TERM if mfma else FLOPS_PER_PAIR_TERM
+    achieved = fpt * terms / (ps_ms * 1e-3) / 1e12
     log(f"[bench] batched graph: {dt * 1e3:.1f} ms/step; pair sum {ps_ms:.1f} ms")
     rec_plain = None
     if not args.no_plain:
@@ -285,11 +289,19 @@ def bench_uneven(args, torch, srm3):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"uneven batch: {len(reqs)} realizations, line grids 2^U{{6..9}} x "
                                f"2^U{{7..12}} (64x128 .. 512x4096), b2 scale U[0.05, 0.3], one "
-                               f"persistent launch, autotuned, hipGraph", "global_batch": len(reqs)},
-        "roofline": {"bound": "alu", "kernel": f"pairsum_persistent<float,{dinfo['rows_per_wave']},true>",
-                     "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                     "pair_terms_per_launch": terms, "avg_launch_ms": round(ps_ms, 3)},
+                               f"persistent launch, autotuned, hipGraph", "global_batch": len(reqs),
+                   "pair_kernel": "matrix cores (FP32 MFMA)" if mfma else "vector ALUs"},
+        "roofline": ({"bound": "mfma", "kernel": "pairsum_persistent_mfma (matrix-core items)",
+                      "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                      "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
+                      "complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms / (ps_ms * 1e-3) / 1e12, 3),
+                      "pair_terms_per_launch": terms, "avg_launch_ms": round(ps_ms, 3)} if mfma else
+                     {"bound": "alu", "kernel": f"pairsum_persistent<float,{dinfo['rows_per_wave']},true>",
+                      "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                      "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
+                      "pair_terms_per_launch": terms, "avg_launch_ms": round(ps_ms, 3)}),
         "tile": {k: info[k] for k in ("rows_per_wave", "blocks_per_cu", "work_items", "groups")},
         "cpu_baseline": None,
     }
@@ -305,6 +317,7 @@ def bench_serve(args, torch, srm3):
     1024x8192 lines, U ~ U[20, 45] m/s, spectrum evaluated on the device)
     arrive as a Poisson process at 0.3 / 0.6 / 0.9 x the measured saturated
     request throughput; continuous batching vs one request at a time."""
+    pk = "mfma" if args.pair_kernel == "mfma" else "direct"
     from paper_2310_03979_amd import serve
     grids = [(64, 256), (256, 1024), (512, 4096), (1024, 8192)]
     n = args.serve_requests
@@ -313,6 +326,8 @@ def bench_serve(args, torch, srm3):
     for g in grids:
         wl = inp.small_grid(*g, b2_scale=0.3)
         plans[g] = (wl, srm3.plan_from_workload(wl, "fp32"))
+        if pk == "mfma":
+            srm3.srm3_plan_set_algorithm(plans[g][1], "mfma")
     reqs = []
     for i in range(n):
         g = grids[int(rng.integers(0, len(grids)))]
@@ -325,7 +340,7 @@ def bench_serve(args, torch, srm3):
     mix = {f"{g[0]}x{g[1]}": sum(1 for r in reqs if r["grid"] == g) for g in grids}
     log(f"[bench] serving: {n} requests per rate, mix {mix}")
     budget = 48 << 30
-    srv = srm3.Server("fp32", max_active=32, hbm_budget=budget)
+    srv = srm3.Server("fp32", max_active=32, hbm_budget=budget, pair_kernel=pk)
     prog = lambda m: log("[bench]   " + m)                 # noqa: E731
     serve.replay(srv, reqs[:2], [0.0, 0.0])           # warm-up (first launches)
     sat = serve.replay(srv, reqs, [0.0] * n, progress=prog)
@@ -340,13 +355,13 @@ def bench_serve(args, torch, srm3):
                                 makespan_s=r["makespan"], grid_points_per_s=points / r["makespan"])
         log(f"[bench] rate {f}: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
     srv.destroy()
-    rr = srm3.Server("fp32", max_active=32, hbm_budget=budget, policy="round_robin")
+    rr = srm3.Server("fp32", max_active=32, hbm_budget=budget, policy="round_robin", pair_kernel=pk)
     arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
     r = serve.replay(rr, reqs, arr, progress=prog)
     rr.destroy()
     out["round_robin_rate_0.9"] = dict(p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"], makespan_s=r["makespan"])
     log(f"[bench] round-robin steps, rate 0.9: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
-    plain = srm3.Server("fp32", max_active=1, hbm_budget=budget, step_pair_terms=1e30)
+    plain = srm3.Server("fp32", max_active=1, hbm_budget=budget, step_pair_terms=1e30, pair_kernel=pk)
     psat = serve.replay(plain, reqs, [0.0] * n, progress=prog)
     log(f"[bench] one at a time, saturated: {psat['makespan']:.2f} s")
     arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
@@ -385,7 +400,8 @@ def bench_serve(args, torch, srm3):
         "value": points / sat["makespan"], "unit": "grid points/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": round(sat["makespan"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"serving: {n} requests per rate, grids 64x256/256x1024/512x4096/1024x8192 "
+        "config": {"pair_kernel": "matrix cores (FP32 MFMA)" if pk == "mfma" else "vector ALUs",
+                   "workload": f"serving: {n} requests per rate, grids 64x256/256x1024/512x4096/1024x8192 "
                                f"lines (mix {mix}), U ~ U[20,45], Poisson arrivals (seed 42) at 0.3/0.6/0.9 x "
                                f"saturated throughput, continuous batching (32 slots, 48 GiB arena, "
                                f"shortest remaining work first)"},

@@ -415,6 +415,9 @@ typedef struct {
     size_t hbm_budget;        /* bytes of the device arena holding request workspaces (allocated once) */
     double step_pair_terms;   /* minimum pair terms per step; <= 0: 2e11 */
     int32_t policy;           /* SRM3_SERVE_SHORTEST_FIRST or SRM3_SERVE_ROUND_ROBIN */
+    int32_t pair_kernel;      /* SRM3_ALGO_DIRECT (0: vector ALUs) or SRM3_ALGO_MFMA (matrix cores, FP32
+                                 only): the kernel of the per-step persistent pair-sum launch; direct-form
+                                 requests must have plans with this algorithm (else SRM3_E_UNSUPPORTED) */
 } srm3_server_config;
 
 typedef struct {

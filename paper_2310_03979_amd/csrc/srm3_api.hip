@@ -937,7 +937,7 @@ double item_cost_impl(const Geometry &g, int R, int kb, int cg)
 
 // Relative cost of a matrix-core item (row group kb, column group cg): its
 // kappa splits times the widest partner range of its waves' column tiles.
-double mfma_item_cost(const Geometry &g, int kb, int cg)
+double mfma_item_cost_impl(const Geometry &g, int kb, int cg)
 {
     const int rows = mfma_rows_per_group(), cols = mfma_cols_per_group(), wcols = cols / waves_per_block();
     int widest = 0;
@@ -1009,7 +1009,7 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
                                 static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
             for (int kb = nrb - 1; kb >= 0; --kb)
                 for (int cg = 0; cg < ncg; ++cg) {
-                    const double c = b->mfma ? mfma_item_cost(gr.g, kb, cg) : item_cost_impl(gr.g, gr.g.R, kb, cg);
+                    const double c = b->mfma ? mfma_item_cost_impl(gr.g, kb, cg) : item_cost_impl(gr.g, gr.g.R, kb, cg);
                     per_req[d].push_back({d, kb, cg, c});
                     req_cost[d] += c;
                 }
@@ -1167,6 +1167,7 @@ void tune_store(const std::string &sig, int R, int bpc)
 
 namespace srm3 {
 double item_cost(const Geometry &g, int R, int kb, int cg) { return item_cost_impl(g, R, kb, cg); }
+double mfma_item_cost(const Geometry &g, int kb, int cg) { return mfma_item_cost_impl(g, kb, cg); }
 }  // namespace srm3
 
 extern "C" {

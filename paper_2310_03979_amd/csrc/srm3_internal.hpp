@@ -222,6 +222,7 @@ double max_sigma(double max_sig, double cap, double scale);
 int rows_for(int nk, int precision, int R_pref);
 // Relative cost of pair-sum work item (row block kb, column group cg).
 double item_cost(const Geometry &g, int R, int kb, int cg);
+double mfma_item_cost(const Geometry &g, int kb, int cg);
 
 }  // namespace srm3
 

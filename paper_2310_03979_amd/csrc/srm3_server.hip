@@ -118,6 +118,7 @@ struct srm3_server_s {
     int R = 16;
     int n_cu = 256;
     int blocks_per_cu = 2;
+    bool mfma = false;                 // persistent launch with matrix-core items
     DevBuf arena_mem;
     Arena arena;
     // staging: headers | qbegin | preq | items
@@ -206,12 +207,18 @@ srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, 
     if (cfg->hbm_budget < (1u << 16)) return fail(SRM3_E_INVALID, "hbm_budget below 64 KiB");
     if (cfg->policy != SRM3_SERVE_SHORTEST_FIRST && cfg->policy != SRM3_SERVE_ROUND_ROBIN)
         return fail(SRM3_E_INVALID, "policy %d", cfg->policy);
+    if (cfg->pair_kernel != SRM3_ALGO_DIRECT && cfg->pair_kernel != SRM3_ALGO_MFMA)
+        return fail(SRM3_E_INVALID, "pair_kernel %d", cfg->pair_kernel);
+    if (cfg->pair_kernel == SRM3_ALGO_MFMA && cfg->precision != SRM3_FP32)
+        return fail(SRM3_E_UNSUPPORTED, "the matrix-core pair sum is FP32 only");
     std::unique_ptr<srm3_server_s> s(new (std::nothrow) srm3_server_s);
     if (!s) return fail(SRM3_E_NOMEM, "host allocation failed");
     s->cfg = *cfg;
     if (!(s->cfg.step_pair_terms > 0)) s->cfg.step_pair_terms = 2e11;
     s->st = static_cast<hipStream_t>(hip_stream);
     s->R = cfg->precision == SRM3_FP64 ? 8 : 16;
+    s->mfma = cfg->pair_kernel == SRM3_ALGO_MFMA;
+    if (s->mfma) s->blocks_per_cu = 3;   // the matrix-core kernel runs 3 waves per SIMD
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
@@ -267,8 +274,10 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     if (spectrum && (!(spectrum->U > 0) || !(spectrum->z > 0) || !(spectrum->lam > 0) || !(spectrum->u_star >= 0)))
         return fail(SRM3_E_INVALID, "bad spectrum parameters");
     if (r.plan->hashed) return fail(SRM3_E_UNSUPPORTED, "bispectra generated per pair run through srm3_generate");
-    if (r.plan->algo == SRM3_ALGO_MFMA)
-        return fail(SRM3_E_UNSUPPORTED, "matrix-core pair sums run through srm3_generate");
+    const bool kfft = r.plan->algo == SRM3_ALGO_KAPPA_FFT || r.plan->algo == SRM3_ALGO_FFT2D;
+    if (!r.plan->gaussian && !kfft && (r.plan->algo == SRM3_ALGO_MFMA) != s->mfma)
+        return fail(SRM3_E_UNSUPPORTED, "the server's direct-form pair sum runs on the %s: the plan's algorithm differs",
+                    s->mfma ? "matrix cores" : "vector ALUs");
     if (r.plan->fixed_spectrum && (r.S_dev || spectrum))
         return fail(SRM3_E_UNSUPPORTED, "a product bispectrum's plan keeps its own spectrum");
     if (spectrum && r.plan->process)
@@ -279,10 +288,13 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     q->own_spec = spectrum != nullptr;
     if (spectrum) q->spec = *spectrum;
     q->g = r.plan->g;
-    q->mode = r.plan->gaussian ? 2 : (r.plan->algo != SRM3_ALGO_DIRECT ? 1 : 0);
+    q->mode = r.plan->gaussian ? 2 : (kfft ? 1 : 0);
     if (q->mode == 0) {
         q->g.R = rows_for(q->g.nk, s->cfg.precision, s->R);
-        if (q->g.R != s->R) return fail(SRM3_E_UNSUPPORTED, "grids with n_kappa < %d are not served", s->R);
+        // the vector kernel's persistent launch has one row count per wave; the
+        // matrix-core items do not depend on it (it only pads the a planes)
+        if (q->g.R != s->R && !s->mfma)
+            return fail(SRM3_E_UNSUPPORTED, "grids with n_kappa < %d are not served", s->R);
         q->g.nkp = ((q->g.nk + q->g.R - 1) / q->g.R) * q->g.R;
     }
     q->bytes = request_bytes(s, q->g, q->own_spec);
@@ -293,10 +305,12 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     if (q->bytes > s->arena.size)
         return fail(SRM3_E_NOMEM, "request needs %zu bytes, more than the server's budget %zu", q->bytes, s->arena.size);
     if (q->mode == 0) {
-        const int nrb = q->g.nkp / q->g.R;
-        const int ncg = ((q->g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
+        const int nrb = s->mfma ? (q->g.nk + mfma_rows_per_group() - 1) / mfma_rows_per_group() : q->g.nkp / q->g.R;
+        const int ncg = s->mfma ? (q->g.nc + mfma_cols_per_group() - 1) / mfma_cols_per_group()
+                                : ((q->g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
         for (int kb = nrb - 1; kb >= 0; --kb)
-            for (int cg = 0; cg < ncg; ++cg) q->items.push_back({kb, cg, item_cost(q->g, q->g.R, kb, cg)});
+            for (int cg = 0; cg < ncg; ++cg)
+                q->items.push_back({kb, cg, s->mfma ? mfma_item_cost(q->g, kb, cg) : item_cost(q->g, q->g.R, kb, cg)});
         std::stable_sort(q->items.begin(), q->items.end(),
                          [](const Item &a, const Item &b) { return a.cost > b.cost; });
         for (const Item &it : q->items) q->left += it.cost;
@@ -453,7 +467,7 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
             char *D = static_cast<char *>(s->dev_stage[c].p);
             e = launch_pairsum_persistent(s->cfg.precision, s->R, D + s->off_req, D + s->off_items,
                                           reinterpret_cast<const int *>(D + s->off_q),
-                                          static_cast<int *>(s->qnext[c].p), s->n_cu * s->blocks_per_cu, st);
+                                          static_cast<int *>(s->qnext[c].p), s->n_cu * s->blocks_per_cu, st, s->mfma);
             if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
         }
         if ((e = hipEventRecord(s->ev_pairsum[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");

@@ -557,7 +557,7 @@ def srm3_generate_uneven(reqs, stream=None):
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_size_t), ("step_pair_terms", ctypes.c_double),
-                ("policy", ctypes.c_int32)]
+                ("policy", ctypes.c_int32), ("pair_kernel", ctypes.c_int32)]
 
 
 SRM3_SERVE_SHORTEST_FIRST, SRM3_SERVE_ROUND_ROBIN = 0, 1
@@ -590,10 +590,11 @@ class Server:
     """srm3_server_t: continuous batching of generation requests."""
 
     def __init__(self, precision="fp32", max_active=64, hbm_budget=32 << 30, step_pair_terms=0.0,
-                 policy="shortest", stream=None):
+                 policy="shortest", stream=None, pair_kernel="direct"):
         L = _server_lib()
         pol = {"shortest": SRM3_SERVE_SHORTEST_FIRST, "round_robin": SRM3_SERVE_ROUND_ROBIN}[policy]
-        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms), pol)
+        pk = _ALGOS[pair_kernel] if isinstance(pair_kernel, str) else int(pair_kernel)
+        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms), pol, pk)
         h = ctypes.c_void_p()
         _check(L.srm3_server_create(ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
         self._h = h

@@ -252,3 +252,54 @@ def test_uneven_batch_equals_single_generation(lib, flags, monkeypatch, tmp_path
         torch.cuda.synchronize()
         for r, s in zip(reqs, singles):
             assert torch.equal(r["out"], s)
+
+
+def test_server_with_matrix_core_items(lib):
+    """A server whose persistent pair-sum launch takes matrix-core items:
+    mixed grids (and a kappa-DFT and a Gaussian plan beside them) give each
+    request's single generation bitwise; plans of the other kernel and FP64
+    servers are refused."""
+    torch = _torch()
+    grids = [(40, 300, 300), (5, 40, 40), (70, 33, 17)]
+    plans = []
+    for nk, nw, W in grids:
+        wl = inp.small_grid(nk, nw, support_w=W)
+        bis, _ = _bispec(wl, "separable", "seeded")
+        plans.append(_plan(lib, wl, bis))
+    wg = inp.small_grid(16, 32)
+    plans.append(lib.srm3_plan(wg.grid_dict(), wg.spectrum(), None, "fp32"))
+    wk = inp.small_grid(16, 40)
+    pk = lib.plan_from_workload(wk, "fp32")
+    lib.srm3_plan_set_algorithm(pk, "kappa_fft")
+    plans.append(pk)
+    reqs, singles = [], []
+    for i in range(10):
+        plan = plans[i % len(plans)]
+        seed = 900 + i
+        one = torch.empty((1,) + plan.field_shape, dtype=torch.float32, device="cuda")
+        lib.srm3_generate(plan, [seed], one)
+        singles.append(one[0])
+        reqs.append(dict(plan=plan, seed=seed, out=torch.zeros(plan.field_shape, dtype=torch.float32, device="cuda")))
+    print("[gpu] mfma server", flush=True)
+    srv = lib.srm3.Server("fp32", max_active=4, hbm_budget=1 << 30, pair_kernel="mfma")
+    tickets = [srv.submit(r["plan"], r["seed"], r["out"]) for r in reqs]
+    done = []
+    for _ in range(10000):
+        srv.step()
+        done += srv.poll()
+        if len(done) == len(tickets):
+            break
+    torch.cuda.synchronize()
+    assert sorted(done) == sorted(tickets)
+    for r, s in zip(reqs, singles):
+        assert torch.equal(r["out"], s)
+    wl = inp.small_grid(8, 16)
+    bis, _ = _bispec(wl, "separable", "seeded")
+    vec = lib.srm3_plan(wl.grid_dict(), wl.spectrum(), bis, "fp32")
+    out = torch.empty(vec.field_shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.Srm3Error) as ei:
+        srv.submit(vec, 1, out)
+    assert ei.value.status == 5
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.srm3.Server("fp64", max_active=2, hbm_budget=1 << 28, pair_kernel="mfma")
+    assert ei.value.status == 5
