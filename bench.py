@@ -542,6 +542,9 @@ def bench_bridge(args, torch, srm3):
     bis = dict(kind="wind", alpha=wl.alpha, cap=wl.cap, support_w=wl.support_w)
     plan = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
     plan_s = time.perf_counter() - t0
+    mfma = args.pair_kernel == "mfma"
+    if mfma:
+        srm3.srm3_plan_set_algorithm(plan, "mfma")
     out = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
     dt = timed_steps(torch, lambda: srm3.srm3_generate(plan, seeds, out), args.steps, args.warmup)
     terms = srm3.srm3_pair_terms(plan)
@@ -550,7 +553,8 @@ def bench_bridge(args, torch, srm3):
     prof = srm3.srm3_profile_read(plan)
     srm3.srm3_profile_enable(plan, False)
     ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
-    tf = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+    fpt = MFMA_FLOPS_PER_PAIR_TERM if mfma else FLOPS_PER_PAIR_TERM
+    tf = fpt * terms * B / (ps_ms * 1e-3) / 1e12
     log(f"[bench] bridge direct fp32: {dt * 1e3:.2f} ms/step (plan {plan_s:.2f} s)")
     kplan = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
     srm3.srm3_plan_set_algorithm(kplan, "kappa_fft")
@@ -632,8 +636,10 @@ def bench_bridge(args, torch, srm3):
         "config": {"workload": f"bridge example: {wl.n_kappa}x{wl.n_omega} lines, {wl.n_x}x{wl.n_t} field, "
                                f"wind bispectrum alpha {wl.alpha} through the partial-bicoherence recursion, "
                                f"cap {wl.cap}, {B} realizations"},
-        "roofline": {"bound": "alu", "kernel": "pairsum_kernel<float,8,true>", "achieved": round(tf, 3),
-                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4),
+        "roofline": {"bound": "mfma" if mfma else "alu",
+                     "kernel": "pairsum_mfma_kernel<2,2>" if mfma else "pairsum_kernel<float,8,true>",
+                     "achieved": round(tf, 3), "peak": PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4), "flops_per_pair_term": fpt,
                      "traffic": None, "pair_terms_per_launch": terms * B, "avg_launch_ms": round(ps_ms, 4)},
         "cpu_baseline": None,
         "kappa_fft_grid_points_per_s": points / dtk, "kappa_fft_over_direct": round(dt / dtk, 3),

@@ -28,10 +28,13 @@ def _plans(lib):
     lib.srm3_plan_set_algorithm(fft2d, "fft2d")
     pw = inp.small_process(256, batch=3)
     proc = lib.process_plan_from_workload(pw, "fp32")
-    return [("direct", wl, direct), ("kappa_fft", wl, kfft), ("fft2d", wl, fft2d), ("process", pw, proc)]
+    mfma = lib.plan_from_workload(wl, "fp32")
+    lib.srm3_plan_set_algorithm(mfma, "mfma")
+    return [("direct", wl, direct), ("kappa_fft", wl, kfft), ("fft2d", wl, fft2d), ("process", pw, proc),
+            ("mfma", wl, mfma)]
 
 
-@pytest.mark.parametrize("which", ["direct", "kappa_fft", "fft2d", "process"])
+@pytest.mark.parametrize("which", ["direct", "kappa_fft", "fft2d", "process", "mfma"])
 def test_generate_replays_from_a_graph(lib, which):
     import torch
     name, wl, plan = [p for p in _plans(lib) if p[0] == which][0]
