@@ -788,6 +788,8 @@ def main():
     # ---- batched FP64 ----
     if not args.no_fp64 and wl.n_t <= 8192:
         plan64 = srm3.plan_from_workload(wl, "fp64")
+        if mfma:
+            srm3.srm3_plan_set_algorithm(plan64, "mfma")
         out64 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float64, device="cuda")
         plans["fp64"] = plan64
         fields["fp64"] = out64
@@ -796,7 +798,10 @@ def main():
         p64 = srm3.srm3_profile_read(plan64)
         ps64 = p64["pairsum"][0] / max(1, p64["pairsum"][1])
         extra["fp64_grid_points_per_s"] = grid_points / dt64
-        extra["fp64_pairsum_tflops"] = round(FLOPS_PER_PAIR_TERM * terms * B / (ps64 * 1e-3) / 1e12, 3)
+        extra["fp64_pair_kernel"] = "matrix cores (FP64 MFMA)" if mfma else "vector ALUs"
+        extra["fp64_pairsum_ms"] = round(ps64, 3)
+        fpt64 = MFMA_FLOPS_PER_PAIR_TERM if mfma else FLOPS_PER_PAIR_TERM
+        extra["fp64_pairsum_tflops"] = round(fpt64 * terms * B / (ps64 * 1e-3) / 1e12, 3)
         extra["fp64_pairsum_frac_of_fp64_peak"] = round(extra["fp64_pairsum_tflops"] / PEAK_FP64_TFLOPS, 4)
         log(f"[bench] batched fp64: {dt64 * 1e3:.2f} ms/step")
         torch.cuda.synchronize()

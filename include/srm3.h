@@ -238,11 +238,12 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  *                        frequency, a squaring and the inverse FFT, then the
  *                        inverse DFT along kappa.  Same result up to rounding;
  *                        O(M L log L) work per realization.
- *   SRM3_ALGO_MFMA       the direct form's unordered pairs (same terms), FP32
- *                        plans only, on the matrix cores: for each kappa split
- *                        the sum over the partner frequency is a dense product
- *                        of a block of phase rows with a block of weighted
- *                        phases, evaluated with 16x16x4 FP32 MFMAs.  Same
+ *   SRM3_ALGO_MFMA       the direct form's unordered pairs (same terms) on the
+ *                        matrix cores: for each kappa split the sum over the
+ *                        partner frequency is a dense product of a block of
+ *                        phase rows with a block of weighted phases, evaluated
+ *                        with 16x16x4 MFMAs (FP32: v_mfma_f32_16x16x4_f32 with
+ *                        two-sum flushes; FP64: v_mfma_f64_16x16x4_f64).  Same
  *                        result up to rounding.  Runs through srm3_generate,
  *                        srm3_coefficients, srm3_transform and uneven batches
  *                        (whose persistent launch then takes matrix-core work
@@ -252,8 +253,7 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  * Switching to SRM3_ALGO_KAPPA_FFT builds its sheared weight table on the
  * device (stream-ordered on hip_stream).  Errors: SRM3_E_INVALID (bad plan or
  * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048; SRM3_ALGO_FFT2D: weights
- * not rank-one, or L above 16384, 8192 in FP64; SRM3_ALGO_MFMA: an FP64 plan),
- * SRM3_E_NOMEM, SRM3_E_DEVICE.  A bispectrum generated per pair
+ * not rank-one, or L above 16384, 8192 in FP64), SRM3_E_NOMEM, SRM3_E_DEVICE.  A bispectrum generated per pair
  * (SRM3_BISPEC_HASHED) takes SRM3_ALGO_DIRECT only. */
 enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1, SRM3_ALGO_FFT2D = 2, SRM3_ALGO_MFMA = 3 };
 srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream);
@@ -415,9 +415,9 @@ typedef struct {
     size_t hbm_budget;        /* bytes of the device arena holding request workspaces (allocated once) */
     double step_pair_terms;   /* minimum pair terms per step; <= 0: 2e11 */
     int32_t policy;           /* SRM3_SERVE_SHORTEST_FIRST or SRM3_SERVE_ROUND_ROBIN */
-    int32_t pair_kernel;      /* SRM3_ALGO_DIRECT (0: vector ALUs) or SRM3_ALGO_MFMA (matrix cores, FP32
-                                 only): the kernel of the per-step persistent pair-sum launch; direct-form
-                                 requests must have plans with this algorithm (else SRM3_E_UNSUPPORTED) */
+    int32_t pair_kernel;      /* SRM3_ALGO_DIRECT (0: vector ALUs) or SRM3_ALGO_MFMA (matrix cores): the
+                                 kernel of the per-step persistent pair-sum launch; direct-form requests
+                                 must have plans with this algorithm (else SRM3_E_UNSUPPORTED) */
 } srm3_server_config;
 
 typedef struct {

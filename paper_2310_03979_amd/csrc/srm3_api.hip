@@ -216,7 +216,7 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
         e = launch_kfft_pairsum(p->precision, p->g, p->kg, plan_ktab(p), batch, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
     } else if (p->algo == SRM3_ALGO_MFMA) {
-        e = launch_pairsum_mfma(p->g, p->wtab.p, batch, ws, st);
+        e = launch_pairsum_mfma(p->g, p->precision, p->wtab.p, batch, ws, st);
         if (e != hipSuccess) return dev_err(e, "matrix-core pair-sum kernel");
     } else {
         e = launch_pairsum(p->g, p->precision, p->wtab.p, batch, ws, st);
@@ -760,7 +760,6 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
     if (plan->hashed)
         return fail(SRM3_E_UNSUPPORTED, "a bispectrum generated per pair has kappa-dependent weights: direct form only");
     if (algorithm == SRM3_ALGO_MFMA) {
-        if (plan->precision != SRM3_FP32) return fail(SRM3_E_UNSUPPORTED, "the matrix-core pair sum is FP32 only");
         plan->algo = SRM3_ALGO_MFMA;
         return SRM3_OK;
     }

@@ -115,16 +115,16 @@ hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds
                          int batch, const Workspace &ws, const double *lr, hipStream_t st);
 hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
                           const Workspace &ws, hipStream_t st);
-// The same pair sum (FP32 only) on the matrix cores: dense products over the
-// partner frequency for each kappa split.
-hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, const Workspace &ws,
+// The same pair sum on the matrix cores: dense products over the partner
+// frequency for each kappa split.
+hipError_t launch_pairsum_mfma(const Geometry &g, int precision, const void *wtab, int batch, const Workspace &ws,
                                hipStream_t st);
 // Bispectrum generated per pair inside the kernel (hashed b^2 and beta).  With
 // ws == nullptr it writes the per-line raw sums sum b^2_raw to sig (FP64).
 hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, double scale, int batch,
                                const Workspace *ws, double *sig, hipStream_t st);
 // Persistent pair sum over a device work list (all requests share R).
-// mfma: items of the matrix-core pair sum (FP32; see mfma_rows_per_group).
+// mfma: items of the matrix-core pair sum (see mfma_rows_per_group).
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
                                      int *q_next, int nblocks, hipStream_t st, bool mfma = false);
 // Output rows and columns of one matrix-core work item (a block of waves).

@@ -125,6 +125,13 @@ __device__ __forceinline__ float bload32(brsrc r, unsigned voff, unsigned soff)
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(voff),
                                                                           static_cast<int>(soff), 0));
 }
+__device__ __forceinline__ double bload64(brsrc r, unsigned voff, unsigned soff)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, static_cast<int>(voff), static_cast<int>(soff), 0);
+    double d;
+    __builtin_memcpy(&d, &v, sizeof(d));
+    return d;
+}
 #else
 struct brsrc {
     const void *p;
@@ -133,6 +140,7 @@ __device__ inline brsrc make_brsrc(const void *p, unsigned) { return brsrc{p}; }
 __device__ inline float2 bload(brsrc, unsigned, unsigned, float) { return float2{}; }
 __device__ inline double2 bload(brsrc, unsigned, unsigned, double) { return double2{}; }
 __device__ inline float bload32(brsrc, unsigned, unsigned) { return 0.0f; }
+__device__ inline double bload64(brsrc, unsigned, unsigned) { return 0.0; }
 #endif
 
 // Layout of the a operand (re, re + im, im - re) of support column ic, row kk:
@@ -521,14 +529,14 @@ __global__ __launch_bounds__(256) void pairsum_kernel(PairsumArgs a)
 // (re + im, im, re):
 //     P1 += A_re (B_re + B_im),  P2 += (A_re + A_im) B_im,  P3 += (A_im - A_re) B_re,
 //     Re T = P1 - P2,  Im T = P1 + P3.
-// The sums are flushed into error-free (two-sum) accumulators every few
-// hundred steps.  A wave owns RT x CT tiles of 16 x 16 outputs; partner
-// columns are stepped 4 at a time (outer loop, weights kept in registers),
-// kappa splits one at a time (inner loop).  Operand layouts of
-// v_mfma_f32_16x16x4_f32 (lane l, i = l % 16, q = l / 16): A[i][q], B[q][i]
-// in, D[4 q + e][i] (e = 0..3) out.
+// FP32 sums are flushed into error-free (two-sum) accumulators every few
+// hundred steps; FP64 sums stay whole.  A wave owns RT x CT tiles of 16 x 16
+// outputs; partner columns are stepped 4 at a time (outer loop, weights kept
+// in registers), kappa splits one at a time (inner loop).  Operand layouts of
+// the 16x16x4 MFMAs (lane l, i = l % 16, q = l / 16): A[i][q], B[q][i] in;
+// out D[4 q + e][i] for v_mfma_f32_16x16x4_f32, D[q + 4 e][i] for
+// v_mfma_f64_16x16x4_f64 (e = 0..3).
 // ---------------------------------------------------------------------------
-typedef float mf4 __attribute__((ext_vector_type(4)));
 
 struct MfmaArgs {
     const void *zrow;   // [B][nk][nc] float2
@@ -545,13 +553,41 @@ struct MfmaArgs {
 
 constexpr int kMfmaFlushSteps = 256;   // 1024 products per accumulator element
 
+// Per-precision pieces of the matrix-core pair sum: the 16x16x4 MFMA and its
+// output row layout, the a
+// operand layout (FP32: three kappa-contiguous planes; FP64: the three values
+// of a (column, row) side by side, rows 32 bytes apart) and whether the sums
+// are flushed into two-sum pairs (FP32 only).
+template <typename T> struct MfmaT;
+template <> struct MfmaT<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static constexpr bool COMP = true;
+    static constexpr bool PLANAR = true;
+    static constexpr unsigned ROW_BYTES = 4;
+    __device__ static v4 mfma(float x, float y, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
+    __device__ static int drow(int q, int e) { return 4 * q + e; }   // output row of lane group q, element e
+    __device__ static float aload(brsrc r, unsigned voff, unsigned soff) { return bload32(r, voff, soff); }
+};
+template <> struct MfmaT<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static constexpr bool COMP = false;
+    static constexpr bool PLANAR = false;
+    static constexpr unsigned ROW_BYTES = 32;
+    __device__ static v4 mfma(double x, double y, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
+    __device__ static int drow(int q, int e) { return q + 4 * e; }   // rows interleaved (checked on the device)
+    __device__ static double aload(brsrc r, unsigned voff, unsigned soff) { return bload64(r, voff, soff); }
+};
+
 // One wave's RT x CT tiles of one realization: output rows from K0 = 16 RT rg,
 // columns c0 .. c0 + 16 CT - 1.
-template <int RT, int CT>
-__device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__restrict__ zrow_b,
-                                          const float *__restrict__ zcol_b, const float2 *__restrict__ wtab,
-                                          float2 *__restrict__ tout_b, int rg, int c0, int flush_steps)
+template <typename T, int RT, int CT>
+__device__ __forceinline__ void mfma_tile(const Geometry &g, const typename vec<T>::v2 *__restrict__ zrow_b,
+                                          const T *__restrict__ zcol_b, const typename vec<T>::v2 *__restrict__ wtab,
+                                          typename vec<T>::v2 *__restrict__ tout_b, int rg, int c0, int flush_steps)
 {
+    using T2 = typename vec<T>::v2;
+    using M = MfmaT<T>;
+    using V4 = typename M::v4;
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lq = lane >> 4;
     const int K0 = rg * 16 * RT;
@@ -572,73 +608,80 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__res
     // (shift - jk rows, never negative).  Reads of rows a split does not use
     // stay inside the plan's workspace (the phase rows precede the a planes)
     // and meet a zero f, a skipped tile or a discarded output row.
-    const unsigned row_bytes = static_cast<unsigned>(g.nc * sizeof(float2));
-    const brsrc zb = make_brsrc(zrow_b, static_cast<unsigned>(lines * sizeof(float2)));
+    const unsigned row_bytes = static_cast<unsigned>(g.nc * sizeof(T2));
+    const brsrc zb = make_brsrc(zrow_b, static_cast<unsigned>(lines * sizeof(T2)));
     const int shift = jk_end + 2;
-    const brsrc za = make_brsrc(reinterpret_cast<const char *>(zcol_b) - static_cast<long>(shift) * sizeof(float),
-                                static_cast<unsigned>((3 * plane + shift + 64) * sizeof(float)));
-    const unsigned plane_bytes = static_cast<unsigned>(plane * sizeof(float));
+    constexpr unsigned RS = M::ROW_BYTES;   // bytes between kappa rows of one a value
+    const brsrc za = make_brsrc(reinterpret_cast<const char *>(zcol_b) - static_cast<long>(shift) * RS,
+                                static_cast<unsigned>(ALayout<T>::NS * plane * sizeof(T) + (shift + 64) * RS));
+    // bytes between the three a values of one (column, row)
+    const unsigned plane_bytes = M::PLANAR ? static_cast<unsigned>(plane * sizeof(T)) : static_cast<unsigned>(sizeof(T));
 
-    mf4 P1[RT][CT], P2[RT][CT], P3[RT][CT];
-    float sre[RT][CT][4], cre[RT][CT][4], sim[RT][CT][4], cim[RT][CT][4];
+    // FP32 flushes the MFMA sums into two-sum pairs; FP64 keeps them whole
+    constexpr int NS = M::COMP ? 4 : 1;
+    V4 P1[RT][CT], P2[RT][CT], P3[RT][CT];
+    T sre[RT][CT][NS], cre[RT][CT][NS], sim[RT][CT][NS], cim[RT][CT][NS];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            P1[r][c] = P2[r][c] = P3[r][c] = mf4{0.f, 0.f, 0.f, 0.f};
+            P1[r][c] = P2[r][c] = P3[r][c] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) sre[r][c][e] = cre[r][c][e] = sim[r][c][e] = cim[r][c][e] = 0.f;
+            for (int e = 0; e < NS; ++e) sre[r][c][e] = cre[r][c][e] = sim[r][c][e] = cim[r][c][e] = T(0);
         }
     auto flush = [&]() {
+        if constexpr (M::COMP) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r)
+            for (int r = 0; r < RT; ++r)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
+                for (int c = 0; c < CT; ++c) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    two_sum(sre[r][c][e], cre[r][c][e], P1[r][c][e] - P2[r][c][e]);
-                    two_sum(sim[r][c][e], cim[r][c][e], P1[r][c][e] + P3[r][c][e]);
+                    for (int e = 0; e < NS; ++e) {
+                        two_sum(sre[r][c][e], cre[r][c][e], P1[r][c][e] - P2[r][c][e]);
+                        two_sum(sim[r][c][e], cim[r][c][e], P1[r][c][e] + P3[r][c][e]);
+                    }
+                    P1[r][c] = P2[r][c] = P3[r][c] = V4{T(0), T(0), T(0), T(0)};
                 }
-                P1[r][c] = P2[r][c] = P3[r][c] = mf4{0.f, 0.f, 0.f, 0.f};
-            }
+        }
     };
 
     // Partner step iw0 (4 columns): the lane's a-plane byte offset (row
     // K0 + li of column ic, plane 0), its b column offsets and weights.
-    auto setup = [&](int s0, unsigned &ao, unsigned (&bo)[CT], float2 (&w)[CT]) {
+    auto setup = [&](int s0, unsigned &ao, unsigned (&bo)[CT], T2 (&w)[CT]) {
         const int iw = s0 + lq;
         const int ic = min(iw + Wm1, g.ncw - 1);
-        ao = static_cast<unsigned>(ic * g.nkp + K0 + li) * static_cast<unsigned>(sizeof(float));
+        ao = static_cast<unsigned>(ic * g.nkp + K0 + li) * RS;
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
             const int col = c0 + 16 * c + li;
             const int jw = col - (g.nw - 1) - iw;
             const bool ok = col < g.nc && iw <= Wm1 && jw > -g.W && jw < g.W;
-            w[c] = make_float2(0.f, 0.f);
+            w[c].x = T(0);
+            w[c].y = T(0);
             if (ok) w[c] = wtab[static_cast<long>(iw + Wm1) * g.ncw + (jw + Wm1)];
-            bo[c] = ok ? static_cast<unsigned>(jw + g.nw - 1) * static_cast<unsigned>(sizeof(float2)) : 0u;
+            bo[c] = ok ? static_cast<unsigned>(jw + g.nw - 1) * static_cast<unsigned>(sizeof(T2)) : 0u;
         }
     };
     // operands of split jk: b phases per column tile, a planes per row tile
-    auto load_split = [&](float2 (&zs)[CT], float (&as)[RT][3], unsigned ao, const unsigned (&bo)[CT], int jk) {
+    auto load_split = [&](T2 (&zs)[CT], T (&as)[RT][3], unsigned ao, const unsigned (&bo)[CT], int jk) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c) zs[c] = bload(zb, bo[c], static_cast<unsigned>(jk) * row_bytes, 0.f);
-        const unsigned so = static_cast<unsigned>(shift - jk) * static_cast<unsigned>(sizeof(float));
+        for (int c = 0; c < CT; ++c) zs[c] = bload(zb, bo[c], static_cast<unsigned>(jk) * row_bytes, T(0));
+        const unsigned so = static_cast<unsigned>(shift - jk) * RS;
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-            const unsigned o = ao + 64u * r;
-            as[r][0] = bload32(za, o, so);
-            as[r][1] = bload32(za, o + plane_bytes, so);
-            as[r][2] = bload32(za, o + 2 * plane_bytes, so);
+            const unsigned o = ao + 16u * RS * r;
+            as[r][0] = M::aload(za, o, so);
+            as[r][1] = M::aload(za, o + plane_bytes, so);
+            as[r][2] = M::aload(za, o + 2 * plane_bytes, so);
         }
     };
-    auto split = [&](int jk, bool tail, const unsigned (&bo)[CT], const float2 (&wc)[CT], const float2 (&zc)[CT],
-                     const float (&ac)[RT][3]) {
-        float bs[CT], bi[CT], br[CT];
+    auto split = [&](int jk, bool tail, const unsigned (&bo)[CT], const T2 (&wc)[CT], const T2 (&zc)[CT],
+                     const T (&ac)[RT][3]) {
+        T bs[CT], bi[CT], br[CT];
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
-            const float Br = fma_(wc[c].x, zc[c].x, -wc[c].y * zc[c].y);
-            const float Bi = fma_(wc[c].x, zc[c].y, wc[c].y * zc[c].x);
+            const T Br = fma_(wc[c].x, zc[c].x, -wc[c].y * zc[c].y);
+            const T Bi = fma_(wc[c].x, zc[c].y, wc[c].y * zc[c].x);
             bs[c] = Br + Bi;
             bi[c] = Bi;
             br[c] = Br;
@@ -646,19 +689,19 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__res
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
             if (tail && 2 * jk > K0 + 16 * r + 15) continue;   // no row of this tile uses the split
-            float x0 = ac[r][0], x1 = ac[r][1], x2 = ac[r][2];
+            T x0 = ac[r][0], x1 = ac[r][1], x2 = ac[r][2];
             if (tail) {
                 const int kk = K0 + 16 * r + li;
-                const float f = 2 * jk < kk ? 1.f : (2 * jk == kk ? 0.5f : 0.f);
+                const T f = 2 * jk < kk ? T(1) : (2 * jk == kk ? T(0.5) : T(0));
                 x0 *= f;
                 x1 *= f;
                 x2 *= f;
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
-                P1[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, bs[c], P1[r][c], 0, 0, 0);
-                P2[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, bi[c], P2[r][c], 0, 0, 0);
-                P3[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(x2, br[c], P3[r][c], 0, 0, 0);
+                P1[r][c] = M::mfma(x0, bs[c], P1[r][c]);
+                P2[r][c] = M::mfma(x1, bi[c], P2[r][c]);
+                P3[r][c] = M::mfma(x2, br[c], P3[r][c]);
             }
         }
     };
@@ -667,14 +710,14 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__res
     for (int iw0 = iw_lo; iw0 <= iw_hi; iw0 += 4) {
         unsigned ao;
         unsigned boff[CT];
-        float2 wc[CT];
+        T2 wc[CT];
         setup(iw0, ao, boff, wc);
         // two operand sets: even splits in set 0, odd ones in set 1; each
         // split first requests the next split's operands (the scheduling
         // barrier keeps those loads ahead of this split's MFMAs; past the
         // last split they read unused rows)
-        float2 z0[CT], z1[CT];
-        float a0[RT][3], a1[RT][3];
+        T2 z0[CT], z1[CT];
+        T a0[RT][3], a1[RT][3];
         load_split(z0, a0, ao, boff, 0);
         auto pair = [&](int jk, bool tail, bool both) {
             load_split(z1, a1, ao, boff, jk + 1);
@@ -691,7 +734,7 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__res
         for (; jk + 1 <= jk_end; jk += 2) pair(jk, true, true);
         if (jk <= jk_end) pair(jk, true, false);
         since += jk_end + 1;
-        if (since >= flush_steps) {
+        if (M::COMP && since >= flush_steps) {
             flush();
             since = 0;
         }
@@ -704,17 +747,24 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const float2 *__res
             const int col = c0 + 16 * c + li;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int kk = K0 + 16 * r + 4 * lq + e;
-                if (kk < g.nk && col < g.nc)
-                    tout_b[static_cast<long>(kk) * g.nc + col] =
-                        make_float2(sre[r][c][e] + cre[r][c][e], sim[r][c][e] + cim[r][c][e]);
+                const int kk = K0 + 16 * r + M::drow(lq, e);
+                T2 v;
+                if constexpr (M::COMP) {
+                    v.x = sre[r][c][e] + cre[r][c][e];
+                    v.y = sim[r][c][e] + cim[r][c][e];
+                } else {
+                    v.x = P1[r][c][e] - P2[r][c][e];
+                    v.y = P1[r][c][e] + P3[r][c][e];
+                }
+                if (kk < g.nk && col < g.nc) tout_b[static_cast<long>(kk) * g.nc + col] = v;
             }
         }
 }
 
-template <int RT, int CT>
+template <typename T, int RT, int CT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_mfma_kernel(MfmaArgs a)
 {
+    using T2 = typename vec<T>::v2;
     const Geometry &g = a.g;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int bid = blockIdx.x;
@@ -738,9 +788,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
     if (c0 >= g.nc) return;
     const long lines = static_cast<long>(g.nk) * g.nc;
     const long plane = static_cast<long>(g.ncw) * g.nkp;
-    mfma_tile<RT, CT>(g, static_cast<const float2 *>(a.zrow) + b * lines,
-                      static_cast<const float *>(a.zcol) + b * 3 * plane, static_cast<const float2 *>(a.wtab),
-                      static_cast<float2 *>(a.tout) + b * lines, rg, c0, a.flush_steps);
+    mfma_tile<T, RT, CT>(g, static_cast<const T2 *>(a.zrow) + b * lines,
+                         static_cast<const T *>(a.zcol) + b * ALayout<T>::NS * plane, static_cast<const T2 *>(a.wtab),
+                         static_cast<T2 *>(a.tout) + b * lines, rg, c0, a.flush_steps);
 }
 
 // Persistent pair sum over an uneven work list.  Work items (request, row
@@ -807,11 +857,13 @@ __global__ __launch_bounds__(256) void pairsum_persistent(PersistArgs a)
 }
 
 // The same queues with matrix-core items: (request, row group of 16 kMfmaRT
-// rows, column group of kWavesPerBlock x 16 kMfmaCT columns), FP32 only.
+// rows, column group of kWavesPerBlock x 16 kMfmaCT columns).
 constexpr int kMfmaRT = 2, kMfmaCT = 2;
 
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_persistent_mfma(PersistArgs a)
 {
+    using T2 = typename vec<T>::v2;
     __shared__ int s_item;
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
     const int home = blockIdx.x % kNumXcd;
@@ -838,9 +890,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
         const PReq rq = a.reqs[w.req];
         const int c0 = (w.cg * kWavesPerBlock + wave) * 16 * kMfmaCT;
         if (c0 < rq.g.nc)
-            mfma_tile<kMfmaRT, kMfmaCT>(rq.g, static_cast<const float2 *>(rq.zrow), static_cast<const float *>(rq.zcol),
-                                        static_cast<const float2 *>(rq.wtab), static_cast<float2 *>(rq.tsum), w.kb, c0,
-                                        kMfmaFlushSteps);
+            mfma_tile<T, kMfmaRT, kMfmaCT>(rq.g, static_cast<const T2 *>(rq.zrow), static_cast<const T *>(rq.zcol),
+                                           static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, c0,
+                                           kMfmaFlushSteps);
     }
 }
 
@@ -1705,8 +1757,8 @@ hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, in
     }
 }
 
-hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, const Workspace &ws,
-                               hipStream_t st)
+template <typename T>
+static hipError_t pairsum_mfma_t(const Geometry &g, const void *wtab, int batch, const Workspace &ws, hipStream_t st)
 {
     constexpr int RT = kMfmaRT, CT = kMfmaCT;
     MfmaArgs a;
@@ -1723,8 +1775,15 @@ hipError_t launch_pairsum_mfma(const Geometry &g, const void *wtab, int batch, c
     const long work = static_cast<long>(a.n_rg) * batch * a.n_cg;
     a.per_xcd = batch >= kNumXcd ? static_cast<int>((work + kNumXcd - 1) / kNumXcd) : 0;
     const long blocks = a.per_xcd > 0 ? static_cast<long>(a.per_xcd) * kNumXcd : work;
-    pairsum_mfma_kernel<RT, CT><<<dim3(static_cast<unsigned>(blocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    pairsum_mfma_kernel<T, RT, CT><<<dim3(static_cast<unsigned>(blocks)), 64 * kWavesPerBlock, 0, st>>>(a);
     return hipGetLastError();
+}
+
+hipError_t launch_pairsum_mfma(const Geometry &g, int precision, const void *wtab, int batch, const Workspace &ws,
+                               hipStream_t st)
+{
+    return precision == SRM3_FP64 ? pairsum_mfma_t<double>(g, wtab, batch, ws, st)
+                                  : pairsum_mfma_t<float>(g, wtab, batch, ws, st);
 }
 
 template <typename T>
@@ -1775,7 +1834,7 @@ static hipError_t persistent_t(const void *reqs, const void *items, const int *q
     a.q_next = q_next;
     a.flush_terms = kFlushTerms;
     if (mfma)
-        pairsum_persistent_mfma<<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+        pairsum_persistent_mfma<T><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
     else
         pairsum_persistent<T, R, COMP><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
     return hipGetLastError();
@@ -1784,10 +1843,9 @@ static hipError_t persistent_t(const void *reqs, const void *items, const int *q
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
                                      int *q_next, int nblocks, hipStream_t st, bool mfma)
 {
-    if (mfma) {
-        if (precision != SRM3_FP32) return hipErrorInvalidValue;
-        return persistent_t<float, 2, true>(reqs, items, q_begin, q_next, nblocks, st, true);
-    }
+    if (mfma)
+        return precision == SRM3_FP64 ? persistent_t<double, 2, false>(reqs, items, q_begin, q_next, nblocks, st, true)
+                                      : persistent_t<float, 2, true>(reqs, items, q_begin, q_next, nblocks, st, true);
     if (precision == SRM3_FP64) {
         switch (R) {
         case 2: return persistent_t<double, 2, false>(reqs, items, q_begin, q_next, nblocks, st);

@@ -209,8 +209,6 @@ srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, 
         return fail(SRM3_E_INVALID, "policy %d", cfg->policy);
     if (cfg->pair_kernel != SRM3_ALGO_DIRECT && cfg->pair_kernel != SRM3_ALGO_MFMA)
         return fail(SRM3_E_INVALID, "pair_kernel %d", cfg->pair_kernel);
-    if (cfg->pair_kernel == SRM3_ALGO_MFMA && cfg->precision != SRM3_FP32)
-        return fail(SRM3_E_UNSUPPORTED, "the matrix-core pair sum is FP32 only");
     std::unique_ptr<srm3_server_s> s(new (std::nothrow) srm3_server_s);
     if (!s) return fail(SRM3_E_NOMEM, "host allocation failed");
     s->cfg = *cfg;
