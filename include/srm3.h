@@ -244,7 +244,10 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  *                        phase rows with a block of weighted phases, evaluated
  *                        with 16x16x4 MFMAs (FP32: v_mfma_f32_16x16x4_f32 with
  *                        two-sum flushes; FP64: v_mfma_f64_16x16x4_f64).  Same
- *                        result up to rounding.  Runs through srm3_generate,
+ *                        result up to rounding.  Output rows go in groups of
+ *                        32 kappa rows: grids with few rows (a 1-D process has
+ *                        one) leave most of each product idle and are better
+ *                        served by SRM3_ALGO_KAPPA_FFT.  Runs through srm3_generate,
  *                        srm3_coefficients, srm3_transform and uneven batches
  *                        (whose persistent launch then takes matrix-core work
  *                        items: a batch's direct-form plans must be all
