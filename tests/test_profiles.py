@@ -1,0 +1,36 @@
+"""The committed rocprofv3 counter summaries belong to the current kernel
+source: bench.py reads their HBM traffic and busy fractions only while the
+recorded SHA-256 matches, so a kernel change without a new profile shows up
+here (and as null fields in the bench line)."""
+import hashlib
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "paper_2310_03979_amd", "csrc", "srm3_kernels.hip")
+SUMMARIES = ["pairsum_mfma_c1_256x1024_b64_counters.md", "pairsum_mfma_c2_512x8192_w2048_b16_counters.md",
+             "pairsum_c1_256x1024_b64_counters.md", "pairsum_c2_512x8192_w2048_b16_counters.md"]
+
+
+def _field(path, key):
+    for line in open(path):
+        if line.startswith("- " + key + ": "):
+            return line.split(": ", 1)[1].strip().strip("`")
+    return None
+
+
+@pytest.mark.parametrize("name", SUMMARIES)
+def test_counter_summary_matches_kernel_source(name):
+    path = os.path.join(ROOT, "profiles", name)
+    digest = hashlib.sha256(open(SRC, "rb").read()).hexdigest()
+    assert _field(path, "kernel source sha256") == digest
+    assert float(_field(path, "HBM bytes per launch")) > 0
+
+
+def test_bench_reads_the_summaries():
+    import bench
+    import srm3_inputs as inp
+    assert bench.counter_traffic(inp.C1, "mfma") > 0
+    assert 0.5 < bench.counter_valu(inp.C1, "mfma", "* MFMA busy") <= 1.0
+    assert 0.5 < bench.counter_valu(inp.C1, "vector") <= 1.0
