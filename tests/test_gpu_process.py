@@ -75,7 +75,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("algorithm", ["kappa_fft", "direct"])
+@pytest.mark.parametrize("algorithm", ["kappa_fft", "direct", "mfma"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}w{c[1]}_{c[3]}_{c[4]}_b{c[5]}" for c in CASES])
 def test_small_processes_match_oracle(lib, oracle_mod, case, precision, algorithm):

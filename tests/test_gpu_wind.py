@@ -52,7 +52,7 @@ LINE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("algorithm", ["direct", "kappa_fft"])
+@pytest.mark.parametrize("algorithm", ["direct", "mfma", "kappa_fft"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", LINE_CASES, ids=[f"{c[0]}x{c[1]}w{c[2]}_{c[5]}_{c[6]}_cap{c[7]}" for c in LINE_CASES])
 def test_line_factors_match_oracle(lib, oracle_mod, case, precision, algorithm):
@@ -98,7 +98,7 @@ WIND_CASES = [
 ]
 
 
-@pytest.mark.parametrize("algorithm", ["direct", "kappa_fft"])
+@pytest.mark.parametrize("algorithm", ["direct", "mfma", "kappa_fft"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", WIND_CASES, ids=[f"{c[0]}x{c[1]}w{c[2]}_a{c[5]}_cap{c[6]}_{c[7]}" for c in WIND_CASES])
 def test_wind_plans_match_oracle(lib, oracle_mod, case, precision, algorithm):
@@ -227,7 +227,7 @@ PRODUCT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("algorithm", ["direct", "kappa_fft", "fft2d"])
+@pytest.mark.parametrize("algorithm", ["direct", "mfma", "kappa_fft", "fft2d"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", PRODUCT_CASES, ids=[f"{c[0]}x{c[1]}w{c[2]}_s{c[5]}_cap{c[6]}_H{c[7]}" for c in PRODUCT_CASES])
 def test_product_bispectrum_matches_oracle(lib, oracle_mod, case, precision, algorithm):
