@@ -1328,13 +1328,30 @@ __global__ __launch_bounds__(256) void pairsum_hash_kernel(HashPairArgs a)
             }
             const T2 zi = z[static_cast<long>(ik) * g.nc + iw + g.nw - 1];
             const T2 zj = z[static_cast<long>(jk) * g.nc + jw + g.nw - 1];
-            const double tr = static_cast<double>(zi.x) * zj.x - static_cast<double>(zi.y) * zj.y;
-            const double ti = static_cast<double>(zi.x) * zj.y + static_cast<double>(zi.y) * zj.x;
-            double sb, cb;
-            sincospi(static_cast<double>(w1) * (1.0 / 2147483648.0), &sb, &cb);
-            const double bp = sqrt(b2);
-            sr += bp * (tr * cb - ti * sb);
-            si += bp * (tr * sb + ti * cb);
+            if constexpr (sizeof(T) == 4) {
+                // FP32 term (its rounding is far below the FP32 path's
+                // tolerance), FP64 sums: the angle pi w1 / 2^31 is split
+                // into its quadrant (top two bits) and a remainder in
+                // [0, pi/2), so the FP32 argument keeps 24 of its 30 bits
+                const float tr = zi.x * zj.x - zi.y * zj.y;
+                const float ti = zi.x * zj.y + zi.y * zj.x;
+                float s0, c0;
+                sincospif(static_cast<float>(w1 & 0x3FFFFFFFu) * (1.0f / 2147483648.0f), &s0, &c0);
+                const unsigned q = w1 >> 30;
+                const float sb = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+                const float cb = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+                const float bp = sqrtf(static_cast<float>(b2));
+                sr += static_cast<double>(bp * (tr * cb - ti * sb));
+                si += static_cast<double>(bp * (tr * sb + ti * cb));
+            } else {
+                const double tr = static_cast<double>(zi.x) * zj.x - static_cast<double>(zi.y) * zj.y;
+                const double ti = static_cast<double>(zi.x) * zj.y + static_cast<double>(zi.y) * zj.x;
+                double sb, cb;
+                sincospi(static_cast<double>(w1) * (1.0 / 2147483648.0), &sb, &cb);
+                const double bp = sqrt(b2);
+                sr += bp * (tr * cb - ti * sb);
+                si += bp * (tr * sb + ti * cb);
+            }
         }
     }
     if (!z) {
