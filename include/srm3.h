@@ -247,17 +247,18 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
  *                        result up to rounding.  Output rows go in groups of
  *                        32 kappa rows: grids with few rows (a 1-D process has
  *                        one) leave most of each product idle and are better
- *                        served by SRM3_ALGO_KAPPA_FFT.  Runs through srm3_generate,
- *                        srm3_coefficients, srm3_transform and uneven batches
- *                        (whose persistent launch then takes matrix-core work
- *                        items: a batch's direct-form plans must be all
- *                        SRM3_ALGO_DIRECT or all SRM3_ALGO_MFMA); the server
- *                        refuses such plans (SRM3_E_UNSUPPORTED).
+ *                        served by SRM3_ALGO_KAPPA_FFT.  Runs through
+ *                        srm3_generate, srm3_coefficients, srm3_transform,
+ *                        uneven batches (whose persistent launch then takes
+ *                        matrix-core work items: a batch's direct-form plans
+ *                        must be all SRM3_ALGO_DIRECT or all SRM3_ALGO_MFMA)
+ *                        and servers created with pair_kernel SRM3_ALGO_MFMA.
  * Switching to SRM3_ALGO_KAPPA_FFT builds its sheared weight table on the
  * device (stream-ordered on hip_stream).  Errors: SRM3_E_INVALID (bad plan or
  * algorithm), SRM3_E_UNSUPPORTED (N_kappa > 2048; SRM3_ALGO_FFT2D: weights
- * not rank-one, or L above 16384, 8192 in FP64), SRM3_E_NOMEM, SRM3_E_DEVICE.  A bispectrum generated per pair
- * (SRM3_BISPEC_HASHED) takes SRM3_ALGO_DIRECT only. */
+ * not rank-one, or L above 16384, 8192 in FP64; any algorithm but
+ * SRM3_ALGO_DIRECT for a bispectrum generated per pair, SRM3_BISPEC_HASHED),
+ * SRM3_E_NOMEM, SRM3_E_DEVICE. */
 enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1, SRM3_ALGO_FFT2D = 2, SRM3_ALGO_MFMA = 3 };
 srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream);
 
