@@ -202,6 +202,31 @@ def pair_terms_total(wl):
     return tot
 
 
+def mfma_instructions(wl, rows=32, cols=32):
+    """16x16x4 MFMAs the matrix-core pair sum issues per realization: for each
+    wave (32 kappa rows x 32 frequencies), partner steps of 4 columns times
+    three MFMAs per 16x16 tile and kappa split, skipping a 16-row tile whose
+    rows all lie below 2 j_kappa.  Work items with no partner issue none."""
+    nk, nw, W = wl.n_kappa, wl.n_omega, wl.support_w
+    nc = 2 * nw - 1
+    tot = 0
+    for K0 in range(0, nk, rows):
+        jk_end = min(K0 + rows - 1, nk - 1) // 2
+        per_step = 0
+        for jk in range(jk_end + 1):
+            for r in range(rows // 16):
+                if jk >= K0 // 2 and 2 * jk > K0 + 16 * r + 15:
+                    continue
+                per_step += 3 * (cols // 16)
+        for c0 in range(0, nc, cols):
+            kw_lo = c0 - (nw - 1)
+            kw_hi = min(c0 + cols - 1, nc - 1) - (nw - 1)
+            lo, hi = max(-(W - 1), kw_lo - (W - 1)), min(W - 1, kw_hi + (W - 1))
+            if lo <= hi:
+                tot += ((hi - lo) // 4 + 1) * per_step
+    return tot
+
+
 def copy_calibration():
     import torch
     n = 1 << 28                      # 1 GiB of float32
@@ -725,6 +750,9 @@ def main():
             "complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12, 3),
             "avg_launch_ms": round(ps_ms, 4),
             "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
+            # products issued, masked triangle and partner padding included
+            "mfma_instructions_per_launch": mfma_instructions(wl) * B,
+            "useful_product_frac": round(terms / (mfma_instructions(wl) / 3 * 1024), 4),
         }
     else:
         achieved_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12

@@ -34,3 +34,23 @@ def test_bench_reads_the_summaries():
     assert bench.counter_traffic(inp.C1, "mfma") > 0
     assert 0.5 < bench.counter_valu(inp.C1, "mfma", "* MFMA busy") <= 1.0
     assert 0.5 < bench.counter_valu(inp.C1, "vector") <= 1.0
+
+
+def test_mfma_instruction_model_matches_the_counters():
+    """The host count of the matrix-core kernel's MFMAs (reported by bench.py)
+    equals SQ_INSTS_MFMA of the profiled launches, and the useful share of the
+    issued products (pair terms over 1024 products per three MFMAs) is the
+    figure quoted for the kernel."""
+    import bench
+    import srm3_inputs as inp
+    for wl, name in ((inp.C1, "pairsum_mfma_c1_256x1024_b64_counters.md"),
+                     (inp.C2, "pairsum_mfma_c2_512x8192_w2048_b16_counters.md")):
+        measured = None
+        for line in open(os.path.join(ROOT, "profiles", name)):
+            if line.startswith("| SQ_INSTS_MFMA |"):
+                measured = float(line.split("|")[2])
+        assert measured is not None
+        model = bench.mfma_instructions(wl) * wl.batch
+        assert abs(model - measured) <= 1e-4 * measured, (name, model, measured)
+    useful = bench.pair_terms_total(inp.C1) / (bench.mfma_instructions(inp.C1) / 3 * 1024)
+    assert 0.93 < useful < 0.94
