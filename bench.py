@@ -167,7 +167,7 @@ def counter_valu(wl, kernel="vector", key="* VALU issue"):
     for line in open(counter_path(wl, kernel)):
         if line.startswith(key) and "**" in line:
             try:
-                return float(line.split("**")[1].split("%")[0]) / 100.0
+                return round(float(line.split("**")[1].split("%")[0]) / 100.0, 4)
             except ValueError:
                 return None
     return None
