@@ -211,6 +211,14 @@ srm3_status srm3_transform(srm3_plan_t plan, const void *C_dev, int32_t batch,
 /* Device workspace bytes that srm3_generate needs for `batch` realizations. */
 srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes);
 
+/* Fill the plan's whole device workspace for `batch` realizations (grown as
+ * srm3_generate would grow it, so that call may allocate) with the 32-bit
+ * pattern `word`, by a kernel on hip_stream.  For tests and tooling: with a
+ * NaN pattern, a later generation shows that no kernel lets a value it did not
+ * write reach the field.  Errors: SRM3_E_INVALID (NULL plan, batch < 0),
+ * SRM3_E_UNSUPPORTED (batch > 65535), SRM3_E_NOMEM, SRM3_E_DEVICE. */
+srm3_status srm3_workspace_fill(srm3_plan_t plan, int32_t batch, uint32_t word, void *hip_stream);
+
 /* Number of unordered pair terms of one realization (sum over lines of |P(k)|). */
 srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms);
 

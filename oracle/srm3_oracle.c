@@ -75,6 +75,7 @@ static uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint64_t key
 void oracle_phases(int nk, int nw, uint64_t seed, uint32_t *U)
 {
     const int nc = 2 * nw - 1;
+#pragma omp parallel for schedule(static)
     for (int kk = 0; kk < nk; ++kk)
         for (int kw = -(nw - 1); kw <= nw - 1; ++kw)
             U[(size_t)kk * nc + (kw + nw - 1)] =
@@ -86,6 +87,7 @@ void oracle_phases(int nk, int nw, uint64_t seed, uint32_t *U)
 void oracle_biphase(int W, int mode, uint64_t beta_seed, uint32_t *beta)
 {
     const int n = 2 * W - 1;
+#pragma omp parallel for schedule(static)
     for (int iw = -(W - 1); iw <= W - 1; ++iw)
         for (int jw = -(W - 1); jw <= W - 1; ++jw) {
             uint32_t v = 0u;

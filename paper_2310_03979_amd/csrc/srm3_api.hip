@@ -733,6 +733,21 @@ srm3_status srm3_workspace_bytes(srm3_plan_t plan, int32_t batch, size_t *bytes)
     return SRM3_OK;
 }
 
+srm3_status srm3_workspace_fill(srm3_plan_t plan, int32_t batch, uint32_t word, void *hip_stream)
+{
+    g_err[0] = 0;
+    if (!plan || batch < 0) return fail(SRM3_E_INVALID, "bad argument");
+    if (batch == 0) return SRM3_OK;
+    if (batch > 65535) return fail(SRM3_E_UNSUPPORTED, "batch %d too large", batch);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    srm3_status s = ensure_workspace(plan, batch, st);
+    if (s) return s;
+    hipError_t e = launch_fill_u32(plan->ws.p, plan->ws.n / 4, word, st);
+    if (e == hipSuccess && kfft_family(plan->algo)) e = launch_fill_u32(plan->kws.p, plan->kws.n / 4, word, st);
+    if (e != hipSuccess) return dev_err(e, "fill kernel");
+    return SRM3_OK;
+}
+
 srm3_status srm3_pair_terms(srm3_plan_t plan, double *terms)
 {
     if (!plan || !terms) return fail(SRM3_E_INVALID, "bad argument");

@@ -136,6 +136,8 @@ void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const v
                          const void *wtab);
 void fill_persistent_item(void *dst, int req, int kb, int cg);
 int waves_per_block();
+// 32-bit fill of device memory by a kernel (graph-safe, unlike hipMemsetAsync)
+hipError_t launch_fill_u32(void *p, size_t words, uint32_t v, hipStream_t st);
 constexpr int kXcds = 8;
 // mode 0: assemble C from pair sums and phases; mode 1: read C from `cin`.
 // rout (n_x == n_kappa == 1 only, else ignored): write the real field [B][n_t]

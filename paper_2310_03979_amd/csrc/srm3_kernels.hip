@@ -606,8 +606,9 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const typename vec<
     // The a planes' resource starts `shift` rows before them: per-lane offsets
     // stay fixed for a partner step and the split moves the uniform offset
     // (shift - jk rows, never negative).  Reads of rows a split does not use
-    // stay inside the plan's workspace (the phase rows precede the a planes)
-    // and meet a zero f, a skipped tile or a discarded output row.
+    // stay inside the plan's workspace (the phase rows precede the a planes);
+    // their values (not necessarily finite) are replaced by zero, skipped with
+    // their tile, or land in an output row that is not stored.
     const unsigned row_bytes = static_cast<unsigned>(g.nc * sizeof(T2));
     const brsrc zb = make_brsrc(zrow_b, static_cast<unsigned>(lines * sizeof(T2)));
     const int shift = jk_end + 2;
@@ -691,11 +692,16 @@ __device__ __forceinline__ void mfma_tile(const Geometry &g, const typename vec<
             if (tail && 2 * jk > K0 + 16 * r + 15) continue;   // no row of this tile uses the split
             T x0 = ac[r][0], x1 = ac[r][1], x2 = ac[r][2];
             if (tail) {
+                // rows above the split keep their values, the split's own row
+                // is halved, rows below it are replaced by zero (a select, not
+                // a product: the values read there lie outside the a planes
+                // and need not be finite)
                 const int kk = K0 + 16 * r + li;
-                const T f = 2 * jk < kk ? T(1) : (2 * jk == kk ? T(0.5) : T(0));
-                x0 *= f;
-                x1 *= f;
-                x2 *= f;
+                const T h = 2 * jk == kk ? T(0.5) : T(1);
+                const bool use = 2 * jk <= kk;
+                x0 = use ? x0 * h : T(0);
+                x1 = use ? x1 * h : T(0);
+                x2 = use ? x2 * h : T(0);
             }
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
@@ -900,6 +906,12 @@ __global__ void fill_int_kernel(int *p, int n, int v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, size_t n, uint32_t v)
+{
+    const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+    for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1905,6 +1917,14 @@ void fill_persistent_item(void *dst, int req, int kb, int cg)
 }
 
 int waves_per_block() { return kWavesPerBlock; }
+
+hipError_t launch_fill_u32(void *p, size_t words, uint32_t v, hipStream_t st)
+{
+    if (words == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 8192);
+    fill_u32_kernel<<<dim3(static_cast<unsigned>(blocks)), 256, 0, st>>>(static_cast<uint32_t *>(p), words, v);
+    return hipGetLastError();
+}
 
 template <typename T>
 static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const AmpRef &amp, const void *wtab,

@@ -99,6 +99,7 @@ def load():
     L.srm3_coefficients.argtypes = [vp, _u64p, ctypes.c_int32, vp, vp]
     L.srm3_transform.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     L.srm3_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.srm3_workspace_fill.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, vp]
     L.srm3_pair_terms.argtypes = [vp, _dp]
     L.srm3_rows_per_wave.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.srm3_plan_set_algorithm.argtypes = [vp, ctypes.c_int32, vp]
@@ -125,7 +126,7 @@ def load():
     L.srm3_batch_destroy.restype = None
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
     for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_product_factors", "srm3_generate", "srm3_coefficients", "srm3_transform",
-              "srm3_workspace_bytes", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
+              "srm3_workspace_bytes", "srm3_workspace_fill", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
               "srm3_algorithm_terms", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
               "srm3_batch_create", "srm3_batch_run", "srm3_batch_info", "srm3_generate_uneven"):
@@ -323,6 +324,13 @@ def srm3_workspace_bytes(plan: Plan, batch: int) -> int:
     n = ctypes.c_size_t()
     _check(load().srm3_workspace_bytes(plan.handle, batch, ctypes.byref(n)))
     return int(n.value)
+
+
+def srm3_workspace_fill(plan: Plan, batch: int, word: int, stream=None):
+    """Fill the plan's workspace for ``batch`` realizations with a 32-bit pattern
+    (e.g. 0x7FC00000, a NaN) by a kernel on the stream."""
+    _check(load().srm3_workspace_fill(plan.handle, int(batch), ctypes.c_uint32(int(word) & 0xFFFFFFFF),
+                                      _stream_ptr(stream)))
 
 
 def srm3_pair_terms(plan: Plan) -> float:

@@ -1,7 +1,7 @@
 """The direct-form pair sum on the matrix cores (SRM3_ALGO_MFMA) against the
 FP64 oracle through the C-ABI, FP64 <= 1e-10 and FP32 <= 2e-5 relative L2: small, ragged and
-degenerate grids with every bispectrum form, the 256x1024 and 512x8192 grids at
-full batch on sampled lines, agreement with the vector kernel, batch
+degenerate grids with every bispectrum form (the 256x1024 and 512x8192 grids at
+full batch: 4096 sampled lines each, in test_gpu_large.py), agreement with the vector kernel, batch
 invariance, uneven batches (matrix-core items in the persistent launch) equal
 to single generation, a process plan, a wind plan with line factors, and
 errors."""
@@ -136,31 +136,6 @@ def test_agrees_with_vector_kernel_and_is_batch_invariant(lib):
     # switching back gives the vector result again, bitwise
     lib.srm3_plan_set_algorithm(mat, "direct")
     assert torch.equal(_coeffs(lib, mat, seeds).to(torch.complex128), a)
-
-
-@pytest.mark.parametrize("name,precision", [("c1", "fp32"), ("c2", "fp32"), ("c1", "fp64")])
-def test_full_size_sampled_lines(lib, oracle_mod, name, precision):
-    """The 256x1024 grid at its full batch of 64 (FP32 and FP64) and the
-    512x8192 grid (support 2048) at batch 16: sampled lines of the first and
-    last realization."""
-    torch = _torch()
-    wl = inp.WORKLOADS[name]
-    print(f"[gpu] mfma {name} batch {wl.batch} {precision}", flush=True)
-    bis, b2 = _bispec(wl, "separable", "seeded")
-    plan = _plan(lib, wl, bis, precision)
-    seeds = wl.seeds()
-    C = _coeffs(lib, plan, seeds)
-    P = _problem(oracle_mod, wl, bis, b2)
-    rng = np.random.default_rng(12)
-    W = wl.support_w
-    for r in (0, wl.batch - 1):
-        kk = np.concatenate([[0, 1, wl.n_kappa - 1, wl.n_kappa - 2], rng.integers(0, wl.n_kappa, 20)])
-        c = (wl.n_omega - 1) + rng.integers(-(2 * W - 2), 2 * W - 1, 24)
-        c = np.clip(c, 0, wl.n_cols - 1)
-        lines = (kk * wl.n_cols + c).astype(np.int64)
-        ref = P.coefficients(seed=int(seeds[r]), lines=lines)
-        got = C[r].reshape(-1)[torch.as_tensor(lines, device="cuda")].to(torch.complex128).cpu().numpy()
-        assert _rel(got, ref) <= TOLS[precision], r
 
 
 def test_process_and_wind_plans(lib, oracle_mod):
