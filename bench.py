@@ -2,16 +2,18 @@
 """Benchmark: space-time grid points/s of the 3rd-order SRM wave generator.
 
 One step = one ``srm3_generate`` call producing a batch of realizations of the
-256 x 1024-line workload (512 x 2048 field, batch 64, FP32 fixed-point-phase
-path): phases, pair sums, coefficients and the 2-D inverse DFT, with the plan
-(spectrum, bicoherence table) resident on the device.  Also reported:
+512 x 8192-line workload (1024 x 16384 field, bicoherence support 2048, batch
+16, FP32 fixed-point-phase path): phases, pair sums, coefficients and the 2-D
+inverse DFT, with the plan (spectrum, bicoherence table) resident on the device.
+Also reported:
 
 * plain   -- the same realizations, one non-batched call per realization
-* fp64    -- the batched FP64 path
 * vector_pairsum -- the FP32 step with the pair sum on the vector ALUs
 * roofline -- the pair-sum kernel (the dominant kernel: on the matrix cores by
               default), timed with HIP events recorded by the library on its
               launch stream during the timed steps
+* transforms -- HBM rate of the phase, t- and x-transform kernels
+* serving -- a short Poisson replay of the served request mix (p50/p99)
 * cpu_baseline -- the FP64 oracle on this host, on a bounded sample
 
 Prints ONE JSON line.
@@ -35,9 +37,11 @@ import srm3_inputs as inp  # noqa: E402
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (published)
 PEAK_FP32_MFMA_TFLOPS = 157.3 # MI355X dense FP32 matrix (published)
 PEAK_FP64_TFLOPS = 78.6       # MI355X vector FP64 (published)
+FMA_ISSUE_FP32_TFLOPS = 78.6  # non-packed FP32 FMA issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR_TERM = 14      # complex product z_i z_j (6) x W (6) + accumulate (2)
 MFMA_FLOPS_PER_PAIR_TERM = 6  # the matrix cores' share: three real products (Gauss form), each a multiply-add
+MFMA_KERNEL = "pairsum_mfma_kernel<float,2,2> (v_mfma_f32_16x16x4_f32)"
 
 
 def log(*a):
@@ -49,7 +53,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c1", choices=sorted(inp.WORKLOADS) + ["c3", "c4", "p1", "bridge"])
+    ap.add_argument("--workload", default="c2", choices=sorted(inp.WORKLOADS) + ["c3", "c4", "p1", "bridge"])
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests per arrival rate in the serving workload (c4)")
     ap.add_argument("--batch", type=int, default=None)
@@ -58,6 +62,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pair-kernel", default="mfma", choices=["mfma", "vector"],
                     help="FP32 pair sum of the measured step: matrix cores or vector ALUs")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short serving replay of the direct workloads")
+    ap.add_argument("--serve-short", type=int, default=32,
+                    help="requests of the short serving replay")
     ap.add_argument("--no-kfft", action="store_true",
                     help="skip the pair sum through an FFT along kappa (reported beside the direct form)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
@@ -227,6 +235,71 @@ def mfma_instructions(wl, rows=32, cols=32):
     return tot
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def transform_bytes(wl, B, e=4):
+    """Algorithmic HBM bytes per launch of the kernels around the pair sum
+    (element size e of the real type): each array read or written once."""
+    lines = wl.n_kappa * wl.n_cols
+    ncw = 2 * wl.support_w - 1
+    return {
+        # writes the phase rows (complex) and the three a-operand planes of the support columns
+        "phases": B * lines * 2 * e + B * 3 * ncw * wl.n_kappa * e,
+        # reads pair sums and phase rows (complex) and the plan's FP64 spectrum and
+        # per-line sums; writes the t-transformed rows (complex)
+        "tfft": 2 * B * lines * 2 * e + lines * 16 + B * wl.n_kappa * wl.n_t * 2 * e,
+        # reads the t-transformed rows, writes the real field
+        "xfft": B * wl.n_kappa * wl.n_t * 2 * e + B * wl.n_x * wl.n_t * e,
+    }
+
+
+SERVE_GRIDS = [(64, 256), (256, 1024), (512, 4096), (1024, 8192)]
+
+
+def serve_short(torch, srm3, n, pair_terms_per_s, pk):
+    """A short replay of the served workload: n requests (grid uniform over
+    the four served line grids, U ~ U[20, 45] m/s, arrival seed 42) at 0.9 x
+    the saturated rate estimated from the measured pair-term rate of the
+    headline step; continuous batching on one server."""
+    from paper_2310_03979_amd import serve
+    rng = np.random.default_rng(42)
+    plans = {}
+    for g in SERVE_GRIDS:
+        wl = inp.small_grid(*g, b2_scale=0.3)
+        plans[g] = (wl, srm3.plan_from_workload(wl, "fp32"))
+        if pk == "mfma":
+            srm3.srm3_plan_set_algorithm(plans[g][1], "mfma")
+    reqs = []
+    for i in range(n):
+        g = SERVE_GRIDS[int(rng.integers(0, len(SERVE_GRIDS)))]
+        wl, plan = plans[g]
+        reqs.append(dict(plan=plan, seed=4000 + i, b2_scale=1.0, spectrum=dict(U=float(rng.uniform(20.0, 45.0))),
+                         out=torch.empty(plan.field_shape, dtype=torch.float32, device="cuda"),
+                         points=wl.grid_points, terms=srm3.srm3_pair_terms(plan)))
+    mean_s = float(np.mean([r["terms"] for r in reqs])) / pair_terms_per_s
+    rate = 0.9 / mean_s
+    srv = srm3.Server("fp32", max_active=32, hbm_budget=48 << 30, pair_kernel=pk)
+    serve.replay(srv, reqs[:2], [0.0, 0.0])
+    arr = serve.poisson_arrivals(n, rate, seed=42)
+    r = serve.replay(srv, reqs, arr, progress=lambda m: log("[bench]   " + m))
+    srv.destroy()
+    mix = {f"{g[0]}x{g[1]}": sum(1 for q in reqs if q["plan"] is plans[g][1]) for g in SERVE_GRIDS}
+    return {"requests": n, "latency_samples": int(r["latency"].size), "mix": mix,
+            "rate_req_per_s": round(rate, 4),
+            "rate_basis": "0.9 x (measured pair terms/s of the headline step / mean pair terms per request)",
+            "p50_s": round(r["p50"], 4), "p99_s": round(r["p99"], 4), "mean_s": round(r["mean"], 4),
+            "makespan_s": round(r["makespan"], 3),
+            "grid_points_per_s": sum(q["points"] for q in reqs) / r["makespan"]}
+
+
 def copy_calibration():
     import torch
     n = 1 << 28                      # 1 GiB of float32
@@ -279,8 +352,9 @@ def bench_uneven(args, torch, srm3):
     dinfo = direct.info()
     terms = info["pair_terms"]
     ps_ms = dinfo["pairsum_ms"]
-    fpt = MFMA_FLOPS_PER_PAIR_TERM if mfma else FLOPS_PER_PAIR_TERM
-    achieved = fpt * terms / (ps_ms * 1e-3) / 1e12
+    # both kernels execute 6 flops per pair term (three real products); the
+    # vector kernel's ceiling is the non-packed FP32 FMA issue rate
+    achieved = MFMA_FLOPS_PER_PAIR_TERM * terms / (ps_ms * 1e-3) / 1e12
     log(f"[bench] batched graph: {dt * 1e3:.1f} ms/step; pair sum {ps_ms:.1f} ms")
     rec_plain = None
     if not args.no_plain:
@@ -320,13 +394,13 @@ def bench_uneven(args, torch, srm3):
                       "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                       "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
                       "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
-                      "complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms / (ps_ms * 1e-3) / 1e12, 3),
                       "pair_terms_per_launch": terms, "avg_launch_ms": round(ps_ms, 3)} if mfma else
                      {"bound": "alu", "kernel": f"pairsum_persistent<float,{dinfo['rows_per_wave']},true>",
-                      "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                      "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                      "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
+                      "achieved": round(achieved, 3), "peak": FMA_ISSUE_FP32_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(achieved / FMA_ISSUE_FP32_TFLOPS, 4), "traffic": None,
+                      "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
                       "pair_terms_per_launch": terms, "avg_launch_ms": round(ps_ms, 3)}),
+        "pair_sum_complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms / (ps_ms * 1e-3) / 1e12, 3),
         "tile": {k: info[k] for k in ("rows_per_wave", "blocks_per_cu", "work_items", "groups")},
         "cpu_baseline": None,
     }
@@ -455,6 +529,7 @@ def bench_process(args, torch, srm3):
     prof = srm3.srm3_profile_read(plan)
     srm3.srm3_profile_enable(plan, False)
     ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
+    # 14 flops per term issued as 8 non-packed VALU instructions (2 multiplies, 6 FMAs)
     tf = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
     log(f"[bench] process fp32: {dt * 1e3:.3f} ms/step, kernels {prof}")
     extra = {}
@@ -510,8 +585,8 @@ def bench_process(args, torch, srm3):
                                f"{wl.n_t} time points, {B} realizations per step (Kaimal spectrum, "
                                f"separable exponential bicoherence capped at {wl.cap}, seeded biphase)"},
         "roofline": {"bound": "alu", "kernel": "ypair2_kernel<float,8,32> (+ two length-1 column copies)",
-                     "achieved": round(tf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tf / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "achieved": round(tf, 3), "peak": FMA_ISSUE_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / FMA_ISSUE_FP32_TFLOPS, 4), "traffic": None,
                      "pair_terms_per_launch": terms * B, "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
                      "avg_launch_ms": round(ps_ms, 4), "pair_terms_per_s": terms * B / (ps_ms * 1e-3)},
         "cpu_baseline": cpu,
@@ -578,7 +653,7 @@ def bench_bridge(args, torch, srm3):
     prof = srm3.srm3_profile_read(plan)
     srm3.srm3_profile_enable(plan, False)
     ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
-    fpt = MFMA_FLOPS_PER_PAIR_TERM if mfma else FLOPS_PER_PAIR_TERM
+    fpt = MFMA_FLOPS_PER_PAIR_TERM   # both pair-sum kernels execute 6 flops per term
     tf = fpt * terms * B / (ps_ms * 1e-3) / 1e12
     log(f"[bench] bridge direct fp32: {dt * 1e3:.2f} ms/step (plan {plan_s:.2f} s)")
     kplan = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
@@ -662,9 +737,11 @@ def bench_bridge(args, torch, srm3):
                                f"wind bispectrum alpha {wl.alpha} through the partial-bicoherence recursion, "
                                f"cap {wl.cap}, {B} realizations"},
         "roofline": {"bound": "mfma" if mfma else "alu",
-                     "kernel": "pairsum_mfma_kernel<2,2>" if mfma else "pairsum_kernel<float,8,true>",
-                     "achieved": round(tf, 3), "peak": PEAK_FP32_MFMA_TFLOPS if mfma else PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tf / PEAK_FP32_TFLOPS, 4), "flops_per_pair_term": fpt,
+                     "kernel": MFMA_KERNEL if mfma else "pairsum_kernel<float,8,true>",
+                     "achieved": round(tf, 3), "peak": PEAK_FP32_MFMA_TFLOPS if mfma else FMA_ISSUE_FP32_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": round(tf / (PEAK_FP32_MFMA_TFLOPS if mfma else FMA_ISSUE_FP32_TFLOPS), 4),
+                     "flops_per_pair_term": fpt,
                      "traffic": None, "pair_terms_per_launch": terms * B, "avg_launch_ms": round(ps_ms, 4)},
         "cpu_baseline": None,
         "kappa_fft_grid_points_per_s": points / dtk, "kappa_fft_over_direct": round(dt / dtk, 3),
@@ -734,11 +811,12 @@ def main():
     ps_ms = prof["pairsum"][0] / max(1, prof["pairsum"][1])
     kname = "mfma" if mfma else "vector"
     full = B == wl.batch
+    complex_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
     if mfma:
         achieved_tflops = MFMA_FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
         roofline = {
             "bound": "mfma",
-            "kernel": "pairsum_mfma_kernel<2,2> (v_mfma_f32_16x16x4_f32)",
+            "kernel": MFMA_KERNEL,
             "achieved": round(achieved_tflops, 3),
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
@@ -747,7 +825,6 @@ def main():
             "mfma_busy_frac": counter_valu(wl, kname, "* MFMA busy") if full else None,
             "pair_terms_per_launch": terms * B,
             "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
-            "complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12, 3),
             "avg_launch_ms": round(ps_ms, 4),
             "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
             # products issued, masked triangle and partner padding included
@@ -755,18 +832,20 @@ def main():
             "useful_product_frac": round(terms / (mfma_instructions(wl) / 3 * 1024), 4),
         }
     else:
-        achieved_tflops = FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
+        # the vector kernel issues 3 FMAs (6 flops) per pair term; packed FP32 is
+        # disabled, so its ceiling is the non-packed FMA issue rate
+        achieved_tflops = MFMA_FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
         roofline = {
             "bound": "alu",
             "kernel": f"pairsum_kernel<float,{srm3.srm3_rows_per_wave(plan32)},true>",
             "achieved": round(achieved_tflops, 3),
-            "peak": PEAK_FP32_TFLOPS,
+            "peak": FMA_ISSUE_FP32_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+            "frac": round(achieved_tflops / FMA_ISSUE_FP32_TFLOPS, 4),
             "traffic": counter_traffic(wl, kname) if full else None,
             "valu_issue_frac": counter_valu(wl, kname) if full else None,
             "pair_terms_per_launch": terms * B,
-            "flops_per_pair_term": FLOPS_PER_PAIR_TERM,
+            "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
             "avg_launch_ms": round(ps_ms, 4),
             "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
         }
@@ -774,7 +853,18 @@ def main():
         roofline["hbm_GB_per_s"] = round(roofline["traffic"] / (ps_ms * 1e-3) / 1e9, 1)
     kernel_ms = {k: round(v[0] / max(1, v[1]), 4) for k, v in prof.items()}
 
-    extra = {}
+    extra = {"pair_sum_complex_form": {
+        "tflops": round(complex_tflops, 3),
+        "note": "the same launch counted at 14 flops per pair term (complex product, weight, accumulate); "
+                "not a roofline figure: the kernel executes 6 flops per term"}}
+    tb = transform_bytes(wl, B)
+    tr = {}
+    for k in ("phases", "tfft", "xfft"):
+        ms = prof[k][0] / max(1, prof[k][1])
+        gbs = tb[k] / (ms * 1e-3) / 1e9
+        tr[k] = {"avg_launch_ms": round(ms, 4), "algorithmic_bytes": tb[k], "GB_per_s": round(gbs, 1),
+                 "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
+    extra["transforms"] = tr
     # ---- plain: one call per realization, same kernels ----
     if not args.no_plain:
         out1 = torch.empty((1, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
@@ -782,11 +872,13 @@ def main():
         def plain():
             for s in seeds:
                 srm3.srm3_generate(plan32, [int(s)], out1)
-        dtp = timed_steps(torch, plain, 1, 1)
+        psteps = max(1, min(args.steps, 5))
+        dtp = timed_steps(torch, plain, psteps, 1)
         extra["plain_fp32_grid_points_per_s"] = grid_points / dtp
         extra["plain_fp32_ms_per_batch"] = round(dtp * 1e3, 3)
+        extra["plain_timed_batches"] = psteps
         extra["batched_over_plain"] = round(dtp / dt, 3)
-        log(f"[bench] plain fp32: {dtp * 1e3:.2f} ms per {B} realizations")
+        log(f"[bench] plain fp32: {dtp * 1e3:.2f} ms per {B} realizations ({psteps} timed)")
     plans = {"fp32": plan32}
     fields = {"fp32": out32}
     # ---- the other FP32 pair-sum kernel (vector ALUs, or the matrix cores) ----
@@ -801,14 +893,18 @@ def main():
         pv = srm3.srm3_profile_read(planv)
         srm3.srm3_profile_enable(planv, False)
         vms = pv["pairsum"][0] / max(1, pv["pairsum"][1])
-        vtf = FLOPS_PER_PAIR_TERM * terms * B / (vms * 1e-3) / 1e12
+        vtf = MFMA_FLOPS_PER_PAIR_TERM * terms * B / (vms * 1e-3) / 1e12
         leg = {"grid_points_per_s": grid_points / dtv, "ms_per_step": round(dtv * 1e3, 3),
                "pairsum_avg_launch_ms": round(vms, 4), "pair_terms_per_s": terms * B / (vms * 1e-3),
-               "complex_form_tflops": round(vtf, 3)}
+               "issued_tflops": round(vtf, 3)}
         if other == "vector":
             leg.update({"kernel": f"pairsum_kernel<float,{srm3.srm3_rows_per_wave(planv)},true>", "bound": "alu",
-                        "frac_of_fp32_vector_peak": round(vtf / PEAK_FP32_TFLOPS, 4),
+                        "frac_of_fma_issue_ceiling": round(vtf / FMA_ISSUE_FP32_TFLOPS, 4),
+                        "fma_issue_ceiling_tflops": FMA_ISSUE_FP32_TFLOPS,
                         "valu_issue_frac": counter_valu(wl, "vector") if full else None})
+        else:
+            leg.update({"kernel": MFMA_KERNEL, "bound": "mfma",
+                        "frac_of_fp32_matrix_peak": round(vtf / PEAK_FP32_MFMA_TFLOPS, 4)})
         extra[f"{other}_pairsum"] = leg
         plans[f"fp32_{other}"] = planv
         fields[f"fp32_{other}"] = outv
@@ -828,8 +924,10 @@ def main():
         extra["fp64_grid_points_per_s"] = grid_points / dt64
         extra["fp64_pair_kernel"] = "matrix cores (FP64 MFMA)" if mfma else "vector ALUs"
         extra["fp64_pairsum_ms"] = round(ps64, 3)
-        fpt64 = MFMA_FLOPS_PER_PAIR_TERM if mfma else FLOPS_PER_PAIR_TERM
-        extra["fp64_pairsum_tflops"] = round(fpt64 * terms * B / (ps64 * 1e-3) / 1e12, 3)
+        # 6 flops per pair term (three real products on the matrix cores, or three
+        # FP64 FMAs on the vector ALUs) against the FP64 peak (matrix and vector
+        # rates are equal)
+        extra["fp64_pairsum_tflops"] = round(MFMA_FLOPS_PER_PAIR_TERM * terms * B / (ps64 * 1e-3) / 1e12, 3)
         extra["fp64_pairsum_frac_of_fp64_peak"] = round(extra["fp64_pairsum_tflops"] / PEAK_FP64_TFLOPS, 4)
         log(f"[bench] batched fp64: {dt64 * 1e3:.2f} ms/step")
         torch.cuda.synchronize()
@@ -856,8 +954,8 @@ def main():
             "terms_per_realization": kterms,
             "pair_stage": {"bound": "alu", "kernels": "colfft_kernel (forward) + ypair2_kernel + colfft_kernel "
                                                       "(inverse)", "avg_launch_ms": round(ksum, 4),
-                           "achieved": round(ktf, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                           "frac": round(ktf / PEAK_FP32_TFLOPS, 4), "flops_per_term": FLOPS_PER_PAIR_TERM},
+                           "achieved": round(ktf, 3), "peak": FMA_ISSUE_FP32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(ktf / FMA_ISSUE_FP32_TFLOPS, 4), "flops_per_term": FLOPS_PER_PAIR_TERM},
             "kernel_avg_ms": {k: round(v[0] / max(1, v[1]), 4) for k, v in pk.items()},
         }
         plans["fp32_kappa_fft"] = plank
@@ -866,7 +964,7 @@ def main():
 
     # ---- a bispectrum generated per 4-index pair inside the kernel (no table) ----
     if not args.no_kfft:
-        bh = 4
+        bh = 1 if wl.n_lines > 4_000_000 else 4
         planh = srm3.srm3_plan(wl.grid_dict(), wl.spectrum(), dict(kind="hashed", alpha=1e-4, beta_seed=wl.beta_seed,
                                                                    cap=wl.cap, support_w=wl.support_w), "fp32")
         outh = torch.empty((bh, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
@@ -889,10 +987,18 @@ def main():
     del outg
     log(f"[bench] zero bicoherence (2nd-order) fp32: {dtg * 1e3:.3f} ms/step")
 
+    # ---- a short replay of the served request mix (latency percentiles) ----
+    if not args.no_serve and args.serve_short > 0:
+        log(f"[bench] serving replay: {args.serve_short} requests ...")
+        extra["serving"] = serve_short(torch, srm3, args.serve_short, terms * B / (ps_ms * 1e-3),
+                                       "mfma" if mfma else "direct")
+        log(f"[bench] serving: {extra['serving']}")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] oracle CPU baseline ...")
         cpu, sample = cpu_baseline(wl, args.cpu_seconds)
+        cpu["cpu_model"] = cpu_model()
         log(f"[bench] oracle: {cpu['value']:.4g} grid points/s on {cpu['cores']} threads")
         extra["accuracy"] = accuracy(torch, srm3, wl, plans, fields, sample)
         log(f"[bench] accuracy: {extra['accuracy']}")
