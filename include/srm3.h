@@ -198,6 +198,21 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum,
 srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch,
                           void *out_dev, void *hip_stream);
 
+/* Allocation-free generation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same work and result as srm3_generate, with the workspace
+ * taken from a fixed device array of the library instead of the plan's own
+ * buffer.  The array holds 64 MiB on each GPU the library runs on and stays allocated until the process ends; the call makes no
+ * device allocation and records no profiling events.  Nothing in it needs to
+ * start at zero.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind: calls that overlap on one GPU (two streams, two threads)
+ * race, so callers serialise them.  Requires the plan's device to be current.
+ * Errors: those of srm3_generate, and SRM3_E_UNSUPPORTED when the workspace of
+ * `batch` realizations (srm3_workspace_bytes, rounded to 256 bytes) exceeds the
+ * array, with the sizes in srm3_last_error(). */
+srm3_status srm3_generate_noalloc(srm3_plan_t plan, const uint64_t *seeds, int32_t batch,
+                                  void *out_dev, void *hip_stream);
+
 /* Coefficients only: C_dev receives batch * n_kappa * (2 n_omega - 1) complex
  * values (interleaved re, im; float or double) laid out [b][k_kappa][c]. */
 srm3_status srm3_coefficients(srm3_plan_t plan, const uint64_t *seeds, int32_t batch,

@@ -10,6 +10,7 @@
 #include <fstream>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -197,7 +198,8 @@ srm3_status check_batch(srm3_plan_t p, const void *seeds, int32_t batch, const v
     return SRM3_OK;
 }
 
-srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const Workspace &ws, hipStream_t st)
+srm3_status run_front_kfft(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const Workspace &ws,
+                           const KfftWorkspace &kw, hipStream_t st)
 {
     srm3_status s;
     if ((s = event_pair(p, 0, st, true))) return s;
@@ -212,7 +214,6 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
         e = launch_pairsum_hash(p->g, p->precision, p->hash_key, p->hash_scale, batch, &ws, nullptr, st);
         if (e != hipSuccess) return dev_err(e, "hashed pair-sum kernel");
     } else if (kfft_family(p->algo)) {
-        const KfftWorkspace kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
         e = launch_kfft_pairsum(p->precision, p->g, p->kg, plan_ktab(p), batch, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
     } else if (p->algo == SRM3_ALGO_MFMA) {
@@ -224,6 +225,14 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
     }
     if ((s = event_pair(p, 1, st, false))) return s;
     return SRM3_OK;
+}
+
+// phases and pair sums with the plan's own kappa-FFT workspace
+srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const Workspace &ws, hipStream_t st)
+{
+    KfftWorkspace kw;
+    if (kfft_family(p->algo)) kw = carve_kfft(p->g, p->kg, p->precision, batch, p->kws.p);
+    return run_front_kfft(p, seeds, batch, ws, kw, st);
 }
 
 srm3_status run_back(srm3_plan_t p, int mode, const void *cin, int32_t batch, const Workspace &ws, void *out,
@@ -828,6 +837,91 @@ srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch
     if ((s = ensure_workspace(plan, batch, st))) return s;
     const Workspace ws = carve_workspace(plan->g, plan->precision, batch, plan->ws.p);
     if ((s = run_front(plan, seeds, batch, ws, st))) return s;
+    return run_back(plan, 0, nullptr, batch, ws, out_dev, st);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free generation: the workspace lives in a fixed device array of
+// this library (one copy per GPU, kept until the process ends) instead of the
+// plan's own buffer, so that callers that cannot allocate device memory (code
+// under stream capture, serving loops, harnesses that forbid it) can generate.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;   // 64 MiB per GPU
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of the scratch array, looked up once per
+// device with that device current (the array's host-side name is not a device
+// address).
+srm3_status scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dev_err(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SRM3_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return dev_err(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SRM3_OK;
+}
+
+// Profiling records events (and may create them): off for the duration of an
+// allocation-free call.
+struct ProfPause {
+    srm3_plan_t p;
+    bool was;
+    explicit ProfPause(srm3_plan_t plan) : p(plan), was(plan->prof) { p->prof = false; }
+    ~ProfPause() { p->prof = was; }
+};
+
+}  // namespace
+
+extern "C" {
+
+srm3_status srm3_generate_noalloc(srm3_plan_t plan, const uint64_t *seeds, int32_t batch, void *out_dev,
+                                  void *hip_stream)
+{
+    g_err[0] = 0;
+    srm3_status s = check_batch(plan, seeds, batch, out_dev);
+    if (s) return s;
+    if (batch == 0) return SRM3_OK;
+    auto al = [](size_t x) { return (x + 255) & ~static_cast<size_t>(255); };
+    const size_t main_bytes = al(workspace_bytes(plan->g, plan->precision, batch));
+    const size_t need = main_bytes + (kfft_family(plan->algo) ? kfft_workspace_bytes(plan->g, plan->kg,
+                                                                                     plan->precision, batch) : 0);
+    if (need > kScratchBytes)
+        return fail(SRM3_E_UNSUPPORTED, "allocation-free generation of %d realizations needs %zu bytes of "
+                    "workspace; the library's scratch array holds %zu", batch, need, kScratchBytes);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dev_err(e, "hipGetDevice");
+    if (dev != plan->device)
+        return fail(SRM3_E_INVALID, "current device %d is not the plan's device %d", dev, plan->device);
+    void *base = nullptr;
+    if ((s = scratch_address(&base))) return s;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    ProfPause pause(plan);
+    const Workspace ws = carve_workspace(plan->g, plan->precision, batch, base);
+    if (kfft_family(plan->algo)) {
+        // the kappa-DFT stage takes its workspace from the scratch too
+        const KfftWorkspace kw = carve_kfft(plan->g, plan->kg, plan->precision, batch,
+                                            static_cast<char *>(base) + main_bytes);
+        if ((s = run_front_kfft(plan, seeds, batch, ws, kw, st))) return s;
+    } else if ((s = run_front(plan, seeds, batch, ws, st))) {
+        return s;
+    }
     return run_back(plan, 0, nullptr, batch, ws, out_dev, st);
 }
 

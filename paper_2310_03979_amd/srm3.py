@@ -97,6 +97,7 @@ def load():
                             ctypes.POINTER(_Bispectrum), ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.srm3_generate.argtypes = [vp, _u64p, ctypes.c_int32, vp, vp]
     L.srm3_coefficients.argtypes = [vp, _u64p, ctypes.c_int32, vp, vp]
+    L.srm3_generate_noalloc.argtypes = [vp, _u64p, ctypes.c_int32, vp, vp]
     L.srm3_transform.argtypes = [vp, vp, ctypes.c_int32, vp, vp]
     L.srm3_workspace_bytes.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
     L.srm3_workspace_fill.argtypes = [vp, ctypes.c_int32, ctypes.c_uint32, vp]
@@ -125,7 +126,7 @@ def load():
     L.srm3_batch_destroy.argtypes = [vp]
     L.srm3_batch_destroy.restype = None
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
-    for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_product_factors", "srm3_generate", "srm3_coefficients", "srm3_transform",
+    for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_product_factors", "srm3_generate", "srm3_generate_noalloc", "srm3_coefficients", "srm3_transform",
               "srm3_workspace_bytes", "srm3_workspace_fill", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
               "srm3_algorithm_terms", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
@@ -292,6 +293,17 @@ def srm3_generate(plan: Plan, seeds: Sequence[int], out, stream=None):
     _check_tensor(out, plan.real_dtype, s.size * nx * nt, "out")
     _check(load().srm3_generate(plan.handle, s.ctypes.data_as(_u64p), s.size,
                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def srm3_generate_noalloc(plan: Plan, seeds: Sequence[int], out, stream=None):
+    """srm3_generate with the workspace in the library's fixed scratch array
+    (no device allocation; calls on one GPU must not overlap)."""
+    s = _seeds(seeds)
+    nx, nt = plan.field_shape
+    _check_tensor(out, plan.real_dtype, s.size * nx * nt, "out")
+    _check(load().srm3_generate_noalloc(plan.handle, s.ctypes.data_as(_u64p), s.size,
+                                        ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 
