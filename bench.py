@@ -41,7 +41,6 @@ FMA_ISSUE_FP32_TFLOPS = 78.6  # non-packed FP32 FMA issue rate: 256 CUs x 4 SIMD
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR_TERM = 14      # complex product z_i z_j (6) x W (6) + accumulate (2)
 MFMA_FLOPS_PER_PAIR_TERM = 6  # the matrix cores' share: three real products (Gauss form), each a multiply-add
-MFMA_KERNEL = "pairsum_mfma_kernel<float,2,2> (v_mfma_f32_16x16x4_f32)"
 
 
 def log(*a):
@@ -60,6 +59,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--mfma-shape", type=int, default=0,
+                    help="tile shape of the matrix-core pair sum (0: default; see srm3_plan_set_mfma_shape)")
     ap.add_argument("--pair-kernel", default="mfma", choices=["mfma", "vector"],
                     help="FP32 pair sum of the measured step: matrix cores or vector ALUs")
     ap.add_argument("--no-serve", action="store_true",
@@ -212,7 +213,7 @@ def pair_terms_total(wl):
 
 def mfma_instructions(wl, rows=32, cols=32):
     """16x16x4 MFMAs the matrix-core pair sum issues per realization: for each
-    wave (32 kappa rows x 32 frequencies), partner steps of 4 columns times
+    wave (rows kappa rows x cols frequencies), partner steps of 4 columns times
     three MFMAs per 16x16 tile and kappa split, skipping a 16-row tile whose
     rows all lie below 2 j_kappa.  Work items with no partner issue none."""
     nk, nw, W = wl.n_kappa, wl.n_omega, wl.support_w
@@ -344,6 +345,13 @@ def bench_uneven(args, torch, srm3):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     info = batch.info()
+    # the untuned default (shape 0, default workgroups per CU), replayed as a graph
+    dflt = srm3.Batch(reqs, flags=srm3.SRM3_BATCH_GRAPH)
+    dtd = timed_steps(torch, lambda: dflt.run(seeds), args.steps, max(1, args.warmup))
+    rec_default = {"ms_per_step": round(dtd * 1e3, 3), "tuned_over_default": round(dtd / dt, 3),
+                   "tile": {k: dflt.info()[k] for k in ("rows_per_wave", "blocks_per_cu", "mfma_shape")}}
+    log(f"[bench] untuned default: {dtd * 1e3:.1f} ms/step")
+    del dflt
     # the pair-sum launch alone, same tile shape, direct (non-graph) run
     direct = srm3.Batch(reqs, flags=srm3.SRM3_BATCH_AUTOTUNE)
     direct.run(seeds)
@@ -401,7 +409,10 @@ def bench_uneven(args, torch, srm3):
                       "flops_per_pair_term": MFMA_FLOPS_PER_PAIR_TERM,
                       "pair_terms_per_launch": terms, "avg_launch_ms": round(ps_ms, 3)}),
         "pair_sum_complex_form_tflops": round(FLOPS_PER_PAIR_TERM * terms / (ps_ms * 1e-3) / 1e12, 3),
-        "tile": {k: info[k] for k in ("rows_per_wave", "blocks_per_cu", "work_items", "groups")},
+        "tile": dict({k: info[k] for k in ("rows_per_wave", "blocks_per_cu", "work_items", "groups", "mfma_shape")},
+                     **({"mfma_outputs_per_wave": "%d x %d" % srm3.srm3_mfma_shape("fp32", info["mfma_shape"])}
+                        if mfma else {})),
+        "untuned_default": rec_default,
         "cpu_baseline": None,
     }
     if rec_plain:
@@ -737,7 +748,7 @@ def bench_bridge(args, torch, srm3):
                                f"wind bispectrum alpha {wl.alpha} through the partial-bicoherence recursion, "
                                f"cap {wl.cap}, {B} realizations"},
         "roofline": {"bound": "mfma" if mfma else "alu",
-                     "kernel": MFMA_KERNEL if mfma else "pairsum_kernel<float,8,true>",
+                     "kernel": "pairsum_mfma_kernel<float,2,2>" if mfma else "pairsum_kernel<float,8,true>",
                      "achieved": round(tf, 3), "peak": PEAK_FP32_MFMA_TFLOPS if mfma else FMA_ISSUE_FP32_TFLOPS,
                      "unit": "TFLOP/s",
                      "frac": round(tf / (PEAK_FP32_MFMA_TFLOPS if mfma else FMA_ISSUE_FP32_TFLOPS), 4),
@@ -791,6 +802,8 @@ def main():
     mfma = args.pair_kernel == "mfma"
     if mfma:
         srm3.srm3_plan_set_algorithm(plan32, "mfma")
+        srm3.srm3_plan_set_mfma_shape(plan32, args.mfma_shape)
+    mrows, mcols = srm3.srm3_mfma_shape("fp32", args.mfma_shape)
     out32 = torch.empty((B, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
     terms = srm3.srm3_pair_terms(plan32)
 
@@ -816,7 +829,8 @@ def main():
         achieved_tflops = MFMA_FLOPS_PER_PAIR_TERM * terms * B / (ps_ms * 1e-3) / 1e12
         roofline = {
             "bound": "mfma",
-            "kernel": MFMA_KERNEL,
+            "kernel": f"pairsum_mfma_kernel<float,{mrows // 16},{mcols // 16}> (v_mfma_f32_16x16x4_f32)",
+            "tile": f"{mrows} kappa rows x {mcols} frequencies per wave",
             "achieved": round(achieved_tflops, 3),
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
@@ -828,8 +842,8 @@ def main():
             "avg_launch_ms": round(ps_ms, 4),
             "pair_terms_per_s": terms * B / (ps_ms * 1e-3),
             # products issued, masked triangle and partner padding included
-            "mfma_instructions_per_launch": mfma_instructions(wl) * B,
-            "useful_product_frac": round(terms / (mfma_instructions(wl) / 3 * 1024), 4),
+            "mfma_instructions_per_launch": mfma_instructions(wl, mrows, mcols) * B,
+            "useful_product_frac": round(terms / (mfma_instructions(wl, mrows, mcols) / 3 * 1024), 4),
         }
     else:
         # the vector kernel issues 3 FMAs (6 flops) per pair term; packed FP32 is
@@ -903,7 +917,7 @@ def main():
                         "fma_issue_ceiling_tflops": FMA_ISSUE_FP32_TFLOPS,
                         "valu_issue_frac": counter_valu(wl, "vector") if full else None})
         else:
-            leg.update({"kernel": MFMA_KERNEL, "bound": "mfma",
+            leg.update({"kernel": f"pairsum_mfma_kernel<float,{mrows // 16},{mcols // 16}>", "bound": "mfma",
                         "frac_of_fp32_matrix_peak": round(vtf / PEAK_FP32_MFMA_TFLOPS, 4)})
         extra[f"{other}_pairsum"] = leg
         plans[f"fp32_{other}"] = planv

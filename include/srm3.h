@@ -285,6 +285,18 @@ srm3_status srm3_rows_per_wave(srm3_plan_t plan, int32_t *rows);
 enum { SRM3_ALGO_DIRECT = 0, SRM3_ALGO_KAPPA_FFT = 1, SRM3_ALGO_FFT2D = 2, SRM3_ALGO_MFMA = 3 };
 srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *hip_stream);
 
+/* Tile shape of the matrix-core pair sum (SRM3_ALGO_MFMA) used by
+ * srm3_generate / srm3_coefficients on this plan: each wave owns `rows` kappa
+ * rows x `cols` frequency columns of outputs (srm3_mfma_shape tells them for a
+ * precision): shape 0 (the default) 32 x 32, shape 1 32 x 16, shape 2
+ * 16 x 32, in FP32 and FP64.  The smaller tiles leave more waves resident per
+ * SIMD and fit grids with few rows or columns better; every shape sums the same
+ * pair terms, so results agree up to rounding.  Uneven batches created with
+ * SRM3_BATCH_AUTOTUNE pick their shape by timing.  Errors: SRM3_E_INVALID (NULL
+ * plan, shape outside 0..2). */
+srm3_status srm3_plan_set_mfma_shape(srm3_plan_t plan, int32_t shape);
+srm3_status srm3_mfma_shape(int32_t precision, int32_t shape, int32_t *rows, int32_t *cols);
+
 /* Complex multiply-accumulate terms the plan's current pair-sum algorithm
  * evaluates per realization (SRM3_ALGO_DIRECT and SRM3_ALGO_MFMA: the pair
  * terms). */
@@ -404,10 +416,11 @@ typedef struct {
     double pair_terms;      /* unordered pair terms over all requests */
     double run_ms;          /* device time of the last run (HIP events), -1 if none */
     double pairsum_ms;      /* pair-sum launch time of the last non-graph run, else -1 */
-    int32_t rows_per_wave;  /* tile shape in use */
+    int32_t rows_per_wave;  /* tile shape in use (vector-ALU pair sum) */
     int32_t blocks_per_cu;  /* persistent workgroups per compute unit */
     int32_t work_items;
     int32_t groups;         /* distinct plans */
+    int32_t mfma_shape;     /* matrix-core tile shape in use (see srm3_plan_set_mfma_shape), -1 for vector items */
 } srm3_batch_stats;
 srm3_status srm3_batch_info(srm3_batch_t batch, srm3_batch_stats *out); /* waits for the last run */
 void srm3_batch_destroy(srm3_batch_t batch);   /* NULL is a no-op */
@@ -445,6 +458,7 @@ typedef struct {
     int32_t pair_kernel;      /* SRM3_ALGO_DIRECT (0: vector ALUs) or SRM3_ALGO_MFMA (matrix cores): the
                                  kernel of the per-step persistent pair-sum launch; direct-form requests
                                  must have plans with this algorithm (else SRM3_E_UNSUPPORTED) */
+    int32_t mfma_shape;       /* matrix-core tile shape of those launches (0..2, see srm3_plan_set_mfma_shape) */
 } srm3_server_config;
 
 typedef struct {

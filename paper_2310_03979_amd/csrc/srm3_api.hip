@@ -217,7 +217,7 @@ srm3_status run_front_kfft(srm3_plan_t p, const uint64_t *seeds, int32_t batch, 
         e = launch_kfft_pairsum(p->precision, p->g, p->kg, plan_ktab(p), batch, ws, kw, st);
         if (e != hipSuccess) return dev_err(e, "kappa-FFT pair-sum kernels");
     } else if (p->algo == SRM3_ALGO_MFMA) {
-        e = launch_pairsum_mfma(p->g, p->precision, p->wtab.p, batch, ws, st);
+        e = launch_pairsum_mfma(p->g, p->precision, p->mfma_shape, p->wtab.p, batch, ws, st);
         if (e != hipSuccess) return dev_err(e, "matrix-core pair-sum kernel");
     } else {
         e = launch_pairsum(p->g, p->precision, p->wtab.p, batch, ws, st);
@@ -236,13 +236,13 @@ srm3_status run_front(srm3_plan_t p, const uint64_t *seeds, int32_t batch, const
 }
 
 srm3_status run_back(srm3_plan_t p, int mode, const void *cin, int32_t batch, const Workspace &ws, void *out,
-                     hipStream_t st)
+                     hipStream_t st, const uint64_t *seeds = nullptr)
 {
     srm3_status s;
     if ((s = event_pair(p, 2, st, true))) return s;
     const bool direct_out = p->g.nx == 1 && p->g.nk == 1;   // the x-transform is the real part
     hipError_t e = launch_tfft(p->g, p->precision, mode, cin, plan_amp(p), p->wtab.p, p->tw_t.p, batch, ws, st,
-                               direct_out ? out : nullptr);
+                               direct_out ? out : nullptr, seeds);
     if (e != hipSuccess) return dev_err(e, "t-transform kernel");
     if ((s = event_pair(p, 2, st, false))) return s;
     if (direct_out) return SRM3_OK;
@@ -820,6 +820,26 @@ srm3_status srm3_plan_set_algorithm(srm3_plan_t plan, int32_t algorithm, void *h
     return SRM3_OK;
 }
 
+srm3_status srm3_plan_set_mfma_shape(srm3_plan_t plan, int32_t shape)
+{
+    g_err[0] = 0;
+    if (!plan) return fail(SRM3_E_INVALID, "plan is NULL");
+    if (shape < 0 || shape >= kMfmaShapes) return fail(SRM3_E_INVALID, "matrix-core tile shape %d", shape);
+    plan->mfma_shape = shape;
+    return SRM3_OK;
+}
+
+srm3_status srm3_mfma_shape(int32_t precision, int32_t shape, int32_t *rows, int32_t *cols)
+{
+    if (shape < 0 || shape >= kMfmaShapes || !rows || !cols ||
+        (precision != SRM3_FP32 && precision != SRM3_FP64))
+        return fail(SRM3_E_INVALID, "bad argument");
+    const MfmaShape m = mfma_shape(precision, shape);
+    *rows = 16 * m.rt;
+    *cols = 16 * m.ct;
+    return SRM3_OK;
+}
+
 srm3_status srm3_algorithm_terms(srm3_plan_t plan, double *terms)
 {
     if (!plan || !terms) return fail(SRM3_E_INVALID, "bad argument");
@@ -836,6 +856,8 @@ srm3_status srm3_generate(srm3_plan_t plan, const uint64_t *seeds, int32_t batch
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if ((s = ensure_workspace(plan, batch, st))) return s;
     const Workspace ws = carve_workspace(plan->g, plan->precision, batch, plan->ws.p);
+    // zero bicoherence: the t-transform draws the phases itself (no phase rows)
+    if (plan->gaussian && !plan->lr.p) return run_back(plan, 2, nullptr, batch, ws, out_dev, st, seeds);
     if ((s = run_front(plan, seeds, batch, ws, st))) return s;
     return run_back(plan, 0, nullptr, batch, ws, out_dev, st);
 }
@@ -919,6 +941,8 @@ srm3_status srm3_generate_noalloc(srm3_plan_t plan, const uint64_t *seeds, int32
         const KfftWorkspace kw = carve_kfft(plan->g, plan->kg, plan->precision, batch,
                                             static_cast<char *>(base) + main_bytes);
         if ((s = run_front_kfft(plan, seeds, batch, ws, kw, st))) return s;
+    } else if (plan->gaussian && !plan->lr.p) {
+        return run_back(plan, 2, nullptr, batch, ws, out_dev, st, seeds);
     } else if ((s = run_front(plan, seeds, batch, ws, st))) {
         return s;
     }
@@ -1006,6 +1030,7 @@ struct srm3_batch_s {
     std::vector<Group> groups;
     int R = 0;                         // rows per wave of the persistent launch
     bool mfma = false;                 // its items are those of the matrix-core pair sum
+    int mfma_shape = 0;                // and their tile shape
     int blocks_per_cu = 2;
     int n_cu = 256;
     DevBuf ws, seeds, scales, sptr, outs, preq, pitem, qbegin, qnext;
@@ -1045,9 +1070,10 @@ double item_cost_impl(const Geometry &g, int R, int kb, int cg)
 
 // Relative cost of a matrix-core item (row group kb, column group cg): its
 // kappa splits times the widest partner range of its waves' column tiles.
-double mfma_item_cost_impl(const Geometry &g, int kb, int cg)
+double mfma_item_cost_impl(const Geometry &g, int kb, int cg, int precision, int shape)
 {
-    const int rows = mfma_rows_per_group(), cols = mfma_cols_per_group(), wcols = cols / waves_per_block();
+    const int rows = mfma_rows_per_group(precision, shape), cols = mfma_cols_per_group(precision, shape);
+    const int wcols = cols / waves_per_block();
     int widest = 0;
     for (int c0 = cg * cols; c0 < std::min(g.nc, (cg + 1) * cols); c0 += wcols) {
         const int kw_lo = c0 - (g.nw - 1);
@@ -1106,8 +1132,10 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
                                              static_cast<char *>(b->ws.p) + gr.ws_off);
         const size_t lines = static_cast<size_t>(gr.g.nk) * gr.g.nc;
         const size_t plane3 = a_slots(b->precision) * gr.g.ncw * gr.g.nkp;
-        const int nrb = b->mfma ? (gr.g.nk + mfma_rows_per_group() - 1) / mfma_rows_per_group() : gr.g.nkp / gr.g.R;
-        const int ncg = b->mfma ? (gr.g.nc + mfma_cols_per_group() - 1) / mfma_cols_per_group()
+        const int mr = mfma_rows_per_group(b->precision, b->mfma_shape);
+        const int mc = mfma_cols_per_group(b->precision, b->mfma_shape);
+        const int nrb = b->mfma ? (gr.g.nk + mr - 1) / mr : gr.g.nkp / gr.g.R;
+        const int ncg = b->mfma ? (gr.g.nc + mc - 1) / mc
                                 : ((gr.g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
         if (gr.mode != 0) continue;   // no items in the persistent launch
         for (size_t slot = 0; slot < gr.members.size(); ++slot) {
@@ -1117,7 +1145,8 @@ srm3_status batch_layout(srm3_batch_t b, int R, hipStream_t st)
                                 static_cast<char *>(ws.tsum) + slot * lines * 2 * e, gr.plan->wtab.p);
             for (int kb = nrb - 1; kb >= 0; --kb)
                 for (int cg = 0; cg < ncg; ++cg) {
-                    const double c = b->mfma ? mfma_item_cost_impl(gr.g, kb, cg) : item_cost_impl(gr.g, gr.g.R, kb, cg);
+                    const double c = b->mfma ? mfma_item_cost_impl(gr.g, kb, cg, b->precision, b->mfma_shape)
+                                             : item_cost_impl(gr.g, gr.g.R, kb, cg);
                     per_req[d].push_back({d, kb, cg, c});
                     req_cost[d] += c;
                 }
@@ -1186,7 +1215,7 @@ srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
     if (b->n_items > 0) {
         e = launch_pairsum_persistent(b->precision, b->R, b->preq.p, b->pitem.p,
                                       static_cast<const int *>(b->qbegin.p), static_cast<int *>(b->qnext.p),
-                                      b->n_cu * b->blocks_per_cu, st, b->mfma);
+                                      b->n_cu * b->blocks_per_cu, st, b->mfma, b->mfma_shape);
         if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
     }
     if (time_pairsum) (void)hipEventRecord(b->ev_b, st);
@@ -1244,7 +1273,9 @@ std::string batch_signature(srm3_batch_t b)
     return o.str();
 }
 
-bool tune_lookup(const std::string &sig, int *R, int *bpc)
+// Cache lines: signature, rows per wave, workgroups per CU, matrix-core tile
+// shape (a missing shape reads as 0).
+bool tune_lookup(const std::string &sig, int *R, int *bpc, int *shape)
 {
     std::ifstream f(tune_cache_path());
     std::string line;
@@ -1252,30 +1283,35 @@ bool tune_lookup(const std::string &sig, int *R, int *bpc)
     while (std::getline(f, line)) {
         std::istringstream ls(line);
         std::string s;
-        int r, c;
+        int r, c, m = 0;
         if (ls >> s >> r >> c && s == sig) {
+            if (!(ls >> m) || m < 0 || m >= kMfmaShapes) m = 0;
             *R = r;
             *bpc = c;
+            *shape = m;
             found = true;
         }
     }
     return found;
 }
 
-void tune_store(const std::string &sig, int R, int bpc)
+void tune_store(const std::string &sig, int R, int bpc, int shape)
 {
     const std::string path = tune_cache_path();
     const size_t slash = path.rfind('/');
     if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
     std::ofstream f(path, std::ios::app);
-    if (f) f << sig << ' ' << R << ' ' << bpc << '\n';
+    if (f) f << sig << ' ' << R << ' ' << bpc << ' ' << shape << '\n';
 }
 
 }  // namespace
 
 namespace srm3 {
 double item_cost(const Geometry &g, int R, int kb, int cg) { return item_cost_impl(g, R, kb, cg); }
-double mfma_item_cost(const Geometry &g, int kb, int cg) { return mfma_item_cost_impl(g, kb, cg); }
+double mfma_item_cost(const Geometry &g, int kb, int cg, int precision, int shape)
+{
+    return mfma_item_cost_impl(g, kb, cg, precision, shape);
+}
 }  // namespace srm3
 
 extern "C" {
@@ -1367,22 +1403,30 @@ srm3_status srm3_batch_create(const srm3_request *reqs, int32_t n, int32_t flags
 
 // Time the candidate tile shapes on a stride sample of the batch (requests
 // sorted by cost) and keep the fastest; the choice is cached by signature.
+// Vector-ALU batches: rows per wave {R_max, R_max / 2} x workgroups per CU
+// {1, 2, 3, 4}.  Matrix-core batches: the tile shapes (32 x 32, 32 x 16 and
+// 16 x 32 outputs per wave) x workgroups per CU {2, 3, 4, 5} (the smaller
+// tiles leave room for more resident waves).
 static srm3_status batch_autotune(srm3_batch_t b, hipStream_t st)
 {
     const std::string sig = batch_signature(b);
-    int R = b->R, bpc = b->blocks_per_cu;
-    if (tune_lookup(sig, &R, &bpc)) {
+    int R = b->R, bpc = b->blocks_per_cu, shape = b->mfma_shape;
+    if (tune_lookup(sig, &R, &bpc, &shape)) {
         b->blocks_per_cu = bpc;
-        return R == b->R ? SRM3_OK : batch_layout(b, R, st);
+        if (R == b->R && shape == b->mfma_shape) return SRM3_OK;
+        b->mfma_shape = shape;
+        return batch_layout(b, R, st);
     }
-    // Sample every 8th request in cost order (all of them for small batches):
-    // about an eighth of the work, with the same mix of grid sizes, so that
-    // the number of work items per workgroup slot stays close to the batch's.
+    // Sample every 4th request in cost order (all of them for small batches):
+    // about a quarter of the work, with the same mix of grid sizes.  A
+    // candidate replaces the default only if it beats it by 3 % on the sample
+    // (the sample's queues are shorter than the batch's, so small wins there
+    // need not carry over).
     std::vector<int> order(b->n);
     for (int i = 0; i < b->n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->req[x].plan->pair_terms > b->req[y].plan->pair_terms; });
-    const int stride = b->n >= 64 ? 8 : 1;
+    const int stride = b->n >= 64 ? 4 : 1;
     std::vector<srm3_request> sub;
     for (int i = stride / 2; i < b->n; i += stride) sub.push_back(b->req[order[i]]);
     if (sub.empty()) sub.push_back(b->req[order[0]]);
@@ -1390,36 +1434,60 @@ static srm3_status batch_autotune(srm3_batch_t b, hipStream_t st)
     srm3_status s = srm3_batch_create(sub.data(), static_cast<int32_t>(sub.size()), 0, st, &t);
     if (s) return s;
     const int Rmax = t->R;
-    float best = 1e30f;
-    int bestR = Rmax, bestC = t->blocks_per_cu;
-    for (int r : {Rmax, Rmax / 2}) {
-        if (r < 2) continue;
-        if (r != t->R && (s = batch_layout(t, r, st))) break;
-        for (int c : {1, 2, 3, 4}) {
-            t->blocks_per_cu = c;
-            float ms = 0.f;
-            const int reps = (r == Rmax && c == 1) ? 2 : 1;   // the first launch also warms up
-            for (int rep = 0; rep < reps && !s; ++rep) {
-                if ((s = batch_copy_seeds(t, nullptr, st))) break;
-                if ((s = batch_launch(t, st, true))) break;
-                hipError_t e = hipStreamSynchronize(st);
-                if (e != hipSuccess) s = dev_err(e, "hipStreamSynchronize");
-                else (void)hipEventElapsedTime(&ms, t->ev_a, t->ev_b);
-            }
-            if (s) break;
-            if (ms < best) {
-                best = ms;
-                bestR = r;
-                bestC = c;
-            }
+    const int defC = t->blocks_per_cu;
+    float best = 1e30f, base = 1e30f;
+    int bestR = Rmax, bestC = defC, bestM = 0;
+    bool first = true;
+    auto trial = [&](int r, int m, int c) -> srm3_status {
+        if (r != t->R || m != t->mfma_shape) {
+            t->mfma_shape = m;
+            srm3_status e = batch_layout(t, r, st);
+            if (e) return e;
         }
-        if (s) break;
+        t->blocks_per_cu = c;
+        float ms = 0.f;
+        const int reps = first ? 2 : 1;   // the first launch also warms up
+        first = false;
+        for (int rep = 0; rep < reps; ++rep) {
+            srm3_status e = batch_copy_seeds(t, nullptr, st);
+            if (!e) e = batch_launch(t, st, true);
+            if (e) return e;
+            hipError_t he = hipStreamSynchronize(st);
+            if (he != hipSuccess) return dev_err(he, "hipStreamSynchronize");
+            (void)hipEventElapsedTime(&ms, t->ev_a, t->ev_b);
+        }
+        if (r == Rmax && m == 0 && c == defC) base = ms;
+        if (ms < best) {
+            best = ms;
+            bestR = r;
+            bestC = c;
+            bestM = m;
+        }
+        return SRM3_OK;
+    };
+    s = trial(Rmax, 0, defC);   // the default first
+    if (t->mfma) {
+        for (int m = 0; m < kMfmaShapes && !s; ++m)
+            for (int c : {2, 3, 4, 5})
+                if (!(m == 0 && c == defC) && (s = trial(Rmax, m, c))) break;
+    } else {
+        for (int r : {Rmax, Rmax / 2}) {
+            if (r < 2 || s) continue;
+            for (int c : {1, 2, 3, 4})
+                if (!(r == Rmax && c == defC) && (s = trial(r, 0, c))) break;
+        }
     }
     srm3_batch_destroy(t);
     if (s) return s;
-    if (bestR != b->R && (s = batch_layout(b, bestR, st))) return s;
+    if (!(best < 0.97f * base)) {
+        bestR = Rmax;
+        bestC = defC;
+        bestM = 0;
+    }
+    b->mfma_shape = bestM;
+    if ((bestR != b->R || b->mfma) && (s = batch_layout(b, bestR, st))) return s;
     b->blocks_per_cu = bestC;
-    tune_store(sig, bestR, bestC);
+    tune_store(sig, bestR, bestC, bestM);
     return SRM3_OK;
 }
 
@@ -1473,6 +1541,7 @@ srm3_status srm3_batch_info(srm3_batch_t b, srm3_batch_stats *out)
     out->pair_terms = b->pair_terms;
     out->rows_per_wave = b->R;
     out->blocks_per_cu = b->blocks_per_cu;
+    out->mfma_shape = b->mfma ? b->mfma_shape : -1;
     out->work_items = b->n_items;
     out->groups = static_cast<int32_t>(b->groups.size());
     out->run_ms = -1.0;

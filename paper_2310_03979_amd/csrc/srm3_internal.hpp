@@ -116,9 +116,15 @@ hipError_t launch_phases(const Geometry &g, int precision, const uint64_t *seeds
 hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, int batch,
                           const Workspace &ws, hipStream_t st);
 // The same pair sum on the matrix cores: dense products over the partner
-// frequency for each kappa split.
-hipError_t launch_pairsum_mfma(const Geometry &g, int precision, const void *wtab, int batch, const Workspace &ws,
-                               hipStream_t st);
+// frequency for each kappa split.  A wave owns rt x ct tiles of 16 x 16
+// outputs; `shape` picks one of kMfmaShapes per precision (0: the default).
+struct MfmaShape {
+    int rt, ct;
+};
+constexpr int kMfmaShapes = 3;
+MfmaShape mfma_shape(int precision, int shape);
+hipError_t launch_pairsum_mfma(const Geometry &g, int precision, int shape, const void *wtab, int batch,
+                               const Workspace &ws, hipStream_t st);
 // Bispectrum generated per pair inside the kernel (hashed b^2 and beta).  With
 // ws == nullptr it writes the per-line raw sums sum b^2_raw to sig (FP64).
 hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, double scale, int batch,
@@ -126,10 +132,10 @@ hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, d
 // Persistent pair sum over a device work list (all requests share R).
 // mfma: items of the matrix-core pair sum (see mfma_rows_per_group).
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
-                                     int *q_next, int nblocks, hipStream_t st, bool mfma = false);
+                                     int *q_next, int nblocks, hipStream_t st, bool mfma = false, int shape = 0);
 // Output rows and columns of one matrix-core work item (a block of waves).
-int mfma_rows_per_group();
-int mfma_cols_per_group();
+int mfma_rows_per_group(int precision, int shape);
+int mfma_cols_per_group(int precision, int shape);
 size_t persistent_req_bytes();
 size_t persistent_item_bytes();
 void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const void *zcol, void *tsum,
@@ -139,12 +145,14 @@ int waves_per_block();
 // 32-bit fill of device memory by a kernel (graph-safe, unlike hipMemsetAsync)
 hipError_t launch_fill_u32(void *p, size_t words, uint32_t v, hipStream_t st);
 constexpr int kXcds = 8;
-// mode 0: assemble C from pair sums and phases; mode 1: read C from `cin`.
+// mode 0: assemble C from pair sums and phases; mode 1: read C from `cin`;
+// mode 2 (zero bicoherence): C = A_pure e^{i phi} with the phases drawn here
+// from the host `seeds` (no phase rows are read).
 // rout (n_x == n_kappa == 1 only, else ignored): write the real field [B][n_t]
 // directly; the x-transform is then skipped.
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
                        const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st,
-                       void *rout = nullptr);
+                       void *rout = nullptr, const uint64_t *seeds = nullptr);
 hipError_t launch_assemble(const Geometry &g, int precision, const AmpRef &amp, const void *wtab, int batch,
                            const Workspace &ws, void *cout, hipStream_t st);
 hipError_t launch_xfft(const Geometry &g, int precision, const void *tw, int batch, const Workspace &ws,
@@ -224,7 +232,7 @@ double max_sigma(double max_sig, double cap, double scale);
 int rows_for(int nk, int precision, int R_pref);
 // Relative cost of pair-sum work item (row block kb, column group cg).
 double item_cost(const Geometry &g, int R, int kb, int cg);
-double mfma_item_cost(const Geometry &g, int kb, int cg);
+double mfma_item_cost(const Geometry &g, int kb, int cg, int precision, int shape);
 
 }  // namespace srm3
 
@@ -245,6 +253,7 @@ struct srm3_plan_s {
     double hash_scale = 0;
     // pair-sum algorithm; the kappa-FFT form keeps its tables and workspace here
     int algo = SRM3_ALGO_DIRECT;
+    int mfma_shape = 0;   // tile shape of the matrix-core pair sum
     srm3::KfftGeom kg{};
     srm3::DevBuf wsh, tw_k, kws;
     srm3::DevBuf gw, tw_l;   // rank-one weights (SRM3_ALGO_FFT2D): sqrt(g2) and length-L twiddles

@@ -862,11 +862,9 @@ __global__ __launch_bounds__(256) void pairsum_persistent(PersistArgs a)
     }
 }
 
-// The same queues with matrix-core items: (request, row group of 16 kMfmaRT
-// rows, column group of kWavesPerBlock x 16 kMfmaCT columns).
-constexpr int kMfmaRT = 2, kMfmaCT = 2;
-
-template <typename T>
+// The same queues with matrix-core items: (request, row group of 16 RT rows,
+// column group of kWavesPerBlock x 16 CT columns).
+template <typename T, int RT, int CT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void pairsum_persistent_mfma(PersistArgs a)
 {
     using T2 = typename vec<T>::v2;
@@ -894,11 +892,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void p
         if (it < 0) break;
         const PItem w = a.items[it];
         const PReq rq = a.reqs[w.req];
-        const int c0 = (w.cg * kWavesPerBlock + wave) * 16 * kMfmaCT;
+        const int c0 = (w.cg * kWavesPerBlock + wave) * 16 * CT;
         if (c0 < rq.g.nc)
-            mfma_tile<T, kMfmaRT, kMfmaCT>(rq.g, static_cast<const T2 *>(rq.zrow), static_cast<const T *>(rq.zcol),
-                                           static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, c0,
-                                           kMfmaFlushSteps);
+            mfma_tile<T, RT, CT>(rq.g, static_cast<const T2 *>(rq.zrow), static_cast<const T *>(rq.zcol),
+                                 static_cast<const T2 *>(rq.wtab), static_cast<T2 *>(rq.tsum), w.kb, c0,
+                                 kMfmaFlushSteps);
     }
 }
 
@@ -1027,16 +1025,21 @@ struct AmpArgs {
 
 struct TfftArgs {
     Geometry g;
-    int mode;
+    int mode;             // 0: assemble from pair sums and phase rows; 1: read C; 2: zero bicoherence,
+                          // the phase factors generated here (no phase rows)
     const void *cin;      // mode 1: [B][nk][nc]
     const void *zrow;     // mode 0
     const void *tsum;     // mode 0
+    SeedChunk seeds;      // mode 2: seeds of realizations b0 .. b0 + 255 (or seeds_dev)
+    const uint64_t *seeds_dev;
+    int b0;
     AmpArgs amp;
     const void *wtab;     // [ncw][ncw]
     const void *tw;       // [nt]
-    void *gout;           // [B][nk][nt]
+    void *gout;           // [B][nt / xtw][nk][xtw]: t-transformed rows in tiles of xtw columns
     void *rout;           // n_x == 1 only, or null: the field itself, [B][nt] real (no x-transform)
     int tw_lds;           // 1: the twiddles are copied to LDS after the row
+    int xtw;              // columns per tile of gout (the x-transform's tile width)
 };
 
 // Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
@@ -1109,7 +1112,7 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
     extern __shared__ unsigned char smem_raw[];
     T2 *buf = reinterpret_cast<T2 *>(smem_raw);
     const Geometry &g = a.g;
-    const int row = blockIdx.x;                 // b * nk + kk
+    const int row = blockIdx.x;                 // b * nk + kk (b within the launch's chunk)
     const int b = row / g.nk, kk = row - b * g.nk;
     for (int n = threadIdx.x; n < g.nt; n += blockDim.x) {
         T2 zero;
@@ -1126,7 +1129,19 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         const int kw = c - (g.nw - 1);
         const int bin = kw < 0 ? kw + g.nt : kw;
         T2 C;
-        if (a.mode == 0) {
+        if (a.mode == 2) {
+            // C = A_pure e^{i phi}: the phase of the line as the phase kernel
+            // draws it (Philox word, FP64 sincos, rounded)
+            const uint64_t seed = a.seeds_dev ? a.seeds_dev[a.b0 + b] : a.seeds.s[b];
+            const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
+            double sn, cs;
+            sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &sn, &cs);
+            const long li = static_cast<long>(kk) * g.nc + c;
+            const double *Sp = (a.amp.S_b && a.amp.S_b[b]) ? a.amp.S_b[b] : a.amp.S;
+            const T p = static_cast<T>(2.0 * sqrt(Sp[li] * a.amp.dkdw));
+            C.x = p * static_cast<T>(cs);
+            C.y = p * static_cast<T>(sn);
+        } else if (a.mode == 0) {
             C = assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::v2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
                                  a.amp, static_cast<const T2 *>(a.wtab));
         } else {
@@ -1142,8 +1157,13 @@ __global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
         for (int n = threadIdx.x; n < g.nt; n += blockDim.x) u[n] = buf[n].x;
         return;
     }
-    T2 *gout = static_cast<T2 *>(a.gout) + static_cast<long>(row) * g.nt;
-    for (int n = threadIdx.x; n < g.nt; n += blockDim.x) gout[n] = buf[n];
+    // tile-major rows: the x-transform of a tile then reads one contiguous block
+    const int xtw = a.xtw;
+    T2 *gout = static_cast<T2 *>(a.gout) + static_cast<long>(b) * g.nk * g.nt + static_cast<long>(kk) * xtw;
+    for (int n = threadIdx.x; n < g.nt; n += blockDim.x) {
+        const int tile = n / xtw;
+        gout[static_cast<long>(tile) * g.nk * xtw + (n - tile * xtw)] = buf[n];
+    }
 }
 
 template <typename T>
@@ -1164,14 +1184,22 @@ __global__ __launch_bounds__(256) void assemble_kernel(TfftArgs a, typename vec<
 
 struct XfftArgs {
     Geometry g;
-    int tcols;           // columns (t samples) per block
-    const void *gin;     // [B][nk][nt]
+    int tcols;           // columns (t samples) per block: one tile of gin
+    const void *gin;     // [B][nt / tcols][nk][tcols]
     const void *tw;      // [nx]
     void *out;           // [B][nx][nt] real
     void *const *out_b;  // per realization output, or null (out + b * nx * nt)
     int tw_lds;          // 1: the twiddles are copied to LDS after the tile (low-latency stage reads)
+    int ld;              // LDS elements between two packed transforms (>= nx)
 };
 
+// The x-transform takes the real part, so two columns share one complex
+// transform: with a_1, a_2 the columns (non-zero at kk < nk <= nx / 2) and
+// y_j[n] = (a_j[n] + conj a_j[nx - n]) / 2 (Hermitian, so its inverse DFT is
+// Re IDFT(a_j)), the inverse DFT of z = y_1 + i y_2 holds column 1's field in
+// its real part and column 2's in its imaginary part.  One block transforms
+// one tile of tcols columns (a contiguous block of gin) in tcols / 2 packed
+// transforms.
 template <typename T, int MAXB>
 __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
 {
@@ -1180,31 +1208,76 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
     T2 *buf = reinterpret_cast<T2 *>(smem_raw);
     const Geometry &g = a.g;
     const int b = blockIdx.y;
-    const int mt0 = blockIdx.x * a.tcols;
     const int tc = a.tcols;
-    const int ld = g.nx;
-    for (int n = threadIdx.x; n < tc * g.nx; n += blockDim.x) {
-        T2 zero;
-        zero.x = T(0);
-        zero.y = T(0);
-        buf[n] = zero;
-    }
-    T2 *twl = buf + tc * ld;
+    const int np = (tc + 1) / 2;   // packed transforms (a single column when tc == 1)
+    const int mt0 = blockIdx.x * tc;
+    const int N = g.nx;
+    const int nk = g.nk;
+    const int ld = a.ld;   // transforms N + 8 apart: consecutive transforms start 16 banks apart
+    T2 *twl = buf + np * ld;
     const bool twin = a.tw_lds;
     if (twin)
-        for (int n = threadIdx.x; n < g.nx; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
-    __syncthreads();
-    const T2 *gin = static_cast<const T2 *>(a.gin) + static_cast<long>(b) * g.nk * g.nt;
-    for (int n = threadIdx.x; n < tc * g.nk; n += blockDim.x) {
-        const int kk = n / tc, col = n - kk * tc;
-        buf[col * ld + kk] = gin[static_cast<long>(kk) * g.nt + mt0 + col];
+        for (int n = threadIdx.x; n < N; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
+    const T2 *gin = static_cast<const T2 *>(a.gin) + (static_cast<long>(b) * g.nt + mt0) * nk;
+    if (2 * nk <= N) {
+        // a[n] and a[N - n] never both non-zero: each input lands in two entries
+        // zero the entries no input reaches: nk <= n <= N - nk of every transform
+        const int gap = N - 2 * nk + 1;
+        for (int n = threadIdx.x; n < np * gap; n += blockDim.x) {
+            const int p = n / gap;
+            T2 zero;
+            zero.x = T(0);
+            zero.y = T(0);
+            buf[p * ld + nk + (n - p * gap)] = zero;
+        }
+        for (int n = threadIdx.x; n < np * nk; n += blockDim.x) {
+            const int kk = n / np, p = n - kk * np;
+            const T2 a1 = gin[static_cast<long>(kk) * tc + 2 * p];
+            T2 a2;
+            a2.x = T(0);
+            a2.y = T(0);
+            if (2 * p + 1 < tc) a2 = gin[static_cast<long>(kk) * tc + 2 * p + 1];
+            T2 *B = buf + p * ld;
+            if (kk == 0) {
+                B[0].x = a1.x;
+                B[0].y = a2.x;
+            } else {
+                B[kk].x = T(0.5) * (a1.x - a2.y);
+                B[kk].y = T(0.5) * (a1.y + a2.x);
+                B[N - kk].x = T(0.5) * (a1.x + a2.y);
+                B[N - kk].y = T(0.5) * (a2.x - a1.y);
+            }
+        }
+    } else {
+        // n_x < 2 n_kappa: entry n takes a[n] and conj a[N - n] together
+        for (int n = threadIdx.x; n < np * N; n += blockDim.x) {
+            const int kk = n / np, p = n - kk * np;
+            const int km = (N - kk) & (N - 1);
+            T2 y[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                T2 u, v;
+                u.x = u.y = v.x = v.y = T(0);
+                if (2 * p + j < tc) {
+                    if (kk < nk) u = gin[static_cast<long>(kk) * tc + 2 * p + j];
+                    if (km < nk) v = gin[static_cast<long>(km) * tc + 2 * p + j];
+                }
+                y[j].x = T(0.5) * (u.x + v.x);
+                y[j].y = T(0.5) * (u.y - v.y);
+            }
+            buf[p * ld + kk].x = y[0].x - y[1].y;
+            buf[p * ld + kk].y = y[0].y + y[1].x;
+        }
     }
     __syncthreads();
-    fft_lds<T, MAXB>(buf, g.nx, ld, tc, twin ? twl : static_cast<const T2 *>(a.tw));
+    fft_lds<T, MAXB>(buf, N, ld, np, twin ? twl : static_cast<const T2 *>(a.tw));
     T *out = a.out_b ? static_cast<T *>(a.out_b[b]) : static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
-    for (int n = threadIdx.x; n < tc * g.nx; n += blockDim.x) {
-        const int mx = n / tc, col = n - mx * tc;
-        out[static_cast<long>(mx) * g.nt + mt0 + col] = buf[col * ld + mx].x;
+    for (int n = threadIdx.x; n < np * N; n += blockDim.x) {
+        const int mx = n / np, p = n - mx * np;
+        const T2 z = buf[p * ld + mx];
+        T *o = out + static_cast<long>(mx) * g.nt + mt0 + 2 * p;
+        o[0] = z.x;
+        if (2 * p + 1 < tc) o[1] = z.y;
     }
 }
 
@@ -1786,10 +1859,9 @@ hipError_t launch_pairsum(const Geometry &g, int precision, const void *wtab, in
     }
 }
 
-template <typename T>
+template <typename T, int RT, int CT>
 static hipError_t pairsum_mfma_t(const Geometry &g, const void *wtab, int batch, const Workspace &ws, hipStream_t st)
 {
-    constexpr int RT = kMfmaRT, CT = kMfmaCT;
     MfmaArgs a;
     a.zrow = ws.zrow;
     a.zcol = ws.zcol;
@@ -1808,11 +1880,31 @@ static hipError_t pairsum_mfma_t(const Geometry &g, const void *wtab, int batch,
     return hipGetLastError();
 }
 
-hipError_t launch_pairsum_mfma(const Geometry &g, int precision, const void *wtab, int batch, const Workspace &ws,
-                               hipStream_t st)
+// Tile shapes of the matrix-core pair sum: 16 x 16 MFMA tiles per wave,
+// RT along kappa x CT along the frequency.  Shape 0 is the default.
+MfmaShape mfma_shape(int precision, int id)
 {
-    return precision == SRM3_FP64 ? pairsum_mfma_t<double>(g, wtab, batch, ws, st)
-                                  : pairsum_mfma_t<float>(g, wtab, batch, ws, st);
+    static const MfmaShape f32[kMfmaShapes] = {{2, 2}, {2, 1}, {1, 2}};
+    static const MfmaShape f64[kMfmaShapes] = {{2, 2}, {2, 1}, {1, 2}};
+    if (id < 0 || id >= kMfmaShapes) id = 0;
+    return precision == SRM3_FP64 ? f64[id] : f32[id];
+}
+
+hipError_t launch_pairsum_mfma(const Geometry &g, int precision, int shape, const void *wtab, int batch,
+                               const Workspace &ws, hipStream_t st)
+{
+    if (precision == SRM3_FP64) {
+        switch (shape) {
+        case 1: return pairsum_mfma_t<double, 2, 1>(g, wtab, batch, ws, st);
+        case 2: return pairsum_mfma_t<double, 1, 2>(g, wtab, batch, ws, st);
+        default: return pairsum_mfma_t<double, 2, 2>(g, wtab, batch, ws, st);
+        }
+    }
+    switch (shape) {
+    case 1: return pairsum_mfma_t<float, 2, 1>(g, wtab, batch, ws, st);
+    case 2: return pairsum_mfma_t<float, 1, 2>(g, wtab, batch, ws, st);
+    default: return pairsum_mfma_t<float, 2, 2>(g, wtab, batch, ws, st);
+    }
 }
 
 template <typename T>
@@ -1849,9 +1941,9 @@ hipError_t launch_pairsum_hash(const Geometry &g, int precision, uint64_t key, d
                                   : pairsum_hash_t<float>(g, key, scale, batch, ws, sig, st);
 }
 
-template <typename T, int R, bool COMP>
-static hipError_t persistent_t(const void *reqs, const void *items, const int *q_begin, int *q_next, int nblocks,
-                               hipStream_t st, bool mfma = false)
+template <typename T, int RT, int CT>
+static hipError_t persistent_mfma_t(const void *reqs, const void *items, const int *q_begin, int *q_next,
+                                    int nblocks, hipStream_t st)
 {
     fill_int_kernel<<<1, 64, 0, st>>>(q_next, kNumXcd, 0);
     hipError_t e = hipGetLastError();
@@ -1862,19 +1954,44 @@ static hipError_t persistent_t(const void *reqs, const void *items, const int *q
     a.q_begin = q_begin;
     a.q_next = q_next;
     a.flush_terms = kFlushTerms;
-    if (mfma)
-        pairsum_persistent_mfma<T><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
-    else
-        pairsum_persistent<T, R, COMP><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    pairsum_persistent_mfma<T, RT, CT><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, int R, bool COMP>
+static hipError_t persistent_t(const void *reqs, const void *items, const int *q_begin, int *q_next, int nblocks,
+                               hipStream_t st)
+{
+    fill_int_kernel<<<1, 64, 0, st>>>(q_next, kNumXcd, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PersistArgs a;
+    a.reqs = static_cast<const PReq *>(reqs);
+    a.items = static_cast<const PItem *>(items);
+    a.q_begin = q_begin;
+    a.q_next = q_next;
+    a.flush_terms = kFlushTerms;
+    pairsum_persistent<T, R, COMP><<<dim3(static_cast<unsigned>(nblocks)), 64 * kWavesPerBlock, 0, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, const void *items, const int *q_begin,
-                                     int *q_next, int nblocks, hipStream_t st, bool mfma)
+                                     int *q_next, int nblocks, hipStream_t st, bool mfma, int shape)
 {
-    if (mfma)
-        return precision == SRM3_FP64 ? persistent_t<double, 2, false>(reqs, items, q_begin, q_next, nblocks, st, true)
-                                      : persistent_t<float, 2, true>(reqs, items, q_begin, q_next, nblocks, st, true);
+    if (mfma) {
+        if (precision == SRM3_FP64) {
+            switch (shape) {
+            case 1: return persistent_mfma_t<double, 2, 1>(reqs, items, q_begin, q_next, nblocks, st);
+            case 2: return persistent_mfma_t<double, 1, 2>(reqs, items, q_begin, q_next, nblocks, st);
+            default: return persistent_mfma_t<double, 2, 2>(reqs, items, q_begin, q_next, nblocks, st);
+            }
+        }
+        switch (shape) {
+        case 1: return persistent_mfma_t<float, 2, 1>(reqs, items, q_begin, q_next, nblocks, st);
+        case 2: return persistent_mfma_t<float, 1, 2>(reqs, items, q_begin, q_next, nblocks, st);
+        default: return persistent_mfma_t<float, 2, 2>(reqs, items, q_begin, q_next, nblocks, st);
+        }
+    }
     if (precision == SRM3_FP64) {
         switch (R) {
         case 2: return persistent_t<double, 2, false>(reqs, items, q_begin, q_next, nblocks, st);
@@ -1893,8 +2010,8 @@ hipError_t launch_pairsum_persistent(int precision, int R, const void *reqs, con
 }
 
 size_t persistent_req_bytes() { return sizeof(PReq); }
-int mfma_rows_per_group() { return 16 * kMfmaRT; }
-int mfma_cols_per_group() { return 16 * kMfmaCT * kWavesPerBlock; }
+int mfma_rows_per_group(int precision, int shape) { return 16 * mfma_shape(precision, shape).rt; }
+int mfma_cols_per_group(int precision, int shape) { return 16 * mfma_shape(precision, shape).ct * kWavesPerBlock; }
 size_t persistent_item_bytes() { return sizeof(PItem); }
 
 void fill_persistent_req(void *dst, const Geometry &g, const void *zrow, const void *zcol, void *tsum,
@@ -1926,10 +2043,25 @@ hipError_t launch_fill_u32(void *p, size_t words, uint32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
+// Columns per tile of the t-transformed rows = the x-transform's tile width:
+// 64 KB of packed transforms (nx complex values per pair of columns), at most
+// n_t.  Both launchers take it from here, so the two layouts agree.
+template <typename T>
+static int xfft_cols(const Geometry &g)
+{
+    const size_t pair_bytes = static_cast<size_t>(g.nx) * sizeof(typename vec<T>::v2);
+    int tc = static_cast<int>(std::max<size_t>(1, 65536 / pair_bytes)) * 2;
+    if (tc > 64) tc = 64;
+    if (tc > g.nt) tc = g.nt;
+    return tc;
+}
+
 template <typename T>
 static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const AmpRef &amp, const void *wtab,
-                         const void *tw, int batch, const Workspace &ws, void *rout, hipStream_t st)
+                         const void *tw, int batch, const Workspace &ws, void *rout, const uint64_t *seeds,
+                         hipStream_t st)
 {
+    using T2 = typename vec<T>::v2;
     TfftArgs a;
     a.rout = (g.nx == 1 && g.nk == 1) ? rout : nullptr;
     a.g = g;
@@ -1937,23 +2069,42 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     a.cin = cin;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
+    a.seeds_dev = nullptr;
+    a.b0 = 0;
     a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr};
     a.wtab = wtab;
     a.tw = tw;
     a.gout = ws.g;
+    a.xtw = xfft_cols<T>(g);
     const int thr = fft_threads(g.nt / 2);
-    size_t lds = static_cast<size_t>(g.nt) * sizeof(typename vec<T>::v2);
+    size_t lds = static_cast<size_t>(g.nt) * sizeof(T2);
     a.tw_lds = 2 * lds <= 131072 ? 1 : 0;
     if (a.tw_lds) lds *= 2;
-    tfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(batch * g.nk)), thr, lds, st>>>(a);
-    return hipGetLastError();
+    // mode 2 with host seeds: kernel-argument chunks of realizations (the
+    // per-realization spectrum and scale arrays are not used in this mode)
+    const int chunk = mode == 2 ? kMaxSeedsPerLaunch : batch;
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
+        TfftArgs c = a;
+        if (mode == 2) {
+            for (int i = 0; i < nb; ++i) c.seeds.s[i] = seeds[b0 + i];
+            c.gout = static_cast<T2 *>(ws.g) + static_cast<long>(b0) * g.nk * g.nt;
+            if (c.rout) c.rout = static_cast<T *>(rout) + static_cast<long>(b0) * g.nt;
+        }
+        tfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(nb * g.nk)), thr, lds, st>>>(c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
-                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st, void *rout)
+                       const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st, void *rout,
+                       const uint64_t *seeds)
 {
-    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, amp, wtab, tw, batch, ws, rout, st)
-                                  : tfft_t<float>(g, mode, cin, amp, wtab, tw, batch, ws, rout, st);
+    if (mode == 2 && !seeds) return hipErrorInvalidValue;
+    return precision == SRM3_FP64 ? tfft_t<double>(g, mode, cin, amp, wtab, tw, batch, ws, rout, seeds, st)
+                                  : tfft_t<float>(g, mode, cin, amp, wtab, tw, batch, ws, rout, seeds, st);
 }
 
 template <typename T>
@@ -1985,18 +2136,18 @@ static hipError_t xfft_t(const Geometry &g, const void *tw, int batch, const Wor
 {
     XfftArgs a;
     a.g = g;
+    const int tc = xfft_cols<T>(g);
+    const int np = (tc + 1) / 2;
     const size_t col_bytes = static_cast<size_t>(g.nx) * sizeof(typename vec<T>::v2);
-    // 32 KB tiles: four blocks per CU beat two 64 KB ones (measured at 512 and 1024 x points)
-    int tc = static_cast<int>(std::max<size_t>(1, 32768 / col_bytes));
-    if (tc > 16) tc = 16;
-    if (tc > g.nt) tc = g.nt;
     a.tcols = tc;
     a.gin = ws.g;
     a.tw = tw;
     a.out = out;
     a.out_b = out_b;
-    const int thr = fft_threads(tc * g.nx / 2);
-    size_t lds = tc * col_bytes;
+    const int thr = fft_threads(np * g.nx / 2);
+    a.ld = g.nx;
+    if (static_cast<size_t>(np) * (g.nx + 8) * sizeof(typename vec<T>::v2) + col_bytes <= 131072) a.ld = g.nx + 8;
+    size_t lds = static_cast<size_t>(np) * a.ld * sizeof(typename vec<T>::v2);
     a.tw_lds = lds + col_bytes <= 131072 ? 1 : 0;
     if (a.tw_lds) lds += col_bytes;
     xfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(g.nt / tc), batch), thr, lds, st>>>(a);

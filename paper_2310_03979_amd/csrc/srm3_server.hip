@@ -119,6 +119,7 @@ struct srm3_server_s {
     int n_cu = 256;
     int blocks_per_cu = 2;
     bool mfma = false;                 // persistent launch with matrix-core items
+    int mfma_shape = 0;                // their tile shape
     DevBuf arena_mem;
     Arena arena;
     // staging: headers | qbegin | preq | items
@@ -209,6 +210,8 @@ srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, 
         return fail(SRM3_E_INVALID, "policy %d", cfg->policy);
     if (cfg->pair_kernel != SRM3_ALGO_DIRECT && cfg->pair_kernel != SRM3_ALGO_MFMA)
         return fail(SRM3_E_INVALID, "pair_kernel %d", cfg->pair_kernel);
+    if (cfg->mfma_shape < 0 || cfg->mfma_shape >= kMfmaShapes)
+        return fail(SRM3_E_INVALID, "mfma_shape %d", cfg->mfma_shape);
     std::unique_ptr<srm3_server_s> s(new (std::nothrow) srm3_server_s);
     if (!s) return fail(SRM3_E_NOMEM, "host allocation failed");
     s->cfg = *cfg;
@@ -216,6 +219,7 @@ srm3_status srm3_server_create(const srm3_server_config *cfg, void *hip_stream, 
     s->st = static_cast<hipStream_t>(hip_stream);
     s->R = cfg->precision == SRM3_FP64 ? 8 : 16;
     s->mfma = cfg->pair_kernel == SRM3_ALGO_MFMA;
+    s->mfma_shape = cfg->mfma_shape;
     if (s->mfma) s->blocks_per_cu = 3;   // the matrix-core kernel runs 3 waves per SIMD
     int dev = 0;
     hipDeviceProp_t prop;
@@ -303,12 +307,14 @@ srm3_status srm3_server_submit(srm3_server_t s, const srm3_request *req, const s
     if (q->bytes > s->arena.size)
         return fail(SRM3_E_NOMEM, "request needs %zu bytes, more than the server's budget %zu", q->bytes, s->arena.size);
     if (q->mode == 0) {
-        const int nrb = s->mfma ? (q->g.nk + mfma_rows_per_group() - 1) / mfma_rows_per_group() : q->g.nkp / q->g.R;
-        const int ncg = s->mfma ? (q->g.nc + mfma_cols_per_group() - 1) / mfma_cols_per_group()
+        const int mr = mfma_rows_per_group(s->cfg.precision, s->mfma_shape);
+        const int mc = mfma_cols_per_group(s->cfg.precision, s->mfma_shape);
+        const int nrb = s->mfma ? (q->g.nk + mr - 1) / mr : q->g.nkp / q->g.R;
+        const int ncg = s->mfma ? (q->g.nc + mc - 1) / mc
                                 : ((q->g.nc + 63) / 64 + waves_per_block() - 1) / waves_per_block();
         for (int kb = nrb - 1; kb >= 0; --kb)
             for (int cg = 0; cg < ncg; ++cg)
-                q->items.push_back({kb, cg, s->mfma ? mfma_item_cost(q->g, kb, cg) : item_cost(q->g, q->g.R, kb, cg)});
+                q->items.push_back({kb, cg, s->mfma ? mfma_item_cost(q->g, kb, cg, s->cfg.precision, s->mfma_shape) : item_cost(q->g, q->g.R, kb, cg)});
         std::stable_sort(q->items.begin(), q->items.end(),
                          [](const Item &a, const Item &b) { return a.cost > b.cost; });
         for (const Item &it : q->items) q->left += it.cost;
@@ -465,7 +471,8 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
             char *D = static_cast<char *>(s->dev_stage[c].p);
             e = launch_pairsum_persistent(s->cfg.precision, s->R, D + s->off_req, D + s->off_items,
                                           reinterpret_cast<const int *>(D + s->off_q),
-                                          static_cast<int *>(s->qnext[c].p), s->n_cu * s->blocks_per_cu, st, s->mfma);
+                                          static_cast<int *>(s->qnext[c].p), s->n_cu * s->blocks_per_cu, st, s->mfma,
+                                          s->mfma_shape);
             if (e != hipSuccess) return dev_err(e, "persistent pair-sum kernel");
         }
         if ((e = hipEventRecord(s->ev_pairsum[c], st)) != hipSuccess) return dev_err(e, "hipEventRecord");

@@ -74,7 +74,7 @@ class _BatchStats(ctypes.Structure):
     _fields_ = [("pair_terms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("pairsum_ms", ctypes.c_double), ("rows_per_wave", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("work_items", ctypes.c_int32),
-                ("groups", ctypes.c_int32)]
+                ("groups", ctypes.c_int32), ("mfma_shape", ctypes.c_int32)]
 
 
 SRM3_BATCH_GRAPH, SRM3_BATCH_AUTOTUNE = 1, 2
@@ -111,6 +111,9 @@ def load():
     L.srm3_process_plan.argtypes = [ctypes.POINTER(_ProcessGrid), _dp, ctypes.POINTER(_Bispectrum),
                                     ctypes.c_int32, vp, ctypes.POINTER(vp)]
     L.srm3_algorithm_terms.argtypes = [vp, _dp]
+    L.srm3_plan_set_mfma_shape.argtypes = [vp, ctypes.c_int32]
+    L.srm3_mfma_shape.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]
     L.srm3_profile_enable.argtypes = [vp, ctypes.c_int32]
     L.srm3_profile_read.argtypes = [vp, ctypes.POINTER(_Profile)]
     L.srm3_destroy.argtypes = [vp]
@@ -128,7 +131,7 @@ def load():
     L.srm3_generate_uneven.argtypes = [ctypes.POINTER(_Request), ctypes.c_int32, vp]
     for f in ("srm3_plan", "srm3_process_plan", "srm3_wind_factors", "srm3_product_factors", "srm3_generate", "srm3_generate_noalloc", "srm3_coefficients", "srm3_transform",
               "srm3_workspace_bytes", "srm3_workspace_fill", "srm3_pair_terms", "srm3_rows_per_wave", "srm3_plan_set_algorithm",
-              "srm3_algorithm_terms", "srm3_profile_enable",
+              "srm3_algorithm_terms", "srm3_plan_set_mfma_shape", "srm3_mfma_shape", "srm3_profile_enable",
               "srm3_profile_read", "srm3_set_spectrum", "srm3_spectrum_kaimal_davenport",
               "srm3_batch_create", "srm3_batch_run", "srm3_batch_info", "srm3_generate_uneven"):
         getattr(L, f).restype = ctypes.c_int
@@ -362,6 +365,18 @@ def srm3_plan_set_algorithm(plan: Plan, algorithm="direct", stream=None):
     _check(load().srm3_plan_set_algorithm(plan.handle, a, _stream_ptr(stream)))
 
 
+def srm3_plan_set_mfma_shape(plan: Plan, shape: int):
+    """Tile shape (0, 1, 2) of the plan's matrix-core pair sum."""
+    _check(load().srm3_plan_set_mfma_shape(plan.handle, int(shape)))
+
+
+def srm3_mfma_shape(precision, shape: int):
+    """(rows, cols) of outputs a wave owns under a matrix-core tile shape."""
+    r, c = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().srm3_mfma_shape(_precision(precision), int(shape), ctypes.byref(r), ctypes.byref(c)))
+    return int(r.value), int(c.value)
+
+
 def srm3_algorithm_terms(plan: Plan) -> float:
     v = ctypes.c_double()
     _check(load().srm3_algorithm_terms(plan.handle, ctypes.byref(v)))
@@ -577,7 +592,7 @@ def srm3_generate_uneven(reqs, stream=None):
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_active", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_size_t), ("step_pair_terms", ctypes.c_double),
-                ("policy", ctypes.c_int32), ("pair_kernel", ctypes.c_int32)]
+                ("policy", ctypes.c_int32), ("pair_kernel", ctypes.c_int32), ("mfma_shape", ctypes.c_int32)]
 
 
 SRM3_SERVE_SHORTEST_FIRST, SRM3_SERVE_ROUND_ROBIN = 0, 1
@@ -610,11 +625,12 @@ class Server:
     """srm3_server_t: continuous batching of generation requests."""
 
     def __init__(self, precision="fp32", max_active=64, hbm_budget=32 << 30, step_pair_terms=0.0,
-                 policy="shortest", stream=None, pair_kernel="direct"):
+                 policy="shortest", stream=None, pair_kernel="direct", mfma_shape=0):
         L = _server_lib()
         pol = {"shortest": SRM3_SERVE_SHORTEST_FIRST, "round_robin": SRM3_SERVE_ROUND_ROBIN}[policy]
         pk = _ALGOS[pair_kernel] if isinstance(pair_kernel, str) else int(pair_kernel)
-        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms), pol, pk)
+        cfg = _ServerConfig(_precision(precision), int(max_active), int(hbm_budget), float(step_pair_terms), pol, pk,
+                            int(mfma_shape))
         h = ctypes.c_void_p()
         _check(L.srm3_server_create(ctypes.byref(cfg), _stream_ptr(stream), ctypes.byref(h)))
         self._h = h

@@ -152,7 +152,7 @@ def test_autotuned_batch_is_cached_and_accurate(lib, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     info = tuned.info()
     r_max = plain.info()["rows_per_wave"]          # the untuned batch takes the largest tile
-    assert info["rows_per_wave"] in (r_max, r_max // 2) and info["blocks_per_cu"] in (1, 2, 4)
+    assert info["rows_per_wave"] in (r_max, r_max // 2) and info["blocks_per_cu"] in (1, 2, 3, 4)
     text = (tmp_path / "tune.txt").read_text()
     assert "fp32" in text and "32x96w80" in text
     for a, b in zip(reqs, ref):

@@ -96,14 +96,16 @@ SMALL = [
 ]
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", SMALL, ids=[f"{c[0]}x{c[1]}w{c[2]}_{c[5]}_{c[6]}" for c in SMALL])
-def test_small_grids_match_oracle(lib, oracle_mod, case, precision):
+def test_small_grids_match_oracle(lib, oracle_mod, case, precision, shape):
     nk, nw, W, nx, nt, kind, beta_mode = case
     wl = inp.small_grid(nk, nw, support_w=W, n_x=nx, n_t=nt, batch=3, seed_base=71)
-    print(f"[gpu] mfma {case} {precision}", flush=True)
+    print(f"[gpu] mfma {case} {precision} shape {shape}", flush=True)
     bis, b2 = _bispec(wl, kind, beta_mode)
     plan = _plan(lib, wl, bis, precision)
+    lib.srm3_plan_set_mfma_shape(plan, shape)
     C = _coeffs(lib, plan, wl.seeds()).to(_torch().complex128).cpu().numpy()
     u = _field(lib, plan, nx, nt, wl.seeds()).double().cpu().numpy()
     P = _problem(oracle_mod, wl, bis, b2)
@@ -115,6 +117,35 @@ def test_small_grids_match_oracle(lib, oracle_mod, case, precision):
             continue
         assert _rel(C[r], Cref) <= TOLS[precision], r
         assert _rel(u[r], ref) <= TOLS[precision], r
+
+
+def test_tile_shapes(lib):
+    assert lib.srm3_mfma_shape("fp32", 0) == (32, 32)
+    assert lib.srm3_mfma_shape("fp32", 1) == (32, 16)
+    assert lib.srm3_mfma_shape("fp64", 2) == (16, 32)
+    wl = inp.small_grid(8, 16)
+    bis, _ = _bispec(wl, "separable", "seeded")
+    plan = _plan(lib, wl, bis)
+    for bad in (-1, 3):
+        with pytest.raises(lib.Srm3Error) as ei:
+            lib.srm3_plan_set_mfma_shape(plan, bad)
+        assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_shapes_agree(lib, shape):
+    """Every tile shape sums the same pair terms: coefficients agree with the
+    default shape's to rounding, on a grid with ragged row groups."""
+    torch = _torch()
+    wl = inp.small_grid(100, 300, support_w=260, batch=5, seed_base=400)
+    bis, _ = _bispec(wl, "separable", "seeded")
+    ref = _plan(lib, wl, bis)
+    other = _plan(lib, wl, bis)
+    lib.srm3_plan_set_mfma_shape(other, shape)
+    a = _coeffs(lib, ref, wl.seeds()).to(torch.complex128)
+    b = _coeffs(lib, other, wl.seeds()).to(torch.complex128)
+    rel = ((a - b).abs().pow(2).sum() / a.abs().pow(2).sum()).sqrt().item()
+    assert rel <= 2e-6
 
 
 def test_agrees_with_vector_kernel_and_is_batch_invariant(lib):
@@ -208,18 +239,25 @@ def test_uneven_batch_equals_single_generation(lib, flags, precision, monkeypatc
     pk = lib.plan_from_workload(wk, precision)
     lib.srm3_plan_set_algorithm(pk, "kappa_fft")
     plans.append(pk)
-    reqs, singles = [], []
+    reqs = []
     for i in range(11):
         plan = plans[i % len(plans)]
-        seed = 700 + 3 * i
-        one = torch.empty((1,) + plan.field_shape, dtype=plan.real_dtype, device="cuda")
-        lib.srm3_generate(plan, [seed], one)
-        singles.append(one[0])
-        reqs.append(dict(plan=plan, seed=seed, out=torch.empty(plan.field_shape, dtype=plan.real_dtype,
-                                                                device="cuda")))
+        reqs.append(dict(plan=plan, seed=700 + 3 * i, out=torch.empty(plan.field_shape, dtype=plan.real_dtype,
+                                                                       device="cuda")))
     print(f"[gpu] mfma uneven batch {flags} {precision}", flush=True)
     fl = 0 if flags == "plain" else lib.SRM3_BATCH_GRAPH | lib.SRM3_BATCH_AUTOTUNE
     b = lib.Batch(reqs, flags=fl)
+    b.run()
+    torch.cuda.synchronize()
+    shape = b.info()["mfma_shape"]
+    assert shape in (0, 1, 2) and (flags != "plain" or shape == 0)
+    # single generation with the tile shape the batch runs (the tuner may pick any)
+    singles = []
+    for r in reqs:
+        lib.srm3_plan_set_mfma_shape(r["plan"], shape)
+        one = torch.empty((1,) + r["plan"].field_shape, dtype=r["plan"].real_dtype, device="cuda")
+        lib.srm3_generate(r["plan"], [r["seed"]], one)
+        singles.append(one[0])
     for _ in range(2):
         for r in reqs:
             r["out"].zero_()
@@ -229,11 +267,12 @@ def test_uneven_batch_equals_single_generation(lib, flags, precision, monkeypatc
             assert torch.equal(r["out"], s)
 
 
-def test_server_with_matrix_core_items(lib):
-    """A server whose persistent pair-sum launch takes matrix-core items:
-    mixed grids (and a kappa-DFT and a Gaussian plan beside them) give each
-    request's single generation bitwise; plans of the other kernel and unknown
-    kernels are refused."""
+@pytest.mark.parametrize("shape", [0, 2])
+def test_server_with_matrix_core_items(lib, shape):
+    """A server whose persistent pair-sum launch takes matrix-core items (of a
+    given tile shape): mixed grids (and a kappa-DFT and a Gaussian plan beside
+    them) give each request's single generation with that shape bitwise; plans
+    of the other kernel and unknown kernels or shapes are refused."""
     torch = _torch()
     grids = [(40, 300, 300), (5, 40, 40), (70, 33, 17)]
     plans = []
@@ -241,6 +280,7 @@ def test_server_with_matrix_core_items(lib):
         wl = inp.small_grid(nk, nw, support_w=W)
         bis, _ = _bispec(wl, "separable", "seeded")
         plans.append(_plan(lib, wl, bis))
+        lib.srm3_plan_set_mfma_shape(plans[-1], shape)
     wg = inp.small_grid(16, 32)
     plans.append(lib.srm3_plan(wg.grid_dict(), wg.spectrum(), None, "fp32"))
     wk = inp.small_grid(16, 40)
@@ -256,7 +296,7 @@ def test_server_with_matrix_core_items(lib):
         singles.append(one[0])
         reqs.append(dict(plan=plan, seed=seed, out=torch.zeros(plan.field_shape, dtype=torch.float32, device="cuda")))
     print("[gpu] mfma server", flush=True)
-    srv = lib.srm3.Server("fp32", max_active=4, hbm_budget=1 << 30, pair_kernel="mfma")
+    srv = lib.srm3.Server("fp32", max_active=4, hbm_budget=1 << 30, pair_kernel="mfma", mfma_shape=shape)
     tickets = [srv.submit(r["plan"], r["seed"], r["out"]) for r in reqs]
     done = []
     for _ in range(10000):
@@ -277,4 +317,7 @@ def test_server_with_matrix_core_items(lib):
     assert ei.value.status == 5
     with pytest.raises(lib.Srm3Error) as ei:
         lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 28, pair_kernel=7)
+    assert ei.value.status == 1
+    with pytest.raises(lib.Srm3Error) as ei:
+        lib.srm3.Server("fp32", max_active=2, hbm_budget=1 << 28, pair_kernel="mfma", mfma_shape=3)
     assert ei.value.status == 1
