@@ -263,8 +263,10 @@ class ProductProblem(WindProblem):
 
 class HashedProblem(Problem):
     """A bispectrum drawn per 4-index pair: for the canonical member (i, j) of
-    an unordered pair, Philox4x32-10 (key ``key``, counter (i_kappa, i_w,
-    j_kappa, j_w)) gives b2_raw = scale * U / 2^32 and beta = 2 pi V / 2^32."""
+    an unordered pair (k = i + j), word i_w - 4 floor(i_w / 4) of
+    Philox4x32-10 (key ``key``, counter (i_kappa, floor(i_w / 4), j_kappa,
+    k_w)) gives u = its high and v = its low 16 bits; b2_raw = scale (u /
+    2^16)^2 and beta = 2 pi v / 2^16."""
 
     def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, scale, key, cap):
         W = support_w

@@ -122,19 +122,24 @@ typedef struct {
     const double *F;        /* mode 2: [nk][2nw-1] complex */
     const double *G;        /* mode 2: [nk][2nw-1] complex */
     const double *H;        /* mode 2: [2W-1][2W-1] complex, or NULL */
-    uint64_t hash_key;      /* mode 3: a bispectrum drawn per 4-index pair, b2_raw = alpha U, beta = V */
+    uint64_t hash_key;      /* mode 3: a bispectrum drawn per 4-index pair (see pair_words) */
 } oracle_problem;
 
-/* Mode 3: the two uniform words of the canonical pair (i, j): Philox4x32-10,
- * key = hash_key, counter (i_kappa, i_w, j_kappa, j_w). */
+/* Mode 3: the two 16-bit draws of the canonical pair (i, j), k = i + j: the
+ * word t = i_w - 4 m (m = floor(i_w / 4)) of Philox4x32-10 with key =
+ * hash_key and counter (i_kappa, m, j_kappa, k_w) -- one call holds the four
+ * pairs of line k whose i_w share m -- split into u = high 16 bits (the
+ * bicoherence) and v = low 16 bits (the biphase). */
 static void pair_words(const oracle_problem *p, int ik, int iw, int jk, int jw, uint32_t *u, uint32_t *v)
 {
-    const uint32_t ctr[4] = {(uint32_t)ik, (uint32_t)(int32_t)iw, (uint32_t)jk, (uint32_t)(int32_t)jw};
+    const int m = iw >= 0 ? iw / 4 : -((-iw + 3) / 4);
+    const int t = iw - 4 * m;
+    const uint32_t ctr[4] = {(uint32_t)ik, (uint32_t)(int32_t)m, (uint32_t)jk, (uint32_t)(int32_t)(iw + jw)};
     const uint32_t key[2] = {(uint32_t)(p->hash_key & 0xffffffffu), (uint32_t)(p->hash_key >> 32)};
     uint32_t out[4];
     oracle_philox4x32_10(ctr, key, out);
-    *u = out[0];
-    *v = out[1];
+    *u = out[t] >> 16;
+    *v = out[t] & 0xffffu;
 }
 
 /* The prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w). */
@@ -182,10 +187,11 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
         if (B == 0.0) return 0.0;
         return B * B * p->dk * p->dw / (p->Sp[li] * p->Sp[lj] * p->S[lk]);
     }
-    if (p->mode == 3) {
+    if (p->mode == 3) {   /* b_p = sqrt(alpha) u / 2^16, so b_p^2 = alpha (u / 2^16)^2 */
         uint32_t u, v;
         pair_words(p, ik, iw, jk, jw, &u, &v);
-        return p->alpha * (double)u / 4294967296.0;
+        const double b = (double)u / 65536.0;
+        return p->alpha * b * b;
     }
     if (p->mode == 2) {
         double re, im;
@@ -203,10 +209,10 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
 static uint32_t pair_beta(const oracle_problem *p, int ik, int iw, int jk, int jw)
 {
     const int W = p->W, n = 2 * W - 1;
-    if (p->mode == 3) {
+    if (p->mode == 3) {   /* beta = 2 pi v / 2^16: the fixed-point angle v 2^16 */
         uint32_t u, v;
         pair_words(p, ik, iw, jk, jw, &u, &v);
-        return v;
+        return v << 16;
     }
     return p->mode != 0 ? 0u : p->beta[(size_t)(iw + W - 1) * n + (jw + W - 1)];
 }

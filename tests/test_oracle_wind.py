@@ -278,8 +278,10 @@ def test_product_third_moment_is_the_bispectrum_integral(oracle_mod):
 
 def test_hashed_bispectrum_brute_force(oracle_mod):
     """A bispectrum drawn per 4-index pair: the pair sum written out in Python
-    with the generator called per canonical pair (b2_raw = scale U / 2^32,
-    beta = 2 pi V / 2^32), cap included."""
+    with the generator called per canonical pair (i, j), k = i + j: word
+    i_w mod 4 of Philox4x32-10 at counter (i_kappa, floor(i_w / 4), j_kappa,
+    k_w), high 16 bits u, low 16 bits v, b2_raw = scale (u / 2^16)^2,
+    beta = 2 pi v / 2^16; cap included."""
     nk, nw, W, scale, key, cap = 4, 5, 4, 0.05, 0xABCDEF12345, 0.3
     S = inp.random_spectrum(nk, nw, seed=9)
     P = oracle_mod.HashedProblem(nk, nw, W, 0.3, 0.2, S, scale, key, cap)
@@ -292,15 +294,17 @@ def test_hashed_bispectrum_brute_force(oracle_mod):
     for kk in range(nk):
         for kw in range(-(nw - 1), nw):
             prs = list(_pairs(nk, nw, W, kk, kw))
-            words = [oracle_mod.philox4x32_10([ik, iw & 0xFFFFFFFF, jk, jw & 0xFFFFFFFF], kw0) for ik, iw, jk, jw in prs]
-            b2 = [scale * float(w[0]) / 2.0 ** 32 for w in words]
+            words = [int(oracle_mod.philox4x32_10([ik, (iw // 4) & 0xFFFFFFFF, jk, (iw + jw) & 0xFFFFFFFF],
+                                                  kw0)[iw % 4]) for ik, iw, jk, jw in prs]
+            b2 = [scale * (float(w >> 16) / 2.0 ** 16) ** 2 for w in words]
             for (ik, iw, jk, jw), v in zip(prs, b2):
                 b2_seen.setdefault((iw, jw), set()).add(round(v, 15))
             tot = sum(b2)
             rho = cap / tot if tot > cap else 1.0
             acc = math.sqrt(1.0 - rho * tot) * np.exp(1j * phi[kk, kw + c0])
             for (ik, iw, jk, jw), v, w in zip(prs, b2, words):
-                acc += math.sqrt(rho * v) * np.exp(1j * (phi[ik, iw + c0] + phi[jk, jw + c0] + TWO_PI * float(w[1]) / 2.0 ** 32))
+                acc += math.sqrt(rho * v) * np.exp(1j * (phi[ik, iw + c0] + phi[jk, jw + c0]
+                                                         + TWO_PI * float(w & 0xFFFF) / 2.0 ** 16))
             ref = 2.0 * math.sqrt(S[kk, kw + c0] * 0.3 * 0.2) * acc
             assert abs(C[kk, kw + c0] - ref) <= 1e-12 * max(1.0, abs(ref))
     # the same frequency pair takes different values at different wavenumbers
