@@ -263,10 +263,11 @@ class ProductProblem(WindProblem):
 
 class HashedProblem(Problem):
     """A bispectrum drawn per 4-index pair: for the canonical member (i, j) of
-    an unordered pair (k = i + j), word i_w - 4 floor(i_w / 4) of
-    Philox4x32-10 (key ``key``, counter (i_kappa, floor(i_w / 4), j_kappa,
-    k_w)) gives u = its high and v = its low 16 bits; b2_raw = scale (u /
-    2^16)^2 and beta = 2 pi v / 2^16."""
+    an unordered pair (k = i + j), with m = floor(i_w / 8) and t = i_w - 8 m,
+    Philox4x32-10 (key ``key``, counter (i_kappa, m, j_kappa, k_w)) gives in
+    word floor(t / 2) the 16-bit half h of the pair (high half for even t,
+    low half for odd t); u = h >> 8, v = h & 255, b2_raw = scale (u / 2^8)^2
+    and beta = 2 pi v / 2^8."""
 
     def __init__(self, n_kappa, n_omega, support_w, d_kappa, d_omega, S, scale, key, cap):
         W = support_w

@@ -125,21 +125,24 @@ typedef struct {
     uint64_t hash_key;      /* mode 3: a bispectrum drawn per 4-index pair (see pair_words) */
 } oracle_problem;
 
-/* Mode 3: the two 16-bit draws of the canonical pair (i, j), k = i + j: the
- * word t = i_w - 4 m (m = floor(i_w / 4)) of Philox4x32-10 with key =
- * hash_key and counter (i_kappa, m, j_kappa, k_w) -- one call holds the four
- * pairs of line k whose i_w share m -- split into u = high 16 bits (the
- * bicoherence) and v = low 16 bits (the biphase). */
+/* Mode 3: the two 8-bit draws of the canonical pair (i, j), k = i + j.
+ * Philox4x32-10 with key = hash_key and counter (i_kappa, m, j_kappa, k_w),
+ * m = floor(i_w / 8), holds the eight pairs of line k whose i_w share m: pair
+ * t = i_w - 8 m takes the 16-bit half h of word floor(t / 2) (the high half
+ * for even t, the low half for odd t), split into u = h >> 8 (the
+ * bicoherence) and v = h & 255 (the biphase). */
 static void pair_words(const oracle_problem *p, int ik, int iw, int jk, int jw, uint32_t *u, uint32_t *v)
 {
-    const int m = iw >= 0 ? iw / 4 : -((-iw + 3) / 4);
-    const int t = iw - 4 * m;
+    const int m = iw >= 0 ? iw / 8 : -((-iw + 7) / 8);
+    const int t = iw - 8 * m;
     const uint32_t ctr[4] = {(uint32_t)ik, (uint32_t)(int32_t)m, (uint32_t)jk, (uint32_t)(int32_t)(iw + jw)};
     const uint32_t key[2] = {(uint32_t)(p->hash_key & 0xffffffffu), (uint32_t)(p->hash_key >> 32)};
     uint32_t out[4];
     oracle_philox4x32_10(ctr, key, out);
-    *u = out[t] >> 16;
-    *v = out[t] & 0xffffu;
+    const uint32_t w = out[t / 2];
+    const uint32_t h = (t % 2 == 0) ? (w >> 16) : (w & 0xffffu);
+    *u = h >> 8;
+    *v = h & 0xffu;
 }
 
 /* The prescribed product bispectrum B(i, j) = F_k G_i G_j H(i_w, j_w). */
@@ -187,10 +190,10 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
         if (B == 0.0) return 0.0;
         return B * B * p->dk * p->dw / (p->Sp[li] * p->Sp[lj] * p->S[lk]);
     }
-    if (p->mode == 3) {   /* b_p = sqrt(alpha) u / 2^16, so b_p^2 = alpha (u / 2^16)^2 */
+    if (p->mode == 3) {   /* b_p = sqrt(alpha) u / 2^8, so b_p^2 = alpha (u / 2^8)^2 */
         uint32_t u, v;
         pair_words(p, ik, iw, jk, jw, &u, &v);
-        const double b = (double)u / 65536.0;
+        const double b = (double)u / 256.0;
         return p->alpha * b * b;
     }
     if (p->mode == 2) {
@@ -209,10 +212,10 @@ static double pair_b2(const oracle_problem *p, int ik, int iw, int jk, int jw)
 static uint32_t pair_beta(const oracle_problem *p, int ik, int iw, int jk, int jw)
 {
     const int W = p->W, n = 2 * W - 1;
-    if (p->mode == 3) {   /* beta = 2 pi v / 2^16: the fixed-point angle v 2^16 */
+    if (p->mode == 3) {   /* beta = 2 pi v / 2^8: the fixed-point angle v 2^24 */
         uint32_t u, v;
         pair_words(p, ik, iw, jk, jw, &u, &v);
-        return v << 16;
+        return v << 24;
     }
     return p->mode != 0 ? 0u : p->beta[(size_t)(iw + W - 1) * n + (jw + W - 1)];
 }

@@ -278,10 +278,11 @@ def test_product_third_moment_is_the_bispectrum_integral(oracle_mod):
 
 def test_hashed_bispectrum_brute_force(oracle_mod):
     """A bispectrum drawn per 4-index pair: the pair sum written out in Python
-    with the generator called per canonical pair (i, j), k = i + j: word
-    i_w mod 4 of Philox4x32-10 at counter (i_kappa, floor(i_w / 4), j_kappa,
-    k_w), high 16 bits u, low 16 bits v, b2_raw = scale (u / 2^16)^2,
-    beta = 2 pi v / 2^16; cap included."""
+    with the generator called per canonical pair (i, j), k = i + j: with
+    t = i_w mod 8, the 16-bit half of word t // 2 (high half for even t) of
+    Philox4x32-10 at counter (i_kappa, floor(i_w / 8), j_kappa, k_w), its
+    high byte u and low byte v, b2_raw = scale (u / 2^8)^2,
+    beta = 2 pi v / 2^8; cap included."""
     nk, nw, W, scale, key, cap = 4, 5, 4, 0.05, 0xABCDEF12345, 0.3
     S = inp.random_spectrum(nk, nw, seed=9)
     P = oracle_mod.HashedProblem(nk, nw, W, 0.3, 0.2, S, scale, key, cap)
@@ -294,9 +295,12 @@ def test_hashed_bispectrum_brute_force(oracle_mod):
     for kk in range(nk):
         for kw in range(-(nw - 1), nw):
             prs = list(_pairs(nk, nw, W, kk, kw))
-            words = [int(oracle_mod.philox4x32_10([ik, (iw // 4) & 0xFFFFFFFF, jk, (iw + jw) & 0xFFFFFFFF],
-                                                  kw0)[iw % 4]) for ik, iw, jk, jw in prs]
-            b2 = [scale * (float(w >> 16) / 2.0 ** 16) ** 2 for w in words]
+            words = []
+            for ik, iw, jk, jw in prs:
+                w = int(oracle_mod.philox4x32_10([ik, (iw // 8) & 0xFFFFFFFF, jk, (iw + jw) & 0xFFFFFFFF],
+                                                 kw0)[(iw % 8) // 2])
+                words.append(w >> 16 if iw % 2 == 0 else w & 0xFFFF)
+            b2 = [scale * (float(h >> 8) / 2.0 ** 8) ** 2 for h in words]
             for (ik, iw, jk, jw), v in zip(prs, b2):
                 b2_seen.setdefault((iw, jw), set()).add(round(v, 15))
             tot = sum(b2)
@@ -304,7 +308,7 @@ def test_hashed_bispectrum_brute_force(oracle_mod):
             acc = math.sqrt(1.0 - rho * tot) * np.exp(1j * phi[kk, kw + c0])
             for (ik, iw, jk, jw), v, w in zip(prs, b2, words):
                 acc += math.sqrt(rho * v) * np.exp(1j * (phi[ik, iw + c0] + phi[jk, jw + c0]
-                                                         + TWO_PI * float(w & 0xFFFF) / 2.0 ** 16))
+                                                         + TWO_PI * float(w & 0xFF) / 2.0 ** 8))
             ref = 2.0 * math.sqrt(S[kk, kw + c0] * 0.3 * 0.2) * acc
             assert abs(C[kk, kw + c0] - ref) <= 1e-12 * max(1.0, abs(ref))
     # the same frequency pair takes different values at different wavenumbers
