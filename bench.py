@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(inp.WORKLOADS) + ["c3", "c4", "p1", "bridge"])
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests per arrival rate in the serving workload (c4)")
+    ap.add_argument("--serve-legs", default="sat,0.3,0.6,0.9,rr,plain,kfft",
+                    help="c4 legs to run: sat (saturated), 0.3/0.6/0.9 (Poisson rates), rr (round-robin at 0.9), "
+                         "plain (one request at a time), kfft (kappa-DFT plans)")
+    ap.add_argument("--serve-sat-rate", type=float, default=0.0,
+                    help="saturated request rate (req/s) to scale the arrival rates by, instead of measuring it")
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -71,6 +76,9 @@ def parse():
                     help="skip the pair sum through an FFT along kappa (reported beside the direct form)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--only", default=None, choices=["gaussian", "hashed"],
+                    help="run one leg of a direct workload alone (for profiling): the zero-bicoherence "
+                         "transforms, or the bispectrum generated per pair")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     return ap.parse_args()
@@ -265,6 +273,52 @@ def transform_bytes(wl, B, e=4):
 SERVE_GRIDS = [(64, 256), (256, 1024), (512, 4096), (1024, 8192)]
 
 
+def gaussian_bytes(wl, B, e=4):
+    """Algorithmic HBM bytes per launch of the zero-bicoherence path: the
+    t-transform reads the plan's FP64 spectrum and writes the t-transformed
+    rows (its phases are drawn in the kernel); the x-transform as above."""
+    lines = wl.n_kappa * wl.n_cols
+    return {"tfft": lines * 8 + B * wl.n_kappa * wl.n_t * 2 * e,
+            "xfft": B * wl.n_kappa * wl.n_t * 2 * e + B * wl.n_x * wl.n_t * e}
+
+
+def bench_only(args, torch, srm3, wl):
+    """One leg of a direct workload alone, timed with the plan's HIP events."""
+    B = args.batch or wl.batch
+    seeds = wl.seeds(B)
+    if args.only == "gaussian":
+        plan = srm3.srm3_plan(wl.grid_dict(), wl.spectrum(), None, "fp32")
+        nb = B
+    else:
+        plan = srm3.srm3_plan(wl.grid_dict(), wl.spectrum(), dict(kind="hashed", alpha=1e-4, beta_seed=wl.beta_seed,
+                                                                  cap=wl.cap, support_w=wl.support_w), "fp32")
+        nb = args.batch or (1 if wl.n_lines > 4_000_000 else 4)
+    out = torch.empty((nb, wl.n_x, wl.n_t), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        srm3.srm3_generate(plan, seeds[:nb], out)
+    torch.cuda.synchronize()
+    srm3.srm3_profile_enable(plan, True)
+    dt = timed_steps(torch, lambda: srm3.srm3_generate(plan, seeds[:nb], out), args.steps, 0)
+    prof = srm3.srm3_profile_read(plan)
+    ms = {k: v[0] / v[1] for k, v in prof.items() if v[1]}
+    rec = {"metric": "space-time grid points/sec", "value": nb * wl.grid_points / dt, "unit": "grid points/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{wl.name}: {wl.n_kappa}x{wl.n_omega} lines, {wl.n_x}x{wl.n_t} field, "
+                                  f"batch {nb}, {args.only} leg"},
+           "kernel_avg_ms": {k: round(v, 4) for k, v in ms.items()}}
+    if args.only == "gaussian":
+        tb = gaussian_bytes(wl, nb)
+        rec["transforms"] = {k: {"avg_launch_ms": round(ms[k], 4), "algorithmic_bytes": tb[k],
+                                 "GB_per_s": round(tb[k] / (ms[k] * 1e-3) / 1e9, 1),
+                                 "frac_of_hbm_peak": round(tb[k] / (ms[k] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                             for k in tb}
+    else:
+        terms = srm3.srm3_pair_terms(plan)
+        rec["pair_terms_per_s"] = terms * nb / (ms["pairsum"] * 1e-3)
+    print(json.dumps(rec))
+
+
 def serve_short(torch, srm3, n, pair_terms_per_s, pk):
     """A short replay of the served workload: n requests (grid uniform over
     the four served line grids, U ~ U[20, 45] m/s, arrival seed 42) at 0.9 x
@@ -426,95 +480,111 @@ def bench_serve(args, torch, srm3):
     """Serving: requests (grid uniform over 64x256 / 256x1024 / 512x4096 /
     1024x8192 lines, U ~ U[20, 45] m/s, spectrum evaluated on the device)
     arrive as a Poisson process at 0.3 / 0.6 / 0.9 x the measured saturated
-    request throughput; continuous batching vs one request at a time."""
+    request throughput; continuous batching vs one request at a time.  Legs can
+    be run separately (--serve-legs), the rates scaled by a given saturated
+    rate (--serve-sat-rate)."""
     pk = "mfma" if args.pair_kernel == "mfma" else "direct"
     from paper_2310_03979_amd import serve
-    grids = [(64, 256), (256, 1024), (512, 4096), (1024, 8192)]
+    legs = set(args.serve_legs.split(","))
     n = args.serve_requests
     rng = np.random.default_rng(42)
     plans = {}
-    for g in grids:
+    for g in SERVE_GRIDS:
         wl = inp.small_grid(*g, b2_scale=0.3)
         plans[g] = (wl, srm3.plan_from_workload(wl, "fp32"))
         if pk == "mfma":
             srm3.srm3_plan_set_algorithm(plans[g][1], "mfma")
     reqs = []
     for i in range(n):
-        g = grids[int(rng.integers(0, len(grids)))]
+        g = SERVE_GRIDS[int(rng.integers(0, len(SERVE_GRIDS)))]
         wl, plan = plans[g]
         reqs.append(dict(plan=plan, seed=4000 + i, b2_scale=1.0,
                          spectrum=dict(U=float(rng.uniform(20.0, 45.0))),
                          out=torch.empty(plan.field_shape, dtype=torch.float32, device="cuda"),
                          points=wl.grid_points, grid=g))
     points = sum(r["points"] for r in reqs)
-    mix = {f"{g[0]}x{g[1]}": sum(1 for r in reqs if r["grid"] == g) for g in grids}
-    log(f"[bench] serving: {n} requests per rate, mix {mix}")
+    mix = {f"{g[0]}x{g[1]}": sum(1 for r in reqs if r["grid"] == g) for g in SERVE_GRIDS}
+    log(f"[bench] serving: {n} requests per rate, mix {mix}, legs {sorted(legs)}")
     budget = 48 << 30
-    srv = srm3.Server("fp32", max_active=32, hbm_budget=budget, pair_kernel=pk)
     prog = lambda m: log("[bench]   " + m)                 # noqa: E731
+
+    def pct(r):
+        lat = r["latency"]
+        return dict(p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"], max_s=float(lat.max()),
+                    latency_samples=int(lat.size), makespan_s=r["makespan"],
+                    grid_points_per_s=points / r["makespan"])
+    out = {}
+    srv = srm3.Server("fp32", max_active=32, hbm_budget=budget, pair_kernel=pk)
     serve.replay(srv, reqs[:2], [0.0, 0.0])           # warm-up (first launches)
-    sat = serve.replay(srv, reqs, [0.0] * n, progress=prog)
-    thr = n / sat["makespan"]
-    log(f"[bench] saturated: {sat['makespan']:.2f} s for {n} requests ({thr:.3f} req/s)")
-    out = {"saturated": dict(makespan_s=sat["makespan"], requests_per_s=thr,
-                             grid_points_per_s=points / sat["makespan"])}
+    thr = args.serve_sat_rate
+    if "sat" in legs or thr <= 0:
+        sat = serve.replay(srv, reqs, [0.0] * n, progress=prog)
+        thr = n / sat["makespan"]
+        out["saturated"] = dict(makespan_s=sat["makespan"], requests_per_s=thr,
+                                grid_points_per_s=points / sat["makespan"], p50_s=sat["p50"], p99_s=sat["p99"])
+        log(f"[bench] saturated: {sat['makespan']:.2f} s for {n} requests ({thr:.3f} req/s)")
+    else:
+        out["saturated_rate_given"] = thr
     for f in (0.3, 0.6, 0.9):
+        if str(f) not in legs:
+            continue
         arr = serve.poisson_arrivals(n, f * thr, seed=42)
-        r = serve.replay(srv, reqs, arr, progress=prog)
-        out[f"rate_{f}"] = dict(rate_req_per_s=f * thr, p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"],
-                                makespan_s=r["makespan"], grid_points_per_s=points / r["makespan"])
+        r = serve.replay(srv, reqs, arr, progress=prog, timeout_s=3600.0)
+        out[f"rate_{f}"] = dict(rate_req_per_s=f * thr, **pct(r))
         log(f"[bench] rate {f}: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
     srv.destroy()
-    rr = srm3.Server("fp32", max_active=32, hbm_budget=budget, policy="round_robin", pair_kernel=pk)
-    arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
-    r = serve.replay(rr, reqs, arr, progress=prog)
-    rr.destroy()
-    out["round_robin_rate_0.9"] = dict(p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"], makespan_s=r["makespan"])
-    log(f"[bench] round-robin steps, rate 0.9: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
-    plain = srm3.Server("fp32", max_active=1, hbm_budget=budget, step_pair_terms=1e30, pair_kernel=pk)
-    psat = serve.replay(plain, reqs, [0.0] * n, progress=prog)
-    log(f"[bench] one at a time, saturated: {psat['makespan']:.2f} s")
-    arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
-    p9 = serve.replay(plain, reqs, arr, progress=prog)
-    plain.destroy()
-    # the same requests with plans that use the pair sum through a DFT along kappa
-    kplans = {}
-    for g in grids:
-        wl = plans[g][0]
-        kp = srm3.plan_from_workload(wl, "fp32")
-        srm3.srm3_plan_set_algorithm(kp, "kappa_fft")
-        kplans[g] = kp
-    kreqs = [dict(r, plan=kplans[r["grid"]]) for r in reqs]
-    ksrv = srm3.Server("fp32", max_active=32, hbm_budget=budget)
-    serve.replay(ksrv, kreqs[:2], [0.0, 0.0])
-    ksat = serve.replay(ksrv, kreqs, [0.0] * n, progress=prog)
-    kthr = n / ksat["makespan"]
-    kout = {"saturated": dict(makespan_s=ksat["makespan"], requests_per_s=kthr,
-                              grid_points_per_s=points / ksat["makespan"])}
-    for f in (0.3, 0.6, 0.9):
-        arr = serve.poisson_arrivals(n, f * kthr, seed=42)
-        r = serve.replay(ksrv, kreqs, arr, progress=prog)
-        kout[f"rate_{f}"] = dict(rate_req_per_s=f * kthr, p50_s=r["p50"], p99_s=r["p99"], mean_s=r["mean"],
-                                 makespan_s=r["makespan"])
-    ksrv.destroy()
-    out["kappa_fft"] = kout
-    log(f"[bench] kappa-DFT plans: saturated {ksat['makespan']:.3f} s ({kthr:.2f} req/s); rate 0.9 p50 "
-        f"{kout['rate_0.9']['p50_s']:.4f} s p99 {kout['rate_0.9']['p99_s']:.4f} s")
-    out["plain_one_at_a_time"] = {
-        "saturated_makespan_s": psat["makespan"], "saturated_grid_points_per_s": points / psat["makespan"],
-        "rate_0.9_p50_s": p9["p50"], "rate_0.9_p99_s": p9["p99"]}
-    log(f"[bench] one at a time: saturated {psat['makespan']:.2f} s; rate 0.9 p50 {p9['p50']:.3f} "
-        f"p99 {p9['p99']:.3f} s")
+    if "rr" in legs:
+        rr = srm3.Server("fp32", max_active=32, hbm_budget=budget, policy="round_robin", pair_kernel=pk)
+        arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
+        r = serve.replay(rr, reqs, arr, progress=prog, timeout_s=3600.0)
+        rr.destroy()
+        out["round_robin_rate_0.9"] = pct(r)
+        log(f"[bench] round-robin steps, rate 0.9: p50 {r['p50']:.3f} s p99 {r['p99']:.3f} s")
+    if "plain" in legs:
+        plain = srm3.Server("fp32", max_active=1, hbm_budget=budget, step_pair_terms=1e30, pair_kernel=pk)
+        psat = serve.replay(plain, reqs, [0.0] * n, progress=prog, timeout_s=3600.0)
+        log(f"[bench] one at a time, saturated: {psat['makespan']:.2f} s")
+        arr = serve.poisson_arrivals(n, 0.9 * thr, seed=42)
+        p9 = serve.replay(plain, reqs, arr, progress=prog, timeout_s=3600.0)
+        plain.destroy()
+        out["plain_one_at_a_time"] = {
+            "saturated_makespan_s": psat["makespan"], "saturated_grid_points_per_s": points / psat["makespan"],
+            "rate_0.9": pct(p9)}
+        log(f"[bench] one at a time: saturated {psat['makespan']:.2f} s; rate 0.9 p50 {p9['p50']:.3f} "
+            f"p99 {p9['p99']:.3f} s")
+    if "kfft" in legs:
+        # the same requests with plans that use the pair sum through a DFT along kappa
+        kplans = {}
+        for g in SERVE_GRIDS:
+            kp = srm3.plan_from_workload(plans[g][0], "fp32")
+            srm3.srm3_plan_set_algorithm(kp, "kappa_fft")
+            kplans[g] = kp
+        kreqs = [dict(r, plan=kplans[r["grid"]]) for r in reqs]
+        ksrv = srm3.Server("fp32", max_active=32, hbm_budget=budget)
+        serve.replay(ksrv, kreqs[:2], [0.0, 0.0])
+        ksat = serve.replay(ksrv, kreqs, [0.0] * n, progress=prog)
+        kthr = n / ksat["makespan"]
+        kout = {"saturated": dict(makespan_s=ksat["makespan"], requests_per_s=kthr,
+                                  grid_points_per_s=points / ksat["makespan"])}
+        for f in (0.3, 0.6, 0.9):
+            arr = serve.poisson_arrivals(n, f * kthr, seed=42)
+            r = serve.replay(ksrv, kreqs, arr, progress=prog, timeout_s=3600.0)
+            kout[f"rate_{f}"] = dict(rate_req_per_s=f * kthr, **pct(r))
+        ksrv.destroy()
+        out["kappa_fft"] = kout
+        log(f"[bench] kappa-DFT plans: saturated {ksat['makespan']:.3f} s ({kthr:.2f} req/s); rate 0.9 p50 "
+            f"{kout['rate_0.9']['p50_s']:.4f} s p99 {kout['rate_0.9']['p99_s']:.4f} s")
+    mk = out.get("saturated", {}).get("makespan_s")
     rec = {
         "metric": "space-time grid points/sec, batched FP32 vs plain; p50/p99 request latency",
-        "value": points / sat["makespan"], "unit": "grid points/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(sat["makespan"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "value": points / mk if mk else None, "unit": "grid points/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(mk * 1e3, 1) if mk else None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"pair_kernel": "matrix cores (FP32 MFMA)" if pk == "mfma" else "vector ALUs",
                    "workload": f"serving: {n} requests per rate, grids 64x256/256x1024/512x4096/1024x8192 "
                                f"lines (mix {mix}), U ~ U[20,45], Poisson arrivals (seed 42) at 0.3/0.6/0.9 x "
                                f"saturated throughput, continuous batching (32 slots, 48 GiB arena, "
-                               f"shortest remaining work first)"},
+                               f"shortest remaining work first)", "legs": sorted(legs)},
         "serving": out, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(rec))
@@ -637,6 +707,59 @@ def wind_theory(wl, c, r, sig):
     return var, m3 / var ** 1.5
 
 
+def bridge_same_sign(srm3, wl, S, B, outk, pooled):
+    """The bridge example under the other reading of the wind bispectrum on
+    signed frequencies: only interactions of partners of the same frequency
+    sign (sum interactions within the positive or the negative half; no
+    difference interactions).  Built as the product bispectrum B = F_k G_i G_j
+    H(i_w, j_w) with the wind's F = alpha 2 sqrt(S_k) / (3 sqrt(3 |w_k| kappa_k))
+    (zero where singular), G = sqrt(S) and H = 1 for i_w j_w >= 0, else 0;
+    the recursion decides whether the cap is needed.  1000 realizations
+    through the kappa-DFT pair sum, pooled moments, and the closed forms
+    E[u^2] = 2 sum S dk dw and E[u^3] = 6 (dk dw)^2 sum_k Re F_k (G * G)_k over
+    same-sign ordered pairs (exact when no cap applies)."""
+    nk, nw, W = wl.n_kappa, wl.n_omega, wl.support_w
+    kw = np.arange(-(nw - 1), nw)
+    kap = np.arange(nk) * wl.d_kappa
+    wabs = np.abs(kw) * wl.d_omega
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = wl.alpha * 2.0 * np.sqrt(S) / (3.0 * np.sqrt(3.0 * wabs[None, :] * kap[:, None]))
+    F[~np.isfinite(F)] = 0.0
+    F[0, :] = 0.0
+    F[:, kw == 0] = 0.0
+    G = np.sqrt(S)
+    iw = np.arange(-(W - 1), W)
+    H = (iw[:, None] * iw[None, :] >= 0).astype(np.complex128)
+    out = {"reading": "only same-sign frequency interactions (H = 1 where i_w j_w >= 0)"}
+    cap = 0.0
+    try:
+        srm3.srm3_product_factors(wl.grid_dict(), S, F.astype(np.complex128), G.astype(np.complex128), H, W, 0.0)
+    except srm3.Srm3Error as e:
+        out["uncapped"] = f"no admissible pure spectrum without a cap ({e})"
+        cap = wl.cap
+    out["cap"] = cap
+    bis = dict(kind="product", F=F.astype(np.complex128), G=G.astype(np.complex128), H=H, cap=cap, support_w=W)
+    kp = srm3.srm3_plan(wl.grid_dict(), S, bis, "fp32")
+    srm3.srm3_plan_set_algorithm(kp, "kappa_fft")
+    _, _, sig, sweeps = srm3.srm3_product_factors(wl.grid_dict(), S, F.astype(np.complex128),
+                                                  G.astype(np.complex128), H, W, cap)
+    out["recursion_sweeps"] = sweeps
+    out["lines_at_cap"] = float(np.mean(sig[S > 0] >= cap - 1e-12)) if cap > 0 else 0.0
+    out["max_sigma"] = float(sig.max())
+    out["1000_realizations"] = pooled(kp, 1000, 10000)
+    var = 2.0 * float(np.sum(S * wl.d_kappa * wl.d_omega))
+    Gp = np.where(kw[None, :] >= 0, G, 0.0)
+    Gm = np.where(kw[None, :] <= 0, G, 0.0)
+    shape = (2 * nk, 4 * nw)
+    conv = sum(np.fft.ifft2(np.fft.fft2(X, s=shape) ** 2).real[:nk, :] for X in (Gp, Gm))
+    # conv column c' corresponds to k_w = c' - 2 (nw - 1); lines hold |k_w| < nw
+    conv_l = conv[:, nw - 1:nw - 1 + 2 * nw - 1]
+    m3 = 6.0 * (wl.d_kappa * wl.d_omega) ** 2 * float(np.sum(F * conv_l))
+    out["theory"] = {"variance": round(var, 3), "skewness": round(m3 / var ** 1.5, 4),
+                     "exact": cap == 0.0 or out["lines_at_cap"] == 0.0}
+    return out
+
+
 def bench_bridge(args, torch, srm3):
     """The bridge example of Section 5: 256 x 128 lines, 1024 x 2048 field, the
     printed Kaimal/Davenport spectrum, the wind bispectrum through the
@@ -721,6 +844,7 @@ def bench_bridge(args, torch, srm3):
                                   "second_order_same_phases": pooled(gplan, 1000, 10000),
                                   "theory": stats["theory"]}
     stats["1000_realizations"]["seconds"] = round(time.perf_counter() - t1, 3)
+    stats["same_sign_reading"] = bridge_same_sign(srm3, wl, S, B, outk, pooled)
     log(f"[bench] statistics {stats}")
     extra = {}
     if not args.no_cpu:
@@ -793,6 +917,9 @@ def main():
         bench_bridge(args, torch, srm3)
         return
     wl = inp.WORKLOADS[args.workload]
+    if args.only:
+        bench_only(args, torch, srm3, wl)
+        return
     B = args.batch or wl.batch
     seeds = wl.seeds(B)
     grid_points = wl.grid_points * B

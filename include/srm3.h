@@ -154,10 +154,13 @@ typedef struct {
 
 /* SRM3_BISPEC_HASHED.  A bispectrum that depends on all four indices of a
  * pair, generated just in time: for the canonical member (i, j) of an
- * unordered pair (i_kappa > j_kappa, or equal and i_w >= j_w), Philox4x32-10
- * with key = beta_seed and counter (i_kappa, (uint32)i_w, j_kappa, (uint32)j_w)
- * gives b^2_raw = alpha * word0 / 2^32 and beta = 2 pi word1 / 2^32.  The
- * per-line raw sums are computed on the device when the plan is built
+ * unordered pair (i_kappa > j_kappa, or equal and i_w >= j_w), with
+ * m = floor(i_w / 8) and t = i_w - 8 m, Philox4x32-10 with key = beta_seed and
+ * counter (i_kappa, (uint32)m, j_kappa, (uint32)(i_w + j_w)) holds the pair's
+ * 16 bits h in word floor(t / 2) (high half for even t, low half for odd t):
+ * u = h >> 8, v = h & 255, b_p = sqrt(alpha) u / 2^8 (so b^2_raw =
+ * alpha (u / 2^8)^2) and beta = 2 pi v / 2^8.  One generator call thus serves
+ * the eight pairs of a line whose i_w share m.  The per-line raw sums are computed on the device when the plan is built
  * (O(pairs)), then the cap applies as usual.  Direct pair sum only (the
  * weights depend on kappa); not in batches or the server (SRM3_E_UNSUPPORTED);
  * g2, b2, beta tables and line factors are ignored. */

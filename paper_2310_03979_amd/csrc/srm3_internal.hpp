@@ -59,6 +59,30 @@ __host__ __device__ inline void philox_words01(uint32_t c0, uint32_t c1, uint32_
     *w1 = c1;
 }
 
+// All four output words of the same generator.
+__host__ __device__ inline void philox_words4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t key,
+                                              uint32_t (&w)[4])
+{
+    uint32_t k0 = static_cast<uint32_t>(key), k1 = static_cast<uint32_t>(key >> 32);
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    w[0] = c0;
+    w[1] = c1;
+    w[2] = c2;
+    w[3] = c3;
+}
+
 template <typename T> struct vec;
 template <> struct vec<float> { using v2 = float2; using v4 = float4; };
 template <> struct vec<double> { using v2 = double2; using v4 = double4; };

@@ -1375,78 +1375,152 @@ __global__ __launch_bounds__(256) void zero_cols_kernel(typename vec<T>::v2 *tsu
 // (self pair in full) and sums in FP64.  Without phases (zrow null) it sums
 // b^2_raw per line (plan time); else it writes the unscaled pair sum
 // sum sqrt(b^2_raw) e^{i(phi_i + phi_j + beta)}.
+// A bispectrum drawn per 4-index pair, just in time (no table).  For the
+// canonical member (i, j) of an unordered pair of line k = i + j, with
+// m = floor(i_w / 8) and t = i_w - 8 m, Philox4x32-10 (key, counter
+// (i_kappa, m, j_kappa, k_w)) holds the pair's 16 bits in word floor(t / 2)
+// (high half for even t, low half for odd t): u = the high byte, v = the low
+// byte, b_p = sqrt(alpha) u / 2^8 and beta = 2 pi v / 2^8.  One call thus
+// serves the eight pairs of a line whose i_w share m.
+//
+// A wave owns one output row k_kappa and 64 consecutive output columns (one
+// per lane); it walks the kappa splits i_kappa >= j_kappa and the partner
+// columns in steps of eight (one generator call per lane and step).  z_i is
+// the same for every lane (scalar loads), z_j is read at consecutive columns;
+// the next step's phase factors are loaded while the generator runs.
+// e^{i beta} comes from a 256-entry LDS table (FP64 sincospi, rounded to T).
+// FP32 plans sum blocks of 32 steps in FP32 and the blocks in FP64; FP64 plans
+// sum in FP64.  The SIGMA form writes the per-line raw sums
+// alpha sum_P (u / 2^8)^2 instead (integer sum of u^2, exact).
 struct HashPairArgs {
     Geometry g;
     uint64_t key;
     double scale;
-    const void *zrow;   // [B][nk][nc] phase factors, or null
-    void *tsum;         // [B][nk][nc] complex out
-    double *sig;        // [nk][nc] out when zrow is null
+    const void *zrow;   // [B][nk][nc] phase factors (pair-sum form)
+    void *tsum;         // [B][nk][nc] complex out (pair-sum form)
+    double *sig;        // [nk][nc] out (SIGMA form)
+    int n_cg;           // column groups of 256 (four waves of 64 columns)
 };
 
-template <typename T>
+__device__ __forceinline__ int floor_div8(int x) { return x >= 0 ? x >> 3 : -((-x + 7) >> 3); }
+
+template <typename T, bool SIGMA>
 __global__ __launch_bounds__(256) void pairsum_hash_kernel(HashPairArgs a)
 {
     using T2 = typename vec<T>::v2;
+    __shared__ T2 tab[256];
+    if (!SIGMA) {
+        const int m = threadIdx.x;
+        double sn, cs;
+        sincospi(static_cast<double>(m) * (1.0 / 128.0), &sn, &cs);   // 2 pi m / 256
+        tab[m].x = static_cast<T>(cs);
+        tab[m].y = static_cast<T>(sn);
+        __syncthreads();
+    }
     const Geometry &g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    const int kk = blockIdx.x / a.n_cg;
+    const int cg = blockIdx.x - kk * a.n_cg;
+    const int cw0 = (cg * 4 + wave) * 64;             // first column of the wave
+    if (cw0 >= g.nc) return;
+    const int c = cw0 + lane;
+    const bool col_ok = c < g.nc;
+    const int kw = c - (g.nw - 1);
+    const int Wm1 = g.W - 1;
+    // partner range of the lane and of the wave
+    const int lo = max(-Wm1, kw - Wm1), hi = min(Wm1, kw + Wm1);
+    const int kw_last = min(cw0 + 63, g.nc - 1) - (g.nw - 1);
+    const int wlo = max(-Wm1, cw0 - (g.nw - 1) - Wm1), whi = min(Wm1, kw_last + Wm1);
+    const int m_lo = floor_div8(wlo), m_hi = floor_div8(whi);
     const long per = static_cast<long>(g.nk) * g.nc;
-    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= per) return;
-    const int kk = static_cast<int>(idx / g.nc);
-    const int kw = static_cast<int>(idx - static_cast<long>(kk) * g.nc) - (g.nw - 1);
-    const T2 *z = a.zrow ? static_cast<const T2 *>(a.zrow) + static_cast<long>(blockIdx.y) * per : nullptr;
-    const int W = g.W;
-    const int lo0 = max(-(W - 1), kw - (W - 1)), hi = min(W - 1, kw + (W - 1));
-    double sr = 0.0, si = 0.0, s2 = 0.0;
-    for (int ik = (kk + 1) >> 1; ik <= kk; ++ik) {
-        const int jk = kk - ik;
-        const int lo = ik == jk ? max(lo0, (kw + 1) >> 1) : lo0;
-        for (int iw = lo; iw <= hi; ++iw) {
-            const int jw = kw - iw;
-            uint32_t w0, w1;
-            philox_words01(static_cast<uint32_t>(ik), static_cast<uint32_t>(iw), static_cast<uint32_t>(jk),
-                           static_cast<uint32_t>(jw), a.key, &w0, &w1);
-            const double b2 = a.scale * static_cast<double>(w0) * (1.0 / 4294967296.0);
-            if (!z) {
-                s2 += b2;
-                continue;
-            }
-            const T2 zi = z[static_cast<long>(ik) * g.nc + iw + g.nw - 1];
-            const T2 zj = z[static_cast<long>(jk) * g.nc + jw + g.nw - 1];
-            if constexpr (sizeof(T) == 4) {
-                // FP32 term (its rounding is far below the FP32 path's
-                // tolerance), FP64 sums: the angle pi w1 / 2^31 is split
-                // into its quadrant (top two bits) and a remainder in
-                // [0, pi/2), so the FP32 argument keeps 24 of its 30 bits
-                const float tr = zi.x * zj.x - zi.y * zj.y;
-                const float ti = zi.x * zj.y + zi.y * zj.x;
-                float s0, c0;
-                sincospif(static_cast<float>(w1 & 0x3FFFFFFFu) * (1.0f / 2147483648.0f), &s0, &c0);
-                const unsigned q = w1 >> 30;
-                const float sb = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
-                const float cb = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
-                const float bp = sqrtf(static_cast<float>(b2));
-                sr += static_cast<double>(bp * (tr * cb - ti * sb));
-                si += static_cast<double>(bp * (tr * sb + ti * cb));
-            } else {
-                const double tr = static_cast<double>(zi.x) * zj.x - static_cast<double>(zi.y) * zj.y;
-                const double ti = static_cast<double>(zi.x) * zj.y + static_cast<double>(zi.y) * zj.x;
-                double sb, cb;
-                sincospi(static_cast<double>(w1) * (1.0 / 2147483648.0), &sb, &cb);
-                const double bp = sqrt(b2);
-                sr += bp * (tr * cb - ti * sb);
-                si += bp * (tr * sb + ti * cb);
+    if (SIGMA) {
+        uint64_t su = 0;
+        for (int ik = (kk + 1) >> 1; ik <= kk; ++ik) {
+            const int jk = kk - ik;
+            for (int m = m_lo; m <= m_hi; ++m) {
+                uint32_t w[4];
+                philox_words4(static_cast<uint32_t>(ik), static_cast<uint32_t>(m), static_cast<uint32_t>(jk),
+                              static_cast<uint32_t>(kw), a.key, w);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const int iw = 8 * m + t;
+                    const bool ok = col_ok && iw >= lo && iw <= hi && (ik > jk || 2 * iw >= kw);
+                    const uint32_t h = (t & 1) ? (w[t >> 1] & 0xFFFFu) : (w[t >> 1] >> 16);
+                    const uint32_t u = ok ? (h >> 8) : 0u;
+                    su += u * u;
+                }
             }
         }
-    }
-    if (!z) {
-        a.sig[idx] = s2;
+        if (col_ok) a.sig[static_cast<long>(kk) * g.nc + c] = a.scale * (static_cast<double>(su) * (1.0 / 65536.0));
         return;
     }
-    T2 v;
-    v.x = static_cast<T>(sr);
-    v.y = static_cast<T>(si);
-    static_cast<T2 *>(a.tsum)[static_cast<long>(blockIdx.y) * per + idx] = v;
+    const T2 *z = static_cast<const T2 *>(a.zrow) + static_cast<long>(blockIdx.y) * per;
+    // z_j through a buffer resource over this realization's rows: partner
+    // columns outside the row read a neighbouring row's (finite) factor and
+    // offsets before the first or past the last row read zero; both carry a
+    // zero weight
+    const brsrc zr = make_brsrc(z, static_cast<unsigned>(per * sizeof(T2)));
+    double sr = 0.0, si = 0.0;
+    for (int ik = (kk + 1) >> 1; ik <= kk; ++ik) {
+        const int jk = kk - ik;
+        const T2 *zi_row = z + static_cast<long>(ik) * g.nc + (g.nw - 1);
+        // pair (i_w, k_w - i_w) applies to the lane iff lo2 <= i_w <= hi (canonical
+        // member: 2 i_w >= k_w when i_kappa = j_kappa); empty for lanes past the row
+        const int lo2 = ik > jk ? lo : max(lo, (kw + 1) >> 1);
+        const unsigned span = col_ok && hi >= lo2 ? static_cast<unsigned>(hi - lo2) : 0u;
+        const int base = col_ok && hi >= lo2 ? lo2 : 0x40000000;
+        // byte offset of z_j for i_w = 0 (row j_kappa, column k_w)
+        const int jo = (jk * g.nc + (g.nw - 1) + kw) * static_cast<int>(sizeof(T2));
+        T2 zi[8], zj[8];
+        auto load = [&](int m) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int iw = 8 * m + t;
+                zi[t] = zi_row[min(max(iw, -Wm1), Wm1)];
+                zj[t] = bload(zr, static_cast<unsigned>(jo - iw * static_cast<int>(sizeof(T2))), 0u, T(0));
+            }
+        };
+        load(m_lo);
+        for (int m0 = m_lo; m0 <= m_hi; m0 += 32) {
+            const int m1 = min(m_hi, m0 + 31);
+            T br = T(0), bi = T(0);
+            for (int m = m0; m <= m1; ++m) {
+                T2 ci[8], cj[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    ci[t] = zi[t];
+                    cj[t] = zj[t];
+                }
+                load(m + 1);   // clamped or range-checked, so safe past the last step too
+                uint32_t w[4];
+                philox_words4(static_cast<uint32_t>(ik), static_cast<uint32_t>(m), static_cast<uint32_t>(jk),
+                              static_cast<uint32_t>(kw), a.key, w);
+                const int d = 8 * m - base;
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const bool ok = static_cast<unsigned>(d + t) <= span;
+                    const uint32_t h = (t & 1) ? (w[t >> 1] & 0xFFFFu) : (w[t >> 1] >> 16);
+                    const T b = ok ? static_cast<T>(h >> 8) : T(0);   // u; the 1/2^8 is applied at the end
+                    const T2 e = tab[h & 0xFFu];
+                    const T pr = ci[t].x * cj[t].x - ci[t].y * cj[t].y;
+                    const T pi = ci[t].x * cj[t].y + ci[t].y * cj[t].x;
+                    const T fr = b * e.x, fi = b * e.y;
+                    br = fma_(fr, pr, fma_(-fi, pi, br));
+                    bi = fma_(fr, pi, fma_(fi, pr, bi));
+                }
+            }
+            sr += static_cast<double>(br);
+            si += static_cast<double>(bi);
+        }
+    }
+    if (!col_ok) return;
+    const long idx = static_cast<long>(kk) * g.nc + c;
+    const double sa = sqrt(a.scale) * (1.0 / 256.0);
+    T2 o;
+    o.x = static_cast<T>(sa * sr);
+    o.y = static_cast<T>(sa * si);
+    static_cast<T2 *>(a.tsum)[static_cast<long>(blockIdx.y) * per + idx] = o;
 }
 
 // Rank-one weights W(i_w, j_w) = g_i g_j (separable bicoherence, beta = 0):
@@ -1918,8 +1992,9 @@ static hipError_t pairsum_hash_t(const Geometry &g, uint64_t key, double scale, 
     a.zrow = ws ? ws->zrow : nullptr;
     a.tsum = ws ? ws->tsum : nullptr;
     a.sig = sig;
+    a.n_cg = (g.nc + 255) / 256;
     const long per = static_cast<long>(g.nk) * g.nc;
-    const unsigned gx = static_cast<unsigned>((per + 255) / 256);
+    const unsigned gx = static_cast<unsigned>(static_cast<long>(a.n_cg) * g.nk);
     hipError_t e = hipSuccess;
     for (int b0 = 0; b0 < (ws ? batch : 1); b0 += 65535) {
         const int nb = ws ? std::min(65535, batch - b0) : 1;
@@ -1928,7 +2003,10 @@ static hipError_t pairsum_hash_t(const Geometry &g, uint64_t key, double scale, 
             c.zrow = static_cast<const typename vec<T>::v2 *>(ws->zrow) + static_cast<long>(b0) * per;
             c.tsum = static_cast<typename vec<T>::v2 *>(ws->tsum) + static_cast<long>(b0) * per;
         }
-        pairsum_hash_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(c);
+        if (ws)
+            pairsum_hash_kernel<T, false><<<dim3(gx, nb), 256, 0, st>>>(c);
+        else
+            pairsum_hash_kernel<T, true><<<dim3(gx, nb), 256, 0, st>>>(c);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return e;

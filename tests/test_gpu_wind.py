@@ -266,6 +266,8 @@ HASH_CASES = [
     (13, 20, 9, 32, 64, 0.01, 0.0),
     (1, 8, 8, 1, 16, 0.05, 0.0),
     (24, 40, 40, 64, 128, 0.004, 0.9),
+    # several 256-column groups, a ragged last wave, partner range below the line range
+    (20, 300, 120, 32, 1024, 0.002, 0.5),
 ]
 
 
