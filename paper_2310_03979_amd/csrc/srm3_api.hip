@@ -127,6 +127,26 @@ srm3_status upload(DevBuf &buf, const std::vector<double> &v, int precision, hip
     return upload_bytes(buf, bytes.data(), bytes.size(), st);
 }
 
+// Twiddles of the register-blocked FFT's passes (fft_schedule): for pass p,
+// e^{+2 pi i r k / (R Ns)} at off[p] + (r - 1) Ns + k, interleaved (at least
+// one entry, so that N = 1 still has a table).
+std::vector<double> pass_twiddles(int N)
+{
+    const FftSched s = fft_schedule(N);
+    std::vector<double> v(2 * static_cast<size_t>(std::max(1, N - 1)), 0.0);
+    for (int p = 0; p < s.npass; ++p) {
+        const int R = s.R[p], Ns = s.Ns[p];
+        for (int r = 1; r < R; ++r)
+            for (int k = 0; k < Ns; ++k) {
+                const long double a = 2.0L * 3.14159265358979323846264338327950288L * (r * k) / (R * Ns);
+                const size_t i = static_cast<size_t>(s.off[p] + (r - 1) * Ns + k);
+                v[2 * i] = static_cast<double>(cosl(a));
+                v[2 * i + 1] = static_cast<double>(sinl(a));
+            }
+    }
+    return v;
+}
+
 // exp(+2 pi i n / N), n < N, interleaved
 std::vector<double> twiddles(int N)
 {
@@ -530,8 +550,8 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
     if (!lcx.empty() && (s = upload_bytes(p->lc, lcx.data(), lcx.size() * sizeof(double), st))) return s;
     if (!lrx.empty() && (s = upload_bytes(p->lr, lrx.data(), lrx.size() * sizeof(double), st))) return s;
     if (!hcx.empty() && (s = upload(p->wtab, hcx, precision, st))) return s;   // the prescribed H as the weights
-    if ((s = upload(p->tw_t, twiddles(nt), precision, st))) return s;
-    if ((s = upload(p->tw_x, twiddles(nx), precision, st))) return s;
+    if ((s = upload(p->tw_t, pass_twiddles(nt), precision, st))) return s;
+    if ((s = upload(p->tw_x, pass_twiddles(nx), precision, st))) return s;
     if (hashed) {
         // per-line raw sums of the generated bicoherence, on the device, then the cap check
         e = launch_pairsum_hash(g, precision, hash_key, hash_scale, 1, nullptr, static_cast<double *>(p->sig.p), st);

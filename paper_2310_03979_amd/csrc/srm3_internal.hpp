@@ -174,6 +174,37 @@ constexpr int kXcds = 8;
 // from the host `seeds` (no phase rows are read).
 // rout (n_x == n_kappa == 1 only, else ignored): write the real field [B][n_t]
 // directly; the x-transform is then skipped.
+// Pass schedule of the register-blocked Stockham FFT of length N (a power of
+// two, 1 <= N <= 16384): radix-16 passes while a factor 16 is left, then one
+// pass of radix 2, 4 or 8.  Pass p has radix R[p] and span Ns[p] (product of
+// the earlier radices); its twiddles e^{+2 pi i r k / (R Ns)}, r = 1 .. R - 1,
+// k < Ns, sit at off[p] + (r - 1) Ns + k of the plan's table (N - 1 entries).
+struct FftSched {
+    int N, npass;
+    int R[6], Ns[6], off[6];
+};
+inline FftSched fft_schedule(int N)
+{
+    FftSched s{};
+    s.N = N;
+    int ns = 1, off = 0;
+    while (ns * 16 <= N) {
+        s.R[s.npass] = 16;
+        s.Ns[s.npass] = ns;
+        s.off[s.npass] = off;
+        off += 15 * ns;
+        ns *= 16;
+        ++s.npass;
+    }
+    if (ns < N) {
+        s.R[s.npass] = N / ns;
+        s.Ns[s.npass] = ns;
+        s.off[s.npass] = off;
+        ++s.npass;
+    }
+    return s;
+}
+
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
                        const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st,
                        void *rout = nullptr, const uint64_t *seeds = nullptr);

@@ -1035,11 +1035,13 @@ struct TfftArgs {
     int b0;
     AmpArgs amp;
     const void *wtab;     // [ncw][ncw]
-    const void *tw;       // [nt]
+    const void *tw;       // pass twiddles of n_t (fft_schedule)
     void *gout;           // [B][nt / xtw][nk][xtw]: t-transformed rows in tiles of xtw columns
     void *rout;           // n_x == 1 only, or null: the field itself, [B][nt] real (no x-transform)
-    int tw_lds;           // 1: the twiddles are copied to LDS after the row
-    int xtw;              // columns per tile of gout (the x-transform's tile width)
+    int xtw;              // columns per tile of gout (the x-transform's tile width, a power of two)
+    FftSched sched;       // length n_t
+    int np;               // rows per block (a power of two)
+    int rows;             // rows of the launch (realizations x n_kappa)
 };
 
 // Coefficient of line (b, kk, c) from its pair sum, phase and amplitudes.
@@ -1105,65 +1107,296 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
     return C;
 }
 
-template <typename T, int MAXB>
-__global__ __launch_bounds__(1024) void tfft_kernel(TfftArgs a)
+// ---------------------------------------------------------------------------
+// Register-blocked Stockham FFT (inverse, e^{+2 pi i n m / N}) of the t- and
+// x-transforms (Section 4.3: the double sum as two batches of 1-D FFTs).
+// Every thread holds 16 elements: the 16 / R butterflies of a radix-R pass
+// (fft_schedule: radix 16, then one pass of radix 2, 4 or 8).  The first pass
+// takes its inputs from a functor (computed or read from global memory, no
+// LDS staging), the last hands its outputs to another (written to global
+// memory), and the passes in between exchange through LDS.  LDS addresses go
+// through an XOR swizzle of bits 0-3 by bits 4-8, which spreads the stride-16
+// writes of the first pass over the banks.  Twiddles of a pass come from the
+// plan's table in global memory, indexed (r - 1) Ns + k with k running over
+// the lanes.  Two layouts: transform-major (element n of transform f at
+// f N + n, a transform's butterflies on consecutive lanes; the t-transform,
+// whose inputs and outputs run along n) and interleaved (at n np + f, the
+// transforms on consecutive lanes; the x-transform, whose inputs and outputs
+// run along the transforms).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lds_swz(int e) { return e ^ (((e >> 4) ^ (e >> 5)) & 15); }
+__device__ __forceinline__ int ilog2i(int x) { return __builtin_ctz(static_cast<unsigned>(x)); }
+
+template <typename T2>
+__device__ __forceinline__ void idft4(T2 &x0, T2 &x1, T2 &x2, T2 &x3)
+{
+    const auto ar = x0.x + x2.x, ai = x0.y + x2.y, br = x0.x - x2.x, bi = x0.y - x2.y;
+    const auto cr = x1.x + x3.x, ci = x1.y + x3.y, dr = x1.x - x3.x, di = x1.y - x3.y;
+    x0.x = ar + cr;
+    x0.y = ai + ci;
+    x2.x = ar - cr;
+    x2.y = ai - ci;
+    x1.x = br - di;   // (x0 - x2) + i (x1 - x3)
+    x1.y = bi + dr;
+    x3.x = br + di;   // (x0 - x2) - i (x1 - x3)
+    x3.y = bi - dr;
+}
+
+// x * (cr + i ci)
+template <typename T, typename T2>
+__device__ __forceinline__ T2 cmulc(T2 x, T cr, T ci)
+{
+    T2 r;
+    r.x = x.x * cr - x.y * ci;
+    r.y = x.x * ci + x.y * cr;
+    return r;
+}
+
+// In-register inverse DFT of R points; output m sits at x[idft_pos<R>(m)].
+template <int R>
+__device__ __forceinline__ constexpr int idft_pos(int m)
+{
+    return R == 16 ? 4 * (m & 3) + (m >> 2) : m;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void idft(typename vec<T>::v2 (&x)[R])
+{
+    using T2 = typename vec<T>::v2;
+    constexpr T h = T(0.70710678118654752440);    // cos(pi/4)
+    constexpr T c8 = T(0.92387953251128675613);   // cos(pi/8)
+    constexpr T s8 = T(0.38268343236508977173);   // sin(pi/8)
+    if constexpr (R == 2) {
+        const T2 a = x[0];
+        x[0].x = a.x + x[1].x;
+        x[0].y = a.y + x[1].y;
+        x[1].x = a.x - x[1].x;
+        x[1].y = a.y - x[1].y;
+    } else if constexpr (R == 4) {
+        idft4(x[0], x[1], x[2], x[3]);
+    } else if constexpr (R == 8) {
+        idft4(x[0], x[2], x[4], x[6]);   // even half: E_m at x[2m]
+        idft4(x[1], x[3], x[5], x[7]);   // odd half:  O_m at x[2m + 1]
+        T2 o[4];
+        o[0] = x[1];
+        o[1].x = (x[3].x - x[3].y) * h;   // O_1 e^{i pi/4}
+        o[1].y = (x[3].x + x[3].y) * h;
+        o[2].x = -x[5].y;                 // O_2 e^{i pi/2}
+        o[2].y = x[5].x;
+        o[3].x = -(x[7].x + x[7].y) * h;  // O_3 e^{3 i pi/4}
+        o[3].y = (x[7].x - x[7].y) * h;
+        T2 y[8];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            y[m].x = x[2 * m].x + o[m].x;
+            y[m].y = x[2 * m].y + o[m].y;
+            y[m + 4].x = x[2 * m].x - o[m].x;
+            y[m + 4].y = x[2 * m].y - o[m].y;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = y[m];
+    } else {
+        static_assert(R == 16, "radix 2, 4, 8 or 16");
+        // n = 4 n1 + n2, m = k1 + 4 k2: four 4-point DFTs over n1, twiddles
+        // e^{2 pi i n2 k1 / 16}, four 4-point DFTs over n2
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) idft4(x[n2], x[4 + n2], x[8 + n2], x[12 + n2]);
+        x[5] = cmulc(x[5], c8, s8);     // k1 = 1, n2 = 1: e^{i pi/8}
+        x[6] = cmulc(x[6], h, h);       //         n2 = 2: e^{i pi/4}
+        x[7] = cmulc(x[7], s8, c8);     //         n2 = 3: e^{3 i pi/8}
+        x[9] = cmulc(x[9], h, h);       // k1 = 2, n2 = 1: e^{i pi/4}
+        {
+            const T t = x[10].x;        //         n2 = 2: e^{i pi/2}
+            x[10].x = -x[10].y;
+            x[10].y = t;
+        }
+        x[11] = cmulc(x[11], -h, h);    //         n2 = 3: e^{3 i pi/4}
+        x[13] = cmulc(x[13], s8, c8);   // k1 = 3, n2 = 1: e^{3 i pi/8}
+        x[14] = cmulc(x[14], -h, h);    //         n2 = 2: e^{3 i pi/4}
+        x[15] = cmulc(x[15], -c8, -s8); //         n2 = 3: e^{9 i pi/8}
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) idft4(x[4 * k1], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
+    }
+}
+
+// One radix-R pass over np transforms of length N = 2^lg_n (span Ns = 2^lg_s):
+// butterfly q = threadIdx.x + i blockDim.x, i < 16 / R, reads elements
+// j + r N / R of its transform, twiddles them by e^{2 pi i r k / (R Ns)}
+// (k = j mod Ns), and writes output r to (j / Ns) R Ns + k + r Ns.
+template <typename T, int R, bool INTER, bool FIRST, bool LAST, class In, class Out>
+__device__ __forceinline__ void fft_pass(typename vec<T>::v2 *buf, int lg_n, int lg_s, int np, int lg_np,
+                                         const typename vec<T>::v2 *__restrict__ tw, const In &in, const Out &out)
+{
+    using T2 = typename vec<T>::v2;
+    constexpr int NB = 16 / R;
+    constexpr int LR = R == 16 ? 4 : (R == 8 ? 3 : (R == 4 ? 2 : 1));
+    const int lg_nb = lg_n - LR;
+    const int nb = 1 << lg_nb;
+    const int Ns = 1 << lg_s;
+    const int total = np << lg_nb;
+    T2 x[NB][R];
+    int fq[NB], jq[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int q = threadIdx.x + i * blockDim.x;
+        const int f = INTER ? (q & (np - 1)) : (q >> lg_nb);
+        const int j = INTER ? (q >> lg_np) : (q & (nb - 1));
+        fq[i] = q < total ? f : -1;
+        jq[i] = j;
+        const int k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int n = j + r * nb;
+            T2 v;
+            v.x = T(0);
+            v.y = T(0);
+            if (q < total) {
+                if (FIRST) {
+                    v = in(f, n);
+                } else {
+                    v = buf[lds_swz(INTER ? (n << lg_np) + f : (f << lg_n) + n)];
+                    if (r > 0) v = cmul<T>(v, tw[(r - 1) * Ns + k]);
+                }
+            }
+            x[i][r] = v;
+        }
+        idft<T, R>(x[i]);
+    }
+    if (!FIRST) __syncthreads();   // every read of the pass before its writes
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        if (fq[i] < 0) continue;
+        const int f = fq[i], j = jq[i];
+        const int d0 = ((j >> lg_s) << (lg_s + LR)) + (j & (Ns - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int d = d0 + r * Ns;
+            const T2 v = x[i][idft_pos<R>(r)];
+            if (LAST)
+                out(f, d, v);
+            else
+                buf[lds_swz(INTER ? (d << lg_np) + f : (f << lg_n) + d)] = v;
+        }
+    }
+    if (!LAST) __syncthreads();
+}
+
+template <typename T, bool INTER, bool FIRST, bool LAST, class In, class Out>
+__device__ __forceinline__ void fft_pass_r(int R, typename vec<T>::v2 *buf, int lg_n, int lg_s, int np, int lg_np,
+                                           const typename vec<T>::v2 *tw, const In &in, const Out &out)
+{
+    switch (R) {
+    case 16: fft_pass<T, 16, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
+    case 8: fft_pass<T, 8, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
+    case 4: fft_pass<T, 4, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
+    default: fft_pass<T, 2, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
+    }
+}
+
+// np transforms of length s.N (blockDim.x * 16 >= np N elements).
+template <typename T, bool INTER, class In, class Out>
+__device__ __forceinline__ void fft_block(typename vec<T>::v2 *buf, const FftSched &s, int np, const typename vec<T>::v2 *tw,
+                          const In &in, const Out &out)
+{
+    if (s.npass == 0) {   // N = 1
+        for (int f = threadIdx.x; f < np; f += blockDim.x) out(f, 0, in(f, 0));
+        return;
+    }
+    const int lg_n = ilog2i(s.N), lg_np = ilog2i(np);
+    if (s.npass == 1) {
+        fft_pass_r<T, INTER, true, true>(s.R[0], buf, lg_n, 0, np, lg_np, tw, in, out);
+        return;
+    }
+    // two or more passes: the first and the middle ones are radix 16
+    fft_pass<T, 16, INTER, true, false>(buf, lg_n, 0, np, lg_np, tw, in, out);
+    for (int p = 1; p + 1 < s.npass; ++p)
+        fft_pass<T, 16, INTER, false, false>(buf, lg_n, ilog2i(s.Ns[p]), np, lg_np, tw + s.off[p], in, out);
+    const int p = s.npass - 1;
+    fft_pass_r<T, INTER, false, true>(s.R[p], buf, lg_n, ilog2i(s.Ns[p]), np, lg_np, tw + s.off[p], in, out);
+}
+
+template <typename T>
+__global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftArgs a)
 {
     using T2 = typename vec<T>::v2;
     extern __shared__ unsigned char smem_raw[];
     T2 *buf = reinterpret_cast<T2 *>(smem_raw);
-    const Geometry &g = a.g;
-    const int row = blockIdx.x;                 // b * nk + kk (b within the launch's chunk)
-    const int b = row / g.nk, kk = row - b * g.nk;
-    for (int n = threadIdx.x; n < g.nt; n += blockDim.x) {
-        T2 zero;
-        zero.x = T(0);
-        zero.y = T(0);
-        buf[n] = zero;
+    // the functors below capture copies of the arguments they use (a
+    // reference to the kernel argument itself would move it to scratch)
+    const Geometry g = a.g;
+    const int np = a.np, rows = a.rows, mode = a.mode;
+    const int row0 = blockIdx.x * np;   // rows b * nk + kk of the launch's chunk
+    // mode 2: the seeds of the block's rows (one row: a scalar; several: after the rows in LDS)
+    uint64_t seed0 = 0;
+    uint64_t *seed_l = reinterpret_cast<uint64_t *>(buf + static_cast<long>(np) * g.nt);
+    if (mode == 2) {
+        auto seed_of = [](const TfftArgs &x, int row, int nk) -> uint64_t {
+            const int b = row / nk;
+            return x.seeds_dev ? x.seeds_dev[x.b0 + b] : x.seeds.s[b];
+        };
+        if (np == 1) {
+            seed0 = seed_of(a, row0, g.nk);
+        } else {
+            for (int f = threadIdx.x; f < np; f += blockDim.x)
+                seed_l[f] = row0 + f < rows ? seed_of(a, row0 + f, g.nk) : 0;
+            __syncthreads();
+        }
     }
-    T2 *twl = buf + g.nt;
-    const bool twin = a.tw_lds;
-    if (twin)
-        for (int n = threadIdx.x; n < g.nt; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
-    __syncthreads();
-    for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
-        const int kw = c - (g.nw - 1);
-        const int bin = kw < 0 ? kw + g.nt : kw;
+    const AmpArgs amp = a.amp;
+    const T2 *zrow = static_cast<const T2 *>(a.zrow);
+    const T2 *tsum = static_cast<const T2 *>(a.tsum);
+    const T2 *wtab = static_cast<const T2 *>(a.wtab);
+    const T2 *cin = static_cast<const T2 *>(a.cin);
+    // coefficient of bin n (k_w = n, or n - n_t above the zero gap) of row row0 + f
+    auto in = [=](int f, int n) -> T2 {
         T2 C;
-        if (a.mode == 2) {
+        C.x = T(0);
+        C.y = T(0);
+        const int row = row0 + f;
+        int kw = n;
+        if (n >= g.nw) {
+            if (n <= g.nt - g.nw || row >= rows) return C;
+            kw = n - g.nt;
+        } else if (row >= rows) {
+            return C;
+        }
+        const int b = row / g.nk, kk = row - b * g.nk;
+        const int c = kw + g.nw - 1;
+        if (mode == 2) {
             // C = A_pure e^{i phi}: the phase of the line as the phase kernel
             // draws it (Philox word, FP64 sincos, rounded)
-            const uint64_t seed = a.seeds_dev ? a.seeds_dev[a.b0 + b] : a.seeds.s[b];
+            const uint64_t seed = np == 1 ? seed0 : seed_l[f];
             const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
             double sn, cs;
             sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &sn, &cs);
             const long li = static_cast<long>(kk) * g.nc + c;
-            const double *Sp = (a.amp.S_b && a.amp.S_b[b]) ? a.amp.S_b[b] : a.amp.S;
-            const T p = static_cast<T>(2.0 * sqrt(Sp[li] * a.amp.dkdw));
+            const double *Sp = (amp.S_b && amp.S_b[b]) ? amp.S_b[b] : amp.S;
+            const T p = static_cast<T>(2.0 * sqrt(Sp[li] * amp.dkdw));
             C.x = p * static_cast<T>(cs);
             C.y = p * static_cast<T>(sn);
-        } else if (a.mode == 0) {
-            C = assemble_line<T>(g, b, kk, c, static_cast<const typename vec<T>::v2 *>(a.zrow), static_cast<const T2 *>(a.tsum),
-                                 a.amp, static_cast<const T2 *>(a.wtab));
+        } else if (mode == 0) {
+            C = assemble_line<T>(g, b, kk, c, zrow, tsum, amp, wtab);
         } else {
-            C = static_cast<const T2 *>(a.cin)[static_cast<long>(row) * g.nc + c];
+            C = cin[static_cast<long>(row) * g.nc + c];
         }
-        buf[bin] = C;
-    }
-    __syncthreads();
-    fft_lds<T, MAXB>(buf, g.nt, g.nt, 1, twin ? twl : static_cast<const T2 *>(a.tw));
-    if (a.rout) {
-        // one kappa line and one x point: the x-transform is the real part
-        T *u = static_cast<T *>(a.rout) + static_cast<long>(row) * g.nt;
-        for (int n = threadIdx.x; n < g.nt; n += blockDim.x) u[n] = buf[n].x;
-        return;
-    }
-    // tile-major rows: the x-transform of a tile then reads one contiguous block
-    const int xtw = a.xtw;
-    T2 *gout = static_cast<T2 *>(a.gout) + static_cast<long>(b) * g.nk * g.nt + static_cast<long>(kk) * xtw;
-    for (int n = threadIdx.x; n < g.nt; n += blockDim.x) {
-        const int tile = n / xtw;
-        gout[static_cast<long>(tile) * g.nk * xtw + (n - tile * xtw)] = buf[n];
-    }
+        return C;
+    };
+    const int xtw = a.xtw, lg_w = ilog2i(xtw);
+    T *rout = static_cast<T *>(a.rout);
+    T2 *gout = static_cast<T2 *>(a.gout);
+    auto out = [=](int f, int n, T2 v) {
+        const int row = row0 + f;
+        if (row >= rows) return;
+        if (rout) {   // one kappa line and one x point: the x-transform is the real part
+            rout[static_cast<long>(row) * g.nt + n] = v.x;
+            return;
+        }
+        // tile-major rows: the x-transform of a tile then reads one contiguous block
+        const int b = row / g.nk, kk = row - b * g.nk;
+        const int tile = n >> lg_w;
+        gout[static_cast<long>(b) * g.nk * g.nt + (static_cast<long>(tile) * g.nk + kk) * xtw + (n - (tile << lg_w))] = v;
+    };
+    fft_block<T, false>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
 }
 
 template <typename T>
@@ -1184,24 +1417,24 @@ __global__ __launch_bounds__(256) void assemble_kernel(TfftArgs a, typename vec<
 
 struct XfftArgs {
     Geometry g;
+    FftSched sched;      // length n_x
     int tcols;           // columns (t samples) per block: one tile of gin
     const void *gin;     // [B][nt / tcols][nk][tcols]
-    const void *tw;      // [nx]
+    const void *tw;      // pass twiddles of n_x
     void *out;           // [B][nx][nt] real
     void *const *out_b;  // per realization output, or null (out + b * nx * nt)
-    int tw_lds;          // 1: the twiddles are copied to LDS after the tile (low-latency stage reads)
-    int ld;              // LDS elements between two packed transforms (>= nx)
 };
 
 // The x-transform takes the real part, so two columns share one complex
-// transform: with a_1, a_2 the columns (non-zero at kk < nk <= nx / 2) and
+// transform: with a_1, a_2 the columns (non-zero at kk < nk <= nx) and
 // y_j[n] = (a_j[n] + conj a_j[nx - n]) / 2 (Hermitian, so its inverse DFT is
 // Re IDFT(a_j)), the inverse DFT of z = y_1 + i y_2 holds column 1's field in
 // its real part and column 2's in its imaginary part.  One block transforms
 // one tile of tcols columns (a contiguous block of gin) in tcols / 2 packed
-// transforms.
-template <typename T, int MAXB>
-__global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
+// transforms, transform f on lane f: the tile's rows are read and the field's
+// rows written as runs of tcols consecutive values.
+template <typename T>
+__global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void xfft_kernel(XfftArgs a)
 {
     using T2 = typename vec<T>::v2;
     extern __shared__ unsigned char smem_raw[];
@@ -1213,72 +1446,68 @@ __global__ __launch_bounds__(1024) void xfft_kernel(XfftArgs a)
     const int mt0 = blockIdx.x * tc;
     const int N = g.nx;
     const int nk = g.nk;
-    const int ld = a.ld;   // transforms N + 8 apart: consecutive transforms start 16 banks apart
-    T2 *twl = buf + np * ld;
-    const bool twin = a.tw_lds;
-    if (twin)
-        for (int n = threadIdx.x; n < N; n += blockDim.x) twl[n] = static_cast<const T2 *>(a.tw)[n];
     const T2 *gin = static_cast<const T2 *>(a.gin) + (static_cast<long>(b) * g.nt + mt0) * nk;
-    if (2 * nk <= N) {
-        // a[n] and a[N - n] never both non-zero: each input lands in two entries
-        // zero the entries no input reaches: nk <= n <= N - nk of every transform
-        const int gap = N - 2 * nk + 1;
-        for (int n = threadIdx.x; n < np * gap; n += blockDim.x) {
-            const int p = n / gap;
-            T2 zero;
-            zero.x = T(0);
-            zero.y = T(0);
-            buf[p * ld + nk + (n - p * gap)] = zero;
-        }
-        for (int n = threadIdx.x; n < np * nk; n += blockDim.x) {
-            const int kk = n / np, p = n - kk * np;
-            const T2 a1 = gin[static_cast<long>(kk) * tc + 2 * p];
-            T2 a2;
+    const bool sparse = 2 * nk <= N;   // a[n] and a[N - n] never both non-zero
+    auto col2 = [&](int kk, int f, T2 &a1, T2 &a2) {
+        const T2 *p = gin + static_cast<long>(kk) * tc + 2 * f;
+        a1 = p[0];
+        if (2 * f + 1 < tc) {
+            a2 = p[1];
+        } else {
             a2.x = T(0);
             a2.y = T(0);
-            if (2 * p + 1 < tc) a2 = gin[static_cast<long>(kk) * tc + 2 * p + 1];
-            T2 *B = buf + p * ld;
-            if (kk == 0) {
-                B[0].x = a1.x;
-                B[0].y = a2.x;
-            } else {
-                B[kk].x = T(0.5) * (a1.x - a2.y);
-                B[kk].y = T(0.5) * (a1.y + a2.x);
-                B[N - kk].x = T(0.5) * (a1.x + a2.y);
-                B[N - kk].y = T(0.5) * (a2.x - a1.y);
-            }
         }
-    } else {
+    };
+    auto in = [&](int f, int n) -> T2 {
+        T2 r;
+        r.x = T(0);
+        r.y = T(0);
+        T2 a1, a2;
+        if (sparse) {
+            if (n == 0) {
+                col2(0, f, a1, a2);
+                r.x = a1.x;
+                r.y = a2.x;
+            } else if (n < nk) {
+                col2(n, f, a1, a2);
+                r.x = T(0.5) * (a1.x - a2.y);
+                r.y = T(0.5) * (a1.y + a2.x);
+            } else if (n > N - nk) {
+                col2(N - n, f, a1, a2);
+                r.x = T(0.5) * (a1.x + a2.y);
+                r.y = T(0.5) * (a2.x - a1.y);
+            }
+            return r;
+        }
         // n_x < 2 n_kappa: entry n takes a[n] and conj a[N - n] together
-        for (int n = threadIdx.x; n < np * N; n += blockDim.x) {
-            const int kk = n / np, p = n - kk * np;
-            const int km = (N - kk) & (N - 1);
-            T2 y[2];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                T2 u, v;
-                u.x = u.y = v.x = v.y = T(0);
-                if (2 * p + j < tc) {
-                    if (kk < nk) u = gin[static_cast<long>(kk) * tc + 2 * p + j];
-                    if (km < nk) v = gin[static_cast<long>(km) * tc + 2 * p + j];
-                }
-                y[j].x = T(0.5) * (u.x + v.x);
-                y[j].y = T(0.5) * (u.y - v.y);
+        const int km = (N - n) & (N - 1);
+        T2 u1, u2, v1, v2;
+        u1.x = u1.y = u2.x = u2.y = v1.x = v1.y = v2.x = v2.y = T(0);
+        if (n < nk) col2(n, f, u1, u2);
+        if (km < nk) col2(km, f, v1, v2);
+        const T y1r = T(0.5) * (u1.x + v1.x), y1i = T(0.5) * (u1.y - v1.y);
+        const T y2r = T(0.5) * (u2.x + v2.x), y2i = T(0.5) * (u2.y - v2.y);
+        r.x = y1r - y2i;
+        r.y = y1i + y2r;
+        return r;
+    };
+    T *outp = a.out_b ? static_cast<T *>(a.out_b[b]) : static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
+    // pairs of columns as one store where the field is aligned for it
+    const bool vec_out = (reinterpret_cast<uintptr_t>(outp) & (sizeof(T2) - 1)) == 0 && (g.nt & 1) == 0;
+    auto out = [&](int f, int mx, T2 z) {
+        T *o = outp + static_cast<long>(mx) * g.nt + mt0 + 2 * f;
+        if (2 * f + 1 < tc) {
+            if (vec_out) {
+                *reinterpret_cast<T2 *>(o) = z;
+            } else {
+                o[0] = z.x;
+                o[1] = z.y;
             }
-            buf[p * ld + kk].x = y[0].x - y[1].y;
-            buf[p * ld + kk].y = y[0].y + y[1].x;
+        } else {
+            o[0] = z.x;
         }
-    }
-    __syncthreads();
-    fft_lds<T, MAXB>(buf, N, ld, np, twin ? twl : static_cast<const T2 *>(a.tw));
-    T *out = a.out_b ? static_cast<T *>(a.out_b[b]) : static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
-    for (int n = threadIdx.x; n < np * N; n += blockDim.x) {
-        const int mx = n / np, p = n - mx * np;
-        const T2 z = buf[p * ld + mx];
-        T *o = out + static_cast<long>(mx) * g.nt + mt0 + 2 * p;
-        o[0] = z.x;
-        if (2 * p + 1 < tc) o[1] = z.y;
-    }
+    };
+    fft_block<T, true>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2124,14 +2353,34 @@ hipError_t launch_fill_u32(void *p, size_t words, uint32_t v, hipStream_t st)
 // Columns per tile of the t-transformed rows = the x-transform's tile width:
 // 64 KB of packed transforms (nx complex values per pair of columns), at most
 // n_t.  Both launchers take it from here, so the two layouts agree.
+// Elements of one block of the register-blocked FFT: 16 per thread, at most
+// 1024 threads (512 for FP64), 128 KB of LDS.
+template <typename T>
+constexpr int fft_block_elems()
+{
+    return sizeof(T) == 8 ? 8192 : 16384;
+}
+
+// Columns per block of the x-transform, which is also the tile width of the
+// t-transform's output: two columns per packed transform, as many transforms
+// as fill a block (at most 32), never more than n_t.  A power of two.  Both
+// launchers take it from here, so the two layouts agree.
 template <typename T>
 static int xfft_cols(const Geometry &g)
 {
-    const size_t pair_bytes = static_cast<size_t>(g.nx) * sizeof(typename vec<T>::v2);
-    int tc = static_cast<int>(std::max<size_t>(1, 65536 / pair_bytes)) * 2;
-    if (tc > 64) tc = 64;
+    int np = fft_block_elems<T>() / g.nx;
+    if (np > 32) np = 32;
+    if (np < 1) np = 1;
+    int tc = 2 * np;
     if (tc > g.nt) tc = g.nt;
     return tc;
+}
+
+static int fft_block_threads(long elems)
+{
+    long t = (elems + 15) / 16;
+    t = ((t + 63) / 64) * 64;
+    return static_cast<int>(std::max(64L, std::min(1024L, t)));
 }
 
 template <typename T>
@@ -2154,22 +2403,26 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     a.tw = tw;
     a.gout = ws.g;
     a.xtw = xfft_cols<T>(g);
-    const int thr = fft_threads(g.nt / 2);
-    size_t lds = static_cast<size_t>(g.nt) * sizeof(T2);
-    a.tw_lds = 2 * lds <= 131072 ? 1 : 0;
-    if (a.tw_lds) lds *= 2;
+    a.sched = fft_schedule(g.nt);
+    // short rows share a block (1024 elements per block, at most 64 rows)
+    a.np = g.nt >= 1024 ? 1 : std::min(64, 1024 / g.nt);
+    const int thr = fft_block_threads(static_cast<long>(a.np) * g.nt);
+    // rows, then (several rows per block) their seeds
+    const size_t lds = static_cast<size_t>(a.np) * g.nt * sizeof(T2) + (a.np > 1 ? a.np * sizeof(uint64_t) : 0);
     // mode 2 with host seeds: kernel-argument chunks of realizations (the
     // per-realization spectrum and scale arrays are not used in this mode)
     const int chunk = mode == 2 ? kMaxSeedsPerLaunch : batch;
     for (int b0 = 0; b0 < batch; b0 += chunk) {
         const int nb = std::min(chunk, batch - b0);
         TfftArgs c = a;
+        c.rows = nb * g.nk;
         if (mode == 2) {
             for (int i = 0; i < nb; ++i) c.seeds.s[i] = seeds[b0 + i];
             c.gout = static_cast<T2 *>(ws.g) + static_cast<long>(b0) * g.nk * g.nt;
             if (c.rout) c.rout = static_cast<T *>(rout) + static_cast<long>(b0) * g.nt;
         }
-        tfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(nb * g.nk)), thr, lds, st>>>(c);
+        const unsigned blocks = static_cast<unsigned>((c.rows + a.np - 1) / a.np);
+        tfft_kernel<T><<<dim3(blocks), thr, lds, st>>>(c);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -2214,21 +2467,17 @@ static hipError_t xfft_t(const Geometry &g, const void *tw, int batch, const Wor
 {
     XfftArgs a;
     a.g = g;
+    a.sched = fft_schedule(g.nx);
     const int tc = xfft_cols<T>(g);
     const int np = (tc + 1) / 2;
-    const size_t col_bytes = static_cast<size_t>(g.nx) * sizeof(typename vec<T>::v2);
     a.tcols = tc;
     a.gin = ws.g;
     a.tw = tw;
     a.out = out;
     a.out_b = out_b;
-    const int thr = fft_threads(np * g.nx / 2);
-    a.ld = g.nx;
-    if (static_cast<size_t>(np) * (g.nx + 8) * sizeof(typename vec<T>::v2) + col_bytes <= 131072) a.ld = g.nx + 8;
-    size_t lds = static_cast<size_t>(np) * a.ld * sizeof(typename vec<T>::v2);
-    a.tw_lds = lds + col_bytes <= 131072 ? 1 : 0;
-    if (a.tw_lds) lds += col_bytes;
-    xfft_kernel<T, kFftMaxB><<<dim3(static_cast<unsigned>(g.nt / tc), batch), thr, lds, st>>>(a);
+    const int thr = fft_block_threads(static_cast<long>(np) * g.nx);
+    const size_t lds = static_cast<size_t>(np) * g.nx * sizeof(typename vec<T>::v2);
+    xfft_kernel<T><<<dim3(static_cast<unsigned>(g.nt / tc), batch), thr, lds, st>>>(a);
     return hipGetLastError();
 }
 
@@ -2460,7 +2709,7 @@ template <typename T>
 static hipError_t prepare_t()
 {
     const int lds = 131072;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T, kFftMaxB>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rowconv_kernel<T, kFftMaxB>),
@@ -2469,7 +2718,7 @@ static hipError_t prepare_t()
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&colfft_kernel<T, kFftMaxB>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T, kFftMaxB>),
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
