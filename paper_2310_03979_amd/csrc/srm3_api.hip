@@ -84,7 +84,26 @@ AmpRef plan_amp(srm3_plan_t p)
 {
     return AmpRef{static_cast<const double *>(p->S.p), static_cast<const double *>(p->sig.p), nullptr, nullptr,
                   p->dk * p->dw, p->cap, p->gaussian ? 0 : (p->hashed ? 2 : 1), static_cast<const double *>(p->lc.p),
-                  static_cast<const double *>(p->lr.p)};
+                  static_cast<const double *>(p->lr.p), p->amp_t.p};
+}
+
+// The plan's per-line amplitudes at unit scale (plans without line factors);
+// recomputed whenever the spectrum changes.
+srm3_status refresh_amp_table(srm3_plan_t p, hipStream_t st)
+{
+    if (p->lc.p || p->lr.p) return SRM3_OK;
+    const long n = static_cast<long>(p->g.nk) * p->g.nc;
+    const size_t bytes = static_cast<size_t>(n) * (p->precision == SRM3_FP64 ? 16 : 8);
+    if (!p->amp_t.p) {
+        hipError_t e = p->amp_t.alloc(bytes);
+        if (e != hipSuccess) return fail(SRM3_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    hipError_t e = launch_amp_table(p->precision, n, static_cast<const double *>(p->S.p),
+                                    static_cast<const double *>(p->sig.p), p->dk * p->dw, p->cap, p->amp_t.p, st);
+    if (e != hipSuccess) return dev_err(e, "amplitude-table kernel");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
+    return SRM3_OK;
 }
 
 double max_sigma(double max_sig, double cap, double scale)
@@ -565,6 +584,7 @@ srm3_status srm3_plan(const srm3_grid *grid, const srm3_spectrum *spectrum, cons
             return fail(SRM3_E_PURE_NEGATIVE, "a line has sum of b^2 = %.6g >= 1: pure spectrum not positive",
                         max_sigma(p->max_sig, bs.cap, 1.0));
     }
+    if ((s = refresh_amp_table(p.get(), st))) return s;
     *out_plan = p.release();
     return SRM3_OK;
 }
@@ -722,7 +742,7 @@ srm3_status srm3_set_spectrum(srm3_plan_t plan, const srm3_spectrum *spectrum, v
     if (e != hipSuccess) return dev_err(e, "hipMemcpyAsync");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return dev_err(e, "hipStreamSynchronize");
-    return SRM3_OK;
+    return refresh_amp_table(plan, st);
 }
 
 srm3_status srm3_spectrum_kaimal_davenport(const srm3_grid *grid, const srm3_kaimal_davenport *params,
@@ -1245,6 +1265,7 @@ srm3_status batch_launch(srm3_batch_t b, hipStream_t st, bool time_pairsum)
         AmpRef amp = plan_amp(gr.plan);
         amp.scale_b = static_cast<const double *>(b->scales.p) + gr.first;
         amp.S_b = static_cast<const double *const *>(b->sptr.p) + gr.first;
+        amp.tab = nullptr;   // per-realization scales and spectra: amplitudes per line
         e = launch_tfft(gr.g, b->precision, 0, nullptr, amp, gr.plan->wtab.p, gr.plan->tw_t.p, nb, ws, st);
         if (e != hipSuccess) return dev_err(e, "t-transform kernel");
         e = launch_xfft(gr.g, b->precision, gr.plan->tw_x.p, nb, ws, nullptr,

@@ -132,6 +132,8 @@ struct AmpRef {
     const double *lc = nullptr;   // per-line complex pair factor c_k, interleaved (NULL = 1)
     const double *lr = nullptr;   // per-line complex phase factor rho_k, interleaved (NULL = 1);
                                   // the pure part divides it out
+    const void *tab = nullptr;    // per-line (A_pure, A_pair) of the plan's spectrum at unit scale,
+                                  // rounded to the plan's type (NULL: evaluated per line in FP64)
 };
 
 // Kernel launchers (stream-ordered, return the launch status).
@@ -205,6 +207,10 @@ inline FftSched fft_schedule(int N)
     return s;
 }
 
+// Per-line amplitudes (A_pure, A_pair) of a plan at unit scale, in the plan's
+// type, exactly as the assembly evaluates them in FP64 and rounds them.
+hipError_t launch_amp_table(int precision, long n, const double *S, const double *sig, double dkdw, double cap,
+                            void *out, hipStream_t st);
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
                        const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st,
                        void *rout = nullptr, const uint64_t *seeds = nullptr);
@@ -298,6 +304,7 @@ struct srm3_plan_s {
     double pair_terms = 0;
     int device = 0;
     srm3::DevBuf wtab, S, sig, tw_t, tw_x, ws;
+    srm3::DevBuf amp_t;   // per-line (A_pure, A_pair) at unit scale (plans without line factors)
     srm3::DevBuf lc, lr;     // per-line complex bicoherence factors c, rho (interleaved FP64), or empty
     int ws_batch = 0;
     bool gaussian = false;   // zero bicoherence: no pair sum (2nd-order SRM)

@@ -160,7 +160,10 @@ template <> struct ALayout<double> {
 };
 
 // ---------------------------------------------------------------------------
-// Phases.  One thread per (realization, padded row, column).
+// Phases.  A block covers a tile of 64 columns x TR rows of one realization:
+// each thread draws TR / 4 lines of its column (phase rows written along the
+// columns), and the a operand, which is kappa-contiguous, is staged in LDS
+// and written along the rows.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
@@ -168,42 +171,67 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
                                                     typename vec<T>::v2 *__restrict__ zrow,
                                                     T *__restrict__ zcol, const double *__restrict__ lr)
 {
-    const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int bl = blockIdx.y;
-    const long per = static_cast<long>(g.nkp) * g.nc;
-    if (idx >= per) return;
-    const int kk = static_cast<int>(idx / g.nc);
-    const int c = static_cast<int>(idx - static_cast<long>(kk) * g.nc);
-    const int kw = c - (g.nw - 1);
+    constexpr int TR = sizeof(T) == 8 ? 32 : 64;   // rows per tile
+    __shared__ T at[3][64][TR + 1];
+    const int bl = blockIdx.z;
     const int b = b0 + bl;
-    double s = 0.0, co = 0.0;
-    if (kk < g.nk) {
-        const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
-        const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
-        sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
-        if (lr) {
-            // per-line complex bicoherence factor rho_k carried by the phase factor
-            const long l = static_cast<long>(kk) * g.nc + c;
-            const double xr = lr[2 * l], xi = lr[2 * l + 1];
-            const double cr = co * xr - s * xi, ci = co * xi + s * xr;
-            co = cr;
-            s = ci;
+    const int c0 = blockIdx.x * 64, k0 = blockIdx.y * TR;
+    const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
+    const int ct = threadIdx.x & 63;
+    const int c = c0 + ct;
+    const int kw = c - (g.nw - 1);
+    const int ic0 = c0 - (g.nw - g.W);   // support column of the tile's first column
+    const bool planes = zcol && ic0 + 63 >= 0 && ic0 < g.ncw;
+#pragma unroll 4
+    for (int i = 0; i < TR / 4; ++i) {
+        const int kt = (threadIdx.x >> 6) + 4 * i;
+        const int kk = k0 + kt;
+        double s = 0.0, co = 0.0;   // rows past n_kappa (padding) hold zero
+        if (c < g.nc && kk < g.nk) {
+            const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
+            sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
+            if (lr) {
+                // per-line complex bicoherence factor rho_k carried by the phase factor
+                const long l = static_cast<long>(kk) * g.nc + c;
+                const double xr = lr[2 * l], xi = lr[2 * l + 1];
+                const double cr = co * xr - s * xi, ci = co * xi + s * xr;
+                co = cr;
+                s = ci;
+            }
+            typename vec<T>::v2 v;
+            v.x = static_cast<T>(co);
+            v.y = static_cast<T>(s);
+            zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
         }
-        typename vec<T>::v2 v;
-        v.x = static_cast<T>(co);
-        v.y = static_cast<T>(s);
-        zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
+        if (planes) {
+            at[0][ct][kt] = static_cast<T>(co);
+            at[1][ct][kt] = static_cast<T>(co + s);
+            at[2][ct][kt] = static_cast<T>(s - co);
+        }
     }
-    const int ic = c - (g.nw - g.W);
-    if (zcol && ic >= 0 && ic < g.ncw) {   // zcol null: no direct-form pair sum follows
-        using L = ALayout<T>;
-        const long plane = L::plane(g);
-        T *zc = zcol + static_cast<long>(b) * L::NS * g.ncw * g.nkp +
-                (static_cast<long>(ic) * g.nkp + kk) * L::ES;
-        zc[0] = static_cast<T>(co);
-        zc[plane] = static_cast<T>(co + s);
-        zc[2 * plane] = static_cast<T>(s - co);
-        if (L::NS == 4) zc[3] = T(0);
+    if (!planes) return;   // zcol null: no direct-form pair sum follows
+    __syncthreads();
+    using L = ALayout<T>;
+    const long plane = L::plane(g);
+    T *zb = zcol + static_cast<long>(b) * L::NS * g.ncw * g.nkp;
+    const int kt = threadIdx.x % TR;
+    const int kk = k0 + kt;
+#pragma unroll 4
+    for (int i = 0; i < 64 * TR / 256; ++i) {
+        const int ct2 = threadIdx.x / TR + (256 / TR) * i;
+        const int ic = ic0 + ct2;
+        if (ic < 0 || ic >= g.ncw || kk >= g.nkp) continue;
+        T *zc = zb + (static_cast<long>(ic) * g.nkp + kk) * L::ES;
+        if constexpr (L::NS == 4) {
+            // (re, re + im), (im - re, 0): two 16-byte stores per row
+            double2 *z2 = reinterpret_cast<double2 *>(zc);
+            z2[0] = make_double2(at[0][ct2][kt], at[1][ct2][kt]);
+            z2[1] = make_double2(at[2][ct2][kt], 0.0);
+        } else {
+            zc[0] = at[0][ct2][kt];
+            zc[plane] = at[1][ct2][kt];
+            zc[2 * plane] = at[2][ct2][kt];
+        }
     }
 }
 
@@ -1021,6 +1049,7 @@ struct AmpArgs {
     int pairs;                // 0: no pair sums (zero bicoherence)
     const double *lc;         // per-line complex pair factor c_k (interleaved), or null (1)
     const double *lr;         // per-line complex factor rho_k carried by zrow (interleaved), or null (1)
+    const void *tab;          // per-line (A_pure, A_pair) in T at unit scale and the plan's spectrum, or null
 };
 
 struct TfftArgs {
@@ -1071,6 +1100,15 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
             t.x += T(0.5) * d.x;
             t.y += T(0.5) * d.y;
         }
+    }
+    if (amp.tab && !amp.scale_b && !amp.S_b) {
+        // the same amplitudes, evaluated once per plan
+        const T2 pq = static_cast<const T2 *>(amp.tab)[li];
+        const T2 z = zrow[bi];
+        T2 C;
+        C.x = fma_(pq.x, z.x, pq.y * t.x);
+        C.y = fma_(pq.x, z.y, pq.y * t.y);
+        return C;
     }
     const double *Sp = (amp.S_b && amp.S_b[b]) ? amp.S_b[b] : amp.S;
     const double sc = amp.scale_b ? amp.scale_b[b] : 1.0;
@@ -1370,8 +1408,13 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
             double sn, cs;
             sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &sn, &cs);
             const long li = static_cast<long>(kk) * g.nc + c;
-            const double *Sp = (amp.S_b && amp.S_b[b]) ? amp.S_b[b] : amp.S;
-            const T p = static_cast<T>(2.0 * sqrt(Sp[li] * amp.dkdw));
+            T p;
+            if (amp.tab && !amp.S_b) {
+                p = static_cast<const T2 *>(amp.tab)[li].x;
+            } else {
+                const double *Sp = (amp.S_b && amp.S_b[b]) ? amp.S_b[b] : amp.S;
+                p = static_cast<T>(2.0 * sqrt(Sp[li] * amp.dkdw));
+            }
             C.x = p * static_cast<T>(cs);
             C.y = p * static_cast<T>(sn);
         } else if (mode == 0) {
@@ -1397,6 +1440,25 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         gout[static_cast<long>(b) * g.nk * g.nt + (static_cast<long>(tile) * g.nk + kk) * xtw + (n - (tile << lg_w))] = v;
     };
     fft_block<T, false>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
+}
+
+// (A_pure, A_pair) per line at unit scale: the FP64 expressions of
+// assemble_line with scale 1, rounded to T.
+template <typename T>
+__global__ __launch_bounds__(256) void amp_table_kernel(const double *__restrict__ S, const double *__restrict__ sig,
+                                                        double dkdw, double cap, long n,
+                                                        typename vec<T>::v2 *__restrict__ out)
+{
+    const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double sc = 1.0;
+    const double sraw = sc * sig[i];
+    const double rho = (cap > 0.0 && sraw > cap) ? cap / sraw : 1.0;
+    const double base = S[i] * dkdw;
+    typename vec<T>::v2 v;
+    v.x = static_cast<T>(2.0 * sqrt(base * (1.0 - rho * sraw)));
+    v.y = static_cast<T>(2.0 * sqrt(base * rho * sc));
+    out[i] = v;
 }
 
 template <typename T>
@@ -2095,8 +2157,8 @@ template <typename T>
 static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint64_t *seeds_dev, int batch,
                            const Workspace &ws, const double *lr, hipStream_t st)
 {
-    const long per = static_cast<long>(g.nkp) * g.nc;
-    const unsigned gx = static_cast<unsigned>((per + 255) / 256);
+    constexpr int TR = sizeof(T) == 8 ? 32 : 64;
+    const unsigned gx = static_cast<unsigned>((g.nc + 63) / 64), gy = static_cast<unsigned>((g.nkp + TR - 1) / TR);
     // seeds travel as kernel arguments in chunks, or are read from the device
     const int chunk = seeds_dev ? 65535 : kMaxSeedsPerLaunch;
     for (int b0 = 0; b0 < batch; b0 += chunk) {
@@ -2104,7 +2166,7 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
         SeedChunk sc{};
         if (!seeds_dev)
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
-        phase_kernel<T><<<dim3(gx, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
+        phase_kernel<T><<<dim3(gx, gy, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
                                                        static_cast<typename vec<T>::v2 *>(ws.zrow),
                                                        static_cast<T *>(ws.zcol), lr);
         const hipError_t e = hipGetLastError();
@@ -2398,7 +2460,7 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     a.tsum = ws.tsum;
     a.seeds_dev = nullptr;
     a.b0 = 0;
-    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr};
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr, amp.tab};
     a.wtab = wtab;
     a.tw = tw;
     a.gout = ws.g;
@@ -2429,6 +2491,17 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     return hipSuccess;
 }
 
+hipError_t launch_amp_table(int precision, long n, const double *S, const double *sig, double dkdw, double cap,
+                            void *out, hipStream_t st)
+{
+    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+    if (precision == SRM3_FP64)
+        amp_table_kernel<double><<<blocks, 256, 0, st>>>(S, sig, dkdw, cap, n, static_cast<double2 *>(out));
+    else
+        amp_table_kernel<float><<<blocks, 256, 0, st>>>(S, sig, dkdw, cap, n, static_cast<float2 *>(out));
+    return hipGetLastError();
+}
+
 hipError_t launch_tfft(const Geometry &g, int precision, int mode, const void *cin, const AmpRef &amp,
                        const void *wtab, const void *tw, int batch, const Workspace &ws, hipStream_t st, void *rout,
                        const uint64_t *seeds)
@@ -2446,7 +2519,7 @@ static hipError_t assemble_t(const Geometry &g, const AmpRef &amp, const void *w
     a.g = g;
     a.zrow = ws.zrow;
     a.tsum = ws.tsum;
-    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr};
+    a.amp = AmpArgs{amp.S, amp.sig, amp.scale_b, amp.S_b, amp.dkdw, amp.cap, amp.pairs, amp.lc, amp.lr, amp.tab};
     a.wtab = wtab;
     const long per = static_cast<long>(g.nk) * g.nc;
     assemble_kernel<T><<<dim3(static_cast<unsigned>((per + 255) / 256), batch), 256, 0, st>>>(

@@ -495,6 +495,7 @@ srm3_status srm3_server_step(srm3_server_t s, srm3_server_state *state)
             AmpRef amp = plan_amp(q->r.plan);
             amp.scale_b = &hdr_dev[q->slot].scale;
             amp.S_b = &hdr_dev[q->slot].S;
+            amp.tab = nullptr;   // per-realization scales and spectra: amplitudes per line
             e = launch_tfft(q->g, s->cfg.precision, 0, nullptr, amp, q->r.plan->wtab.p, q->r.plan->tw_t.p, 1, ws,
                             st);
             if (e != hipSuccess) return dev_err(e, "t-transform kernel");
