@@ -1152,9 +1152,9 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
 // (fft_schedule: radix 16, then one pass of radix 2, 4 or 8).  The first pass
 // takes its inputs from a functor (computed or read from global memory, no
 // LDS staging), the last hands its outputs to another (written to global
-// memory), and the passes in between exchange through LDS.  LDS addresses go
-// through an XOR swizzle of bits 0-3 by bits 4-8, which spreads the stride-16
-// writes of the first pass over the banks.  Twiddles of a pass come from the
+// memory), and the passes in between exchange through LDS (the transform-major
+// layout padded by one element every 256 bytes against the bank conflicts of
+// the first pass's stride-16 writes).  Twiddles of a pass come from the
 // plan's table in global memory, indexed (r - 1) Ns + k with k running over
 // the lanes.  Two layouts: transform-major (element n of transform f at
 // f N + n, a transform's butterflies on consecutive lanes; the t-transform,
@@ -1162,7 +1162,6 @@ __device__ __forceinline__ typename vec<T>::v2 assemble_line(const Geometry &g, 
 // transforms on consecutive lanes; the x-transform, whose inputs and outputs
 // run along the transforms).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lds_swz(int e) { return e ^ (((e >> 4) ^ (e >> 5)) & 15); }
 __device__ __forceinline__ int ilog2i(int x) { return __builtin_ctz(static_cast<unsigned>(x)); }
 
 template <typename T2>
@@ -1257,21 +1256,42 @@ __device__ __forceinline__ void idft(typename vec<T>::v2 (&x)[R])
     }
 }
 
-// One radix-R pass over np transforms of length N = 2^lg_n (span Ns = 2^lg_s):
-// butterfly q = threadIdx.x + i blockDim.x, i < 16 / R, reads elements
-// j + r N / R of its transform, twiddles them by e^{2 pi i r k / (R Ns)}
-// (k = j mod Ns), and writes output r to (j / Ns) R Ns + k + r Ns.
-template <typename T, int R, bool INTER, bool FIRST, bool LAST, class In, class Out>
-__device__ __forceinline__ void fft_pass(typename vec<T>::v2 *buf, int lg_n, int lg_s, int np, int lg_np,
+// LDS index of element e in the transform-major layout: one pad element every
+// 256 bytes, which puts the stride-16 writes of the first pass on distinct
+// banks (the interleaved layout is not padded: its lanes run along the
+// transforms).
+template <typename T>
+__host__ __device__ constexpr int fft_lds_elems(int n)
+{
+    return n + (n >> (sizeof(T) == 4 ? 5 : 4)) + 1;
+}
+
+template <typename T>
+__device__ __forceinline__ int lpad(int e)
+{
+    return e + (e >> (sizeof(T) == 4 ? 5 : 4));
+}
+
+// One radix-R pass of span Ns = 2^LG_S over np transforms of length
+// N = 2^lg_n: butterfly q = threadIdx.x + i blockDim.x, i < 16 / R, reads
+// elements j + r N / R of its transform, twiddles them by
+// e^{2 pi i r k / (R Ns)} (k = j mod Ns), and writes output r to
+// (j / Ns) R Ns + k + r Ns.
+template <typename T, int R, int LG_S, bool INTER, bool FIRST, bool LAST, class In, class Out>
+__device__ __forceinline__ void fft_pass(typename vec<T>::v2 *buf, int lg_n, int np, int lg_np,
                                          const typename vec<T>::v2 *__restrict__ tw, const In &in, const Out &out)
 {
     using T2 = typename vec<T>::v2;
     constexpr int NB = 16 / R;
     constexpr int LR = R == 16 ? 4 : (R == 8 ? 3 : (R == 4 ? 2 : 1));
+    constexpr int Ns = 1 << LG_S;
+    constexpr int PS = sizeof(T) == 4 ? 5 : 4;   // pad shift
     const int lg_nb = lg_n - LR;
     const int nb = 1 << lg_nb;
-    const int Ns = 1 << lg_s;
     const int total = np << lg_nb;
+    // transform-major reads are linear in r when N / R is a multiple of the pad period
+    const bool lin = nb >= (1 << PS);
+    const int pnb = nb + (nb >> PS);
     T2 x[NB][R];
     int fq[NB], jq[NB];
 #pragma unroll
@@ -1279,24 +1299,39 @@ __device__ __forceinline__ void fft_pass(typename vec<T>::v2 *buf, int lg_n, int
         const int q = threadIdx.x + i * blockDim.x;
         const int f = INTER ? (q & (np - 1)) : (q >> lg_nb);
         const int j = INTER ? (q >> lg_np) : (q & (nb - 1));
-        fq[i] = q < total ? f : -1;
+        const bool valid = q < total;
+        fq[i] = valid ? f : -1;
         jq[i] = j;
-        const int k = j & (Ns - 1);
+        if (valid) {
+            if (FIRST) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int n = j + r * nb;
-            T2 v;
-            v.x = T(0);
-            v.y = T(0);
-            if (q < total) {
-                if (FIRST) {
-                    v = in(f, n);
+                for (int r = 0; r < R; ++r) x[i][r] = in(f, j + r * nb);
+            } else {
+                if (INTER) {
+                    const int b0 = (j << lg_np) + f, st = nb << lg_np;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) x[i][r] = buf[b0 + r * st];
+                } else if (lin) {
+                    const int b0 = lpad<T>((f << lg_n) + j);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) x[i][r] = buf[b0 + r * pnb];
                 } else {
-                    v = buf[lds_swz(INTER ? (n << lg_np) + f : (f << lg_n) + n)];
-                    if (r > 0) v = cmul<T>(v, tw[(r - 1) * Ns + k]);
+                    const int b0 = (f << lg_n) + j;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) x[i][r] = buf[lpad<T>(b0 + r * nb)];
+                }
+                if (Ns > 1) {
+                    const T2 *t = tw + (j & (Ns - 1));
+#pragma unroll
+                    for (int r = 1; r < R; ++r) x[i][r] = cmul<T>(x[i][r], t[(r - 1) * Ns]);
                 }
             }
-            x[i][r] = v;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                x[i][r].x = T(0);
+                x[i][r].y = T(0);
+            }
         }
         idft<T, R>(x[i]);
     }
@@ -1305,55 +1340,63 @@ __device__ __forceinline__ void fft_pass(typename vec<T>::v2 *buf, int lg_n, int
     for (int i = 0; i < NB; ++i) {
         if (fq[i] < 0) continue;
         const int f = fq[i], j = jq[i];
-        const int d0 = ((j >> lg_s) << (lg_s + LR)) + (j & (Ns - 1));
+        const int d0 = ((j >> LG_S) << (LG_S + LR)) + (j & (Ns - 1));
+        if (LAST) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int d = d0 + r * Ns;
-            const T2 v = x[i][idft_pos<R>(r)];
-            if (LAST)
-                out(f, d, v);
-            else
-                buf[lds_swz(INTER ? (d << lg_np) + f : (f << lg_n) + d)] = v;
+            for (int r = 0; r < R; ++r) out(f, d0 + r * Ns, x[i][idft_pos<R>(r)]);
+        } else if (INTER) {
+            const int b0 = (d0 << lg_np) + f;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[b0 + ((r * Ns) << lg_np)] = x[i][idft_pos<R>(r)];
+        } else {
+            const int e0 = (f << lg_n) + d0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[lpad<T>(e0 + r * Ns)] = x[i][idft_pos<R>(r)];
         }
     }
     if (!LAST) __syncthreads();
 }
 
-template <typename T, bool INTER, bool FIRST, bool LAST, class In, class Out>
-__device__ __forceinline__ void fft_pass_r(int R, typename vec<T>::v2 *buf, int lg_n, int lg_s, int np, int lg_np,
+template <typename T, int LG_S, bool INTER, bool FIRST, bool LAST, class In, class Out>
+__device__ __forceinline__ void fft_pass_r(int R, typename vec<T>::v2 *buf, int lg_n, int np, int lg_np,
                                            const typename vec<T>::v2 *tw, const In &in, const Out &out)
 {
     switch (R) {
-    case 16: fft_pass<T, 16, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
-    case 8: fft_pass<T, 8, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
-    case 4: fft_pass<T, 4, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
-    default: fft_pass<T, 2, INTER, FIRST, LAST>(buf, lg_n, lg_s, np, lg_np, tw, in, out); break;
+    case 16: fft_pass<T, 16, LG_S, INTER, FIRST, LAST>(buf, lg_n, np, lg_np, tw, in, out); break;
+    case 8: fft_pass<T, 8, LG_S, INTER, FIRST, LAST>(buf, lg_n, np, lg_np, tw, in, out); break;
+    case 4: fft_pass<T, 4, LG_S, INTER, FIRST, LAST>(buf, lg_n, np, lg_np, tw, in, out); break;
+    default: fft_pass<T, 2, LG_S, INTER, FIRST, LAST>(buf, lg_n, np, lg_np, tw, in, out); break;
     }
 }
 
-// np transforms of length s.N (blockDim.x * 16 >= np N elements).
+// np transforms of length s.N (blockDim.x * 16 >= np N elements).  The pass
+// spans are 1, 16, 256, 4096 (compile time): radix 16 up to the last pass.
 template <typename T, bool INTER, class In, class Out>
-__device__ __forceinline__ void fft_block(typename vec<T>::v2 *buf, const FftSched &s, int np, const typename vec<T>::v2 *tw,
-                          const In &in, const Out &out)
+__device__ __forceinline__ void fft_block(typename vec<T>::v2 *buf, const FftSched &s, int np,
+                                          const typename vec<T>::v2 *tw, const In &in, const Out &out)
 {
     if (s.npass == 0) {   // N = 1
         for (int f = threadIdx.x; f < np; f += blockDim.x) out(f, 0, in(f, 0));
         return;
     }
     const int lg_n = ilog2i(s.N), lg_np = ilog2i(np);
-    if (s.npass == 1) {
-        fft_pass_r<T, INTER, true, true>(s.R[0], buf, lg_n, 0, np, lg_np, tw, in, out);
+    const int last = s.npass - 1, RL = s.R[last];
+    if (last == 0) {
+        fft_pass_r<T, 0, INTER, true, true>(RL, buf, lg_n, np, lg_np, tw, in, out);
         return;
     }
-    // two or more passes: the first and the middle ones are radix 16
-    fft_pass<T, 16, INTER, true, false>(buf, lg_n, 0, np, lg_np, tw, in, out);
-    for (int p = 1; p + 1 < s.npass; ++p)
-        fft_pass<T, 16, INTER, false, false>(buf, lg_n, ilog2i(s.Ns[p]), np, lg_np, tw + s.off[p], in, out);
-    const int p = s.npass - 1;
-    fft_pass_r<T, INTER, false, true>(s.R[p], buf, lg_n, ilog2i(s.Ns[p]), np, lg_np, tw + s.off[p], in, out);
+    fft_pass<T, 16, 0, INTER, true, false>(buf, lg_n, np, lg_np, tw, in, out);
+    if (last >= 2) fft_pass<T, 16, 4, INTER, false, false>(buf, lg_n, np, lg_np, tw + s.off[1], in, out);
+    if (last >= 3) fft_pass<T, 16, 8, INTER, false, false>(buf, lg_n, np, lg_np, tw + s.off[2], in, out);
+    const typename vec<T>::v2 *tl = tw + s.off[last];
+    switch (last) {
+    case 1: fft_pass_r<T, 4, INTER, false, true>(RL, buf, lg_n, np, lg_np, tl, in, out); break;
+    case 2: fft_pass_r<T, 8, INTER, false, true>(RL, buf, lg_n, np, lg_np, tl, in, out); break;
+    default: fft_pass_r<T, 12, INTER, false, true>(RL, buf, lg_n, np, lg_np, tl, in, out); break;
+    }
 }
 
-template <typename T>
+template <typename T, int MODE, bool ONE_ROW>
 __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftArgs a)
 {
     using T2 = typename vec<T>::v2;
@@ -1362,17 +1405,18 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
     // the functors below capture copies of the arguments they use (a
     // reference to the kernel argument itself would move it to scratch)
     const Geometry g = a.g;
-    const int np = a.np, rows = a.rows, mode = a.mode;
+    const int np = ONE_ROW ? 1 : a.np, rows = a.rows;
     const int row0 = blockIdx.x * np;   // rows b * nk + kk of the launch's chunk
+    const int bu = row0 / g.nk, ku = row0 - bu * g.nk;   // realization and row of a one-row block
     // mode 2: the seeds of the block's rows (one row: a scalar; several: after the rows in LDS)
     uint64_t seed0 = 0;
-    uint64_t *seed_l = reinterpret_cast<uint64_t *>(buf + static_cast<long>(np) * g.nt);
-    if (mode == 2) {
+    uint64_t *seed_l = reinterpret_cast<uint64_t *>(buf + fft_lds_elems<T>(np * g.nt));
+    if (MODE == 2) {
         auto seed_of = [](const TfftArgs &x, int row, int nk) -> uint64_t {
             const int b = row / nk;
             return x.seeds_dev ? x.seeds_dev[x.b0 + b] : x.seeds.s[b];
         };
-        if (np == 1) {
+        if (ONE_ROW) {
             seed0 = seed_of(a, row0, g.nk);
         } else {
             for (int f = threadIdx.x; f < np; f += blockDim.x)
@@ -1398,12 +1442,16 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         } else if (row >= rows) {
             return C;
         }
-        const int b = row / g.nk, kk = row - b * g.nk;
+        int b = bu, kk = ku;
+        if (!ONE_ROW) {
+            b = row / g.nk;
+            kk = row - b * g.nk;
+        }
         const int c = kw + g.nw - 1;
-        if (mode == 2) {
+        if constexpr (MODE == 2) {
             // C = A_pure e^{i phi}: the phase of the line as the phase kernel
             // draws it (Philox word, FP64 sincos, rounded)
-            const uint64_t seed = np == 1 ? seed0 : seed_l[f];
+            const uint64_t seed = ONE_ROW ? seed0 : seed_l[f];
             const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
             double sn, cs;
             sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &sn, &cs);
@@ -1417,7 +1465,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
             }
             C.x = p * static_cast<T>(cs);
             C.y = p * static_cast<T>(sn);
-        } else if (mode == 0) {
+        } else if constexpr (MODE == 0) {
             C = assemble_line<T>(g, b, kk, c, zrow, tsum, amp, wtab);
         } else {
             C = cin[static_cast<long>(row) * g.nc + c];
@@ -1435,7 +1483,11 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
             return;
         }
         // tile-major rows: the x-transform of a tile then reads one contiguous block
-        const int b = row / g.nk, kk = row - b * g.nk;
+        int b = bu, kk = ku;
+        if (!ONE_ROW) {
+            b = row / g.nk;
+            kk = row - b * g.nk;
+        }
         const int tile = n >> lg_w;
         gout[static_cast<long>(b) * g.nk * g.nt + (static_cast<long>(tile) * g.nk + kk) * xtw + (n - (tile << lg_w))] = v;
     };
@@ -1554,19 +1606,17 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void xfft_kernel(XfftA
         return r;
     };
     T *outp = a.out_b ? static_cast<T *>(a.out_b[b]) : static_cast<T *>(a.out) + static_cast<long>(b) * g.nx * g.nt;
-    // pairs of columns as one store where the field is aligned for it
-    const bool vec_out = (reinterpret_cast<uintptr_t>(outp) & (sizeof(T2) - 1)) == 0 && (g.nt & 1) == 0;
+    // pairs of columns as one store where the field is aligned for it (the
+    // usual case: an even tile width and an aligned field)
+    const bool vec_out = (reinterpret_cast<uintptr_t>(outp) & (sizeof(T2) - 1)) == 0 && (g.nt & 1) == 0 &&
+                         (tc & 1) == 0;
     auto out = [&](int f, int mx, T2 z) {
         T *o = outp + static_cast<long>(mx) * g.nt + mt0 + 2 * f;
-        if (2 * f + 1 < tc) {
-            if (vec_out) {
-                *reinterpret_cast<T2 *>(o) = z;
-            } else {
-                o[0] = z.x;
-                o[1] = z.y;
-            }
+        if (vec_out) {
+            *reinterpret_cast<T2 *>(o) = z;
         } else {
             o[0] = z.x;
+            if (2 * f + 1 < tc) o[1] = z.y;
         }
     };
     fft_block<T, true>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
@@ -2469,8 +2519,9 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     // short rows share a block (1024 elements per block, at most 64 rows)
     a.np = g.nt >= 1024 ? 1 : std::min(64, 1024 / g.nt);
     const int thr = fft_block_threads(static_cast<long>(a.np) * g.nt);
-    // rows, then (several rows per block) their seeds
-    const size_t lds = static_cast<size_t>(a.np) * g.nt * sizeof(T2) + (a.np > 1 ? a.np * sizeof(uint64_t) : 0);
+    // rows (padded), then (several rows per block) their seeds
+    const size_t lds = static_cast<size_t>(fft_lds_elems<T>(a.np * g.nt)) * sizeof(T2) +
+                       (a.np > 1 ? a.np * sizeof(uint64_t) : 0);
     // mode 2 with host seeds: kernel-argument chunks of realizations (the
     // per-realization spectrum and scale arrays are not used in this mode)
     const int chunk = mode == 2 ? kMaxSeedsPerLaunch : batch;
@@ -2484,7 +2535,16 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
             if (c.rout) c.rout = static_cast<T *>(rout) + static_cast<long>(b0) * g.nt;
         }
         const unsigned blocks = static_cast<unsigned>((c.rows + a.np - 1) / a.np);
-        tfft_kernel<T><<<dim3(blocks), thr, lds, st>>>(c);
+        const bool one = a.np == 1;
+        if (mode == 2)
+            one ? tfft_kernel<T, 2, true><<<dim3(blocks), thr, lds, st>>>(c)
+                : tfft_kernel<T, 2, false><<<dim3(blocks), thr, lds, st>>>(c);
+        else if (mode == 0)
+            one ? tfft_kernel<T, 0, true><<<dim3(blocks), thr, lds, st>>>(c)
+                : tfft_kernel<T, 0, false><<<dim3(blocks), thr, lds, st>>>(c);
+        else
+            one ? tfft_kernel<T, 1, true><<<dim3(blocks), thr, lds, st>>>(c)
+                : tfft_kernel<T, 1, false><<<dim3(blocks), thr, lds, st>>>(c);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -2782,9 +2842,16 @@ template <typename T>
 static hipError_t prepare_t()
 {
     const int lds = 131072;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tfft_kernel<T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
+    // the transforms' padded rows take up to 139 KB (of the 160 KB of a workgroup)
+    const void *tk[] = {reinterpret_cast<const void *>(&tfft_kernel<T, 0, true>),
+                        reinterpret_cast<const void *>(&tfft_kernel<T, 0, false>),
+                        reinterpret_cast<const void *>(&tfft_kernel<T, 1, true>),
+                        reinterpret_cast<const void *>(&tfft_kernel<T, 1, false>),
+                        reinterpret_cast<const void *>(&tfft_kernel<T, 2, true>),
+                        reinterpret_cast<const void *>(&tfft_kernel<T, 2, false>)};
+    hipError_t e = hipSuccess;
+    for (const void *k : tk)
+        if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 163840)) != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&rowconv_kernel<T, kFftMaxB>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
@@ -2792,7 +2859,7 @@ static hipError_t prepare_t()
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void *>(&xfft_kernel<T>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
 }
 
 hipError_t prepare_transforms(int precision)
