@@ -160,6 +160,38 @@ template <> struct ALayout<double> {
 };
 
 // ---------------------------------------------------------------------------
+// Phase factor e^{i phi} of a 32-bit fixed-point phase u (phi = 2 pi u / 2^32)
+// in FP64, shared by every kernel that draws phases: the top 8 bits select
+// e^{2 pi i (u >> 24) / 256} from a 256-entry table (FP64 sincospi, built in
+// LDS by each block), the low 24 bits give theta = 2 pi (u mod 2^24) / 2^32 <
+// 2 pi / 256, whose cosine and sine come from their Taylor series through
+// theta^6 and theta^7 (the next terms are below 1e-17), and the two factors
+// are multiplied: a few ulp of FP64, for a fraction of a sincos.  The
+// arithmetic is written out in fma() calls so that no call site can contract
+// it differently (phases drawn by different kernels agree bitwise).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void phase_table_fill(double2 *tab)
+{
+    for (int m = threadIdx.x; m < 256; m += blockDim.x) {
+        double sn, cs;
+        sincospi(static_cast<double>(m) * (1.0 / 128.0), &sn, &cs);
+        tab[m] = make_double2(cs, sn);
+    }
+}
+
+__device__ __forceinline__ void phase_cs(uint32_t u, const double2 *tab, double &c, double &s)
+{
+    const double2 t = tab[u >> 24];
+    const double th = static_cast<double>(u & 0xFFFFFFu) * 1.4629180792671596e-09;   // 2 pi / 2^32
+    const double t2 = th * th;
+    const double ct = fma(t2, fma(t2, fma(t2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double st = th * fma(t2, fma(t2, fma(t2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    // explicit fused products: every kernel that inlines this rounds alike
+    c = fma(t.x, ct, -(t.y * st));
+    s = fma(t.y, ct, t.x * st);
+}
+
+// ---------------------------------------------------------------------------
 // Phases.  A block covers a tile of 64 columns x TR rows of one realization:
 // each thread draws TR / 4 lines of its column (phase rows written along the
 // columns), and the a operand, which is kappa-contiguous, is staged in LDS
@@ -173,6 +205,9 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
 {
     constexpr int TR = sizeof(T) == 8 ? 32 : 64;   // rows per tile
     __shared__ T at[3][64][TR + 1];
+    __shared__ double2 ptab[256];
+    phase_table_fill(ptab);
+    __syncthreads();
     const int bl = blockIdx.z;
     const int b = b0 + bl;
     const int c0 = blockIdx.x * 64, k0 = blockIdx.y * TR;
@@ -189,7 +224,7 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         double s = 0.0, co = 0.0;   // rows past n_kappa (padding) hold zero
         if (c < g.nc && kk < g.nk) {
             const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
-            sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &s, &co);
+            phase_cs(u, ptab, co, s);
             if (lr) {
                 // per-line complex bicoherence factor rho_k carried by the phase factor
                 const long l = static_cast<long>(kk) * g.nc + c;
@@ -1407,22 +1442,42 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
     const Geometry g = a.g;
     const int np = ONE_ROW ? 1 : a.np, rows = a.rows;
     const int row0 = blockIdx.x * np;   // rows b * nk + kk of the launch's chunk
-    const int bu = row0 / g.nk, ku = row0 - bu * g.nk;   // realization and row of a one-row block
+    // one-row blocks assembling from pair sums run row-major over (kk, b):
+    // consecutive blocks take the same wavenumber row of successive
+    // realizations, so its per-line plan data (amplitudes) is read from L2.
+    // The other modes run over (b, kk): consecutive blocks write adjacent rows
+    // of the tile-major output (measured faster for them).
+    const int nbat = rows / g.nk;
+    int ku = 0, bu = 0;
+    if (ONE_ROW) {
+        if (MODE == 0) {
+            ku = static_cast<int>(blockIdx.x) / nbat;
+            bu = static_cast<int>(blockIdx.x) - ku * nbat;
+        } else {
+            bu = static_cast<int>(blockIdx.x) / g.nk;
+            ku = static_cast<int>(blockIdx.x) - bu * g.nk;
+        }
+    }
+    const int rowu = bu * g.nk + ku;
     // mode 2: the seeds of the block's rows (one row: a scalar; several: after the rows in LDS)
     uint64_t seed0 = 0;
     uint64_t *seed_l = reinterpret_cast<uint64_t *>(buf + fft_lds_elems<T>(np * g.nt));
+    // mode 2: the phase-factor table after the rows and their seeds (16-byte aligned)
+    double2 *ptab = reinterpret_cast<double2 *>(
+        (reinterpret_cast<uintptr_t>(seed_l + (np > 1 ? np : 0)) + 15) & ~static_cast<uintptr_t>(15));
+    if (MODE == 2) phase_table_fill(ptab);
     if (MODE == 2) {
         auto seed_of = [](const TfftArgs &x, int row, int nk) -> uint64_t {
             const int b = row / nk;
             return x.seeds_dev ? x.seeds_dev[x.b0 + b] : x.seeds.s[b];
         };
         if (ONE_ROW) {
-            seed0 = seed_of(a, row0, g.nk);
+            seed0 = a.seeds_dev ? a.seeds_dev[a.b0 + bu] : a.seeds.s[bu];
         } else {
             for (int f = threadIdx.x; f < np; f += blockDim.x)
                 seed_l[f] = row0 + f < rows ? seed_of(a, row0 + f, g.nk) : 0;
-            __syncthreads();
         }
+        __syncthreads();   // seeds and phase table
     }
     const AmpArgs amp = a.amp;
     const T2 *zrow = static_cast<const T2 *>(a.zrow);
@@ -1434,7 +1489,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         T2 C;
         C.x = T(0);
         C.y = T(0);
-        const int row = row0 + f;
+        const int row = ONE_ROW ? rowu : row0 + f;
         int kw = n;
         if (n >= g.nw) {
             if (n <= g.nt - g.nw || row >= rows) return C;
@@ -1450,11 +1505,11 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         const int c = kw + g.nw - 1;
         if constexpr (MODE == 2) {
             // C = A_pure e^{i phi}: the phase of the line as the phase kernel
-            // draws it (Philox word, FP64 sincos, rounded)
+            // draws it (Philox word, phase_cs, rounded)
             const uint64_t seed = ONE_ROW ? seed0 : seed_l[f];
             const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
             double sn, cs;
-            sincospi(static_cast<double>(u) * (1.0 / 2147483648.0), &sn, &cs);
+            phase_cs(u, ptab, cs, sn);
             const long li = static_cast<long>(kk) * g.nc + c;
             T p;
             if (amp.tab && !amp.S_b) {
@@ -1476,7 +1531,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
     T *rout = static_cast<T *>(a.rout);
     T2 *gout = static_cast<T2 *>(a.gout);
     auto out = [=](int f, int n, T2 v) {
-        const int row = row0 + f;
+        const int row = ONE_ROW ? rowu : row0 + f;
         if (row >= rows) return;
         if (rout) {   // one kappa line and one x point: the x-transform is the real part
             rout[static_cast<long>(row) * g.nt + n] = v.x;
@@ -2519,9 +2574,10 @@ static hipError_t tfft_t(const Geometry &g, int mode, const void *cin, const Amp
     // short rows share a block (1024 elements per block, at most 64 rows)
     a.np = g.nt >= 1024 ? 1 : std::min(64, 1024 / g.nt);
     const int thr = fft_block_threads(static_cast<long>(a.np) * g.nt);
-    // rows (padded), then (several rows per block) their seeds
+    // rows (padded), then (several rows per block) their seeds, then (mode 2)
+    // the phase-factor table, 16-byte aligned
     const size_t lds = static_cast<size_t>(fft_lds_elems<T>(a.np * g.nt)) * sizeof(T2) +
-                       (a.np > 1 ? a.np * sizeof(uint64_t) : 0);
+                       (a.np > 1 ? a.np * sizeof(uint64_t) : 0) + (mode == 2 ? 256 * sizeof(double2) + 16 : 0);
     // mode 2 with host seeds: kernel-argument chunks of realizations (the
     // per-realization spectrum and scale arrays are not used in this mode)
     const int chunk = mode == 2 ? kMaxSeedsPerLaunch : batch;

@@ -69,3 +69,44 @@ def test_mfma_instruction_model_matches_the_counters():
         assert abs(model - measured) <= 1e-4 * measured, (name, model, measured)
     useful = bench.pair_terms_total(inp.C1) / (bench.mfma_instructions(inp.C1) / 3 * 1024)
     assert 0.93 < useful < 0.94
+
+
+@pytest.mark.parametrize("name", SUMMARIES)
+def test_counter_summary_duration_is_its_kernels(name):
+    """The duration a counter summary derives its rates from is the kernel
+    trace's average for the same kernel (full name, template arguments
+    included) in the same workload, and the clock it implies is the chip's."""
+    import re
+    path = os.path.join(ROOT, "profiles", name)
+    if not _current(name):
+        pytest.skip(f"{name} predates the kernel source")
+    text = open(path).read()
+    m = re.search(r"kernel duration ([0-9.]+) ms: .*? of `([^`]+)`", text)
+    assert m, name
+    ms, kernel = float(m.group(1)), m.group(2)
+    wl = name.split("_counters")[0].split("pairsum_mfma_")[-1].split("pairsum_")[-1]
+    trace = os.path.join(ROOT, "profiles", f"pairsum_{wl}_kernel_trace.md")
+    avgs = []
+    for line in open(trace):
+        cells = [c.strip() for c in line.split("|")]
+        if len(cells) > 6 and cells[1] == f"`{kernel}`":
+            avgs.append(float(cells[5]))
+    assert any(abs(a - ms) <= 5e-4 * ms for a in avgs), (name, ms, avgs)
+    ghz = float(re.search(r"-> ([0-9.]+) GHz", text).group(1))
+    assert 2.0 <= ghz <= 2.5, (name, ghz)
+
+
+@pytest.mark.parametrize("wl", ["c1_256x1024_b64", "c2_512x8192_w2048_b16"])
+def test_transform_summaries(wl):
+    """Phases and transforms: one row per launch kind, measured HBM traffic
+    within a small factor of the algorithmic bytes (no wasted re-reads)."""
+    path = os.path.join(ROOT, "profiles", f"transforms_{wl}_counters.md")
+    digest = hashlib.sha256(open(SRC, "rb").read()).hexdigest()
+    if _field(path, "kernel source sha256") != digest:
+        pytest.skip("transform summary predates the kernel source")
+    rows = [l for l in open(path) if l.startswith("| ") and "`" in l]
+    assert len(rows) == 5
+    for r in rows:
+        cells = [c.strip() for c in r.split("|")]
+        ratio = float(cells[8])
+        assert 0.9 < ratio < 2.5, r
