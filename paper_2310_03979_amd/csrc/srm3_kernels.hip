@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
                 // per-line complex bicoherence factor rho_k carried by the phase factor
                 const long l = static_cast<long>(kk) * g.nc + c;
                 const double xr = lr[2 * l], xi = lr[2 * l + 1];
-                const double cr = co * xr - s * xi, ci = co * xi + s * xr;
+                const double cr = fma(co, xr, -(s * xi)), ci = fma(co, xi, s * xr);   // fused as in phase_cs
                 co = cr;
                 s = ci;
             }
@@ -267,6 +267,45 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
             zc[plane] = at[1][ct2][kt];
             zc[2 * plane] = at[2][ct2][kt];
         }
+    }
+}
+
+// Phase rows only (no a operand: the kappa-DFT, 2-D FFT, per-pair and
+// process paths): 2048 consecutive lines of one realization per block, eight
+// per thread, written along the rows.
+template <typename T>
+__global__ __launch_bounds__(256) void phase_rows_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
+                                                         int b0, Geometry g, typename vec<T>::v2 *__restrict__ zrow,
+                                                         const double *__restrict__ lr)
+{
+    __shared__ double2 ptab[256];
+    phase_table_fill(ptab);
+    __syncthreads();
+    const int bl = blockIdx.y;
+    const int b = b0 + bl;
+    const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
+    const long per = static_cast<long>(g.nk) * g.nc;
+    const long base = static_cast<long>(blockIdx.x) * 2048 + threadIdx.x;
+#pragma unroll 2
+    for (int i = 0; i < 8; ++i) {
+        const long l = base + 256 * i;
+        if (l >= per) break;
+        const int kk = static_cast<int>(l / g.nc);
+        const int c = static_cast<int>(l - static_cast<long>(kk) * g.nc);
+        const int kw = c - (g.nw - 1);
+        const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
+        double co, s;
+        phase_cs(u, ptab, co, s);
+        if (lr) {
+            const double xr = lr[2 * l], xi = lr[2 * l + 1];
+            const double cr = fma(co, xr, -(s * xi)), ci = fma(co, xi, s * xr);   // fused as in phase_cs
+            co = cr;
+            s = ci;
+        }
+        typename vec<T>::v2 v;
+        v.x = static_cast<T>(co);
+        v.y = static_cast<T>(s);
+        zrow[static_cast<long>(b) * per + l] = v;
     }
 }
 
@@ -2271,6 +2310,14 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
         SeedChunk sc{};
         if (!seeds_dev)
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
+        if (!ws.zcol) {
+            const long per = static_cast<long>(g.nk) * g.nc;
+            phase_rows_kernel<T><<<dim3(static_cast<unsigned>((per + 2047) / 2048), nb), 256, 0, st>>>(
+                sc, seeds_dev, b0, g, static_cast<typename vec<T>::v2 *>(ws.zrow), lr);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            continue;
+        }
         phase_kernel<T><<<dim3(gx, gy, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
                                                        static_cast<typename vec<T>::v2 *>(ws.zrow),
                                                        static_cast<T *>(ws.zcol), lr);
