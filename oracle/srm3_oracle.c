@@ -13,8 +13,10 @@
  * Definitions (readings of the paper are listed in the design notes):
  *  - Lines: k = (kk, kw) with 0 <= kk < NK and -NW < kw < NW (signed frequency,
  *    half-plane kappa >= 0, Section 2 symmetries).  Line value S_k = S(kappa, omega).
- *  - Phase of line k: phi_k = 2 pi U_k / 2^32, U_k = Philox4x32-10 word 0 with
- *    key = realization seed, counter = (kk, kw as uint32, 0, 0).
+ *  - Phase of line k: phi_k = 2 pi U_k / 2^32.  One Philox4x32-10 call (key =
+ *    realization seed) serves four consecutive frequencies of a row: U_k is
+ *    word r of counter (kk, q as uint32, 0, 0), kw = 4 q + r, 0 <= r < 4
+ *    (q = floor(kw / 4)).
  *  - Biphase: beta(iw, jw) = 2 pi V / 2^32, V = Philox word 0 with key = beta
  *    seed, counter = (max(iw,jw), min(iw,jw), 1, 0) -- symmetric in (iw, jw).
  *  - P(k): unordered pairs {i, j} of lines with i + j = k (both components),
@@ -71,6 +73,20 @@ static uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint64_t key
     return out[0];
 }
 
+/* Fixed-point phase of line (kk, kw): word r of the Philox call with counter
+ * (kk, q, 0, 0), where kw = 4 q + r with 0 <= r < 4 (floor division, also for
+ * negative kw). */
+static uint32_t phase_word(int kk, int kw, uint64_t seed)
+{
+    const int q = kw >= 0 ? kw / 4 : -((3 - kw) / 4);
+    const int r = kw - 4 * q;
+    uint32_t ctr[4] = {(uint32_t)kk, (uint32_t)(int32_t)q, 0u, 0u};
+    uint32_t k[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, k, out);
+    return out[r];
+}
+
 /* Random phase angles (fixed point, 2^32 == 2 pi) of every line, [nk][2nw-1]. */
 void oracle_phases(int nk, int nw, uint64_t seed, uint32_t *U)
 {
@@ -78,8 +94,7 @@ void oracle_phases(int nk, int nw, uint64_t seed, uint32_t *U)
 #pragma omp parallel for schedule(static)
     for (int kk = 0; kk < nk; ++kk)
         for (int kw = -(nw - 1); kw <= nw - 1; ++kw)
-            U[(size_t)kk * nc + (kw + nw - 1)] =
-                philox_word0((uint32_t)kk, (uint32_t)(int32_t)kw, 0u, seed);
+            U[(size_t)kk * nc + (kw + nw - 1)] = phase_word(kk, kw, seed);
 }
 
 /* Biphase table (fixed point) over signed frequency indices |iw|,|jw| < W,
@@ -438,7 +453,8 @@ void oracle_field_nested(int nk, int nw, int nx, int nt, const double *C, double
 /*  - Pairs: i + j = k with i >= j >= 0 and i, j < W, each unordered pair    */
 /*    once, the self pair i = j included (the printed index bounds are       */
 /*    garbled; the process has no difference interactions).                 */
-/*  - Phase of frequency k: Philox word 0, key = seed, counter (0, k, 0, 0); */
+/*  - Phase of frequency k: the wave's phase of line (0, k) (key = seed,    */
+/*    word k mod 4 of counter (0, floor(k / 4), 0, 0));                      */
 /*    biphase beta(i, j): key = beta seed, counter (max, min, 1, 0).         */
 /*  - rho_k, b_p^2 = rho_k b2_raw, Sigma_k, pure part sqrt(1 - Sigma_k) as   */
 /*    for the wave (the pure-spectrum equation with b_p^2).                  */
@@ -457,7 +473,7 @@ typedef struct {
 
 void oracle_process_phases(int n, uint64_t seed, uint32_t *U)
 {
-    for (int k = 0; k < n; ++k) U[k] = philox_word0(0u, (uint32_t)k, 0u, seed);
+    for (int k = 0; k < n; ++k) U[k] = phase_word(0, k, seed);
 }
 
 void oracle_process_biphase(int W, int mode, uint64_t beta_seed, uint32_t *beta)

@@ -48,13 +48,19 @@ def test_philox_known_answers(oracle_mod):
 
 
 def test_phase_and_biphase_streams(oracle_mod):
-    """Phases use counter (kk, kw, 0, 0); biphases (max, min, 1, 0), symmetric."""
-    U = oracle_mod.phases(3, 4, seed=0x1234_5678_9ABC)
+    """Phases: word kw mod 4 of counter (kk, floor(kw / 4), 0, 0), so one call
+    serves four consecutive frequencies; biphases (max, min, 1, 0), symmetric."""
+    nw = 11
+    U = oracle_mod.phases(3, nw, seed=0x1234_5678_9ABC)
     key = [0x56789ABC, 0x1234]
     for kk in range(3):
-        for kw in range(-3, 4):
-            ctr = [kk, kw & 0xFFFFFFFF, 0, 0]
-            assert U[kk, kw + 3] == oracle_mod.philox4x32_10(ctr, key)[0]
+        for kw in range(-(nw - 1), nw):
+            ctr = [kk, (kw // 4) & 0xFFFFFFFF, 0, 0]
+            assert U[kk, kw + nw - 1] == oracle_mod.philox4x32_10(ctr, key)[kw % 4]
+    # the four words of one call, e.g. counter (2, -2): k_w = -8 .. -5
+    w = oracle_mod.philox4x32_10([2, (-2) & 0xFFFFFFFF, 0, 0], key)
+    assert [int(x) for x in U[2, -8 + nw - 1:-4 + nw - 1]] == [int(x) for x in w]
+    assert len(set(int(x) for x in U.ravel())) == U.size   # no word serves two lines
     B = oracle_mod.biphase(3, seed=77)
     assert np.array_equal(B, B.T)
     assert B[4, 0] == oracle_mod.philox4x32_10([2, (-2) & 0xFFFFFFFF, 1, 0], [77, 0])[0]
