@@ -23,10 +23,12 @@
  *  - Pairs: unordered {i, j} with i + j = k in both components, both partners
  *    inside the bicoherence support |i_omega|, |j_omega| < support_w, self pair
  *    included, each pair counted once.
- *  - Phases: phi_k = 2 pi U / 2^32 with U the first word of Philox4x32-10
- *    (Salmon et al., SC'11) under key = realization seed (low word first) and
- *    counter = (k_kappa, (uint32)k_omega, 0, 0).  Seeded biphases use key =
- *    beta_seed and counter = (max(i_w, j_w), min(i_w, j_w), 1, 0).
+ *  - Phases: phi_k = 2 pi U / 2^32 with U a word of Philox4x32-10 (Salmon et
+ *    al., SC'11) under key = realization seed (low word first): one call
+ *    serves four consecutive frequencies, U = word r of counter
+ *    (k_kappa, (uint32)q, 0, 0) with k_omega = 4 q + r, 0 <= r < 4.  Seeded
+ *    biphases use key = beta_seed, counter = (max(i_w, j_w), min(i_w, j_w), 1, 0)
+ *    and word 0.
  *  - Streams: every device action is enqueued on the caller's hipStream_t
  *    (passed as void*; NULL = the default stream).  Calls return before the
  *    work finishes.  One plan may be driven by one stream at a time.

@@ -191,30 +191,75 @@ __device__ __forceinline__ void phase_cs(uint32_t u, const double2 *tab, double 
     s = fma(t.y, ct, t.x * st);
 }
 
+// Phase words.  One Philox4x32-10 call (key = the realization's seed) serves
+// the four consecutive frequencies k_omega = 4 q .. 4 q + 3 of row k_kappa:
+// counter (k_kappa, q, 0, 0), word k_omega - 4 q.  q = floor(k_omega / 4).
 // ---------------------------------------------------------------------------
-// Phases.  A block covers a tile of 64 columns x TR rows of one realization:
-// each thread draws TR / 4 lines of its column (phase rows written along the
-// columns), and the a operand, which is kappa-contiguous, is staged in LDS
-// and written along the rows.
+__host__ __device__ inline int floor_div4(int kw) { return (kw >= 0 ? kw : kw - 3) / 4; }
+
+__device__ __forceinline__ void phase_words(int kk, int q, uint64_t seed, uint32_t (&w)[4])
+{
+    philox_words4(static_cast<uint32_t>(kk), static_cast<uint32_t>(q), 0u, 0u, seed, w);
+}
+
+// Phase factor of a line with its per-line complex factor rho_k (if any).
+__device__ __forceinline__ void phase_line(uint32_t u, const double2 *ptab, const double *__restrict__ lr, long l,
+                                           double &co, double &s)
+{
+    phase_cs(u, ptab, co, s);
+    if (lr) {
+        // per-line complex bicoherence factor rho_k carried by the phase factor
+        const double xr = lr[2 * l], xi = lr[2 * l + 1];
+        const double cr = fma(co, xr, -(s * xi)), ci = fma(co, xi, s * xr);   // fused as in phase_cs
+        co = cr;
+        s = ci;
+    }
+}
+
 // ---------------------------------------------------------------------------
-template <typename T>
+// Phases with the a operand.  A block covers a tile of 64 frequencies (16
+// generator calls, aligned to multiples of 4 in k_omega) x TR rows of one
+// realization.  The generator words are drawn call by call into LDS; then
+// each thread takes one column and TR / 4 of its rows, writes the phase rows
+// along the columns, and stages the kappa-contiguous a operand in LDS to
+// write it along the rows.  TR = 16 serves plans with few rows.
+// ---------------------------------------------------------------------------
+template <typename T, int TR>
 __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
                                                     int b0, Geometry g,
                                                     typename vec<T>::v2 *__restrict__ zrow,
                                                     T *__restrict__ zcol, const double *__restrict__ lr)
 {
-    constexpr int TR = sizeof(T) == 8 ? 32 : 64;   // rows per tile
+    static_assert(TR % 16 == 0, "rows per tile");
     __shared__ T at[3][64][TR + 1];
+    __shared__ __align__(16) uint32_t wt[TR][68];
     __shared__ double2 ptab[256];
     phase_table_fill(ptab);
-    __syncthreads();
     const int bl = blockIdx.z;
     const int b = b0 + bl;
-    const int c0 = blockIdx.x * 64, k0 = blockIdx.y * TR;
+    const int k0 = blockIdx.y * TR;
     const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
+    // the tile's first frequency: a multiple of 4 at or below -(n_omega - 1)
+    const int q0 = floor_div4(-(g.nw - 1)) + 16 * static_cast<int>(blockIdx.x);
+    const int kw0 = 4 * q0;
+    {
+        const int gi = threadIdx.x & 15;
+        const int q = q0 + gi;
+        const bool live = 4 * q + 3 >= -(g.nw - 1) && 4 * q <= g.nw - 1;
+#pragma unroll
+        for (int i = 0; i < TR / 16; ++i) {
+            const int kt = (threadIdx.x >> 4) + 16 * i;
+            const int kk = k0 + kt;
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            if (live && kk < g.nk) phase_words(kk, q, seed, w);
+            *reinterpret_cast<uint4 *>(&wt[kt][4 * gi]) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+    __syncthreads();   // words and phase table
     const int ct = threadIdx.x & 63;
-    const int c = c0 + ct;
-    const int kw = c - (g.nw - 1);
+    const int kw = kw0 + ct;
+    const int c = kw + g.nw - 1;
+    const int c0 = kw0 + g.nw - 1;
     const int ic0 = c0 - (g.nw - g.W);   // support column of the tile's first column
     const bool planes = zcol && ic0 + 63 >= 0 && ic0 < g.ncw;
 #pragma unroll 4
@@ -222,21 +267,13 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
         const int kt = (threadIdx.x >> 6) + 4 * i;
         const int kk = k0 + kt;
         double s = 0.0, co = 0.0;   // rows past n_kappa (padding) hold zero
-        if (c < g.nc && kk < g.nk) {
-            const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
-            phase_cs(u, ptab, co, s);
-            if (lr) {
-                // per-line complex bicoherence factor rho_k carried by the phase factor
-                const long l = static_cast<long>(kk) * g.nc + c;
-                const double xr = lr[2 * l], xi = lr[2 * l + 1];
-                const double cr = fma(co, xr, -(s * xi)), ci = fma(co, xi, s * xr);   // fused as in phase_cs
-                co = cr;
-                s = ci;
-            }
+        if (c >= 0 && c < g.nc && kk < g.nk) {
+            const long l = static_cast<long>(kk) * g.nc + c;
+            phase_line(wt[kt][ct], ptab, lr, l, co, s);
             typename vec<T>::v2 v;
             v.x = static_cast<T>(co);
             v.y = static_cast<T>(s);
-            zrow[(static_cast<long>(b) * g.nk + kk) * g.nc + c] = v;
+            zrow[static_cast<long>(b) * g.nk * g.nc + l] = v;
         }
         if (planes) {
             at[0][ct][kt] = static_cast<T>(co);
@@ -271,42 +308,61 @@ __global__ __launch_bounds__(256) void phase_kernel(SeedChunk seeds, const uint6
 }
 
 // Phase rows only (no a operand: the kappa-DFT, 2-D FFT, per-pair and
-// process paths): 2048 consecutive lines of one realization per block, eight
-// per thread, written along the rows.
+// process paths).  A block takes 512 consecutive generator calls (row-major
+// over (k_kappa, q)) of one realization, two per thread; their lines form one
+// contiguous run of the phase rows, staged in LDS and written out along it.
+constexpr int kPhaseRowCalls = 512;
+
 template <typename T>
 __global__ __launch_bounds__(256) void phase_rows_kernel(SeedChunk seeds, const uint64_t *__restrict__ seeds_dev,
                                                          int b0, Geometry g, typename vec<T>::v2 *__restrict__ zrow,
                                                          const double *__restrict__ lr)
 {
+    using T2 = typename vec<T>::v2;
+    __shared__ T2 zl[4 * kPhaseRowCalls];
     __shared__ double2 ptab[256];
     phase_table_fill(ptab);
     __syncthreads();
     const int bl = blockIdx.y;
     const int b = b0 + bl;
     const uint64_t seed = seeds_dev ? seeds_dev[b] : seeds.s[bl];
-    const long per = static_cast<long>(g.nk) * g.nc;
-    const long base = static_cast<long>(blockIdx.x) * 2048 + threadIdx.x;
-#pragma unroll 2
-    for (int i = 0; i < 8; ++i) {
-        const long l = base + 256 * i;
-        if (l >= per) break;
-        const int kk = static_cast<int>(l / g.nc);
-        const int c = static_cast<int>(l - static_cast<long>(kk) * g.nc);
-        const int kw = c - (g.nw - 1);
-        const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
-        double co, s;
-        phase_cs(u, ptab, co, s);
-        if (lr) {
-            const double xr = lr[2 * l], xi = lr[2 * l + 1];
-            const double cr = fma(co, xr, -(s * xi)), ci = fma(co, xi, s * xr);   // fused as in phase_cs
-            co = cr;
-            s = ci;
+    const int qmin = floor_div4(-(g.nw - 1)), qmax = floor_div4(g.nw - 1);
+    const int ng = qmax - qmin + 1;
+    const long calls = static_cast<long>(g.nk) * ng;
+    const long u0 = static_cast<long>(blockIdx.x) * kPhaseRowCalls;
+    const long u1 = std::min(u0 + kPhaseRowCalls, calls) - 1;
+    // first and last line of the block's calls (the rows' end calls are partial)
+    auto first_line = [&](long u) {
+        const int kk = static_cast<int>(u / ng), q = qmin + static_cast<int>(u - static_cast<long>(kk) * ng);
+        return static_cast<long>(kk) * g.nc + std::max(4 * q, -(g.nw - 1)) + g.nw - 1;
+    };
+    const long L0 = first_line(u0);
+    const int kk1 = static_cast<int>(u1 / ng), q1 = qmin + static_cast<int>(u1 - static_cast<long>(kk1) * ng);
+    const long L1 = static_cast<long>(kk1) * g.nc + std::min(4 * q1 + 3, g.nw - 1) + g.nw - 1;
+#pragma unroll
+    for (int i = 0; i < kPhaseRowCalls / 256; ++i) {
+        const long u = u0 + threadIdx.x + 256 * i;
+        if (u > u1) break;
+        const int kk = static_cast<int>(u / ng);
+        const int q = qmin + static_cast<int>(u - static_cast<long>(kk) * ng);
+        uint32_t w[4];
+        phase_words(kk, q, seed, w);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kw = 4 * q + j;
+            if (kw < -(g.nw - 1) || kw > g.nw - 1) continue;
+            const long l = static_cast<long>(kk) * g.nc + kw + g.nw - 1;
+            double co, s;
+            phase_line(w[j], ptab, lr, l, co, s);
+            T2 v;
+            v.x = static_cast<T>(co);
+            v.y = static_cast<T>(s);
+            zl[l - L0] = v;
         }
-        typename vec<T>::v2 v;
-        v.x = static_cast<T>(co);
-        v.y = static_cast<T>(s);
-        zrow[static_cast<long>(b) * per + l] = v;
     }
+    __syncthreads();
+    T2 *zb = zrow + static_cast<long>(b) * g.nk * g.nc + L0;
+    for (int i = threadIdx.x; i <= L1 - L0; i += 256) zb[i] = zl[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1445,21 +1501,23 @@ __device__ __forceinline__ void fft_pass_r(int R, typename vec<T>::v2 *buf, int 
 
 // np transforms of length s.N (blockDim.x * 16 >= np N elements).  The pass
 // spans are 1, 16, 256, 4096 (compile time): radix 16 up to the last pass.
-template <typename T, bool INTER, class In, class Out>
+// STAGED: the inputs are already in LDS (transform-major, padded), written by
+// the caller before a barrier; the first pass reads them from there.
+template <typename T, bool INTER, bool STAGED, class In, class Out>
 __device__ __forceinline__ void fft_block(typename vec<T>::v2 *buf, const FftSched &s, int np,
                                           const typename vec<T>::v2 *tw, const In &in, const Out &out)
 {
     if (s.npass == 0) {   // N = 1
-        for (int f = threadIdx.x; f < np; f += blockDim.x) out(f, 0, in(f, 0));
+        for (int f = threadIdx.x; f < np; f += blockDim.x) out(f, 0, STAGED ? buf[lpad<T>(f)] : in(f, 0));
         return;
     }
     const int lg_n = ilog2i(s.N), lg_np = ilog2i(np);
     const int last = s.npass - 1, RL = s.R[last];
     if (last == 0) {
-        fft_pass_r<T, 0, INTER, true, true>(RL, buf, lg_n, np, lg_np, tw, in, out);
+        fft_pass_r<T, 0, INTER, !STAGED, true>(RL, buf, lg_n, np, lg_np, tw, in, out);
         return;
     }
-    fft_pass<T, 16, 0, INTER, true, false>(buf, lg_n, np, lg_np, tw, in, out);
+    fft_pass<T, 16, 0, INTER, !STAGED, false>(buf, lg_n, np, lg_np, tw, in, out);
     if (last >= 2) fft_pass<T, 16, 4, INTER, false, false>(buf, lg_n, np, lg_np, tw + s.off[1], in, out);
     if (last >= 3) fft_pass<T, 16, 8, INTER, false, false>(buf, lg_n, np, lg_np, tw + s.off[2], in, out);
     const typename vec<T>::v2 *tl = tw + s.off[last];
@@ -1519,6 +1577,62 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         __syncthreads();   // seeds and phase table
     }
     const AmpArgs amp = a.amp;
+    const int lg_n = ilog2i(g.nt);
+    if constexpr (MODE == 2) {
+        // C = A_pure e^{i phi} of every line of the block's rows, staged in
+        // LDS at its bin (k_w, or k_w + n_t below zero), one generator call
+        // (four frequencies) per step; the phases are those the phase kernel
+        // draws (same words, phase_cs, rounding)
+        const int qmin = floor_div4(-(g.nw - 1)), qmax = floor_div4(g.nw - 1);
+        const int ng = qmax - qmin + 1;
+        for (int u = threadIdx.x; u < np * ng; u += blockDim.x) {
+            const int f = u / ng;
+            const int q = qmin + (u - f * ng);
+            const int row = ONE_ROW ? rowu : row0 + f;
+            const bool live = row < rows;
+            int b = bu, kk = ku;
+            if (!ONE_ROW) {
+                b = row / g.nk;
+                kk = row - b * g.nk;
+            }
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            if (live) phase_words(kk, q, ONE_ROW ? seed0 : seed_l[f], w);
+            const double *Sp = (amp.S_b && live && amp.S_b[b]) ? amp.S_b[b] : amp.S;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int kw = 4 * q + j;
+                if (kw < -(g.nw - 1) || kw > g.nw - 1) continue;
+                T2 C;
+                C.x = T(0);
+                C.y = T(0);
+                if (live) {
+                    double sn, cs;
+                    phase_cs(w[j], ptab, cs, sn);
+                    const long li = static_cast<long>(kk) * g.nc + kw + g.nw - 1;
+                    T p;
+                    if (amp.tab && !amp.S_b) {
+                        p = static_cast<const T2 *>(amp.tab)[li].x;
+                    } else {
+                        p = static_cast<T>(2.0 * sqrt(Sp[li] * amp.dkdw));
+                    }
+                    C.x = p * static_cast<T>(cs);
+                    C.y = p * static_cast<T>(sn);
+                }
+                const int n = kw >= 0 ? kw : kw + g.nt;
+                buf[lpad<T>((f << lg_n) + n)] = C;
+            }
+        }
+        // the bins between the positive and the negative frequencies
+        const int gap = g.nt - 2 * g.nw + 1;
+        for (int u = threadIdx.x; u < np * gap; u += blockDim.x) {
+            const int f = u / gap;
+            T2 z;
+            z.x = T(0);
+            z.y = T(0);
+            buf[lpad<T>((f << lg_n) + g.nw + (u - f * gap))] = z;
+        }
+        __syncthreads();
+    }
     const T2 *zrow = static_cast<const T2 *>(a.zrow);
     const T2 *tsum = static_cast<const T2 *>(a.tsum);
     const T2 *wtab = static_cast<const T2 *>(a.wtab);
@@ -1543,22 +1657,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         }
         const int c = kw + g.nw - 1;
         if constexpr (MODE == 2) {
-            // C = A_pure e^{i phi}: the phase of the line as the phase kernel
-            // draws it (Philox word, phase_cs, rounded)
-            const uint64_t seed = ONE_ROW ? seed0 : seed_l[f];
-            const uint32_t u = philox_word0(static_cast<uint32_t>(kk), static_cast<uint32_t>(kw), 0u, 0u, seed);
-            double sn, cs;
-            phase_cs(u, ptab, cs, sn);
-            const long li = static_cast<long>(kk) * g.nc + c;
-            T p;
-            if (amp.tab && !amp.S_b) {
-                p = static_cast<const T2 *>(amp.tab)[li].x;
-            } else {
-                const double *Sp = (amp.S_b && amp.S_b[b]) ? amp.S_b[b] : amp.S;
-                p = static_cast<T>(2.0 * sqrt(Sp[li] * amp.dkdw));
-            }
-            C.x = p * static_cast<T>(cs);
-            C.y = p * static_cast<T>(sn);
+            (void)b;   // staged in LDS above; the first pass reads it from there
         } else if constexpr (MODE == 0) {
             C = assemble_line<T>(g, b, kk, c, zrow, tsum, amp, wtab);
         } else {
@@ -1585,7 +1684,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void tfft_kernel(TfftA
         const int tile = n >> lg_w;
         gout[static_cast<long>(b) * g.nk * g.nt + (static_cast<long>(tile) * g.nk + kk) * xtw + (n - (tile << lg_w))] = v;
     };
-    fft_block<T, false>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
+    fft_block<T, false, MODE == 2>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
 }
 
 // (A_pure, A_pair) per line at unit scale: the FP64 expressions of
@@ -1648,10 +1747,13 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void xfft_kernel(XfftA
     extern __shared__ unsigned char smem_raw[];
     T2 *buf = reinterpret_cast<T2 *>(smem_raw);
     const Geometry &g = a.g;
-    const int b = blockIdx.y;
+    // tiles in the reverse of the order the t-transform writes them (by
+    // realization): the most recently written part of G is read first, while
+    // it is still in the Infinity Cache
+    const int b = gridDim.y - 1 - blockIdx.y;
     const int tc = a.tcols;
     const int np = (tc + 1) / 2;   // packed transforms (a single column when tc == 1)
-    const int mt0 = blockIdx.x * tc;
+    const int mt0 = (gridDim.x - 1 - blockIdx.x) * tc;
     const int N = g.nx;
     const int nk = g.nk;
     const T2 *gin = static_cast<const T2 *>(a.gin) + (static_cast<long>(b) * g.nt + mt0) * nk;
@@ -1713,7 +1815,7 @@ __global__ __launch_bounds__(sizeof(T) == 8 ? 512 : 1024) void xfft_kernel(XfftA
             if (2 * f + 1 < tc) o[1] = z.y;
         }
     };
-    fft_block<T, true>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
+    fft_block<T, true, false>(buf, a.sched, np, static_cast<const T2 *>(a.tw), in, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2297,12 +2399,22 @@ Workspace carve_workspace(const Geometry &g, int precision, int batch, void *bas
     return w;
 }
 
+template <typename T, int TR>
+static void launch_phase_tiles(const Geometry &g, const SeedChunk &sc, const uint64_t *seeds_dev, int b0, int nb,
+                               const Workspace &ws, const double *lr, hipStream_t st)
+{
+    // tiles of 64 frequencies from the multiple of 4 at or below -(n_omega - 1)
+    const int kwb = 4 * floor_div4(-(g.nw - 1));
+    const unsigned gx = static_cast<unsigned>((g.nw - kwb + 63) / 64), gy = static_cast<unsigned>((g.nkp + TR - 1) / TR);
+    phase_kernel<T, TR><<<dim3(gx, gy, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
+                                                          static_cast<typename vec<T>::v2 *>(ws.zrow),
+                                                          static_cast<T *>(ws.zcol), lr);
+}
+
 template <typename T>
 static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint64_t *seeds_dev, int batch,
                            const Workspace &ws, const double *lr, hipStream_t st)
 {
-    constexpr int TR = sizeof(T) == 8 ? 32 : 64;
-    const unsigned gx = static_cast<unsigned>((g.nc + 63) / 64), gy = static_cast<unsigned>((g.nkp + TR - 1) / TR);
     // seeds travel as kernel arguments in chunks, or are read from the device
     const int chunk = seeds_dev ? 65535 : kMaxSeedsPerLaunch;
     for (int b0 = 0; b0 < batch; b0 += chunk) {
@@ -2311,16 +2423,16 @@ static hipError_t phases_t(const Geometry &g, const uint64_t *seeds, const uint6
         if (!seeds_dev)
             for (int i = 0; i < nb; ++i) sc.s[i] = seeds[b0 + i];
         if (!ws.zcol) {
-            const long per = static_cast<long>(g.nk) * g.nc;
-            phase_rows_kernel<T><<<dim3(static_cast<unsigned>((per + 2047) / 2048), nb), 256, 0, st>>>(
-                sc, seeds_dev, b0, g, static_cast<typename vec<T>::v2 *>(ws.zrow), lr);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            continue;
+            const long ng = floor_div4(g.nw - 1) - floor_div4(-(g.nw - 1)) + 1;
+            const long calls = static_cast<long>(g.nk) * ng;
+            phase_rows_kernel<T><<<dim3(static_cast<unsigned>((calls + kPhaseRowCalls - 1) / kPhaseRowCalls), nb),
+                                   256, 0, st>>>(sc, seeds_dev, b0, g, static_cast<typename vec<T>::v2 *>(ws.zrow),
+                                                 lr);
+        } else if (g.nkp <= 16) {
+            launch_phase_tiles<T, 16>(g, sc, seeds_dev, b0, nb, ws, lr, st);
+        } else {
+            launch_phase_tiles<T, sizeof(T) == 8 ? 32 : 64>(g, sc, seeds_dev, b0, nb, ws, lr, st);
         }
-        phase_kernel<T><<<dim3(gx, gy, nb), 256, 0, st>>>(sc, seeds_dev, b0, g,
-                                                       static_cast<typename vec<T>::v2 *>(ws.zrow),
-                                                       static_cast<T *>(ws.zcol), lr);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
